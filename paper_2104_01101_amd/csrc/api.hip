@@ -1,0 +1,668 @@
+// C ABI of libtsk: argument validation, workspace planning and the host-side
+// sequencing of Sketch-Tucker-ALS (Alg. 4) and CP-Sketch-Tucker (Alg. 6).
+// Every arithmetic step runs in the kernels of the other translation units;
+// this file only orders launches on the caller's stream.
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "cp.h"
+#include "fit.h"
+#include "kernels.h"
+#include "leverage.h"
+
+namespace tsk {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+namespace {
+
+__global__ void k_convert(const void* src, int src_dtype, int64_t n, void* dst, int prec) {
+  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double v = src_dtype == TSK_F64 ? static_cast<const double*>(src)[t]
+                                  : double(static_cast<const float*>(src)[t]);
+  store_prec(dst, size_t(t), v, prec);
+}
+
+tsk_status convert_tensor_to_prec(const void* src, int dtype, int64_t n, void* dst, int prec,
+                                  hipStream_t st) {
+  if (n <= 0) return TSK_OK;
+  hipLaunchKernelGGL(k_convert, dim3(ceil_div(n, 256)), dim3(256), 0, st, src, dtype, n, dst,
+                     prec);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+bool prec_matches_dtype(int prec, int dtype) {
+  return (prec == TSK_PREC_F64 && dtype == TSK_F64) || (prec == TSK_PREC_F32 && dtype == TSK_F32);
+}
+
+tsk_status view_tensor(const tsk_tensor* T, TensorView& tv) {
+  TSK_REQUIRE(T, "tensor is NULL");
+  TSK_REQUIRE(T->order >= 2 && T->order <= TSK_MAX_ORDER, "tensor order %d not in [2, %d]",
+              T->order, TSK_MAX_ORDER);
+  TSK_REQUIRE(T->dtype == TSK_F32 || T->dtype == TSK_F64, "unknown dtype %d", T->dtype);
+  TSK_REQUIRE(T->layout == TSK_DENSE || T->layout == TSK_COO, "unknown layout %d", T->layout);
+  std::memset(&tv, 0, sizeof(tv));
+  tv.order = T->order;
+  tv.dtype = T->dtype;
+  tv.layout = T->layout;
+  tv.values = T->values;
+  int64_t total = 1;
+  for (int k = 0; k < T->order; ++k) {
+    TSK_REQUIRE(T->dims[k] >= 1 && T->dims[k] < (int64_t(1) << 31), "dims[%d] = %lld invalid", k,
+                (long long)T->dims[k]);
+    tv.dims[k] = T->dims[k];
+    total *= T->dims[k];
+  }
+  if (T->layout == TSK_DENSE) {
+    tv.nnz = total;
+  } else {
+    TSK_REQUIRE(T->nnz >= 0 && T->nnz < (int64_t(1) << 31), "nnz = %lld invalid",
+                (long long)T->nnz);
+    tv.nnz = T->nnz;
+    for (int k = 0; k < T->order; ++k) {
+      TSK_REQUIRE(T->nnz == 0 || T->idx[k], "COO index array %d is NULL", k);
+      tv.idx[k] = T->idx[k];
+    }
+  }
+  TSK_REQUIRE(tv.nnz == 0 || T->values, "tensor values are NULL");
+  return TSK_OK;
+}
+
+tsk_status check_ranks(const TensorView& tv, const int32_t* ranks, int64_t* R) {
+  TSK_REQUIRE(ranks, "ranks is NULL");
+  for (int k = 0; k < tv.order; ++k) {
+    TSK_REQUIRE(ranks[k] >= 1 && ranks[k] <= tv.dims[k],
+                "rank R_%d = %d must satisfy 1 <= R <= s = %lld", k, ranks[k],
+                (long long)tv.dims[k]);
+    R[k] = ranks[k];
+  }
+  for (int k = 0; k < tv.order; ++k) {
+    int64_t r = prod_except(R, tv.order, k);
+    TSK_REQUIRE(R[k] <= r, "rank R_%d = %lld exceeds the product of the other ranks (%lld)", k,
+                (long long)R[k], (long long)r);
+  }
+  return TSK_OK;
+}
+
+void rrf_sizes(int64_t m, const int64_t* R, int N, int n, int32_t k1o, int32_t k2o, int64_t& k1,
+               int64_t& k2) {
+  double K = double(m) / double(prod_except(R, N, n));
+  k1 = int64_t(std::ceil(std::sqrt(K) * double(R[n]) - 1e-9));
+  if (k1 < R[n]) k1 = R[n];
+  k2 = R[n] * R[n] + k1;
+  if (k1o > 0) k1 = k1o;
+  if (k2o > 0) k2 = k2o;
+}
+
+// ---------------------------------------------------------------- RRF ----
+struct RrfBufs {
+  int64_t k1, k2;
+  void* Wt;       // k2 x s_n, tensor dtype (sketch-pass output)
+  double* Wt64;   // k2 x s_n
+  double* G;      // k2 x k1
+  double* B;      // s_n x k1
+  double* Mq;     // k1 x k1
+  double* lam;    // R
+  double* V;      // k1 x R
+};
+
+tsk_status rrf_plan(const TensorView& T, int n, int64_t R, int64_t k1, int64_t k2, RrfBufs& b,
+                    Ws& ws) {
+  const int64_t s = T.dims[n];
+  b.k1 = k1;
+  b.k2 = k2;
+  b.Wt = T.dtype == TSK_F64 ? (void*)ws.take<double>(k2 * s) : (void*)ws.take<float>(k2 * s);
+  b.Wt64 = ws.take<double>(k2 * s);
+  b.G = ws.take<double>(k2 * k1);
+  b.B = ws.take<double>(s * k1);
+  b.Mq = ws.take<double>(k1 * k1);
+  b.lam = ws.take<double>(R);
+  b.V = ws.take<double>(k1 * R);
+  return TSK_OK;
+}
+
+// after the sketch pass filled b.Wt: B = W G, A = leading left singular vectors of B
+tsk_status rrf_finish(const TensorView& T, int n, int64_t R, uint64_t seed, RrfBufs& b,
+                      double* A, int* info, Ws& ws, hipStream_t st) {
+  const int64_t s = T.dims[n];
+  const bool run = !ws.measuring();
+  if (run) {
+    TSK_TRY(convert_to_f64(b.Wt, T.dtype == TSK_F64 ? 8 : 4, b.k2 * s, b.Wt64, st));
+    TSK_TRY(launch_gauss(stream_key(seed, kRRFGauss, n), b.k2 * b.k1, 1.0 / std::sqrt(double(b.k1)),
+                         b.G, st));
+  }
+  TSK_TRY(gemm_tn(TSK_PREC_F64, s, b.k1, b.k2, b.Wt64, s, s, nullptr, 0, b.G, b.k1, b.B, b.k1, ws,
+                  st));
+  TSK_TRY(gemm_tn(TSK_PREC_F64, b.k1, b.k1, s, b.B, b.k1, b.k1, nullptr, 0, b.B, b.k1, b.Mq, b.k1,
+                  ws, st));
+  TSK_TRY(sym_eig_top(b.Mq, b.k1, R, b.lam, b.V, ws, st));
+  if (run) {
+    TSK_TRY(gemm_small(s, R, b.k1, 1.0, b.B, b.k1, 1, b.V, R, 1, 0.0, A, R, st));
+    TSK_TRY(scale_columns_inv_sqrt(A, s, R, b.lam, st));
+  }
+  TSK_TRY(cholqr(A, s, R, info, ws, st));
+  if (run) TSK_TRY(sign_fix_columns(A, s, R, st));
+  return TSK_OK;
+}
+
+// ------------------------------------------------------------ driver ----
+struct TuckerArgs {
+  TensorView T;
+  int64_t R[TSK_MAX_ORDER];
+  tsk_options opt;
+  double* core;             // device, prod R
+  double* factors[TSK_MAX_ORDER];
+  // results of the run (device pointers into the workspace)
+  double* fit_dev = nullptr;
+  int* info_dev = nullptr;
+};
+
+tsk_status validate_options(const TensorView& T, const int64_t* R, const tsk_options* opt) {
+  TSK_REQUIRE(opt, "options are NULL");
+  TSK_REQUIRE(opt->sketch == TSK_SKETCH_TS || opt->sketch == TSK_SKETCH_LEV, "unknown sketch %d",
+              opt->sketch);
+  TSK_REQUIRE(opt->init >= TSK_INIT_RRF && opt->init <= TSK_INIT_USER, "unknown init %d",
+              opt->init);
+  TSK_REQUIRE(opt->prec >= TSK_PREC_F64 && opt->prec <= TSK_PREC_BF16, "unknown precision %d",
+              opt->prec);
+  TSK_REQUIRE(opt->sweeps >= 0, "sweeps = %d < 0", opt->sweeps);
+  for (int n = 0; n < T.order; ++n) {
+    int64_t r = prod_except(R, T.order, n);
+    TSK_REQUIRE(opt->m >= r,
+                "sketch size m = %lld is smaller than prod_{k != %d} R_k = %lld (the sketched "
+                "problem would not have a unique solution)",
+                (long long)opt->m, n, (long long)r);
+  }
+  TSK_REQUIRE(opt->m < (int64_t(1) << 31), "sketch size too large");
+  if (opt->sketch == TSK_SKETCH_LEV && T.layout == TSK_COO) {
+    set_error("leverage-score sampling of a COO tensor needs a fibre index (not built)");
+    return TSK_EUNSUPPORTED;
+  }
+  return TSK_OK;
+}
+
+tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
+  const TensorView& T = a.T;
+  const tsk_options& o = a.opt;
+  const int N = T.order;
+  const int64_t m = o.m;
+  const int prec = o.prec;
+  const bool run = !ws.measuring();
+  const bool ts = o.sketch == TSK_SKETCH_TS;
+  const bool record = (o.flags & TSK_FLAG_RECORD_FIT) != 0;
+  hipStream_t st = as_stream(o.stream);
+
+  int64_t rmax = 0, smax = 0, Rmax = 0;
+  for (int n = 0; n < N; ++n) {
+    rmax = std::max<int64_t>(rmax, prod_except(a.R, N, n));
+    smax = std::max<int64_t>(smax, T.dims[n]);
+    Rmax = std::max<int64_t>(Rmax, a.R[n]);
+  }
+  // ---- persistent allocations ----
+  a.info_dev = ws.take<int>(4);
+  a.fit_dev = ws.take<double>(std::max(1, o.sweeps));
+  std::vector<int32_t*> h(N * N, nullptr);
+  std::vector<int8_t*> sg(N * N, nullptr);
+  std::vector<CsrTable> csr(N * N);
+  std::vector<void*> Yt(N, nullptr), Yp(N, nullptr);
+  const size_t tbytes = T.dtype == TSK_F64 ? 8 : 4;
+  if (ts) {
+    for (int n = 0; n < N; ++n)
+      for (int k = 0; k < N; ++k) {
+        if (k == n) continue;
+        h[n * N + k] = ws.take<int32_t>(T.dims[k]);
+        sg[n * N + k] = ws.take<int8_t>(T.dims[k]);
+        csr[n * N + k].ptr = ws.take<int32_t>(m + 1);
+        csr[n * N + k].items = ws.take<int32_t>(T.dims[k]);
+      }
+    for (int n = 0; n < N; ++n) {
+      Yt[n] = ws.take<char>(size_t(m) * T.dims[n] * tbytes);
+      Yp[n] = prec_matches_dtype(prec, T.dtype) ? Yt[n]
+                                                  : ws.take<char>(size_t(m) * T.dims[n] *
+                                                                  prec_bytes(prec));
+    }
+  }
+  std::vector<RrfBufs> rrf(N);
+  if (o.init == TSK_INIT_RRF)
+    for (int n = 1; n < N; ++n) {
+      int64_t k1, k2;
+      rrf_sizes(m, a.R, N, n, o.rrf_k1, o.rrf_k2, k1, k2);
+      TSK_REQUIRE(k1 >= a.R[n], "range-finder size k1 = %lld < R_%d", (long long)k1, n);
+      TSK_TRY(rrf_plan(T, n, a.R[n], k1, k2, rrf[n], ws));
+    }
+  void* Z = ws.take<char>(size_t(m) * rmax * prec_bytes(prec));
+  double* W = ws.take<double>(rmax * Rmax);
+  int32_t* lev_idx = nullptr;
+  double* lev_w = nullptr;
+  void* Ylev = nullptr;
+  if (!ts) {
+    lev_idx = ws.take<int32_t>(size_t(m) * (N - 1));
+    lev_w = ws.take<double>(m);
+    Ylev = ws.take<char>(size_t(m) * smax * prec_bytes(prec));
+  }
+  FitScratch fs{};
+  if (record) TSK_TRY(fit_plan(T, a.R, fs, ws));
+
+  const size_t mark = ws.off;
+  size_t peak = mark;
+  auto release = [&]() {
+    peak = std::max(peak, ws.off);
+    ws.off = mark;
+  };
+
+  // ---- preparation: maps, sketched right-hand sides, range finder ----
+  if (run) TSK_HIP(hipMemsetAsync(a.info_dev, 0, 4 * sizeof(int), st));
+  if (ts) {
+    for (int n = 0; n < N; ++n)
+      for (int k = 0; k < N; ++k) {
+        if (k == n) continue;
+        if (run)
+          TSK_TRY(launch_hash_table(stream_key(o.seed, kTS, n, k), T.dims[k], m, h[n * N + k],
+                                    sg[n * N + k], st));
+        TSK_TRY(build_inverse_hash(h[n * N + k], T.dims[k], m, csr[n * N + k], ws, st));
+        release();
+      }
+  }
+  {
+    std::vector<PassJob> jobs;
+    if (ts)
+      for (int n = 0; n < N; ++n)
+        jobs.push_back(PassJob{0, n, m, &h[n * N], &sg[n * N], 0, Yt[n]});
+    if (o.init == TSK_INIT_RRF)
+      for (int n = 1; n < N; ++n)
+        jobs.push_back(PassJob{1, n, rrf[n].k2, nullptr, nullptr, stream_key(o.seed, kRRF, n),
+                               rrf[n].Wt});
+    if (!jobs.empty()) TSK_TRY(sketch_pass(T, jobs.data(), int(jobs.size()), ws, st));
+    release();
+  }
+  if (ts && run)
+    for (int n = 0; n < N; ++n)
+      if (Yp[n] != Yt[n])
+        TSK_TRY(convert_tensor_to_prec(Yt[n], T.dtype, m * T.dims[n], Yp[n], prec, st));
+  if (o.init == TSK_INIT_RRF) {
+    for (int n = 1; n < N; ++n) {
+      TSK_TRY(rrf_finish(T, n, a.R[n], o.seed, rrf[n], a.factors[n], a.info_dev + 2, ws, st));
+      release();
+    }
+  } else if (o.init == TSK_INIT_RANDOM) {
+    for (int n = 1; n < N; ++n) {
+      if (run)
+        TSK_TRY(launch_gauss(stream_key(o.seed, kInit, n), T.dims[n] * a.R[n], 1.0,
+                             a.factors[n], st));
+      TSK_TRY(cholqr(a.factors[n], T.dims[n], a.R[n], a.info_dev + 2, ws, st));
+      if (run) TSK_TRY(sign_fix_columns(a.factors[n], T.dims[n], a.R[n], st));
+      release();
+    }
+  }
+
+  // ---- sweeps (Alg. 4) ----
+  const int64_t csize = [&] {
+    int64_t p = 1;
+    for (int k = 0; k < N; ++k) p *= a.R[k];
+    return p;
+  }();
+  for (int sweep = 0; sweep < o.sweeps; ++sweep) {
+    for (int n = 0; n < N; ++n) {
+      const int64_t r = prod_except(a.R, N, n);
+      const void* Y = nullptr;
+      if (ts) {
+        LhsMode modes[TSK_MAX_ORDER];
+        int q = 0;
+        for (int k = 0; k < N; ++k) {
+          if (k == n) continue;
+          modes[q++] = LhsMode{a.factors[k], T.dims[k], a.R[k], sg[n * N + k], csr[n * N + k]};
+        }
+        TSK_TRY(ts_lhs(modes, N - 1, m, prec, Z, ws, st));
+        Y = Yp[n];
+      } else {
+        TSK_TRY(leverage_sample(N, T.dims, a.R, n, m, o.seed, sweep, a.factors, lev_idx, lev_w,
+                                ws, st));
+        if (run)
+          TSK_TRY(leverage_rows(T, a.R, n, m, lev_idx, lev_w, a.factors, prec, Z, Ylev, st));
+        Y = Ylev;
+      }
+      TSK_TRY(rc_solve(Z, Y, m, r, T.dims[n], int(a.R[n]), prec, a.factors[n], W, a.info_dev, ws,
+                       st));
+      release();
+    }
+    if (run && a.core)
+      TSK_HIP(hipMemcpyAsync(a.core, W, csize * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (record) {
+      TSK_TRY(fit_run(T, a.R, a.core, a.factors, sweep == 0, fs, a.fit_dev + sweep, ws, st));
+      release();
+    }
+  }
+  ws.off = peak;
+  return TSK_OK;
+}
+
+tsk_status make_args(const tsk_tensor* T, const int32_t* ranks, const tsk_options* opt,
+                     TuckerArgs& a) {
+  TSK_TRY(view_tensor(T, a.T));
+  TSK_TRY(check_ranks(a.T, ranks, a.R));
+  TSK_TRY(validate_options(a.T, a.R, opt));
+  a.opt = *opt;
+  return TSK_OK;
+}
+
+tsk_status finish_sync(TuckerArgs& a, double* fit_history, int32_t* sweeps_done) {
+  hipStream_t st = as_stream(a.opt.stream);
+  TSK_HIP(hipStreamSynchronize(st));
+  int info[4] = {0, 0, 0, 0};
+  TSK_HIP(hipMemcpy(info, a.info_dev, sizeof(info), hipMemcpyDeviceToHost));
+  if (fit_history && (a.opt.flags & TSK_FLAG_RECORD_FIT) && a.opt.sweeps > 0)
+    TSK_HIP(hipMemcpy(fit_history, a.fit_dev, a.opt.sweeps * sizeof(double),
+                      hipMemcpyDeviceToHost));
+  if (sweeps_done) *sweeps_done = a.opt.sweeps;
+  if (info[0] || info[1] || info[2]) {
+    set_error("numerical breakdown: sketched Gram not positive definite (info %d %d %d)", info[0],
+              info[1], info[2]);
+    return TSK_ENUMERIC;
+  }
+  return TSK_OK;
+}
+
+// Alg. 6: sketched Tucker into workspace buffers, then CP-ALS on the core
+tsk_status run_cp(TuckerArgs& a, int Rc, int cp_sweeps, double* const* cp_factors,
+                  double** fit_dev, Ws& ws) {
+  CpTuckerBufs tb{};
+  TSK_TRY(cp_tucker_bufs(a.T, a.R, tb, ws));
+  a.core = tb.core;
+  for (int k = 0; k < a.T.order; ++k) a.factors[k] = tb.factors[k];
+  TSK_TRY(run_tucker(a, ws));
+  double* fd = nullptr;
+  TSK_TRY(cp_run(a.T, a.R, Rc, cp_sweeps, tb, cp_factors, &fd, ws, as_stream(a.opt.stream)));
+  if (fit_dev) *fit_dev = fd;
+  return TSK_OK;
+}
+
+}  // namespace
+}  // namespace tsk
+
+using namespace tsk;
+
+extern "C" {
+
+int32_t tsk_abi_version(void) { return TSK_ABI_VERSION; }
+const char* tsk_last_error(void) { return g_err.c_str(); }
+
+uint64_t tsk_stream_key(uint64_t seed, int32_t purpose, int64_t a, int64_t b, int64_t c) {
+  return stream_key(seed, purpose, a, b, c);
+}
+uint64_t tsk_draw(uint64_t key, uint64_t counter) { return draw(key, counter); }
+
+tsk_status tsk_workspace_size(const tsk_tensor* T, const int32_t* ranks, const tsk_options* opt,
+                              size_t* bytes) {
+  clear_error();
+  TSK_REQUIRE(bytes, "bytes is NULL");
+  TuckerArgs a{};
+  TSK_TRY(make_args(T, ranks, opt, a));
+  Ws probe;
+  TSK_TRY(run_tucker(a, probe));
+  *bytes = probe.off + 256;
+  return TSK_OK;
+}
+
+tsk_status tsk_tucker_sketch_als(const tsk_tensor* T, const int32_t* ranks,
+                                 const tsk_options* opt, double* core, double* const* factors,
+                                 double* fit_history, int32_t* sweeps_done) {
+  clear_error();
+  TuckerArgs a{};
+  TSK_TRY(make_args(T, ranks, opt, a));
+  TSK_REQUIRE(core, "core is NULL");
+  TSK_REQUIRE(factors, "factors is NULL");
+  for (int k = 0; k < a.T.order; ++k) {
+    TSK_REQUIRE(factors[k], "factors[%d] is NULL", k);
+    a.factors[k] = factors[k];
+  }
+  a.core = core;
+  size_t need = 0;
+  {
+    Ws probe;
+    TuckerArgs b = a;
+    TSK_TRY(run_tucker(b, probe));
+    need = probe.off + 256;
+  }
+  TSK_REQUIRE(opt->workspace, "workspace is NULL (query tsk_workspace_size)");
+  TSK_REQUIRE((reinterpret_cast<uintptr_t>(opt->workspace) & 255) == 0,
+              "workspace must be 256-byte aligned");
+  if (opt->workspace_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", opt->workspace_bytes, need);
+    return TSK_ENOMEM;
+  }
+  Ws w;
+  w.base = static_cast<char*>(opt->workspace);
+  w.cap = opt->workspace_bytes;
+  TSK_TRY(run_tucker(a, w));
+  return finish_sync(a, fit_history, sweeps_done);
+}
+
+tsk_status tsk_hash_tables(int32_t order, const int64_t* dims, int32_t n, int64_t m,
+                           uint64_t seed, int32_t* const* h, int8_t* const* sign, void* stream) {
+  clear_error();
+  TSK_REQUIRE(order >= 2 && order <= TSK_MAX_ORDER && dims && h && sign, "invalid arguments");
+  TSK_REQUIRE(n >= 0 && n < order && m >= 1, "invalid mode or sketch size");
+  for (int k = 0; k < order; ++k) {
+    if (k == n) continue;
+    TSK_REQUIRE(h[k] && sign[k], "table pointers of mode %d are NULL", k);
+    TSK_TRY(launch_hash_table(stream_key(seed, kTS, n, k), dims[k], m, h[k], sign[k],
+                              as_stream(stream)));
+  }
+  return TSK_OK;
+}
+
+tsk_status tsk_sketch_rhs_ts(const tsk_tensor* T, int32_t n, int64_t m, const int32_t* const* h,
+                             const int8_t* const* sign, void* Y, void* ws, size_t* ws_bytes,
+                             void* stream) {
+  clear_error();
+  TensorView tv;
+  TSK_TRY(view_tensor(T, tv));
+  TSK_REQUIRE(n >= 0 && n < tv.order && m >= 1 && h && sign, "invalid arguments");
+  for (int k = 0; k < tv.order; ++k)
+    TSK_REQUIRE(k == n || (h[k] && sign[k]), "table pointers of mode %d are NULL", k);
+  TSK_REQUIRE(ws == nullptr || Y, "Y is NULL");
+  PassJob job{0, n, m, h, sign, 0, Y};
+  return with_workspace(ws, ws_bytes, [&](Ws& w) {
+    return sketch_pass(tv, &job, 1, w, as_stream(stream));
+  });
+}
+
+tsk_status tsk_sketch_lhs_ts(int32_t order, const int64_t* dims, const int32_t* ranks, int32_t n,
+                             int64_t m, const int32_t* const* h, const int8_t* const* sign,
+                             const double* const* factors, int32_t prec, void* Z, void* ws,
+                             size_t* ws_bytes, void* stream) {
+  clear_error();
+  TSK_REQUIRE(order >= 2 && order <= TSK_MAX_ORDER && dims && ranks && h && sign && factors,
+              "invalid arguments");
+  TSK_REQUIRE(n >= 0 && n < order && m >= 1, "invalid mode or sketch size");
+  TSK_REQUIRE(prec >= TSK_PREC_F64 && prec <= TSK_PREC_BF16, "unknown precision");
+  return with_workspace(ws, ws_bytes, [&](Ws& w) -> tsk_status {
+    hipStream_t st = as_stream(stream);
+    LhsMode modes[TSK_MAX_ORDER];
+    int q = 0;
+    for (int k = 0; k < order; ++k) {
+      if (k == n) continue;
+      CsrTable c{w.take<int32_t>(m + 1), w.take<int32_t>(dims[k])};
+      TSK_TRY(build_inverse_hash(h[k], dims[k], m, c, w, st));
+      modes[q++] = LhsMode{factors[k], dims[k], ranks[k], sign[k], c};
+    }
+    return ts_lhs(modes, q, m, prec, Z, w, st);
+  });
+}
+
+tsk_status tsk_rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s, int32_t R,
+                        int32_t prec, double* A, double* W, void* ws, size_t* ws_bytes,
+                        void* stream) {
+  clear_error();
+  TSK_REQUIRE(m >= r && r >= 1 && s >= 1 && R >= 1 && R <= r && R <= s,
+              "shapes violate m >= r, 1 <= R <= min(r, s)");
+  TSK_REQUIRE(prec >= TSK_PREC_F64 && prec <= TSK_PREC_BF16, "unknown precision");
+  int* info = nullptr;
+  tsk_status stt = with_workspace(ws, ws_bytes, [&](Ws& w) -> tsk_status {
+    info = w.take<int>(4);
+    if (!w.measuring()) TSK_HIP(hipMemsetAsync(info, 0, 4 * sizeof(int), as_stream(stream)));
+    return rc_solve(Z, Y, m, r, s, R, prec, A, W, info, w, as_stream(stream));
+  });
+  if (stt != TSK_OK || ws == nullptr) return stt;
+  TSK_HIP(hipStreamSynchronize(as_stream(stream)));
+  int hinfo[2];
+  TSK_HIP(hipMemcpy(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost));
+  if (hinfo[0] || hinfo[1]) {
+    set_error("numerical breakdown in the sketched solve (info %d %d)", hinfo[0], hinfo[1]);
+    return TSK_ENUMERIC;
+  }
+  return TSK_OK;
+}
+
+tsk_status tsk_rrf_init(const tsk_tensor* T, int32_t n, int32_t R, int32_t k1, int32_t k2,
+                        uint64_t seed, double* A, void* ws, size_t* ws_bytes, void* stream) {
+  clear_error();
+  TensorView tv;
+  TSK_TRY(view_tensor(T, tv));
+  TSK_REQUIRE(n >= 0 && n < tv.order, "invalid mode");
+  TSK_REQUIRE(R >= 1 && R <= k1 && k1 >= 1 && k2 >= 1 && R <= tv.dims[n],
+              "range finder needs 1 <= R <= k1 and R <= s_n");
+  int* info = nullptr;
+  tsk_status stt = with_workspace(ws, ws_bytes, [&](Ws& w) -> tsk_status {
+    hipStream_t st = as_stream(stream);
+    info = w.take<int>(4);
+    RrfBufs b{};
+    TSK_TRY(rrf_plan(tv, n, R, k1, k2, b, w));
+    if (!w.measuring()) TSK_HIP(hipMemsetAsync(info, 0, 4 * sizeof(int), st));
+    PassJob job{1, n, k2, nullptr, nullptr, stream_key(seed, kRRF, n), b.Wt};
+    TSK_TRY(sketch_pass(tv, &job, 1, w, st));
+    return rrf_finish(tv, n, R, seed, b, A, info, w, st);
+  });
+  if (stt != TSK_OK || ws == nullptr) return stt;
+  TSK_HIP(hipStreamSynchronize(as_stream(stream)));
+  int hinfo[1];
+  TSK_HIP(hipMemcpy(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost));
+  if (hinfo[0]) {
+    set_error("numerical breakdown in the range finder (info %d)", hinfo[0]);
+    return TSK_ENUMERIC;
+  }
+  return TSK_OK;
+}
+
+tsk_status tsk_leverage_sample(int32_t order, const int64_t* dims, const int32_t* ranks,
+                               int32_t n, int64_t m, uint64_t seed, int32_t sweep,
+                               const double* const* factors, int32_t* idx, double* w, void* ws,
+                               size_t* ws_bytes, void* stream) {
+  clear_error();
+  TSK_REQUIRE(order >= 2 && order <= TSK_MAX_ORDER && dims && ranks && factors,
+              "invalid arguments");
+  TSK_REQUIRE(n >= 0 && n < order && m >= 1, "invalid mode or sample count");
+  int64_t R[TSK_MAX_ORDER];
+  for (int k = 0; k < order; ++k) R[k] = ranks[k];
+  return with_workspace(ws, ws_bytes, [&](Ws& wk) {
+    return leverage_sample(order, dims, R, n, m, seed, sweep, factors, idx, w, wk,
+                           as_stream(stream));
+  });
+}
+
+tsk_status tsk_sketch_lev(const tsk_tensor* T, const int32_t* ranks, int32_t n, int64_t m,
+                          const int32_t* idx, const double* w, const double* const* factors,
+                          int32_t prec, void* Z, void* Y, void* stream) {
+  clear_error();
+  TensorView tv;
+  TSK_TRY(view_tensor(T, tv));
+  TSK_REQUIRE(ranks && idx && w && factors && n >= 0 && n < tv.order && m >= 1,
+              "invalid arguments");
+  if (tv.layout == TSK_COO && Y) {
+    set_error("sampled fibres of a COO tensor need a fibre index (not built)");
+    return TSK_EUNSUPPORTED;
+  }
+  int64_t R[TSK_MAX_ORDER];
+  for (int k = 0; k < tv.order; ++k) R[k] = ranks[k];
+  return leverage_rows(tv, R, n, m, idx, w, factors, prec, Z, Y, as_stream(stream));
+}
+
+tsk_status tsk_fit(const tsk_tensor* T, const int32_t* ranks, const double* core,
+                   const double* const* factors, double* rel_residual, void* ws,
+                   size_t* ws_bytes, void* stream) {
+  clear_error();
+  TensorView tv;
+  TSK_TRY(view_tensor(T, tv));
+  int64_t R[TSK_MAX_ORDER];
+  TSK_TRY(check_ranks(tv, ranks, R));
+  TSK_REQUIRE(core && factors && rel_residual, "invalid arguments");
+  double* res = nullptr;
+  tsk_status stt = with_workspace(ws, ws_bytes, [&](Ws& w) -> tsk_status {
+    FitScratch fs{};
+    TSK_TRY(fit_plan(tv, R, fs, w));
+    res = w.take<double>(1);
+    return fit_run(tv, R, core, factors, true, fs, res, w, as_stream(stream));
+  });
+  if (stt != TSK_OK || ws == nullptr) return stt;
+  TSK_HIP(hipStreamSynchronize(as_stream(stream)));
+  TSK_HIP(hipMemcpy(rel_residual, res, sizeof(double), hipMemcpyDeviceToHost));
+  return TSK_OK;
+}
+
+tsk_status tsk_cp_workspace_size(const tsk_tensor* T, int32_t cp_rank, const int32_t* tucker_ranks,
+                                 const tsk_options* opt, size_t* bytes) {
+  clear_error();
+  TSK_REQUIRE(bytes, "bytes is NULL");
+  TuckerArgs a{};
+  TSK_TRY(make_args(T, tucker_ranks, opt, a));
+  Ws probe;
+  TSK_TRY(run_cp(a, cp_rank, 0, nullptr, nullptr, probe));
+  *bytes = probe.off + 256;
+  return TSK_OK;
+}
+
+tsk_status tsk_cp_via_tucker(const tsk_tensor* T, int32_t cp_rank, const int32_t* tucker_ranks,
+                             int32_t cp_sweeps, const tsk_options* opt, double* const* cp_factors,
+                             double* cp_fit) {
+  clear_error();
+  TuckerArgs a{};
+  TSK_TRY(make_args(T, tucker_ranks, opt, a));
+  TSK_REQUIRE(cp_factors, "cp_factors is NULL");
+  TSK_REQUIRE(cp_sweeps >= 0, "cp_sweeps < 0");
+  for (int k = 0; k < a.T.order; ++k) {
+    TSK_REQUIRE(cp_factors[k], "cp_factors[%d] is NULL", k);
+    TSK_REQUIRE(cp_rank >= 1 && cp_rank <= a.R[k],
+                "CP rank %d must be in [1, Tucker rank R_%d = %lld]", cp_rank, k,
+                (long long)a.R[k]);
+  }
+  size_t need = 0;
+  {
+    Ws probe;
+    TuckerArgs b = a;
+    TSK_TRY(run_cp(b, cp_rank, cp_sweeps, cp_factors, nullptr, probe));
+    need = probe.off + 256;
+  }
+  TSK_REQUIRE(opt->workspace, "workspace is NULL (query tsk_cp_workspace_size)");
+  TSK_REQUIRE((reinterpret_cast<uintptr_t>(opt->workspace) & 255) == 0,
+              "workspace must be 256-byte aligned");
+  if (opt->workspace_bytes < need) {
+    set_error("workspace too small: %zu bytes given, %zu needed", opt->workspace_bytes, need);
+    return TSK_ENOMEM;
+  }
+  Ws w;
+  w.base = static_cast<char*>(opt->workspace);
+  w.cap = opt->workspace_bytes;
+  double* fit_dev = nullptr;
+  TSK_TRY(run_cp(a, cp_rank, cp_sweeps, cp_factors, &fit_dev, w));
+  TSK_TRY(finish_sync(a, nullptr, nullptr));
+  if (cp_fit) TSK_HIP(hipMemcpy(cp_fit, fit_dev, sizeof(double), hipMemcpyDeviceToHost));
+  return TSK_OK;
+}
+
+}  // extern "C"

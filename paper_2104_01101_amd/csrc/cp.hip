@@ -1,0 +1,269 @@
+// CP decomposition of the Tucker core (Alg. 6, CP-Sketch-Tucker):
+//   init  HOSVD of the core: A_k = leading R_cp left singular vectors of C_(k)
+//         (eigenvectors of C_(k) C_(k)^T, sign rule of the factors)
+//   CP-ALS (Alg. 2) on the core, subproblem eq. (subproblem) by the normal
+//         equations: A_n = MTTKRP(C, n) pinv(hadamard_{k != n} A_k^T A_k);
+//         the pseudo-inverse from the eigen-decomposition of the R_cp x R_cp
+//         Gram, eigenvalues below 1e-15 * max treated as zero
+//   output B^(n) A_n and the CP relative residual against the input tensor.
+// All FP64; the core (at most a few 10^4 entries) stays in device memory.
+
+#include <cmath>
+
+#include "common.h"
+#include "cp.h"
+#include "kernels.h"
+
+namespace tsk {
+
+namespace {
+
+struct CoreDesc {
+  int N;
+  int64_t R[TSK_MAX_ORDER];
+  int64_t csize;
+};
+
+// Gram of the mode-k unfolding: G[a][b] = sum_rest C[..a..] C[..b..]
+__global__ void k_unfold_gram(const double* C, CoreDesc cd, int k, double* G) {
+  const int64_t Rk = cd.R[k];
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= Rk * Rk) return;
+  const int64_t a = t / Rk, b = t % Rk;
+  int64_t inner = 1;
+  for (int l = k + 1; l < cd.N; ++l) inner *= cd.R[l];
+  const int64_t outer = cd.csize / (inner * Rk);
+  double s = 0.0;
+  for (int64_t o = 0; o < outer; ++o)
+    for (int64_t in = 0; in < inner; ++in) {
+      int64_t base = o * Rk * inner + in;
+      s += C[base + a * inner] * C[base + b * inner];
+    }
+  G[t] = s;
+}
+
+struct Facs {
+  const double* A[TSK_MAX_ORDER];
+};
+
+// M[i][r] = sum_{rho : rho_n = i} C[rho] prod_{k != n} A_k[rho_k][r]
+__global__ void k_mttkrp(const double* C, CoreDesc cd, Facs f, int n, int64_t Rc, double* M) {
+  const int64_t Rn = cd.R[n];
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= Rn * Rc) return;
+  const int64_t i = t / Rc, r = t % Rc;
+  double s = 0.0;
+  for (int64_t p = 0; p < cd.csize; ++p) {
+    int64_t x = p, rho_n = 0;
+    double w = 1.0;
+    for (int k = cd.N - 1; k >= 0; --k) {
+      int64_t rk = x % cd.R[k];
+      x /= cd.R[k];
+      if (k == n)
+        rho_n = rk;
+      else
+        w *= f.A[k][rk * Rc + r];
+    }
+    if (rho_n == i) s += C[p] * w;
+  }
+  M[t] = s;
+}
+
+// Gam = hadamard_{k != n} A_k^T A_k (Rc x Rc), from precomputed per-mode Grams
+__global__ void k_hadamard_grams(const double* grams, int N, int n, int64_t Rc, double* Gam) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= Rc * Rc) return;
+  double v = 1.0;
+  for (int k = 0; k < N; ++k)
+    if (k != n) v *= grams[k * Rc * Rc + t];
+  Gam[t] = v;
+}
+
+// P = V diag(1/lam if lam > 1e-15 max lam) V^T
+__global__ void k_pinv_from_eig(const double* V, const double* lam, int64_t Rc, double* P) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= Rc * Rc) return;
+  const int64_t a = t / Rc, b = t % Rc;
+  double lmax = 0.0;
+  for (int64_t c = 0; c < Rc; ++c) lmax = fmax(lmax, fabs(lam[c]));
+  double s = 0.0;
+  for (int64_t c = 0; c < Rc; ++c)
+    if (lam[c] > 1e-15 * lmax) s += V[a * Rc + c] * V[b * Rc + c] / lam[c];
+  P[t] = s;
+}
+
+struct CpFitArgs {
+  int N;
+  int layout;
+  int dtype;
+  int64_t dims[TSK_MAX_ORDER];
+  const int32_t* idx[TSK_MAX_ORDER];
+  const void* vals;
+  const double* F[TSK_MAX_ORDER];
+  int64_t Rc;
+};
+
+__global__ void k_cp_inner(CpFitArgs a, int64_t nnz, int64_t per, double* pn, double* pi) {
+  __shared__ double rn[4], ri[4];
+  int64_t lo = int64_t(blockIdx.x) * per, hi = lo + per < nnz ? lo + per : nnz;
+  double sn = 0.0, si = 0.0;
+  for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+    int64_t ii[TSK_MAX_ORDER];
+    if (a.layout == TSK_COO) {
+      for (int k = 0; k < a.N; ++k) ii[k] = a.idx[k][e];
+    } else {
+      int64_t x = e;
+      for (int k = a.N - 1; k >= 0; --k) ii[k] = x % a.dims[k], x /= a.dims[k];
+    }
+    double tv = 0.0;
+    for (int64_t r = 0; r < a.Rc; ++r) {
+      double p = 1.0;
+      for (int k = 0; k < a.N; ++k) p *= a.F[k][ii[k] * a.Rc + r];
+      tv += p;
+    }
+    double v = a.dtype == TSK_F64 ? static_cast<const double*>(a.vals)[e]
+                                  : double(static_cast<const float*>(a.vals)[e]);
+    sn += v * v;
+    si += v * tv;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sn += __shfl_down(sn, off);
+    si += __shfl_down(si, off);
+  }
+  if ((threadIdx.x & 63) == 0) rn[threadIdx.x >> 6] = sn, ri[threadIdx.x >> 6] = si;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    pn[blockIdx.x] = rn[0] + rn[1] + rn[2] + rn[3];
+    pi[blockIdx.x] = ri[0] + ri[1] + ri[2] + ri[3];
+  }
+}
+
+__global__ void k_cp_finish(const double* pn, const double* pi, int nb, const double* grams,
+                            int N, int64_t Rc, double* out) {
+  if (threadIdx.x != 0) return;
+  double nT2 = 0.0, inner = 0.0, model = 0.0;
+  for (int b = 0; b < nb; ++b) nT2 += pn[b], inner += pi[b];
+  for (int64_t t = 0; t < Rc * Rc; ++t) {
+    double v = 1.0;
+    for (int k = 0; k < N; ++k) v *= grams[k * Rc * Rc + t];
+    model += v;
+  }
+  double r2 = nT2 - 2.0 * inner + model;
+  *out = sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(nT2);
+}
+
+}  // namespace
+
+tsk_status cp_tucker_bufs(const TensorView& T, const int64_t* R, CpTuckerBufs& b, Ws& ws) {
+  int64_t cs = 1;
+  for (int k = 0; k < T.order; ++k) cs *= R[k];
+  b.core = ws.take<double>(cs);
+  for (int k = 0; k < T.order; ++k) b.factors[k] = ws.take<double>(T.dims[k] * R[k]);
+  return TSK_OK;
+}
+
+tsk_status cp_run(const TensorView& T, const int64_t* R, int Rc, int sweeps,
+                  const CpTuckerBufs& tb, double* const* cp_factors, double** fit_dev, Ws& ws,
+                  hipStream_t st) {
+  const int N = T.order;
+  const bool run = !ws.measuring();
+  CoreDesc cd{};
+  cd.N = N;
+  cd.csize = 1;
+  int64_t Rmax = 0;
+  for (int k = 0; k < N; ++k) {
+    cd.R[k] = R[k];
+    cd.csize *= R[k];
+    Rmax = std::max<int64_t>(Rmax, R[k]);
+  }
+  double* A[TSK_MAX_ORDER];
+  for (int k = 0; k < N; ++k) A[k] = ws.take<double>(R[k] * Rc);
+  double* Gu = ws.take<double>(Rmax * Rmax);
+  double* lam = ws.take<double>(Rmax);
+  double* grams = ws.take<double>(N * Rc * Rc);
+  double* Gam = ws.take<double>(Rc * Rc);
+  double* V = ws.take<double>(Rc * Rc);
+  double* P = ws.take<double>(Rc * Rc);
+  double* M = ws.take<double>(Rmax * Rc);
+  double* fgrams = ws.take<double>(N * Rc * Rc);
+  const int nb = 512;
+  double* pn = ws.take<double>(nb);
+  double* pi = ws.take<double>(nb);
+  double* fit = ws.take<double>(1);
+  if (fit_dev) *fit_dev = fit;
+  const size_t mark = ws.off;
+  size_t peak = mark;
+  auto release = [&]() {
+    peak = std::max(peak, ws.off);
+    ws.off = mark;
+  };
+  // HOSVD of the core
+  for (int k = 0; k < N; ++k) {
+    if (run) {
+      hipLaunchKernelGGL(k_unfold_gram, dim3(ceil_div(R[k] * R[k], 256)), dim3(256), 0, st,
+                         tb.core, cd, k, Gu);
+      TSK_LAUNCHED();
+    }
+    TSK_TRY(sym_eig_top(Gu, R[k], Rc, lam, A[k], ws, st));
+    if (run) TSK_TRY(sign_fix_columns(A[k], R[k], Rc, st));
+    release();
+  }
+  Facs f{};
+  for (int k = 0; k < N; ++k) f.A[k] = A[k];
+  for (int sweep = 0; sweep < sweeps; ++sweep)
+    for (int n = 0; n < N; ++n) {
+      for (int k = 0; k < N; ++k)
+        if (k != n && run)
+          TSK_TRY(gemm_small(Rc, Rc, R[k], 1.0, A[k], 1, Rc, A[k], Rc, 1, 0.0, grams + k * Rc * Rc,
+                             Rc, st));
+      if (run) {
+        hipLaunchKernelGGL(k_hadamard_grams, dim3(ceil_div(Rc * Rc, 256)), dim3(256), 0, st, grams,
+                           N, n, int64_t(Rc), Gam);
+        TSK_LAUNCHED();
+      }
+      TSK_TRY(sym_eig_top(Gam, Rc, Rc, lam, V, ws, st));
+      if (run) {
+        hipLaunchKernelGGL(k_pinv_from_eig, dim3(ceil_div(Rc * Rc, 256)), dim3(256), 0, st, V, lam,
+                           int64_t(Rc), P);
+        TSK_LAUNCHED();
+        hipLaunchKernelGGL(k_mttkrp, dim3(ceil_div(R[n] * Rc, 256)), dim3(256), 0, st, tb.core, cd,
+                           f, n, int64_t(Rc), M);
+        TSK_LAUNCHED();
+        TSK_TRY(gemm_small(R[n], Rc, Rc, 1.0, M, Rc, 1, P, Rc, 1, 0.0, A[n], Rc, st));
+      }
+      release();
+    }
+  // CP factors of the input: B^(n) A_n
+  for (int k = 0; k < N; ++k)
+    if (run)
+      TSK_TRY(gemm_small(T.dims[k], Rc, R[k], 1.0, tb.factors[k], R[k], 1, A[k], Rc, 1, 0.0,
+                         cp_factors[k], Rc, st));
+  if (fit_dev) {
+    CpFitArgs a{};
+    a.N = N;
+    a.layout = T.layout;
+    a.dtype = T.dtype;
+    a.vals = T.values;
+    a.Rc = Rc;
+    for (int k = 0; k < N; ++k) {
+      a.dims[k] = T.dims[k];
+      a.idx[k] = T.idx[k];
+      a.F[k] = cp_factors[k];
+      if (run)
+        TSK_TRY(gemm_small(Rc, Rc, T.dims[k], 1.0, cp_factors[k], 1, Rc, cp_factors[k], Rc, 1, 0.0,
+                           fgrams + k * Rc * Rc, Rc, st));
+    }
+    if (run) {
+      int64_t per = ceil_div(T.nnz, nb);
+      hipLaunchKernelGGL(k_cp_inner, dim3(nb), dim3(256), 0, st, a, T.nnz, per, pn, pi);
+      TSK_LAUNCHED();
+      hipLaunchKernelGGL(k_cp_finish, dim3(1), dim3(64), 0, st, pn, pi, nb, fgrams, N,
+                         int64_t(Rc), fit);
+      TSK_LAUNCHED();
+    }
+  }
+  ws.off = peak;
+  return TSK_OK;
+}
+
+}  // namespace tsk

@@ -1,0 +1,258 @@
+// Gram products of the sketched operands on the matrix cores:
+//
+//   C (M x N, FP64) = A^T B,   A = [A1 | A2] (K x M), B (K x N), row-major,
+//
+// i.e. both operands are stored with the contraction index (the sketch row)
+// slowest -- the layout in which Z (m x r) and Y (m x s) are produced.  Used
+// for [Z^T Z ; Y^T Z] in one launch (A = [Z | Y], B = Z), and for the FP64
+// Grams of the solve.  Element types: FP64 (v_mfma_f64_16x16x4f64), FP32
+// (v_mfma_f32_16x16x4f32) and BF16 (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation).  A 256-thread workgroup computes a 64 x 64 tile (four waves,
+// 32 x 32 each as 2 x 2 MFMA blocks); tiles of A and B are staged in LDS with
+// the contraction index contiguous, so each lane feeds its MFMA operands
+// from one vector read.  Split-K partials are FP64 and are summed by a
+// separate kernel in a fixed order (deterministic).
+
+#include "common.h"
+#include "kernels.h"
+
+namespace tsk {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBM = 64, kBN = 64, kThreads = 256;
+
+template <class E>
+struct Cfg;
+template <>
+struct Cfg<double> {
+  static constexpr int BK = 16;   // 4 MFMA k-steps of 4
+  static constexpr int LD = 18;   // row stride in elements (144 B)
+  typedef doublex4 Acc;
+};
+template <>
+struct Cfg<float> {
+  static constexpr int BK = 32;   // 8 MFMA k-steps of 4
+  static constexpr int LD = 36;
+  typedef floatx4 Acc;
+};
+template <>
+struct Cfg<uint16_t> {
+  static constexpr int BK = 64;   // 2 MFMA k-steps of 32
+  static constexpr int LD = 72;
+  typedef floatx4 Acc;
+};
+
+template <class E>
+__device__ inline E zero_e() {
+  return E(0);
+}
+
+template <class E>
+__device__ inline E load_a(const E* A1, int64_t lda1, int64_t M1, const E* A2, int64_t lda2,
+                           int64_t k, int64_t i) {
+  return i < M1 ? A1[k * lda1 + i] : A2[k * lda2 + (i - M1)];
+}
+
+// one 16x16 MFMA block step for lane-local operand runs
+__device__ inline void mfma_step(const double* a, const double* b, doublex4& acc) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[t], acc, 0, 0, 0);
+}
+__device__ inline void mfma_step(const float* a, const float* b, floatx4& acc) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b[t], acc, 0, 0, 0);
+}
+__device__ inline void mfma_step(const uint16_t* a, const uint16_t* b, floatx4& acc) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    bf16x8 av, bv;
+    __builtin_memcpy(&av, a + 8 * t, 16);
+    __builtin_memcpy(&bv, b + 8 * t, 16);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+  }
+}
+
+template <class E>
+__global__ __launch_bounds__(kThreads) void k_gemm_tn(int64_t M, int64_t N, int64_t K,
+                                                      const E* A1, int64_t lda1, int64_t M1,
+                                                      const E* A2, int64_t lda2, const E* B,
+                                                      int64_t ldb, int64_t kchunk, double* C,
+                                                      int64_t ldc, int64_t split_stride) {
+  constexpr int BK = Cfg<E>::BK, LD = Cfg<E>::LD, RUN = BK / 4;
+  typedef typename Cfg<E>::Acc Acc;
+  __shared__ __attribute__((aligned(16))) E As[kBM * LD];
+  __shared__ __attribute__((aligned(16))) E Bs[kBN * LD];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t i0 = int64_t(blockIdx.x) * kBM, j0 = int64_t(blockIdx.y) * kBN;
+  const int64_t kbeg = int64_t(blockIdx.z) * kchunk;
+  const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
+  const int g = lane >> 4, li = lane & 15;
+
+  Acc acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    // stage A (K x M slice) and B (K x N slice) transposed: X[row][k]
+    for (int e = tid; e < BK * kBM; e += kThreads) {
+      int kk = e / kBM, ii = e % kBM;
+      int64_t k = k0 + kk, i = i0 + ii, j = j0 + ii;
+      E av = zero_e<E>(), bv = zero_e<E>();
+      if (k < kend) {
+        if (i < M) av = load_a(A1, lda1, M1, A2, lda2, k, i);
+        if (j < N) bv = B[k * ldb + j];
+      }
+      As[ii * LD + kk] = av;
+      Bs[ii * LD + kk] = bv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sm = 0; sm < 2; ++sm) {
+      E ar[RUN];
+      const E* pa = As + (wm * 32 + sm * 16 + li) * LD + g * RUN;
+#pragma unroll
+      for (int t = 0; t < RUN; ++t) ar[t] = pa[t];
+#pragma unroll
+      for (int sn = 0; sn < 2; ++sn) {
+        E br[RUN];
+        const E* pb = Bs + (wn * 32 + sn * 16 + li) * LD + g * RUN;
+#pragma unroll
+        for (int t = 0; t < RUN; ++t) br[t] = pb[t];
+        mfma_step(ar, br, acc[sm][sn]);
+      }
+    }
+    __syncthreads();
+  }
+  double* Cz = C + int64_t(blockIdx.z) * split_stride;
+#pragma unroll
+  for (int sm = 0; sm < 2; ++sm)
+#pragma unroll
+    for (int sn = 0; sn < 2; ++sn)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int64_t i = i0 + wm * 32 + sm * 16 + 4 * g + v;
+        int64_t j = j0 + wn * 32 + sn * 16 + li;
+        if (i < M && j < N) Cz[i * ldc + j] = double(acc[sm][sn][v]);
+      }
+}
+
+__global__ void k_reduce_splits(const double* part, int64_t M, int64_t N, int splits,
+                                double* C, int64_t ldc) {
+  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= M * N) return;
+  int64_t i = t / N, j = t % N;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += part[int64_t(z) * M * N + t];
+  C[i * ldc + j] = s;
+}
+
+__global__ void k_gemm_small(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                             int64_t sai, int64_t sak, const double* B, int64_t sbk, int64_t sbj,
+                             double beta, double* C, int64_t ldc) {
+  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= M * N) return;
+  int64_t i = t / N, j = t % N;
+  double s = 0.0;
+  for (int64_t k = 0; k < K; ++k) s += A[i * sai + k * sak] * B[k * sbk + j * sbj];
+  double* c = C + i * ldc + j;
+  *c = beta == 0.0 ? alpha * s : alpha * s + beta * *c;
+}
+
+__global__ void k_to_f64(const void* src, int bytes, int64_t n, double* dst) {
+  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  if (bytes == 8)
+    dst[t] = static_cast<const double*>(src)[t];
+  else if (bytes == 4)
+    dst[t] = double(static_cast<const float*>(src)[t]);
+  else
+    dst[t] = double(bf16_bits_to_f32(static_cast<const uint16_t*>(src)[t]));
+}
+
+template <class E>
+tsk_status gemm_tn_t(int64_t M, int64_t N, int64_t K, const void* A1, int64_t lda1, int64_t M1,
+                     const void* A2, int64_t lda2, const void* B, int64_t ldb, double* C,
+                     int64_t ldc, Ws& ws, hipStream_t st) {
+  constexpr int BK = Cfg<E>::BK;
+  int64_t tm = ceil_div(M, kBM), tn = ceil_div(N, kBN);
+  int64_t kblocks = ceil_div(K, BK);
+  int64_t splits = ceil_div(512, tm * tn);
+  int64_t maxs = kblocks / 4;
+  if (splits > maxs) splits = maxs;
+  if (splits < 1) splits = 1;
+  int64_t kchunk = ceil_div(kblocks, splits) * BK;
+  splits = K > 0 ? ceil_div(K, kchunk) : 1;
+  double* part = splits > 1 ? ws.take<double>(splits * M * N) : nullptr;
+  if (ws.measuring()) return TSK_OK;
+  if (M == 0 || N == 0) return TSK_OK;
+  if (K == 0) {
+    for (int64_t i = 0; i < M; ++i) TSK_HIP(hipMemsetAsync(C + i * ldc, 0, N * 8, st));
+    return TSK_OK;
+  }
+  dim3 grid(tm, tn, splits);
+  if (splits == 1) {
+    hipLaunchKernelGGL(k_gemm_tn<E>, grid, dim3(kThreads), 0, st, M, N, K,
+                       static_cast<const E*>(A1), lda1, M1, static_cast<const E*>(A2), lda2,
+                       static_cast<const E*>(B), ldb, kchunk, C, ldc, int64_t(0));
+    TSK_LAUNCHED();
+  } else {
+    hipLaunchKernelGGL(k_gemm_tn<E>, grid, dim3(kThreads), 0, st, M, N, K,
+                       static_cast<const E*>(A1), lda1, M1, static_cast<const E*>(A2), lda2,
+                       static_cast<const E*>(B), ldb, kchunk, part, N, M * N);
+    TSK_LAUNCHED();
+    hipLaunchKernelGGL(k_reduce_splits, dim3(ceil_div(M * N, 256)), dim3(256), 0, st, part, M, N,
+                       int(splits), C, ldc);
+    TSK_LAUNCHED();
+  }
+  return TSK_OK;
+}
+
+}  // namespace
+
+tsk_status gemm_tn(int prec, int64_t M, int64_t N, int64_t K, const void* A1, int64_t lda1,
+                   int64_t M1, const void* A2, int64_t lda2, const void* B, int64_t ldb,
+                   double* C, int64_t ldc, Ws& ws, hipStream_t st) {
+  if (!A2) {
+    A2 = A1;
+    lda2 = lda1;
+    M1 = M;
+  }
+  switch (prec) {
+    case TSK_PREC_F64:
+      return gemm_tn_t<double>(M, N, K, A1, lda1, M1, A2, lda2, B, ldb, C, ldc, ws, st);
+    case TSK_PREC_F32:
+      return gemm_tn_t<float>(M, N, K, A1, lda1, M1, A2, lda2, B, ldb, C, ldc, ws, st);
+    default:
+      return gemm_tn_t<uint16_t>(M, N, K, A1, lda1, M1, A2, lda2, B, ldb, C, ldc, ws, st);
+  }
+}
+
+tsk_status gemm_small(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                      int64_t sai, int64_t sak, const double* B, int64_t sbk, int64_t sbj,
+                      double beta, double* C, int64_t ldc, hipStream_t st) {
+  if (M * N == 0) return TSK_OK;
+  hipLaunchKernelGGL(k_gemm_small, dim3(ceil_div(M * N, 256)), dim3(256), 0, st, M, N, K, alpha,
+                     A, sai, sak, B, sbk, sbj, beta, C, ldc);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+tsk_status convert_to_f64(const void* src, int bytes, int64_t count, double* dst,
+                          hipStream_t st) {
+  if (count <= 0) return TSK_OK;
+  hipLaunchKernelGGL(k_to_f64, dim3(ceil_div(count, 256)), dim3(256), 0, st, src, bytes, count,
+                     dst);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+}  // namespace tsk

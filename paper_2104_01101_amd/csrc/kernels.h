@@ -1,0 +1,111 @@
+// Internal interfaces between the host driver and the kernel translation units.
+#pragma once
+
+#include "common.h"
+
+namespace tsk {
+
+// A tensor as seen by the kernels (copied from tsk_tensor after validation).
+struct TensorView {
+  int order;
+  int64_t dims[TSK_MAX_ORDER];
+  int dtype;
+  int layout;
+  const void* values;
+  int64_t nnz;  // number of stored entries (prod dims for DENSE)
+  const int32_t* idx[TSK_MAX_ORDER];
+};
+
+// ---- sketch pass (sketch_pass.hip) ----
+// type 0: Y[(sum_{k != col_mode} h[k][i_k]) mod rows, i_col] += prod sg[k][i_k] * v
+// type 1: Y[g(j), i_col] += tau(j) * v, (g, tau) from draw(key, j), j = row-major
+//         index of the other modes
+struct PassJob {
+  int type;
+  int col_mode;
+  int64_t rows;
+  const int32_t* const* h;  // host array of device pointers (type 0)
+  const int8_t* const* sg;
+  uint64_t key;  // type 1
+  void* out;     // device rows x dims[col_mode], dtype of the tensor
+};
+tsk_status sketch_pass(const TensorView& T, const PassJob* jobs, int njobs, Ws& ws,
+                       hipStream_t st);
+
+// ---- random tables (rng.hip) ----
+// h[i] = bucket_m(draw(key, i)), sg[i] = sign(draw(key, i)), i < s
+tsk_status launch_hash_table(uint64_t key, int64_t s, int64_t m, int32_t* h, int8_t* sg,
+                             hipStream_t st);
+// out[i] = scale * gauss(key, i), i < count (FP64)
+tsk_status launch_gauss(uint64_t key, int64_t count, double scale, double* out, hipStream_t st);
+
+// ---- TensorSketch of the Kronecker chain (ts_lhs.hip) ----
+struct CsrTable {  // inverse hash of one mode: bucket b holds items[ptr[b] .. ptr[b+1])
+  int32_t* ptr;    // m + 1
+  int32_t* items;  // s, increasing within a bucket
+};
+tsk_status build_inverse_hash(const int32_t* h, int64_t s, int64_t m, CsrTable csr, Ws& ws,
+                              hipStream_t st);
+// Z (m x r row-major, precision prec) = TensorSketch of kron_{k in modes} A^(k)
+struct LhsMode {
+  const double* A;  // s_k x R_k
+  int64_t s, R;
+  const int8_t* sg;
+  CsrTable csr;
+};
+tsk_status ts_lhs(const LhsMode* modes, int nmodes, int64_t m, int prec, void* Z, Ws& ws,
+                  hipStream_t st);
+// Pieces of ts_lhs shared with the adjoint.  CS: m x sum R_k (mode blocks,
+// each m x R_k row-major); spec: complex FFT of every CS column (column-major
+// blocks of m complex); tw: m complex twiddles.
+tsk_status ts_lhs_spectra(const LhsMode* modes, int nmodes, int64_t m, double* CS,
+                          double* spec, double* tw, Ws& ws, hipStream_t st);
+tsk_status ts_compose(const LhsMode* modes, int nmodes, int64_t m, const double* spec,
+                      const double* tw, int prec, void* Z, hipStream_t st);
+tsk_status fft_columns(const double* X, int64_t m, int64_t cols, const double* tw, double* spec,
+                       hipStream_t st);
+tsk_status ts_conv_adjoint(const LhsMode* modes, int nmodes, int64_t m, const double* spec,
+                           const double* gspec, const double* tw, double* gCS, hipStream_t st);
+
+// ---- GEMM (gemm.hip) ----
+// C (M x N, FP64) = A^T B with A = [A1 | A2] (K x M1, K x (M - M1), row-major,
+// leading dims lda1/lda2) and B (K x N, ldb), all of element type `prec`.
+// `ldc` leading dimension of C.  Deterministic split-K.
+tsk_status gemm_tn(int prec, int64_t M, int64_t N, int64_t K, const void* A1, int64_t lda1,
+                   int64_t M1, const void* A2, int64_t lda2, const void* B, int64_t ldb,
+                   double* C, int64_t ldc, Ws& ws, hipStream_t st);
+// C (M x N) = alpha * op(A) op(B) + beta * C, FP64, small sizes; op given by
+// strides: A(i,k) = A[i*sai + k*sak], B(k,j) = B[k*sbk + j*sbj], C(i,j) = C[i*ldc + j]
+tsk_status gemm_small(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                      int64_t sai, int64_t sak, const double* B, int64_t sbk, int64_t sbj,
+                      double beta, double* C, int64_t ldc, hipStream_t st);
+tsk_status convert_to_f64(const void* src, int dtype_or_prec_bytes, int64_t count, double* dst,
+                          hipStream_t st);
+
+// ---- FP64 dense linear algebra (linalg.hip) ----
+// In-place lower Cholesky of the n x n matrix G (row-major, lda); sets *info
+// (device int) to j+1 at the first non-positive pivot j (0 = success).
+tsk_status cholesky(double* G, int64_t n, int64_t lda, int* info, hipStream_t st);
+// Rows of X (rows x n, ldx) <- rows of X G^{-1} with G = L L^T (L from
+// cholesky); forward_only: X <- X L^{-T}.
+tsk_status chol_solve_rows(const double* L, int64_t n, int64_t ldl, double* X, int64_t rows,
+                           int64_t ldx, bool forward_only, hipStream_t st);
+// Leading R eigenpairs (descending) of the symmetric q x q matrix M (row-major);
+// M is overwritten.  lam: R doubles, V: q x R row-major.
+tsk_status sym_eig_top(double* M, int64_t q, int64_t R, double* lam, double* V, Ws& ws,
+                       hipStream_t st);
+// Make the entry of largest magnitude of every column of A (rows x R) positive.
+tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, hipStream_t st);
+// A (rows x R): A <- A * diag(scale) with scale[c] = 1/sqrt(lam[c])
+tsk_status scale_columns_inv_sqrt(double* A, int64_t rows, int64_t R, const double* lam,
+                                  hipStream_t st);
+tsk_status transpose_f64(const double* A, int64_t rows, int64_t cols, double* At,
+                         hipStream_t st);
+// A (rows x R) <- A chol(A^T A)^{-T} (one CholeskyQR pass, FP64)
+tsk_status cholqr(double* A, int64_t rows, int64_t R, int* info, Ws& ws, hipStream_t st);
+
+// ---- exact rank-constrained solve (solve.cpp) ----
+tsk_status rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s, int R,
+                    int prec, double* A, double* W, int* info, Ws& ws, hipStream_t st);
+
+}  // namespace tsk

@@ -1,0 +1,13 @@
+// Leverage-score sampling launchers.
+#pragma once
+#include "kernels.h"
+
+namespace tsk {
+tsk_status leverage_sample(int N, const int64_t* dims, const int64_t* ranks, int n, int64_t m,
+                           uint64_t seed, int sweep, const double* const* factors, int32_t* idx,
+                           double* w, Ws& ws, hipStream_t st);
+// Z (m x r) and/or Y (m x dims[n], dense T only), precision prec
+tsk_status leverage_rows(const TensorView& T, const int64_t* ranks, int n, int64_t m,
+                         const int32_t* idx, const double* w, const double* const* factors,
+                         int prec, void* Z, void* Y, hipStream_t st);
+}  // namespace tsk

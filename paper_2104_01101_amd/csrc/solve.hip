@@ -1,0 +1,49 @@
+// Exact sketched rank-constrained solve of one Tucker subproblem (Sec. 4
+// theorems; Sec. 2.2 for the roles of A^(n) and C_(n)^T):
+//
+//   [Z^T Z ; Y^T Z]      one MFMA Gram launch in the operands' precision
+//   X^T = (Y^T Z)(Z^T Z)^{-1}     FP64 Cholesky + row-block triangular solves
+//   A   = leading R right singular vectors of X
+//         r <= s: eigenvectors U of X X^T (r x r), A = X^T U Lambda^{-1/2}
+//         r >  s: eigenvectors of X^T X (s x s)
+//   A  <- CholeskyQR(A), largest-magnitude entry of each column positive
+//   W   = X A = C_(n)^T
+// All FP64 after the Gram products; no host synchronisation.
+
+#include "common.h"
+#include "kernels.h"
+
+namespace tsk {
+
+tsk_status rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s, int R,
+                    int prec, double* A, double* W, int* info, Ws& ws, hipStream_t st) {
+  double* GH = ws.take<double>(size_t(r + s) * r);
+  double* G = GH;
+  double* Xt = GH + size_t(r) * r;  // s x r, holds Y^T Z then X^T
+  const bool small_r = r <= s;
+  const int64_t q = small_r ? r : s;
+  double* Mq = ws.take<double>(size_t(q) * q);
+  double* lam = ws.take<double>(R);
+  double* U = small_r ? ws.take<double>(size_t(r) * R) : nullptr;
+  double* X = small_r ? nullptr : ws.take<double>(size_t(r) * s);
+  const bool run = !ws.measuring();
+  TSK_TRY(gemm_tn(prec, r + s, r, m, Z, r, r, Y, s, Z, r, GH, r, ws, st));
+  if (run) TSK_TRY(cholesky(G, r, r, info, st));
+  if (run) TSK_TRY(chol_solve_rows(G, r, r, Xt, s, r, false, st));
+  if (small_r) {
+    TSK_TRY(gemm_tn(TSK_PREC_F64, r, r, s, Xt, r, r, nullptr, 0, Xt, r, Mq, r, ws, st));
+    TSK_TRY(sym_eig_top(Mq, r, R, lam, U, ws, st));
+    if (run) TSK_TRY(gemm_small(s, R, r, 1.0, Xt, r, 1, U, R, 1, 0.0, A, R, st));
+    if (run) TSK_TRY(scale_columns_inv_sqrt(A, s, R, lam, st));
+  } else {
+    if (run) TSK_TRY(transpose_f64(Xt, s, r, X, st));
+    TSK_TRY(gemm_tn(TSK_PREC_F64, s, s, r, X, s, s, nullptr, 0, X, s, Mq, s, ws, st));
+    TSK_TRY(sym_eig_top(Mq, s, R, lam, A, ws, st));
+  }
+  TSK_TRY(cholqr(A, s, R, info + 1, ws, st));
+  if (run) TSK_TRY(sign_fix_columns(A, s, R, st));
+  TSK_TRY(gemm_tn(TSK_PREC_F64, r, R, s, Xt, r, r, nullptr, 0, A, R, W, R, ws, st));
+  return TSK_OK;
+}
+
+}  // namespace tsk

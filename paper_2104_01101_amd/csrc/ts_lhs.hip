@@ -1,0 +1,404 @@
+// TensorSketch of a Kronecker chain, Z = S^(n) kron_{k != n} A^(k) (Sec. 3.1):
+//
+//   CS_k  = S^(k) A^(k)                 CountSketch of every factor (m x R_k)
+//   Z(:, rho) = IFFT( prod_k FFT(CS_k(:, rho_k)) )   length-m circular convolution
+//
+// CountSketch is a gather over the inverse hash (bucket -> increasing row
+// indices), so each CS entry is the in-order sum of its rows.  The FFTs are
+// exact-length mixed-radix Stockham transforms (radix 4, 2, 3, 5, direct DFT
+// for other primes) staged in LDS, in FP64; the inverse transform of two
+// output columns is done at once by packing them as real and imaginary parts.
+
+#include "common.h"
+#include "kernels.h"
+
+namespace tsk {
+
+namespace {
+
+constexpr int kFftBlock = 256;
+constexpr int kMaxRadices = 48;
+
+struct Radices {
+  int n;
+  int r[kMaxRadices];
+};
+
+Radices factor_length(int64_t m) {
+  Radices rd{};
+  int64_t x = m;
+  while (x % 4 == 0) rd.r[rd.n++] = 4, x /= 4;
+  while (x % 2 == 0) rd.r[rd.n++] = 2, x /= 2;
+  for (int p = 3; p <= 5; p += 2)
+    while (x % p == 0) rd.r[rd.n++] = p, x /= p;
+  for (int64_t q = 7; x > 1; q += 2)
+    while (x % q == 0) rd.r[rd.n++] = int(q), x /= q;
+  return rd;
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 conj_if(double2 a, bool c) { return c ? make_double2(a.x, -a.y) : a; }
+// multiply by -i (forward) or +i (inverse)
+__device__ inline double2 rot(double2 a, bool inv) {
+  return inv ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+// In-place-by-ping-pong FFT of a[0..m) in LDS (b is scratch of the same size).
+// Returns the buffer holding the result.  tw[t] = exp(-2 pi i t / m).
+__device__ double2* fft_lds(double2* a, double2* b, int m, const Radices& rd, const double2* tw,
+                            bool inv) {
+  int Ns = 1;
+  for (int p = 0; p < rd.n; ++p) {
+    const int R = rd.r[p];
+    const int nb = m / R;
+    const int tstep = m / (Ns * R);
+    const int wstep = m / R;
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+      const int k = j % Ns;
+      const int idxD = (j / Ns) * Ns * R + k;
+      if (R <= 5) {
+        double2 v[5];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+          if (r >= R) break;
+          double2 x = a[j + r * nb];
+          v[r] = r == 0 ? x : cmul(x, conj_if(tw[r * k * tstep], inv));
+        }
+        if (R == 2) {
+          b[idxD] = cadd(v[0], v[1]);
+          b[idxD + Ns] = csub(v[0], v[1]);
+        } else if (R == 4) {
+          double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+          double2 s13 = cadd(v[1], v[3]), d13 = rot(csub(v[1], v[3]), inv);
+          b[idxD] = cadd(s02, s13);
+          b[idxD + Ns] = cadd(d02, d13);
+          b[idxD + 2 * Ns] = csub(s02, s13);
+          b[idxD + 3 * Ns] = csub(d02, d13);
+        } else {
+          for (int o = 0; o < R; ++o) {
+            double2 acc = v[0];
+            for (int r = 1; r < R; ++r)
+              acc = cadd(acc, cmul(v[r], conj_if(tw[((o * r) % R) * wstep], inv)));
+            b[idxD + o * Ns] = acc;
+          }
+        }
+      } else {  // prime radix > 5: direct DFT from LDS
+        for (int o = 0; o < R; ++o) {
+          double2 acc = make_double2(0.0, 0.0);
+          for (int r = 0; r < R; ++r) {
+            double2 x = a[j + r * nb];
+            if (r) x = cmul(x, conj_if(tw[r * k * tstep], inv));
+            acc = cadd(acc, cmul(x, conj_if(tw[((o * r) % R) * wstep], inv)));
+          }
+          b[idxD + o * Ns] = acc;
+        }
+      }
+    }
+    __syncthreads();
+    double2* t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
+__global__ void k_twiddles(int64_t m, double2* tw) {
+  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  double s, c;
+  sincospi(-2.0 * double(t) / double(m), &s, &c);
+  tw[t] = make_double2(c, s);
+}
+
+// ---- inverse hash (bucket -> rows), stable: rows increasing in a bucket ----
+__global__ void k_inverse_hash(const int32_t* h, int64_t s, int64_t m, int32_t* ptr,
+                               int32_t* items, int32_t* cursor_g) {
+  // single wave; cursor in global scratch (m + 1 ints)
+  const int lane = threadIdx.x;
+  for (int64_t b = lane; b <= m; b += 64) cursor_g[b] = 0;
+  __syncthreads();
+  for (int64_t i = lane; i < s; i += 64) atomicAdd(&cursor_g[h[i] + 1], 1);  // exact counts
+  __syncthreads();
+  if (lane == 0) {
+    int32_t run = 0;
+    for (int64_t b = 0; b <= m; ++b) {
+      run += cursor_g[b];
+      cursor_g[b] = run;  // inclusive of the shifted counts = exclusive start of bucket b
+      ptr[b] = run;
+    }
+  }
+  __syncthreads();
+  int bits = 1;
+  while ((int64_t(1) << bits) < m) ++bits;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (int64_t i0 = 0; i0 < s; i0 += 64) {
+    int64_t i = i0 + lane;
+    bool valid = i < s;
+    uint32_t key = valid ? uint32_t(h[i]) : 0u;
+    uint64_t mt = __ballot(valid);
+    for (int bt = 0; bt < bits; ++bt) {
+      bool bit = (key >> bt) & 1u;
+      uint64_t bal = __ballot(bit);
+      mt &= bit ? bal : ~bal;
+    }
+    int rank = __popcll(mt & lt);
+    int base = 0;
+    if (valid && rank == 0) {
+      base = cursor_g[key];
+      cursor_g[key] = base + __popcll(mt);
+    }
+    int leader = valid ? __ffsll((unsigned long long)mt) - 1 : lane;
+    base = __shfl(base, leader);
+    if (valid) items[base + rank] = int32_t(i);
+    __syncthreads();
+  }
+}
+
+// ---- CountSketch by gather: CS[b, c] = sum_{i in bucket b} sg[i] A[i, c] ----
+__global__ void k_cs_gather(const double* A, int64_t R, const int8_t* sg, const int32_t* ptr,
+                            const int32_t* items, int64_t m, double* CS) {
+  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= m * R) return;
+  int64_t b = t / R, c = t % R;
+  double acc = 0.0;
+  for (int32_t q = ptr[b]; q < ptr[b + 1]; ++q) {
+    int32_t i = items[q];
+    double v = A[int64_t(i) * R + c];
+    acc += sg[i] > 0 ? v : -v;
+  }
+  CS[t] = acc;
+}
+
+// ---- forward FFT of every CountSketch column ----
+struct SpecJob {
+  int nmodes;
+  int64_t R[TSK_MAX_ORDER];
+  int64_t coloff[TSK_MAX_ORDER];  // first column index of mode q in the spectra array
+  const double* CS[TSK_MAX_ORDER];
+};
+
+__global__ void k_spectra(SpecJob sj, int64_t m, Radices rd, const double2* tw, double2* spec) {
+  extern __shared__ double2 buf[];
+  double2* a = buf;
+  double2* b = buf + m;
+  int col = blockIdx.x;
+  int q = 0;
+  while (q + 1 < sj.nmodes && col >= sj.coloff[q + 1]) ++q;
+  int64_t c = col - sj.coloff[q];
+  const double* CS = sj.CS[q];
+  int64_t R = sj.R[q];
+  for (int64_t f = threadIdx.x; f < m; f += blockDim.x) a[f] = make_double2(CS[f * R + c], 0.0);
+  __syncthreads();
+  double2* out = fft_lds(a, b, int(m), rd, tw, false);
+  double2* dst = spec + int64_t(col) * m;
+  for (int64_t f = threadIdx.x; f < m; f += blockDim.x) dst[f] = out[f];
+}
+
+// ---- Hadamard product of spectra and inverse FFT of two columns at once ----
+__global__ void k_compose(SpecJob sj, int64_t m, int64_t r, Radices rd, const double2* tw,
+                          const double2* spec, int prec, void* Z) {
+  extern __shared__ double2 buf[];
+  double2* a = buf;
+  double2* b = buf + m;
+  int64_t ra = 2 * int64_t(blockIdx.x), rb = ra + 1;
+  bool has_b = rb < r;
+  // column indices of each mode for rho_a, rho_b (row-major over modes)
+  int64_t ca[TSK_MAX_ORDER], cb[TSK_MAX_ORDER];
+  {
+    int64_t xa = ra, xb = has_b ? rb : 0;
+    for (int q = sj.nmodes - 1; q >= 0; --q) {
+      ca[q] = xa % sj.R[q];
+      xa /= sj.R[q];
+      cb[q] = xb % sj.R[q];
+      xb /= sj.R[q];
+    }
+  }
+  for (int64_t f = threadIdx.x; f < m; f += blockDim.x) {
+    double2 pa = make_double2(1.0, 0.0), pb = make_double2(has_b ? 1.0 : 0.0, 0.0);
+    for (int q = 0; q < sj.nmodes; ++q) {
+      pa = cmul(pa, spec[(sj.coloff[q] + ca[q]) * m + f]);
+      if (has_b) pb = cmul(pb, spec[(sj.coloff[q] + cb[q]) * m + f]);
+    }
+    a[f] = make_double2(pa.x - pb.y, pa.y + pb.x);  // pa + i pb
+  }
+  __syncthreads();
+  double2* out = fft_lds(a, b, int(m), rd, tw, true);
+  const double inv_m = 1.0 / double(m);
+  for (int64_t f = threadIdx.x; f < m; f += blockDim.x) {
+    store_prec(Z, size_t(f * r + ra), out[f].x * inv_m, prec);
+    if (has_b) store_prec(Z, size_t(f * r + rb), out[f].y * inv_m, prec);
+  }
+}
+
+// one workgroup per (mode q, column c) of the CountSketches; output gCS in
+// the CS layout (mode q block: m x R_q row-major, blocks in mode order)
+__global__ void k_conv_adjoint(SpecJob sj, int64_t m, int64_t r, Radices rd, const double2* tw,
+                               const double2* spec, const double2* gspec, double* gCS) {
+  extern __shared__ double2 buf[];
+  double2* a = buf;
+  double2* b = buf + m;
+  const int col = blockIdx.x;
+  int q = 0;
+  while (q + 1 < sj.nmodes && col >= sj.coloff[q + 1]) ++q;
+  const int64_t c = col - sj.coloff[q];
+  int64_t inner = 1;
+  for (int l = q + 1; l < sj.nmodes; ++l) inner *= sj.R[l];
+  const int64_t outer = r / (inner * sj.R[q]);
+  for (int64_t f = threadIdx.x; f < m; f += blockDim.x) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t o = 0; o < outer; ++o)
+      for (int64_t in = 0; in < inner; ++in) {
+        const int64_t rho = (o * sj.R[q] + c) * inner + in;
+        double2 prod = make_double2(1.0, 0.0);
+        int64_t x = rho;
+        for (int l = sj.nmodes - 1; l >= 0; --l) {
+          const int64_t cl = x % sj.R[l];
+          x /= sj.R[l];
+          if (l != q) prod = cmul(prod, spec[(sj.coloff[l] + cl) * m + f]);
+        }
+        acc = cadd(acc, cmul(conj_if(prod, true), gspec[rho * m + f]));
+      }
+    a[f] = acc;
+  }
+  __syncthreads();
+  double2* out = fft_lds(a, b, int(m), rd, tw, true);
+  double* dst = gCS;
+  for (int l = 0; l < q; ++l) dst += m * sj.R[l];
+  const double inv_m = 1.0 / double(m);
+  for (int64_t f = threadIdx.x; f < m; f += blockDim.x) dst[f * sj.R[q] + c] = out[f].x * inv_m;
+}
+
+}  // namespace
+
+tsk_status build_inverse_hash(const int32_t* h, int64_t s, int64_t m, CsrTable csr, Ws& ws,
+                              hipStream_t st) {
+  int32_t* cursor = ws.take<int32_t>(m + 1);
+  if (ws.measuring()) return TSK_OK;
+  hipLaunchKernelGGL(k_inverse_hash, dim3(1), dim3(64), 0, st, h, s, m, csr.ptr, csr.items,
+                     cursor);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+static tsk_status check_fft_lds(int64_t m) {
+  static int max_lds = -1;
+  if (max_lds < 0) {
+    int dev = 0;
+    TSK_HIP(hipGetDevice(&dev));
+    TSK_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  }
+  if (int64_t(2) * m * 16 > max_lds) {
+    set_error("TensorSketch length m = %lld exceeds the LDS-resident FFT limit (%d bytes)",
+              (long long)m, max_lds);
+    return TSK_EUNSUPPORTED;
+  }
+  return TSK_OK;
+}
+
+tsk_status ts_lhs_spectra(const LhsMode* modes, int nmodes, int64_t m, double* CS, double* spec,
+                          double* tw, Ws& ws, hipStream_t st) {
+  (void)ws;
+  Radices rd = factor_length(m);
+  SpecJob sj{};
+  sj.nmodes = nmodes;
+  int64_t off = 0, csoff = 0;
+  for (int q = 0; q < nmodes; ++q) {
+    sj.R[q] = modes[q].R;
+    sj.coloff[q] = off;
+    sj.CS[q] = CS + csoff;
+    off += modes[q].R;
+    csoff += m * modes[q].R;
+  }
+  TSK_TRY(check_fft_lds(m));
+  hipLaunchKernelGGL(k_twiddles, dim3(ceil_div(m, 256)), dim3(256), 0, st, m,
+                     reinterpret_cast<double2*>(tw));
+  TSK_LAUNCHED();
+  for (int q = 0; q < nmodes; ++q) {
+    const LhsMode& md = modes[q];
+    int64_t n = m * md.R;
+    hipLaunchKernelGGL(k_cs_gather, dim3(ceil_div(n, 256)), dim3(256), 0, st, md.A, md.R, md.sg,
+                       md.csr.ptr, md.csr.items, m, const_cast<double*>(sj.CS[q]));
+    TSK_LAUNCHED();
+  }
+  hipLaunchKernelGGL(k_spectra, dim3(off), dim3(kFftBlock), size_t(2 * m * 16), st, sj, m, rd,
+                     reinterpret_cast<const double2*>(tw), reinterpret_cast<double2*>(spec));
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+tsk_status ts_compose(const LhsMode* modes, int nmodes, int64_t m, const double* spec,
+                      const double* tw, int prec, void* Z, hipStream_t st) {
+  int64_t r = 1;
+  for (int q = 0; q < nmodes; ++q) r *= modes[q].R;
+  Radices rd = factor_length(m);
+  SpecJob sj{};
+  sj.nmodes = nmodes;
+  int64_t off = 0;
+  for (int q = 0; q < nmodes; ++q) {
+    sj.R[q] = modes[q].R;
+    sj.coloff[q] = off;
+    off += modes[q].R;
+  }
+  hipLaunchKernelGGL(k_compose, dim3(ceil_div(r, 2)), dim3(kFftBlock), size_t(2 * m * 16), st,
+                     sj, m, r, rd, reinterpret_cast<const double2*>(tw),
+                     reinterpret_cast<const double2*>(spec), prec, Z);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+tsk_status ts_lhs(const LhsMode* modes, int nmodes, int64_t m, int prec, void* Z, Ws& ws,
+                  hipStream_t st) {
+  int64_t totR = 0;
+  for (int q = 0; q < nmodes; ++q) totR += modes[q].R;
+  double* CS = ws.take<double>(m * totR);
+  double* spec = ws.take<double>(2 * m * totR);
+  double* tw = ws.take<double>(2 * m);
+  if (ws.measuring()) return TSK_OK;
+  TSK_TRY(ts_lhs_spectra(modes, nmodes, m, CS, spec, tw, ws, st));
+  return ts_compose(modes, nmodes, m, spec, tw, prec, Z, st);
+}
+
+// FFT of the columns of a real m x cols row-major matrix (twiddles already set)
+tsk_status fft_columns(const double* X, int64_t m, int64_t cols, const double* tw, double* spec,
+                       hipStream_t st) {
+  TSK_TRY(check_fft_lds(m));
+  Radices rd = factor_length(m);
+  SpecJob sj{};
+  sj.nmodes = 1;
+  sj.R[0] = cols;
+  sj.coloff[0] = 0;
+  sj.CS[0] = X;
+  hipLaunchKernelGGL(k_spectra, dim3(cols), dim3(kFftBlock), size_t(2 * m * 16), st, sj, m, rd,
+                     reinterpret_cast<const double2*>(tw), reinterpret_cast<double2*>(spec));
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+// Adjoint of the convolution: for mode q (of the modes list) and column c,
+// gCS_q[:, c] = IFFT( sum_{rho : rho_q = c} conj(prod_{l != q} F_l[:, rho_l]) * G[:, rho] )
+tsk_status ts_conv_adjoint(const LhsMode* modes, int nmodes, int64_t m, const double* spec,
+                           const double* gspec, const double* tw, double* gCS, hipStream_t st) {
+  Radices rd = factor_length(m);
+  SpecJob sj{};
+  sj.nmodes = nmodes;
+  int64_t off = 0, r = 1;
+  for (int q = 0; q < nmodes; ++q) {
+    sj.R[q] = modes[q].R;
+    sj.coloff[q] = off;
+    off += modes[q].R;
+    r *= modes[q].R;
+  }
+  hipLaunchKernelGGL(k_conv_adjoint, dim3(off), dim3(kFftBlock), size_t(2 * m * 16), st, sj, m, r,
+                     rd, reinterpret_cast<const double2*>(tw),
+                     reinterpret_cast<const double2*>(spec),
+                     reinterpret_cast<const double2*>(gspec), gCS);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+}  // namespace tsk

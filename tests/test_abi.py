@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol the header declares, reports its version, implements the keyed
+generator exactly as the oracle's written specification, and rejects invalid
+arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsk.h")
+
+
+def _lib():
+    from paper_2104_01101_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libtsk.so not built")
+    return L
+
+
+def test_header_symbols_exported():
+    L = _lib()
+    lib = L.lib()
+    names = re.findall(r"\b(tsk_[a-z0-9_]+)\s*\(", open(HEADER).read())
+    assert len(set(names)) >= 18
+    for n in set(names):
+        assert hasattr(lib, n), n
+
+
+def test_abi_version():
+    L = _lib()
+    assert L.lib().tsk_abi_version() == 1
+
+
+def test_generator_matches_oracle_spec():
+    L = _lib()
+    from oracle import rng
+    lib = L.lib()
+    for seed, purpose, a, b, c in [(0, -1, 0, 0, 0), (7, 1, 2, 0, 0), (123, 4, 3, 1, 2)]:
+        k_lib = lib.tsk_stream_key(seed, purpose, a, b, c)
+        k_or = int(rng.stream_key(seed, None if purpose < 0 else purpose, a, b, c)[0])
+        assert k_lib == k_or
+        for i in (0, 1, 17, 123456789):
+            assert lib.tsk_draw(k_lib, i) == int(rng.draw(k_or, [i])[0])
+
+
+def _tensor(L, dims, layout=0, dtype=1, nnz=0):
+    t = L._Tensor()
+    t.order = len(dims)
+    for k, d in enumerate(dims):
+        t.dims[k] = d
+    t.dtype, t.layout, t.nnz = dtype, layout, nnz
+    t.values = 1 if nnz or layout == 0 else 0
+    return t
+
+
+def _opts(L, m, sketch=0):
+    o = L._Options()
+    o.m, o.sketch, o.sweeps, o.prec = m, sketch, 1, 0
+    return o
+
+
+@pytest.mark.parametrize("dims,ranks,m,sketch,layout,expect", [
+    ((10, 10, 10), (3, 3, 3), 5, 0, 0, -1),        # m < prod of other ranks
+    ((10, 10, 10), (11, 3, 3), 50, 0, 0, -1),      # rank above dimension
+    ((10,), (3,), 50, 0, 0, -1),                   # order 1
+    ((10, 10, 10), (3, 3, 3), 50, 1, 1, -2),       # leverage on COO: unsupported
+    ((10, 10, 10), (3, 3, 20), 50, 0, 0, -1),      # R_n above the product of the others... and s
+])
+def test_validation_errors(dims, ranks, m, sketch, layout, expect):
+    L = _lib()
+    t = _tensor(L, dims, layout=layout, nnz=5 if layout else 0)
+    if layout:
+        for k in range(len(dims)):
+            t.idx[k] = 8
+    o = _opts(L, m, sketch)
+    nb = ctypes.c_size_t(0)
+    st = L.lib().tsk_workspace_size(ctypes.byref(t), L.i32_array(ranks), ctypes.byref(o),
+                                    ctypes.byref(nb))
+    assert st == expect
+    assert len(L.lib().tsk_last_error()) > 0
+
+
+def test_workspace_query_sizes_grow_with_problem():
+    L = _lib()
+    sizes = []
+    for s in (20, 40, 80):
+        t = _tensor(L, (s, s, s))
+        o = _opts(L, 200)
+        nb = ctypes.c_size_t(0)
+        assert L.lib().tsk_workspace_size(ctypes.byref(t), L.i32_array((5, 5, 5)),
+                                          ctypes.byref(o), ctypes.byref(nb)) == 0
+        sizes.append(nb.value)
+    assert sizes[0] < sizes[1] < sizes[2]

@@ -1,0 +1,269 @@
+"""GPU parity of each step of the hot path against the FP64 oracle, through the
+C ABI.  Integer outputs (hash maps, signs, sampled indices) must be bit-exact;
+FP64 outputs that are sums in a fixed order must match to the stated rounding
+bound; FP32/BF16 outputs within their precision's bound."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import sketch as osk, solve as osv, tucker as otk, adjoint as oadj
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def tsk():
+    import paper_2104_01101_amd as t
+    t.lib()  # fail loudly if the library is missing
+    return t
+
+
+def _gpu_tensor(tsk, dims, idx=None, val=None, dense=None):
+    if dense is not None:
+        return tsk.Tensor.dense(torch.from_numpy(np.ascontiguousarray(dense)).to(DEV))
+    return tsk.Tensor.coo(torch.from_numpy(idx).to(DEV), torch.from_numpy(val).to(DEV), dims)
+
+
+def _tables_np(h, s):
+    return {k: (h[k].cpu().numpy().astype(np.int64), s[k].cpu().numpy().astype(np.float64))
+            for k in range(len(h)) if h[k] is not None}
+
+
+# ---------------------------------------------------------------- a1 ----
+@pytest.mark.parametrize("dims,m,n,seed", [((40, 40, 40), 200, 0, 0), ((2000, 37, 5), 1600, 1, 3),
+                                           ((7, 9, 11, 13), 2048, 3, 11), ((10000, 3), 2048, 0, 0)])
+def test_hash_tables_bit_exact(tsk, dims, m, n, seed):
+    h, s = tsk.hash_tables(dims, n, m, seed, DEV)
+    ref = osk.ts_tables(dims, m, seed, n)
+    for k, (hr, sr) in ref.items():
+        assert np.array_equal(h[k].cpu().numpy().astype(np.int64), hr)
+        assert np.array_equal(s[k].cpu().numpy().astype(np.float64), sr)
+
+
+# ---------------------------------------------------------------- a2 ----
+def test_sketch_rhs_golden(tsk):
+    d = json.load(open(os.path.join(GOLDEN, "ts_worked_example.json")))
+    dims, m, n = tuple(d["dims"]), d["m"], d["n"]
+    X = np.fromfunction(lambda a, b, c: 1 + 6 * a + 2 * b + c, dims)
+    T = _gpu_tensor(tsk, dims, dense=X)
+    h = [None] + [torch.tensor(d["h"][str(k)], dtype=torch.int32, device=DEV) for k in (1, 2)]
+    s = [None] + [torch.tensor(d["sigma"][str(k)], dtype=torch.int8, device=DEV) for k in (1, 2)]
+    Y = tsk.sketch_rhs_ts(T, n, m, h, s)
+    assert np.array_equal(Y.cpu().numpy(), np.array(d["Y"]))
+
+
+@pytest.mark.parametrize("dims,nnz,m,n", [((40, 40, 40), 0, 200, 0),          # dense
+                                          ((300, 200, 100), 50_000, 1600, 1),
+                                          ((30, 20, 10, 7), 9_000, 97, 2),    # ragged, prime m
+                                          ((5000, 6, 4), 20_000, 64, 0),      # wide rows: tiles split columns
+                                          ((50, 50, 50), 1, 16, 2)])
+def test_sketch_rhs_fp64_bitwise(tsk, dims, nnz, m, n):
+    """FP64 cells are the in-order sum of their entries, exactly as the oracle's
+    sequential bincount: bitwise equal."""
+    rs = np.random.default_rng(nnz + m)
+    if nnz == 0:
+        X = rs.standard_normal(dims)
+        T = _gpu_tensor(tsk, dims, dense=X)
+        To = osk.Tensor.from_dense(X)
+    else:
+        idx = np.stack([rs.integers(0, d, nnz) for d in dims], 1).astype(np.int32)
+        idx[nnz // 2:nnz // 2 + min(100, nnz // 4)] = idx[:min(100, nnz // 4)]  # duplicates
+        val = rs.standard_normal(nnz)
+        T = _gpu_tensor(tsk, dims, idx, val)
+        To = osk.Tensor(dims, idx, val)
+    h, s = tsk.hash_tables(dims, n, m, 5, DEV)
+    Y = tsk.sketch_rhs_ts(T, n, m, h, s).cpu().numpy()
+    Yo = osk.ts_rhs(To, m, _tables_np(h, s), n)
+    assert np.array_equal(Y, Yo)
+
+
+def test_sketch_rhs_fp32_bound_and_determinism(tsk):
+    dims, nnz, m, n = (2000, 2000, 2000), 200_000, 1600, 2
+    w = workloads.sparse_tucker(dims, nnz, (10, 10, 10), seed=2)
+    idx, val = w
+    T = _gpu_tensor(tsk, dims, idx, val)
+    h, s = tsk.hash_tables(dims, n, m, 0, DEV)
+    Y1 = tsk.sketch_rhs_ts(T, n, m, h, s)
+    Y2 = tsk.sketch_rhs_ts(T, n, m, h, s)
+    assert torch.equal(Y1, Y2)
+    To = osk.Tensor(dims, idx, val.astype(np.float64))
+    tabs = _tables_np(h, s)
+    Yo = osk.ts_rhs(To, m, tabs, n)
+    H, S = osk.ts_hash_sign(tabs, To.idx, m)
+    key = H * dims[n] + To.idx[:, n]
+    absum = np.bincount(key, weights=np.abs(To.val), minlength=m * dims[n]).reshape(m, -1)
+    cnt = np.bincount(key, minlength=m * dims[n]).reshape(m, -1)
+    bound = (cnt + 2) * 2.0 ** -24 * absum
+    assert np.all(np.abs(Y1.cpu().numpy().astype(np.float64) - Yo) <= bound + 1e-30)
+
+
+def test_sketch_rhs_empty_tensor(tsk):
+    dims = (10, 20, 30)
+    T = tsk.Tensor.coo([torch.zeros(0, dtype=torch.int32, device=DEV)] * 3,
+                       torch.zeros(0, dtype=torch.float32, device=DEV), dims)
+    h, s = tsk.hash_tables(dims, 1, 50, 0, DEV)
+    Y = tsk.sketch_rhs_ts(T, 1, 50, h, s)
+    assert Y.shape == (50, 20) and torch.count_nonzero(Y) == 0
+
+
+# ------------------------------------------------------------- a3, a4 ----
+@pytest.mark.parametrize("dims,ranks,m,n", [((40, 40, 40), (5, 5, 5), 200, 0),
+                                            ((2000, 300, 200), (10, 10, 10), 1600, 1),
+                                            ((500, 400, 300), (16, 16, 16), 2048, 2),
+                                            ((30, 20, 10, 12), (3, 4, 2, 5), 77, 3),
+                                            ((9, 8, 7), (2, 3, 3), 7, 0),
+                                            ((9, 8, 7), (2, 1, 1), 1, 0)])
+def test_sketch_lhs_matches_convolution(tsk, dims, ranks, m, n):
+    rs = np.random.default_rng(m)
+    facs = [np.linalg.qr(rs.standard_normal((d, r)))[0] for d, r in zip(dims, ranks)]
+    fg = [torch.from_numpy(F).to(DEV) for F in facs]
+    h, s = tsk.hash_tables(dims, n, m, 1, DEV)
+    Zo = osk.ts_lhs(facs, _tables_np(h, s), m, n)
+    scale = np.abs(Zo).max() + 1e-300
+    Z = tsk.sketch_lhs_ts(dims, ranks, n, m, h, s, fg, "f64").cpu().numpy()
+    assert np.abs(Z - Zo).max() <= 1e-13 * scale * np.log2(m + 1)
+    Z32 = tsk.sketch_lhs_ts(dims, ranks, n, m, h, s, fg, "f32").cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(Z32 - Zo) <= 2.0 ** -24 * np.abs(Zo) + 1e-13 * scale * np.log2(m + 1))
+    Zb = tsk.sketch_lhs_ts(dims, ranks, n, m, h, s, fg, "bf16").float().cpu().numpy()
+    assert np.all(np.abs(Zb - Zo) <= 2.0 ** -8 * np.abs(Zo) + 1e-7 * scale)
+
+
+# ---------------------------------------------------------------- a6, a7 ----
+@pytest.mark.parametrize("m,r,s,R", [(200, 25, 40, 5), (1600, 100, 2000, 10), (400, 30, 20, 4),
+                                     (333, 64, 65, 7), (4000, 100, 200, 10), (90, 90, 1, 1)])
+def test_rc_solve_fp64(tsk, m, r, s, R):
+    rs = np.random.default_rng(r * s)
+    Z = rs.standard_normal((m, r)) / np.sqrt(m)
+    Y = Z @ rs.standard_normal((r, R)) @ rs.standard_normal((R, s)) + 0.1 * rs.standard_normal((m, s))
+    A, W = tsk.rc_solve(torch.from_numpy(Z).to(DEV), torch.from_numpy(Y).to(DEV), R)
+    Ao, Wo, Xo = osv.rc_solve(Z, Y, R)
+    A, W = A.cpu().numpy(), W.cpu().numpy()
+    np.testing.assert_allclose(A, Ao, atol=1e-10 * max(1, np.abs(Ao).max()))
+    np.testing.assert_allclose(W, Wo, atol=1e-10 * max(1, np.abs(Wo).max()))
+    np.testing.assert_allclose(A.T @ A, np.eye(R), atol=1e-13)
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("bf16", 3e-2)])
+def test_rc_solve_low_precision(tsk, prec, tol):
+    m, r, s, R = 1600, 100, 300, 10
+    rs = np.random.default_rng(3)
+    Z = rs.standard_normal((m, r)) / np.sqrt(m)
+    Y = Z @ (10 * rs.standard_normal((r, R))) @ rs.standard_normal((R, s)) + 0.1 * rs.standard_normal((m, s))
+    dt = {"f32": torch.float32, "bf16": torch.bfloat16}[prec]
+    Zg, Yg = torch.from_numpy(Z).to(DEV).to(dt), torch.from_numpy(Y).to(DEV).to(dt)
+    A, W = tsk.rc_solve(Zg, Yg, R, prec)
+    # oracle on the rounded operands: the only difference left is the accumulation
+    Ao, Wo, _ = osv.rc_solve(Zg.double().cpu().numpy(), Yg.double().cpu().numpy(), R)
+    A = A.cpu().numpy()
+    assert np.abs(A @ A.T - Ao @ Ao.T).max() < tol
+
+
+# ---------------------------------------------------------------- a9 ----
+def test_rrf_init_matches_oracle(tsk):
+    w = workloads.c1()
+    T = _gpu_tensor(tsk, w.dims, dense=w.dense)
+    To = osk.Tensor.from_dense(w.dense)
+    for n in (1, 2):
+        A = tsk.rrf_init(T, n, 5, 15, 40, 0).cpu().numpy()
+        Ao = otk.init_rrf(To, n, 5, 15, 40, 0)
+        np.testing.assert_allclose(A, Ao, atol=1e-10)
+
+
+def test_rrf_init_sparse_fp32(tsk):
+    dims = (300, 250, 200)
+    idx, val = workloads.sparse_tucker(dims, 40_000, (6, 6, 6), seed=4)
+    T = _gpu_tensor(tsk, dims, idx, val)
+    To = osk.Tensor(dims, idx, val.astype(np.float64))
+    A = tsk.rrf_init(T, 1, 6, 30, 66, 9).cpu().numpy()
+    Ao = otk.init_rrf(To, 1, 6, 30, 66, 9)
+    assert np.abs(A @ A.T - Ao @ Ao.T).max() < 1e-4
+
+
+# ---------------------------------------------------------------- a5 ----
+@pytest.mark.parametrize("dims,ranks,m,n", [((200, 200, 200, 200), (10, 10, 10, 10), 4000, 1),
+                                            ((500, 500, 500), (30, 30, 30), 14400, 0),
+                                            ((40, 40, 40), (5, 5, 5), 200, 2)])
+def test_leverage_sample_bit_exact(tsk, dims, ranks, m, n):
+    rs = np.random.default_rng(sum(dims))
+    facs = [np.linalg.qr(rs.standard_normal((d, r)))[0] for d, r in zip(dims, ranks)]
+    fg = [torch.from_numpy(F).to(DEV) for F in facs]
+    idx, w = tsk.leverage_sample(dims, ranks, n, m, 3, 2, fg)
+    io, wo = osk.leverage_sample(facs, m, 3, 2, n)
+    assert np.array_equal(idx.cpu().numpy().astype(np.int64), io)
+    np.testing.assert_allclose(w.cpu().numpy(), wo, rtol=1e-15)
+
+
+def test_leverage_rows_match(tsk):
+    dims, ranks, m, n = (30, 25, 20, 15), (3, 4, 2, 3), 500, 2
+    rs = np.random.default_rng(1)
+    X = rs.standard_normal(dims)
+    facs = [np.linalg.qr(rs.standard_normal((d, r)))[0] for d, r in zip(dims, ranks)]
+    fg = [torch.from_numpy(F).to(DEV) for F in facs]
+    idx, w = tsk.leverage_sample(dims, ranks, n, m, 1, 0, fg)
+    T = _gpu_tensor(tsk, dims, dense=X)
+    Z, Y = tsk.sketch_lev(T, ranks, n, m, idx, w, fg, "f64")
+    io, wo = idx.cpu().numpy().astype(np.int64), w.cpu().numpy()
+    np.testing.assert_array_equal(Z.cpu().numpy(), osk.leverage_lhs(facs, io, wo, n))
+    np.testing.assert_allclose(Y.cpu().numpy(), osk.leverage_rhs_dense(X, io, wo, n), rtol=1e-15)
+
+
+# ---------------------------------------------------------------- a11 ----
+@pytest.mark.parametrize("sparse", [False, True])
+def test_fit_matches_oracle(tsk, sparse):
+    dims, ranks = (30, 25, 20), (4, 3, 5)
+    rs = np.random.default_rng(2)
+    facs = [np.linalg.qr(rs.standard_normal((d, r)))[0] for d, r in zip(dims, ranks)]
+    core = rs.standard_normal(ranks)
+    X = otk.reconstruct(core, facs) + 0.1 * rs.standard_normal(dims)
+    if sparse:
+        To = osk.Tensor.from_dense(X)
+        To = osk.Tensor(dims, To.idx[::3], To.val[::3])
+        T = _gpu_tensor(tsk, dims, To.idx.astype(np.int32), To.val)
+    else:
+        To = osk.Tensor.from_dense(X)
+        T = _gpu_tensor(tsk, dims, dense=X)
+    f = tsk.fit(T, torch.from_numpy(core).to(DEV), [torch.from_numpy(F).to(DEV) for F in facs])
+    assert abs(f - otk.relative_residual(To, core, facs)) < 1e-12
+
+
+# ---------------------------------------------------------------- a12 ----
+def test_adjoint_matches_oracle_and_fd(tsk):
+    dims, ranks, m, n = (60, 50, 40), (3, 4, 2), 64, 1
+    rs = np.random.default_rng(5)
+    facs = [rs.standard_normal((d, r)) for d, r in zip(dims, ranks)]
+    core = rs.standard_normal(ranks)
+    X = rs.standard_normal(dims)
+    h, s = tsk.hash_tables(dims, n, m, 2, DEV)
+    tabs = _tables_np(h, s)
+    Yo = osk.ts_rhs(osk.Tensor.from_dense(X), m, tabs, n)
+    fg = [torch.from_numpy(F).to(DEV) for F in facs]
+    cg = torch.from_numpy(core).to(DEV)
+    Yg = torch.from_numpy(Yo).to(DEV)
+    L = tsk.sketched_residual(dims, ranks, n, m, h, s, fg, cg, Yg).item()
+    Lo, go, gCo = oadj.residual_and_grads(facs, core, tabs, Yo, m, n)
+    assert abs(L - Lo) <= 1e-11 * Lo
+    grads, gC = tsk.sketched_residual_grads(dims, ranks, n, m, h, s, fg, cg, Yg)
+    for k in range(3):
+        np.testing.assert_allclose(grads[k].cpu().numpy(), go[k], atol=1e-9 * np.abs(go[k]).max())
+    np.testing.assert_allclose(gC.cpu().numpy(), gCo, atol=1e-9 * np.abs(gCo).max())
+    # autograd.Function + central differences on the GPU forward (L quadratic per entry)
+    fa = [F.clone().requires_grad_(True) for F in fg]
+    ca = cg.clone().requires_grad_(True)
+    out = tsk.SketchedResidual.apply((dims, ranks, n, m, h, s, Yg), ca, *fa)
+    out.backward()
+    hstep = 1e-3
+    for k in range(3):
+        for _ in range(4):
+            i, c = rs.integers(dims[k]), rs.integers(ranks[k])
+            fp = [F.clone() for F in fg]; fm = [F.clone() for F in fg]
+            fp[k][i, c] += hstep; fm[k][i, c] -= hstep
+            fd = (tsk.sketched_residual(dims, ranks, n, m, h, s, fp, cg, Yg).item() -
+                  tsk.sketched_residual(dims, ranks, n, m, h, s, fm, cg, Yg).item()) / (2 * hstep)
+            g = fa[k].grad[i, c].item()
+            assert abs(fd - g) <= 1e-7 * max(1.0, abs(fd))
