@@ -622,7 +622,7 @@ tsk_status tsk_cp_workspace_size(const tsk_tensor* T, int32_t cp_rank, const int
   TuckerArgs a{};
   TSK_TRY(make_args(T, tucker_ranks, opt, a));
   Ws probe;
-  TSK_TRY(run_cp(a, cp_rank, 0, nullptr, nullptr, probe));
+  TSK_TRY(run_cp(a, cp_rank, 1, nullptr, nullptr, probe));
   *bytes = probe.off + 256;
   return TSK_OK;
 }

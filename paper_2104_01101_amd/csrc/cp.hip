@@ -235,10 +235,10 @@ tsk_status cp_run(const TensorView& T, const int64_t* R, int Rc, int sweeps,
     }
   // CP factors of the input: B^(n) A_n
   for (int k = 0; k < N; ++k)
-    if (run)
+    if (run && cp_factors)
       TSK_TRY(gemm_small(T.dims[k], Rc, R[k], 1.0, tb.factors[k], R[k], 1, A[k], Rc, 1, 0.0,
                          cp_factors[k], Rc, st));
-  if (fit_dev) {
+  if (fit_dev && cp_factors) {
     CpFitArgs a{};
     a.N = N;
     a.layout = T.layout;

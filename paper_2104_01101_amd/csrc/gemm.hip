@@ -28,22 +28,27 @@ constexpr int kBM = 64, kBN = 64, kThreads = 256;
 
 template <class E>
 struct Cfg;
+// Output layout of a 16x16 MFMA block: lane l holds column l % 16; its four
+// accumulators are rows 4*(l/16) + v (FP32 accumulation) or l/16 + 4*v (FP64).
 template <>
 struct Cfg<double> {
   static constexpr int BK = 16;   // 4 MFMA k-steps of 4
   static constexpr int LD = 18;   // row stride in elements (144 B)
+  static constexpr bool kRowsInterleaved = true;
   typedef doublex4 Acc;
 };
 template <>
 struct Cfg<float> {
   static constexpr int BK = 32;   // 8 MFMA k-steps of 4
   static constexpr int LD = 36;
+  static constexpr bool kRowsInterleaved = false;
   typedef floatx4 Acc;
 };
 template <>
 struct Cfg<uint16_t> {
   static constexpr int BK = 64;   // 2 MFMA k-steps of 32
   static constexpr int LD = 72;
+  static constexpr bool kRowsInterleaved = false;
   typedef floatx4 Acc;
 };
 
@@ -139,7 +144,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn(int64_t M, int64_t N, int6
     for (int sn = 0; sn < 2; ++sn)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int64_t i = i0 + wm * 32 + sm * 16 + 4 * g + v;
+        int64_t i = i0 + wm * 32 + sm * 16 + (Cfg<E>::kRowsInterleaved ? g + 4 * v : 4 * g + v);
         int64_t j = j0 + wn * 32 + sn * 16 + li;
         if (i < M && j < N) Cz[i * ldc + j] = double(acc[sm][sn][v]);
       }
