@@ -115,6 +115,17 @@ const char* tsk_last_error(void);
 uint64_t tsk_stream_key(uint64_t seed, int32_t purpose, int64_t a, int64_t b, int64_t c);
 uint64_t tsk_draw(uint64_t key, uint64_t counter);
 
+/* Launch timing for measurement.  tsk_profile_enable(name) makes the library
+ * record HIP events on the launching stream around every launch group called
+ * `name` ("sketch_pass", "gram", "ts_lhs", "solve_la", "eig", "fit", "rrf",
+ * "leverage", "cp_core", "adjoint"; "*" = all; NULL or "" = off, the default)
+ * and clears earlier records.  tsk_profile_read(name) waits for the recorded
+ * events and returns the summed milliseconds and the number of groups (name
+ * NULL = all).  Not thread-safe with respect to concurrent library calls that
+ * record events. */
+tsk_status tsk_profile_enable(const char* name);
+tsk_status tsk_profile_read(const char* name, double* total_ms, int64_t* launches);
+
 /* ---------------------------------------------------------------------- */
 /* Drivers                                                                 */
 /* ---------------------------------------------------------------------- */

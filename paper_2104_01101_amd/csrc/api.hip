@@ -142,6 +142,7 @@ tsk_status rrf_finish(const TensorView& T, int n, int64_t R, uint64_t seed, RrfB
                       double* A, int* info, Ws& ws, hipStream_t st) {
   const int64_t s = T.dims[n];
   const bool run = !ws.measuring();
+  ProfScope prof(run ? "rrf" : "", st);
   if (run) {
     TSK_TRY(convert_to_f64(b.Wt, T.dtype == TSK_F64 ? 8 : 4, b.k2 * s, b.Wt64, st));
     TSK_TRY(launch_gauss(stream_key(seed, kRRFGauss, n), b.k2 * b.k1, 1.0 / std::sqrt(double(b.k1)),

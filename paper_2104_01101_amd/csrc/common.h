@@ -168,4 +168,18 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 hipStream_t as_stream(void* s);
 
+// HIP-event timing of a named launch group (see prof.hip); a no-op unless
+// enabled through tsk_profile_enable.
+class ProfScope {
+ public:
+  ProfScope(const char* name, hipStream_t st);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  hipStream_t st_;
+  int idx_;
+};
+
 }  // namespace tsk

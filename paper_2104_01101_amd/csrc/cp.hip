@@ -197,6 +197,7 @@ tsk_status cp_run(const TensorView& T, const int64_t* R, int Rc, int sweeps,
     peak = std::max(peak, ws.off);
     ws.off = mark;
   };
+  ProfScope prof(run ? "cp_core" : "", st);
   // HOSVD of the core
   for (int k = 0; k < N; ++k) {
     if (run) {

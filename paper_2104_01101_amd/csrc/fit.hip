@@ -1,5 +1,7 @@
 // Relative residual ||T - T~||_F / ||T||_F of a Tucker model (1 - fitness,
-// Sec. 7), in FP64 as ||T||^2 - 2 <T, T~> + ||T~||^2:
+// Sec. 7), in FP64.  Dense tensors: sum of (T - T~)^2 over all entries.  COO
+// tensors (T~ is dense, T is not): ||T||^2 - 2 <T, T~> + ||T~||^2, whose
+// cancellation limits the relative residual to ~1e-8 near an exact fit:
 //   <T, T~>  per stored entry, T~(i) = sum_rho C(rho) prod_k A^(k)(i_k, rho_k)
 //   ||T~||^2 = <C x_1 G_1 ... x_N G_N, C>, G_k = A^(k)T A^(k)
 // Reductions are two-level with a fixed order (deterministic).
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(kT) void k_norm2(FitArgs a, int64_t nnz, int64_t pe
 
 __global__ __launch_bounds__(kT) void k_inner(FitArgs a, int64_t nnz, int64_t per_block,
                                               const double* core, int64_t csize, int core_lds,
-                                              double* partial) {
+                                              double* partial, double* partial_direct) {
   extern __shared__ double cs[];
   __shared__ double red[kT / 64];
   const double* C = core;
@@ -64,7 +66,7 @@ __global__ __launch_bounds__(kT) void k_inner(FitArgs a, int64_t nnz, int64_t pe
   const int64_t Rl = a.R[N - 1];
   const int64_t outer = csize / Rl;
   int64_t lo = int64_t(blockIdx.x) * per_block, hi = lo + per_block < nnz ? lo + per_block : nnz;
-  double s = 0.0;
+  double s = 0.0, s2 = 0.0;
   for (int64_t e = lo + threadIdx.x; e < hi; e += kT) {
     int64_t ii[TSK_MAX_ORDER];
     if (a.layout == TSK_COO) {
@@ -91,9 +93,75 @@ __global__ __launch_bounds__(kT) void k_inner(FitArgs a, int64_t nnz, int64_t pe
     double v = a.dtype == TSK_F64 ? static_cast<const double*>(a.vals)[e]
                                   : double(static_cast<const float*>(a.vals)[e]);
     s += v * tv;
+    s2 += (v - tv) * (v - tv);
   }
   s = block_reduce(s, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  __syncthreads();
+  s2 = block_reduce(s2, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s, partial_direct[blockIdx.x] = s2;
+}
+
+// Order-3 and order-4 forms of k_inner: each lane owns one entry, keeps the
+// factor rows of its coordinates in registers (RM >= every rank) and reads the
+// core from LDS (all lanes read the same core element: broadcast).
+template <int RM>
+__global__ __launch_bounds__(kT) void k_inner3(FitArgs a, int64_t nnz, int64_t per_block,
+                                               const double* core, int core_lds,
+                                               double* partial, double* partial_direct) {
+  extern __shared__ double cs_lds[];
+  __shared__ double red[kT / 64];
+  const int R0 = int(a.R[0]), R1 = int(a.R[1]), R2 = int(a.R[2]);
+  const double* cs = core;
+  if (core_lds) {
+    for (int t = threadIdx.x; t < R0 * R1 * R2; t += kT) cs_lds[t] = core[t];
+    __syncthreads();
+    cs = cs_lds;
+  }
+  int64_t lo = int64_t(blockIdx.x) * per_block, hi = lo + per_block < nnz ? lo + per_block : nnz;
+  double acc = 0.0, acc2 = 0.0;
+  for (int64_t e = lo + threadIdx.x; e < hi; e += kT) {
+    int64_t i0, i1, i2;
+    if (a.layout == TSK_COO) {
+      i0 = a.idx[0][e], i1 = a.idx[1][e], i2 = a.idx[2][e];
+    } else {
+      i2 = e % a.dims[2];
+      int64_t r = e / a.dims[2];
+      i1 = r % a.dims[1];
+      i0 = r / a.dims[1];
+    }
+    double u2[RM], u1[RM];
+#pragma unroll
+    for (int c = 0; c < RM; ++c) {
+      u2[c] = c < R2 ? a.A[2][i2 * R2 + c] : 0.0;
+      u1[c] = c < R1 ? a.A[1][i1 * R1 + c] : 0.0;
+    }
+    const double* a0 = a.A[0] + i0 * R0;
+    double tv = 0.0;
+    for (int x = 0; x < R0; ++x) {
+      double wx = 0.0;
+      const double* cx = cs + x * R1 * R2;
+#pragma unroll
+      for (int y = 0; y < RM; ++y) {
+        if (y >= R1) break;
+        double s = 0.0;
+#pragma unroll
+        for (int z = 0; z < RM; ++z) {
+          if (z >= R2) break;
+          s += cx[y * R2 + z] * u2[z];
+        }
+        wx += s * u1[y];
+      }
+      tv += wx * a0[x];
+    }
+    double v = a.dtype == TSK_F64 ? static_cast<const double*>(a.vals)[e]
+                                  : double(static_cast<const float*>(a.vals)[e]);
+    acc += v * tv;
+    acc2 += (v - tv) * (v - tv);
+  }
+  acc = block_reduce(acc, red);
+  __syncthreads();
+  acc2 = block_reduce(acc2, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc, partial_direct[blockIdx.x] = acc2;
 }
 
 // ||T~||^2 = <C x_k G_k, C>, single block; buf0/buf1 scratch of csize
@@ -127,7 +195,8 @@ __global__ __launch_bounds__(kT) void k_model_norm2(FitArgs a, const double* cor
 }
 
 __global__ void k_finish(const double* pn, int nbn, const double* pi, int nbi,
-                         const double* model2, double* nT2_out, double* res_out) {
+                         const double* pd, int dense, const double* model2, double* nT2_out,
+                         double* res_out) {
   if (threadIdx.x != 0) return;
   double nT2 = 0.0, inner = 0.0;
   if (pn) {
@@ -138,6 +207,10 @@ __global__ void k_finish(const double* pn, int nbn, const double* pi, int nbi,
   }
   for (int b = 0; b < nbi; ++b) inner += pi[b];
   double r2 = nT2 - 2.0 * inner + *model2;
+  if (dense) {  // every entry stored: sum of squared differences, no cancellation
+    r2 = 0.0;
+    for (int b = 0; b < nbi; ++b) r2 += pd[b];
+  }
   *res_out = sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(nT2);
 }
 
@@ -146,11 +219,12 @@ __global__ void k_finish(const double* pn, int nbn, const double* pi, int nbi,
 tsk_status fit_plan(const TensorView& T, const int64_t* R, FitScratch& fs, Ws& ws) {
   int64_t csize = 1, gsz = 0;
   for (int k = 0; k < T.order; ++k) csize *= R[k], gsz += R[k] * R[k];
-  fs.nblocks = int(ceil_div(T.nnz, 8192));
-  if (fs.nblocks > 1024) fs.nblocks = 1024;
+  fs.nblocks = int(ceil_div(T.nnz, 1024));
+  if (fs.nblocks > 2048) fs.nblocks = 2048;
   if (fs.nblocks < 1) fs.nblocks = 1;
   fs.partial_norm = ws.take<double>(fs.nblocks);
   fs.partial_inner = ws.take<double>(fs.nblocks);
+  fs.partial_direct = ws.take<double>(fs.nblocks);
   fs.grams = ws.take<double>(gsz);
   fs.buf0 = ws.take<double>(csize);
   fs.buf1 = ws.take<double>(csize);
@@ -182,21 +256,39 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
     goff += R[k] * R[k];
   }
   if (ws.measuring()) return TSK_OK;
+  ProfScope prof("fit", st);
   int64_t per = ceil_div(T.nnz, fs.nblocks);
   if (with_norm) {
     hipLaunchKernelGGL(k_norm2, dim3(fs.nblocks), dim3(kT), 0, st, a, T.nnz, per,
                        fs.partial_norm);
     TSK_LAUNCHED();
   }
-  int core_lds = csize * 8 <= 49152 ? 1 : 0;
-  hipLaunchKernelGGL(k_inner, dim3(fs.nblocks), dim3(kT), core_lds ? size_t(csize * 8) : 0, st, a,
-                     T.nnz, per, core, csize, core_lds, fs.partial_inner);
+  int64_t rmax = 0;
+  for (int k = 0; k < T.order; ++k) rmax = std::max<int64_t>(rmax, R[k]);
+  if (T.order == 3 && rmax <= 32) {
+    const int core_lds = csize * 8 <= 150000 ? 1 : 0;
+    const size_t lds = core_lds ? size_t(csize) * 8 : 0;
+    if (rmax <= 8)
+      hipLaunchKernelGGL(k_inner3<8>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
+                         core_lds, fs.partial_inner, fs.partial_direct);
+    else if (rmax <= 16)
+      hipLaunchKernelGGL(k_inner3<16>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
+                         core_lds, fs.partial_inner, fs.partial_direct);
+    else
+      hipLaunchKernelGGL(k_inner3<32>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
+                         core_lds, fs.partial_inner, fs.partial_direct);
+  } else {
+    int core_lds = csize * 8 <= 49152 ? 1 : 0;
+    hipLaunchKernelGGL(k_inner, dim3(fs.nblocks), dim3(kT), core_lds ? size_t(csize * 8) : 0, st,
+                       a, T.nnz, per, core, csize, core_lds, fs.partial_inner, fs.partial_direct);
+  }
   TSK_LAUNCHED();
   hipLaunchKernelGGL(k_model_norm2, dim3(1), dim3(kT), 0, st, a, core, csize, fs.grams, fs.buf0,
                      fs.buf1, fs.model2);
   TSK_LAUNCHED();
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, with_norm ? fs.partial_norm : nullptr,
-                     fs.nblocks, fs.partial_inner, fs.nblocks, fs.model2, fs.nT2, res);
+                     fs.nblocks, fs.partial_inner, fs.nblocks, fs.partial_direct,
+                     T.layout == TSK_DENSE ? 1 : 0, fs.model2, fs.nT2, res);
   TSK_LAUNCHED();
   return TSK_OK;
 }

@@ -1,6 +1,7 @@
 // Gram products of the sketched operands on the matrix cores:
 //
 //   C (M x N, FP64) = A^T B,   A = [A1 | A2] (K x M), B (K x N), row-major,
+//   (and, FP64 only, C = A B with A given M x K row-major),
 //
 // i.e. both operands are stored with the contraction index (the sketch row)
 // slowest -- the layout in which Z (m x r) and Y (m x s) are produced.  Used
@@ -82,7 +83,7 @@ __device__ inline void mfma_step(const uint16_t* a, const uint16_t* b, floatx4& 
   }
 }
 
-template <class E>
+template <class E, bool A_MK>
 __global__ __launch_bounds__(kThreads) void k_gemm_tn(int64_t M, int64_t N, int64_t K,
                                                       const E* A1, int64_t lda1, int64_t M1,
                                                       const E* A2, int64_t lda2, const E* B,
@@ -107,17 +108,26 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn(int64_t M, int64_t N, int6
     for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-    // stage A (K x M slice) and B (K x N slice) transposed: X[row][k]
+    // stage A and B (K x N slice) as X[row][k]; A is K x M (transposed on
+    // the way in) or, for A_MK, M x K (copied)
     for (int e = tid; e < BK * kBM; e += kThreads) {
       int kk = e / kBM, ii = e % kBM;
-      int64_t k = k0 + kk, i = i0 + ii, j = j0 + ii;
-      E av = zero_e<E>(), bv = zero_e<E>();
-      if (k < kend) {
-        if (i < M) av = load_a(A1, lda1, M1, A2, lda2, k, i);
-        if (j < N) bv = B[k * ldb + j];
-      }
-      As[ii * LD + kk] = av;
+      int64_t k = k0 + kk, j = j0 + ii;
+      E bv = zero_e<E>();
+      if (k < kend && j < N) bv = B[k * ldb + j];
       Bs[ii * LD + kk] = bv;
+      if (!A_MK) {
+        int64_t i = i0 + ii;
+        E av = zero_e<E>();
+        if (k < kend && i < M) av = load_a(A1, lda1, M1, A2, lda2, k, i);
+        As[ii * LD + kk] = av;
+      } else {
+        int ii2 = e / BK, kk2 = e % BK;
+        int64_t i = i0 + ii2, k2 = k0 + kk2;
+        E av = zero_e<E>();
+        if (k2 < kend && i < M) av = A1[i * lda1 + k2];
+        As[ii2 * LD + kk2] = av;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -183,7 +193,7 @@ __global__ void k_to_f64(const void* src, int bytes, int64_t n, double* dst) {
     dst[t] = double(bf16_bits_to_f32(static_cast<const uint16_t*>(src)[t]));
 }
 
-template <class E>
+template <class E, bool A_MK>
 tsk_status gemm_tn_t(int64_t M, int64_t N, int64_t K, const void* A1, int64_t lda1, int64_t M1,
                      const void* A2, int64_t lda2, const void* B, int64_t ldb, double* C,
                      int64_t ldc, Ws& ws, hipStream_t st) {
@@ -205,12 +215,12 @@ tsk_status gemm_tn_t(int64_t M, int64_t N, int64_t K, const void* A1, int64_t ld
   }
   dim3 grid(tm, tn, splits);
   if (splits == 1) {
-    hipLaunchKernelGGL(k_gemm_tn<E>, grid, dim3(kThreads), 0, st, M, N, K,
+    hipLaunchKernelGGL((k_gemm_tn<E, A_MK>), grid, dim3(kThreads), 0, st, M, N, K,
                        static_cast<const E*>(A1), lda1, M1, static_cast<const E*>(A2), lda2,
                        static_cast<const E*>(B), ldb, kchunk, C, ldc, int64_t(0));
     TSK_LAUNCHED();
   } else {
-    hipLaunchKernelGGL(k_gemm_tn<E>, grid, dim3(kThreads), 0, st, M, N, K,
+    hipLaunchKernelGGL((k_gemm_tn<E, A_MK>), grid, dim3(kThreads), 0, st, M, N, K,
                        static_cast<const E*>(A1), lda1, M1, static_cast<const E*>(A2), lda2,
                        static_cast<const E*>(B), ldb, kchunk, part, N, M * N);
     TSK_LAUNCHED();
@@ -233,12 +243,18 @@ tsk_status gemm_tn(int prec, int64_t M, int64_t N, int64_t K, const void* A1, in
   }
   switch (prec) {
     case TSK_PREC_F64:
-      return gemm_tn_t<double>(M, N, K, A1, lda1, M1, A2, lda2, B, ldb, C, ldc, ws, st);
+      return gemm_tn_t<double, false>(M, N, K, A1, lda1, M1, A2, lda2, B, ldb, C, ldc, ws, st);
     case TSK_PREC_F32:
-      return gemm_tn_t<float>(M, N, K, A1, lda1, M1, A2, lda2, B, ldb, C, ldc, ws, st);
+      return gemm_tn_t<float, false>(M, N, K, A1, lda1, M1, A2, lda2, B, ldb, C, ldc, ws, st);
     default:
-      return gemm_tn_t<uint16_t>(M, N, K, A1, lda1, M1, A2, lda2, B, ldb, C, ldc, ws, st);
+      return gemm_tn_t<uint16_t, false>(M, N, K, A1, lda1, M1, A2, lda2, B, ldb, C, ldc, ws, st);
   }
+}
+
+tsk_status gemm_nn_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                       const double* B, int64_t ldb, double* C, int64_t ldc, Ws& ws,
+                       hipStream_t st) {
+  return gemm_tn_t<double, true>(M, N, K, A, lda, M, A, lda, B, ldb, C, ldc, ws, st);
 }
 
 tsk_status gemm_small(int64_t M, int64_t N, int64_t K, double alpha, const double* A,

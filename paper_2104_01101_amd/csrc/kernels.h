@@ -74,6 +74,10 @@ tsk_status ts_conv_adjoint(const LhsMode* modes, int nmodes, int64_t m, const do
 tsk_status gemm_tn(int prec, int64_t M, int64_t N, int64_t K, const void* A1, int64_t lda1,
                    int64_t M1, const void* A2, int64_t lda2, const void* B, int64_t ldb,
                    double* C, int64_t ldc, Ws& ws, hipStream_t st);
+// C (M x N, FP64) = A B, A (M x K) and B (K x N) row-major FP64 (matrix cores)
+tsk_status gemm_nn_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                       const double* B, int64_t ldb, double* C, int64_t ldc, Ws& ws,
+                       hipStream_t st);
 // C (M x N) = alpha * op(A) op(B) + beta * C, FP64, small sizes; op given by
 // strides: A(i,k) = A[i*sai + k*sak], B(k,j) = B[k*sbk + j*sbj], C(i,j) = C[i*ldc + j]
 tsk_status gemm_small(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
@@ -94,6 +98,11 @@ tsk_status chol_solve_rows(const double* L, int64_t n, int64_t ldl, double* X, i
 // M is overwritten.  lam: R doubles, V: q x R row-major.
 tsk_status sym_eig_top(double* M, int64_t q, int64_t R, double* lam, double* V, Ws& ws,
                        hipStream_t st);
+// In-place inverse of the SPD n x n matrix G (row-major, lda) by Gauss-Jordan
+// elimination without pivoting (single workgroup, LDS); *info = j+1 at the first
+// non-positive pivot.  Returns EUNSUPPORTED if G does not fit in LDS.
+tsk_status spd_inverse(double* G, int64_t n, int64_t lda, int* info, hipStream_t st);
+bool spd_inverse_fits(int64_t n);
 // Make the entry of largest magnitude of every column of A (rows x R) positive.
 tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, hipStream_t st);
 // A (rows x R): A <- A * diag(scale) with scale[c] = 1/sqrt(lam[c])

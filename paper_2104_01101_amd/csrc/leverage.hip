@@ -140,6 +140,7 @@ tsk_status leverage_sample(int N, const int64_t* dims, const int64_t* ranks, int
     if (dims[k] > smax) smax = dims[k];
   }
   if (ws.measuring()) return TSK_OK;
+  ProfScope prof("leverage", st);
   hipLaunchKernelGGL(k_scores, dim3(ceil_div(smax, 256), lm.nm), dim3(256), 0, st, lm);
   TSK_LAUNCHED();
   hipLaunchKernelGGL(k_cdf, dim3(lm.nm), dim3(64), 0, st, lm);
@@ -166,6 +167,7 @@ tsk_status leverage_rows(const TensorView& T, const int64_t* ranks, int n, int64
   for (int k = 0; k < T.order; ++k) lr.dims[k] = T.dims[k];
   lr.dtype = T.dtype;
   lr.vals = T.values;
+  ProfScope prof("leverage", st);
   if (Z) {
     hipLaunchKernelGGL(k_lev_Z, dim3(ceil_div(m * lr.r, 256)), dim3(256), 0, st, lr, m, idx, w,
                        prec, Z);

@@ -43,109 +43,217 @@ __device__ double wave_sum(double v) {
 }
 
 // -------------------------------------------------------------- cholesky ----
-constexpr int kCholT = 512;
-__global__ __launch_bounds__(kCholT) void k_cholesky(double* G, int64_t n, int64_t lda,
-                                                     int* info, int use_lds) {
+constexpr int kCholT = 256;
+constexpr int kCholWaves = kCholT / 64;
+template <bool LDS>
+__global__ __launch_bounds__(kCholT) void k_cholesky(double* G, int n, int lda, int* info) {
   extern __shared__ double smem[];
-  __shared__ double diag;
-  double* a = G;
-  int64_t ld = lda;
-  if (use_lds) {
-    a = smem;
-    ld = n;
-    for (int64_t t = threadIdx.x; t < n * n; t += kCholT) smem[t] = G[(t / n) * lda + t % n];
+  double* a = LDS ? smem : G;
+  const int ld = LDS ? n : lda;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (LDS) {
+    for (int i = wave; i < n; i += kCholWaves)
+      for (int k = lane; k <= i; k += 64) smem[i * n + k] = G[i * lda + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *info = 0;
-  for (int64_t j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      double d = a[j * ld + j];
-      if (!(d > 0.0) && *info == 0) *info = int(j + 1);
-      d = sqrt(d);
-      a[j * ld + j] = d;
-      diag = d;
-    }
+  int bad = 0;
+  for (int j = 0; j < n; ++j) {
+    const double piv = a[j * ld + j];
+    if (!(piv > 0.0) && bad == 0) bad = j + 1;
+    const double dj = sqrt(piv), rj = 1.0 / dj;
+    // column j below the diagonal
+    for (int i = j + 1 + tid; i < n; i += kCholT) a[i * ld + j] *= rj;
     __syncthreads();
-    const double d = diag;
-    for (int64_t i = j + 1 + threadIdx.x; i < n; i += kCholT) a[i * ld + j] /= d;
-    __syncthreads();
-    const int64_t L = n - j - 1;
-    for (int64_t t = threadIdx.x; t < L * L; t += kCholT) {
-      int64_t i = j + 1 + t / L, k = j + 1 + t % L;
-      if (k <= i) a[i * ld + k] -= a[i * ld + j] * a[k * ld + j];
+    if (tid == 0) a[j * ld + j] = dj;
+    // trailing lower triangle: rows by wave, columns by lane
+    for (int i = j + 1 + wave; i < n; i += kCholWaves) {
+      const double lij = a[i * ld + j];
+      for (int k = j + 1 + lane; k <= i; k += 64) a[i * ld + k] -= lij * a[k * ld + j];
     }
     __syncthreads();
   }
-  if (use_lds)
-    for (int64_t t = threadIdx.x; t < n * n; t += kCholT) {
-      int64_t i = t / n, k = t % n;
-      G[i * lda + k] = k <= i ? smem[t] : 0.0;
-    }
-  else
-    for (int64_t t = threadIdx.x; t < n * n; t += kCholT) {
-      int64_t i = t / n, k = t % n;
-      if (k > i) G[i * lda + k] = 0.0;
-    }
+  if (tid == 0) *info = bad;
+  for (int i = wave; i < n; i += kCholWaves)
+    for (int k = lane; k < n; k += 64) G[i * lda + k] = k <= i ? a[i * ld + k] : 0.0;
 }
 
-// rows of X <- rows of X L^{-T} (forward) then X L^{-1} (backward): X G^{-1}
-constexpr int kSolveT = 256;
-__global__ __launch_bounds__(kSolveT) void k_chol_solve_rows(const double* L, int64_t n,
-                                                             int64_t ldl, double* X,
-                                                             int64_t rows, int64_t ldx,
-                                                             int64_t rb, int forward_only) {
-  extern __shared__ double xs[];  // rb x n
-  const int64_t r0 = int64_t(blockIdx.x) * rb;
-  const int64_t nr = rows - r0 < rb ? rows - r0 : rb;
-  for (int64_t t = threadIdx.x; t < nr * n; t += kSolveT) xs[t] = X[(r0 + t / n) * ldx + t % n];
+// ------------------------------------------------------ SPD inverse (GJ) ----
+// Gauss-Jordan on an SPD matrix needs no pivoting; the pivots are the
+// Cholesky pivots squared, so a non-positive one flags a non-SPD Gram.
+constexpr int kGjT = 512;
+__global__ __launch_bounds__(kGjT) void k_spd_inverse(double* G, int n, int lda, int* info) {
+  extern __shared__ double a[];  // n x n
+  constexpr int NW = kGjT / 64;
+  __shared__ double prow_inv;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = wave; i < n; i += NW)
+    for (int k = lane; k < n; k += 64) a[i * n + k] = G[i * lda + k];
   __syncthreads();
-  // forward: y L^T = x  ->  y_j = (x_j - sum_{i<j} L_ji y_i) / L_jj, column-oriented
-  for (int64_t j = 0; j < n; ++j) {
-    const double djj = L[j * ldl + j];
-    for (int64_t rr = threadIdx.x; rr < nr; rr += kSolveT) xs[rr * n + j] /= djj;
+  int bad = 0;
+  for (int j = 0; j < n; ++j) {
+    const double piv = a[j * n + j];
+    if (!(piv > 0.0) && bad == 0) bad = j + 1;
+    const double pinv = 1.0 / piv;
+    __syncthreads();  // everyone has read the pivot
+    for (int k = tid; k < n; k += kGjT) a[j * n + k] = k == j ? pinv : a[j * n + k] * pinv;
     __syncthreads();
-    const int64_t rem = n - j - 1;
-    for (int64_t t = threadIdx.x; t < nr * rem; t += kSolveT) {
-      int64_t rr = t / rem, i = j + 1 + t % rem;
-      xs[rr * n + i] -= L[i * ldl + j] * xs[rr * n + j];
+    for (int i = wave; i < n; i += NW) {
+      if (i == j) continue;
+      const double f = a[i * n + j];
+      for (int k = lane; k < n; k += 64) {
+        const double rk = a[j * n + k];
+        a[i * n + k] = k == j ? -f * pinv : a[i * n + k] - f * rk;
+      }
+    }
+    __syncthreads();
+  }
+  (void)prow_inv;
+  if (tid == 0) *info = bad;
+  for (int i = wave; i < n; i += NW)
+    for (int k = lane; k < n; k += 64) G[i * lda + k] = a[i * n + k];
+}
+
+// rows of X <- rows of X G^{-1} (X L^{-T} then L^{-1}); forward_only: X L^{-T}.
+// Thread per row with L in LDS (used when L and the row block fit).
+constexpr int kRowT = 64;
+__global__ __launch_bounds__(kRowT) void k_chol_solve_rows_lds(const double* Lg, int n, int ldl,
+                                                               double* X, int rows, int ldx,
+                                                               int forward_only) {
+  extern __shared__ double smem[];
+  double* L = smem;                 // n x n (lower)
+  double* xs = smem + n * n;        // kRowT rows, stride n + 1
+  const int stride = n + 1;
+  for (int t = threadIdx.x; t < n * n; t += kRowT) {
+    const int i = t / n, k = t - (t / n) * n;
+    L[t] = k <= i ? Lg[i * ldl + k] : 0.0;
+  }
+  const int r0 = blockIdx.x * kRowT;
+  const int nr = rows - r0 < kRowT ? rows - r0 : kRowT;
+  for (int t = threadIdx.x; t < nr * n; t += kRowT) {
+    const int rr = t / n, c = t - (t / n) * n;
+    xs[rr * stride + c] = X[int64_t(r0 + rr) * ldx + c];
+  }
+  __syncthreads();
+  const int rr = threadIdx.x;
+  if (rr < nr) {
+    double* x = xs + rr * stride;
+    for (int j = 0; j < n; ++j) {  // y L^T = x
+      const double* lj = L + j * n;
+      double a0 = x[j], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int i = 0;
+      for (; i + 3 < j; i += 4) {
+        a0 -= lj[i] * x[i];
+        a1 -= lj[i + 1] * x[i + 1];
+        a2 -= lj[i + 2] * x[i + 2];
+        a3 -= lj[i + 3] * x[i + 3];
+      }
+      for (; i < j; ++i) a0 -= lj[i] * x[i];
+      x[j] = ((a0 + a1) + (a2 + a3)) / lj[j];
+    }
+    if (!forward_only)
+      for (int j = n - 1; j >= 0; --j) {  // x L = y
+        double a0 = x[j], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int i = j + 1;
+        for (; i + 3 < n; i += 4) {
+          a0 -= L[i * n + j] * x[i];
+          a1 -= L[(i + 1) * n + j] * x[i + 1];
+          a2 -= L[(i + 2) * n + j] * x[i + 2];
+          a3 -= L[(i + 3) * n + j] * x[i + 3];
+        }
+        for (; i < n; ++i) a0 -= L[i * n + j] * x[i];
+        x[j] = ((a0 + a1) + (a2 + a3)) / L[j * n + j];
+      }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nr * n; t += kRowT) {
+    const int q = t / n, c = t - (t / n) * n;
+    X[int64_t(r0 + q) * ldx + c] = xs[q * stride + c];
+  }
+}
+
+// same, column-oriented over a row block, L read from global memory (large n)
+constexpr int kSolveT = 256;
+__global__ __launch_bounds__(kSolveT) void k_chol_solve_rows(const double* L, int n, int ldl,
+                                                             double* X, int rows, int ldx, int rb,
+                                                             int forward_only) {
+  extern __shared__ double xs[];  // rb x n
+  const int r0 = blockIdx.x * rb;
+  const int nr = rows - r0 < rb ? rows - r0 : rb;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kSolveT / 64;
+  for (int q = wave; q < nr; q += nw)
+    for (int c = lane; c < n; c += 64) xs[q * n + c] = X[int64_t(r0 + q) * ldx + c];
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double djj = L[j * ldl + j];
+    for (int q = tid; q < nr; q += kSolveT) xs[q * n + j] /= djj;
+    __syncthreads();
+    for (int q = wave; q < nr; q += nw) {
+      const double xj = xs[q * n + j];
+      for (int i = j + 1 + lane; i < n; i += 64) xs[q * n + i] -= L[i * ldl + j] * xj;
     }
     __syncthreads();
   }
   if (!forward_only) {
-    // backward: x L = y  ->  x_j = (y_j - sum_{i>j} x_i L_ij) / L_jj
-    for (int64_t j = n - 1; j >= 0; --j) {
+    for (int j = n - 1; j >= 0; --j) {
       const double djj = L[j * ldl + j];
-      for (int64_t rr = threadIdx.x; rr < nr; rr += kSolveT) xs[rr * n + j] /= djj;
+      for (int q = tid; q < nr; q += kSolveT) xs[q * n + j] /= djj;
       __syncthreads();
-      for (int64_t t = threadIdx.x; t < nr * j; t += kSolveT) {
-        int64_t rr = t / j, i = t % j;
-        xs[rr * n + i] -= L[j * ldl + i] * xs[rr * n + j];
+      for (int q = wave; q < nr; q += nw) {
+        const double xj = xs[q * n + j];
+        for (int i = lane; i < j; i += 64) xs[q * n + i] -= L[j * ldl + i] * xj;
       }
       __syncthreads();
     }
   }
-  for (int64_t t = threadIdx.x; t < nr * n; t += kSolveT) X[(r0 + t / n) * ldx + t % n] = xs[t];
+  for (int q = wave; q < nr; q += nw)
+    for (int c = lane; c < n; c += 64) X[int64_t(r0 + q) * ldx + c] = xs[q * n + c];
 }
 
 // ----------------------------------------------------------- eigen (top R) ----
 constexpr int kEigT = 512;
-constexpr int kEigWaves = kEigT / 64;
 
-// number of eigenvalues of the tridiagonal (d, e2 = e^2) smaller than x
+// 1/t from the hardware reciprocal plus one Newton step (close to full FP64
+// accuracy, no division sequence).
+__device__ inline double rcp64(double t) {
+  const double r = __builtin_amdgcn_rcp(t);
+  return fma(r, fma(-t, r, 1.0), r);
+}
+
+// number of eigenvalues of the tridiagonal (d, e2 = e^2) smaller than x; the
+// pivot recurrence uses rcp64, i.e. it counts for a tridiagonal perturbed in
+// the last bits, which moves eigenvalue boundaries by O(eps ||T||).
 __device__ int sturm_count(const double* d, const double* e2, int q, double x, double pivmin) {
   int c = 0;
   double t = d[0] - x;
   if (t < 0.0) ++c;
-  for (int i = 1; i < q; ++i) {
+  int i = 1;
+  for (; i + 3 < q; i += 4) {  // loads batched ahead of the dependent chain
+    const double d0 = d[i] - x, d1 = d[i + 1] - x, d2 = d[i + 2] - x, d3 = d[i + 3] - x;
+    const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
     if (fabs(t) <= pivmin) t = -pivmin;
-    t = d[i] - x - e2[i - 1] / t;
+    t = d0 - f0 * rcp64(t);
+    c += t < 0.0;
+    if (fabs(t) <= pivmin) t = -pivmin;
+    t = d1 - f1 * rcp64(t);
+    c += t < 0.0;
+    if (fabs(t) <= pivmin) t = -pivmin;
+    t = d2 - f2 * rcp64(t);
+    c += t < 0.0;
+    if (fabs(t) <= pivmin) t = -pivmin;
+    t = d3 - f3 * rcp64(t);
+    c += t < 0.0;
+  }
+  for (; i < q; ++i) {
+    if (fabs(t) <= pivmin) t = -pivmin;
+    t = (d[i] - x) - e2[i - 1] * rcp64(t);
     if (t < 0.0) ++c;
   }
   return c;
 }
 
 // Solve (T - lam I) x = b by LU with partial pivoting (tridiagonal, fill in
-// the second superdiagonal).  Factors in u0,u1,u2,mu, piv; b overwritten by x.
+// the second superdiagonal).  Factors in u0 (reciprocal pivots), u1, u2, mu,
+// piv; b overwritten by x.
 __device__ void tri_factor(const double* d, const double* e, int q, double lam, double tiny,
                            double* u0, double* u1, double* u2, double* mu, int8_t* piv) {
   double p = d[0] - lam, qq = q > 1 ? e[0] : 0.0, rr = 0.0;
@@ -153,14 +261,14 @@ __device__ void tri_factor(const double* d, const double* e, int q, double lam, 
     const double c = e[i], a1 = d[i + 1] - lam, b1 = i + 1 < q - 1 ? e[i + 1] : 0.0;
     if (fabs(p) >= fabs(c)) {
       double pv = p == 0.0 ? tiny : p;
-      u0[i] = pv, u1[i] = qq, u2[i] = rr, piv[i] = 0;
+      u0[i] = 1.0 / pv, u1[i] = qq, u2[i] = rr, piv[i] = 0;
       double mlt = c / pv;
       mu[i] = mlt;
       p = a1 - mlt * qq;
       qq = b1 - mlt * rr;
       rr = 0.0;
     } else {
-      u0[i] = c, u1[i] = a1, u2[i] = b1, piv[i] = 1;
+      u0[i] = 1.0 / c, u1[i] = a1, u2[i] = b1, piv[i] = 1;
       double mlt = p / c;
       mu[i] = mlt;
       double np = qq - mlt * a1, nq = rr - mlt * b1;
@@ -169,96 +277,183 @@ __device__ void tri_factor(const double* d, const double* e, int q, double lam, 
       rr = 0.0;
     }
   }
-  u0[q - 1] = p == 0.0 ? tiny : p;
+  u0[q - 1] = 1.0 / (p == 0.0 ? tiny : p);
   u1[q - 1] = 0.0;
   u2[q - 1] = 0.0;
 }
 
-__device__ void tri_solve(int q, const double* u0, const double* u1, const double* u2,
-                          const double* mu, const int8_t* piv, double* x) {
+// x <- (T - lam I)^{-1} (scale * x); returns ||x||^2
+__device__ double tri_solve(int q, const double* u0, const double* u1, const double* u2,
+                            const double* mu, const int8_t* piv, double* x, double scale) {
+  double prev = x[0] * scale;
   for (int i = 0; i < q - 1; ++i) {
+    double nx = x[i + 1] * scale;
     if (piv[i]) {
-      double t = x[i];
-      x[i] = x[i + 1];
-      x[i + 1] = t;
+      const double t = prev;
+      prev = nx;
+      nx = t;
     }
-    x[i + 1] -= mu[i] * x[i];
+    x[i] = prev;
+    prev = nx - mu[i] * prev;
   }
+  x[q - 1] = prev;
+  double n2 = 0.0, x1 = 0.0, x2 = 0.0;
   for (int i = q - 1; i >= 0; --i) {
-    double s = x[i];
-    if (i + 1 < q) s -= u1[i] * x[i + 1];
-    if (i + 2 < q) s -= u2[i] * x[i + 2];
-    x[i] = s / u0[i];
+    const double xi = (x[i] - u1[i] * x1 - u2[i] * x2) * u0[i];
+    x[i] = xi;
+    n2 += xi * xi;
+    x2 = x1;
+    x1 = xi;
   }
+  return n2;
 }
 
-__global__ __launch_bounds__(kEigT) void k_sym_eig_top(double* Mg, int q, int R, double* lam,
-                                                       double* V, double* scratch,
-                                                       int8_t* pivs, int use_lds) {
+// Layout of the kernel's working set: M (q x q) and the vector scratch
+// (d, e, e2, p, beta: 5q; y: R q; LU factors: 4 R q; pivots: R q bytes) each
+// live in LDS when they fit, else in the global scratch.  `timers` (optional)
+// receives wall-clock stamps at the phase boundaries.
+template <int NT, bool MLDS, bool VLDS>
+__global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, double* lam,
+                                                    double* V, double* gscratch, int8_t* gpivs,
+                                                    uint64_t* timers) {
+  constexpr int NW = NT / 64;
   extern __shared__ double smem[];
-  __shared__ double red[kEigWaves];
+  __shared__ double redK[NW];
+  __shared__ double redN[2][NW];
   __shared__ double sh[4];
-  double* M = use_lds ? smem : Mg;
-  double* d = (use_lds ? smem + size_t(q) * q : smem);
+  // small vectors always in LDS: d, e, e2, p, beta (5q); then M (q^2) and the
+  // inverse-iteration vectors/factors (5 R q doubles + R q bytes) if they fit
+  double* d = smem;
   double* e = d + q;
   double* e2 = e + q;
-  double* pw = e2 + q;  // p then w
+  double* pw = e2 + q;
   double* bet = pw + q;
-  if (use_lds) {
-    for (int t = threadIdx.x; t < q * q; t += kEigT) M[t] = Mg[t];
+  double* M = MLDS ? smem + 5 * q : Mg;
+  double* y = VLDS ? smem + 5 * q + (MLDS ? q * q : 0) : gscratch;  // R x q
+  double* lu = y + R * q;                                            // R x 4q
+  int8_t* pivs = VLDS ? reinterpret_cast<int8_t*>(lu + 4 * R * q) : gpivs;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (timers && tid == 0) timers[0] = wall_clock64();
+  if (MLDS) {
+    for (int t = tid; t < q * q; t += NT) M[t] = Mg[t];
     __syncthreads();
   }
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  // ---- Householder tridiagonalisation (lower) ----
+  // ---- Householder tridiagonalisation (lower); reflector k: I - beta v v^T on
+  // indices k+1.., v stored in column k below the diagonal.  Two barriers per
+  // step: p = beta A22 v (wave per row, lane-parallel dot products) with v^T p,
+  // then the rank-2 update, which also accumulates the squared norm of the
+  // next column. ----
+  if (q >= 3) {
+    double part = 0.0;
+    for (int i = 1 + tid; i < q; i += NT) part += M[i * q] * M[i * q];
+    part = wave_sum(part);
+    if (lane == 0) redN[0][wave] = part;
+    __syncthreads();
+  }
   for (int k = 0; k + 2 < q; ++k) {
     const int L = q - k - 1;
-    const double* x = M + size_t(k + 1) * q + k;  // stride q
-    double part = 0.0;
-    for (int i = tid; i < L; i += kEigT) part += x[size_t(i) * q] * x[size_t(i) * q];
-    const double norm2 = block_sum<kEigT>(part, red);
+    const double* x = M + (k + 1) * q + k;  // stride q
+    double norm2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) norm2 += redN[k & 1][w];
     const double x0 = x[0];
     const double alpha = norm2 > 0.0 ? -copysign(sqrt(norm2), x0) : 0.0;
     const double v0 = x0 - alpha;
     const double vtv = norm2 - x0 * x0 + v0 * v0;
     const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
-    __syncthreads();
+    double* A22 = M + (k + 1) * q + (k + 1);
+    double nxt = 0.0;
+    if (beta != 0.0) {
+      // p_i = beta sum_j A22[j][i] v_j: two threads per column (halves of j),
+      // four partial sums each; v_j read from column k (v_0 = x0 - alpha)
+      const int half = (L + 1) >> 1;
+      double pp = 0.0;
+      for (int base = 0; base < L; base += NT / 2) {
+        const int i = base + (tid >> 1), h = tid & 1;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (i < L) {
+          const int j0 = h * half, j1 = h ? L : half;
+          int j = j0;
+          if (j == 0) {
+            a0 = A22[i] * v0;
+            j = 1;
+          }
+          for (; j + 3 < j1; j += 4) {
+            a0 += A22[j * q + i] * x[j * q];
+            a1 += A22[(j + 1) * q + i] * x[(j + 1) * q];
+            a2 += A22[(j + 2) * q + i] * x[(j + 2) * q];
+            a3 += A22[(j + 3) * q + i] * x[(j + 3) * q];
+          }
+          for (; j < j1; ++j) a0 += A22[j * q + i] * x[j * q];
+        }
+        double sacc = (a0 + a1) + (a2 + a3);
+        sacc += __shfl_xor(sacc, 1);
+        if (i < L && h == 0) {
+          const double pi = beta * sacc;
+          pw[i] = pi;
+          pp += (i == 0 ? v0 : x[i * q]) * pi;
+        }
+      }
+      pp = wave_sum(pp);
+      if (lane == 0) redK[wave] = pp;
+      __syncthreads();
+      double vp = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) vp += redK[w];
+      const double K = 0.5 * beta * vp;
+      // rank-2 update: lane owns columns j, its v_j, w_j stay in registers;
+      // rows in groups of four with every load issued before the stores
+      for (int j = lane; j < L; j += 64) {
+        const double vj = j == 0 ? v0 : x[j * q];
+        const double wj = pw[j] - K * vj;
+        int i = wave;
+        for (; i + 3 * NW < L; i += 4 * NW) {
+          double v4[4], w4[4], r4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int ii = i + u * NW;
+            v4[u] = ii == 0 ? v0 : x[ii * q];
+            w4[u] = pw[ii];
+            r4[u] = A22[ii * q + j];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int ii = i + u * NW;
+            const double nv = r4[u] - (v4[u] * wj + (w4[u] - K * v4[u]) * vj);
+            A22[ii * q + j] = nv;
+            if (j == 0 && ii >= 1) nxt += nv * nv;
+          }
+        }
+        for (; i < L; i += NW) {
+          const double vi = i == 0 ? v0 : x[i * q];
+          const double nv = A22[i * q + j] - (vi * wj + (pw[i] - K * vi) * vj);
+          A22[i * q + j] = nv;
+          if (j == 0 && i >= 1) nxt += nv * nv;
+        }
+      }
+    } else {
+      for (int i = 1 + tid; i < L; i += NT) nxt += A22[i * q] * A22[i * q];
+    }
+    nxt = wave_sum(nxt);
+    if (lane == 0) redN[(k + 1) & 1][wave] = nxt;
     if (tid == 0) {
-      d[k] = M[size_t(k) * q + k];
+      d[k] = M[k * q + k];
       e[k] = norm2 > 0.0 ? alpha : x0;
       bet[k] = beta;
-      M[size_t(k + 1) * q + k] = v0;  // v stored in column k below the diagonal
     }
     __syncthreads();
-    if (beta != 0.0) {
-      double* A22 = M + size_t(k + 1) * q + (k + 1);
-      // p_i = beta sum_j A22[j][i] v_j
-      for (int i = tid; i < L; i += kEigT) {
-        double s = 0.0;
-        for (int j = 0; j < L; ++j) s += A22[size_t(j) * q + i] * x[size_t(j) * q];
-        pw[i] = beta * s;
-      }
-      __syncthreads();
-      double part2 = 0.0;
-      for (int i = tid; i < L; i += kEigT) part2 += x[size_t(i) * q] * pw[i];
-      const double K = 0.5 * beta * block_sum<kEigT>(part2, red);
-      __syncthreads();
-      for (int i = tid; i < L; i += kEigT) pw[i] = pw[i] - K * x[size_t(i) * q];
-      __syncthreads();
-      for (int t = tid; t < L * L; t += kEigT) {
-        int i = t / L, j = t % L;
-        A22[size_t(i) * q + j] -= x[size_t(i) * q] * pw[j] + pw[i] * x[size_t(j) * q];
-      }
-      __syncthreads();
-    }
+    if (tid == 0) M[(k + 1) * q + k] = v0;  // column k is not read again until the back-transform
   }
+  __syncthreads();
+  if (timers && tid == 0) timers[1] = wall_clock64();
   if (tid == 0) {
     if (q >= 2) {
-      d[q - 2] = M[size_t(q - 2) * q + (q - 2)];
-      e[q - 2] = M[size_t(q - 1) * q + (q - 2)];
+      d[q - 2] = M[(q - 2) * q + (q - 2)];
+      e[q - 2] = M[(q - 1) * q + (q - 2)];
       if (q >= 3) bet[q - 2] = 0.0;
     }
-    d[q - 1] = M[size_t(q - 1) * q + (q - 1)];
+    d[q - 1] = M[(q - 1) * q + (q - 1)];
     double lo = DBL_MAX, hi = -DBL_MAX, emax2 = 0.0, onenrm = 0.0;
     for (int i = 0; i < q; ++i) {
       double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < q ? fabs(e[i]) : 0.0);
@@ -279,96 +474,184 @@ __global__ __launch_bounds__(kEigT) void k_sym_eig_top(double* Mg, int q, int R,
   __syncthreads();
   const double glo = sh[0], ghi = sh[1], pivmin = sh[2], onenrm = sh[3];
 
-  // ---- eigenvalues: multisection, one wave per eigenvalue ----
-  for (int t = wave; t < R; t += kEigWaves) {
-    const int target = q - 1 - t;  // ascending index
-    double lo = glo, hi = ghi;
-    for (int it = 0; it < 64; ++it) {
-      const double width = hi - lo;
-      if (width <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-      const double xl = lo + width * double(lane + 1) / 65.0;
-      const int c = sturm_count(d, e2, q, xl, pivmin);
-      const uint64_t above = __ballot(c > target);
-      double nlo, nhi;
-      if (above == 0ull) {
-        nlo = __shfl(xl, 63);
-        nhi = hi;
-      } else {
-        const int f = __ffsll((unsigned long long)above) - 1;
-        nhi = __shfl(xl, f);
-        nlo = f > 0 ? __shfl(xl, f - 1) : lo;
+  // ---- eigenvalues: multisection; G lanes per eigenvalue (G = 64, 32 or 16,
+  // chosen so that all R eigenvalues are bracketed in as few rounds as
+  // possible), G points per step ----
+  {
+    const int per_wave = R <= NW ? 1 : (R <= 2 * NW ? 2 : 4);
+    const int G = 64 / per_wave;
+    const int gi = lane / G, gl = lane % G;
+    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+    for (int t0 = 0; t0 < R; t0 += NW * per_wave) {
+      const int t = t0 + wave * per_wave + gi;
+      const int target = q - 1 - (t < R ? t : 0);  // ascending index
+      double lo = glo, hi = ghi;
+      bool done = t >= R;
+      for (int it = 0; it < 64; ++it) {
+        const double width = hi - lo;
+        if (width <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) done = true;
+        if (__ballot(!done) == 0ull) break;
+        const double xl = lo + width * double(gl + 1) / double(G + 1);
+        const int c = done ? 0 : sturm_count(d, e2, q, xl, pivmin);
+        const uint64_t above = (__ballot(c > target) >> (gi * G)) & gmask;
+        double nlo, nhi;
+        if (above == 0ull) {
+          nlo = __shfl(xl, gi * G + G - 1);
+          nhi = hi;
+        } else {
+          const int f = __ffsll((unsigned long long)above) - 1;
+          nhi = __shfl(xl, gi * G + f);
+          nlo = f > 0 ? __shfl(xl, gi * G + f - 1) : lo;
+        }
+        if (!done) {
+          if (nlo == lo && nhi == hi) done = true;
+          lo = nlo;
+          hi = nhi;
+        }
       }
-      if (nlo == lo && nhi == hi) break;
-      lo = nlo;
-      hi = nhi;
+      if (t < R && gl == 0) lam[t] = 0.5 * (lo + hi);
     }
-    if (lane == 0) lam[t] = 0.5 * (lo + hi);
   }
   __syncthreads();
+  if (timers && tid == 0) timers[2] = wall_clock64();
 
   // ---- eigenvectors of the tridiagonal: inverse iteration, one lane each ----
-  double* y = scratch;                       // R x q
-  double* lu = scratch + size_t(R) * q;      // R x 4q
   const double tiny = DBL_EPSILON * fmax(onenrm, DBL_MIN);
-  for (int t = tid; t < R; t += kEigT) {
-    double* yt = y + size_t(t) * q;
-    double* u0 = lu + size_t(t) * 4 * q;
+  for (int t = tid; t < R; t += NT) {
+    double* yt = y + t * q;
+    double* u0 = lu + t * 4 * q;
     double* u1 = u0 + q;
     double* u2 = u1 + q;
     double* mu = u2 + q;
-    int8_t* pv = pivs + size_t(t) * q;
+    int8_t* pv = pivs + t * q;
     tri_factor(d, e, q, lam[t], tiny, u0, u1, u2, mu, pv);
     for (int i = 0; i < q; ++i) {
       uint32_t hsh = uint32_t(i) * 2654435761u + uint32_t(t + 1) * 40503u;
       yt[i] = 1.0 + double((hsh >> 8) & 1023u) / 2048.0;
     }
-    for (int it = 0; it < 4; ++it) {
-      tri_solve(q, u0, u1, u2, mu, pv, yt);
-      double nrm = 0.0, mx = 0.0;
-      for (int i = 0; i < q; ++i) mx = fmax(mx, fabs(yt[i]));
-      mx = mx > 0.0 ? mx : 1.0;
-      for (int i = 0; i < q; ++i) {
-        yt[i] /= mx;
-        nrm += yt[i] * yt[i];
-      }
-      nrm = 1.0 / sqrt(nrm);
-      for (int i = 0; i < q; ++i) yt[i] *= nrm;
-    }
+    double scale = 1.0;
+    for (int it = 0; it < 3; ++it) scale = 1.0 / sqrt(tri_solve(q, u0, u1, u2, mu, pv, yt, scale));
+    for (int i = 0; i < q; ++i) yt[i] *= scale;
   }
   __syncthreads();
+  if (timers && tid == 0) timers[3] = wall_clock64();
   // ---- modified Gram-Schmidt in eigenvalue order (wave 0) ----
   if (wave == 0) {
     for (int t = 0; t < R; ++t) {
-      double* yt = y + size_t(t) * q;
+      double* yt = y + t * q;
       for (int u = 0; u < t; ++u) {
-        const double* yu = y + size_t(u) * q;
-        double s = 0.0;
-        for (int i = lane; i < q; i += 64) s += yu[i] * yt[i];
-        s = wave_sum(s);
-        for (int i = lane; i < q; i += 64) yt[i] -= s * yu[i];
+        const double* yu = y + u * q;
+        double sdot = 0.0;
+        for (int i = lane; i < q; i += 64) sdot += yu[i] * yt[i];
+        sdot = wave_sum(sdot);
+        for (int i = lane; i < q; i += 64) yt[i] -= sdot * yu[i];
       }
-      double s = 0.0;
-      for (int i = lane; i < q; i += 64) s += yt[i] * yt[i];
-      s = 1.0 / sqrt(wave_sum(s));
-      for (int i = lane; i < q; i += 64) yt[i] *= s;
+      double sn = 0.0;
+      for (int i = lane; i < q; i += 64) sn += yt[i] * yt[i];
+      sn = 1.0 / sqrt(wave_sum(sn));
+      for (int i = lane; i < q; i += 64) yt[i] *= sn;
     }
   }
   __syncthreads();
-  // ---- back-transform y <- H_0 H_1 ... H_{q-3} y, one wave per vector ----
-  for (int t = wave; t < R; t += kEigWaves) {
-    double* yt = y + size_t(t) * q;
-    for (int k = q - 3; k >= 0; --k) {
-      const double beta = bet[k];
-      if (beta == 0.0) continue;
-      const int L = q - k - 1;
-      const double* v = M + size_t(k + 1) * q + k;
-      double s = 0.0;
-      for (int i = lane; i < L; i += 64) s += v[size_t(i) * q] * yt[k + 1 + i];
-      s = beta * wave_sum(s);
-      for (int i = lane; i < L; i += 64) yt[k + 1 + i] -= s * v[size_t(i) * q];
+  // ---- back-transform y <- H_0 H_1 ... H_{q-3} y: 16 lanes per vector, the
+  // vectors of a wave are independent, so no block barrier per reflector ----
+  {
+    const int seg = lane & 15;
+    for (int t0 = wave * 4; t0 < R; t0 += NW * 4) {
+      const int t = t0 + (lane >> 4);
+      double* yt = y + (t < R ? t : 0) * q;
+      for (int k = q - 3; k >= 0; --k) {
+        const double beta = bet[k];
+        if (beta == 0.0) continue;
+        const int L = q - k - 1;
+        const double* v = M + (k + 1) * q + k;
+        double sdot = 0.0;
+        for (int i = seg; i < L; i += 16) sdot += v[i * q] * yt[k + 1 + i];
+        sdot += __shfl_xor(sdot, 1);
+        sdot += __shfl_xor(sdot, 2);
+        sdot += __shfl_xor(sdot, 4);
+        sdot += __shfl_xor(sdot, 8);
+        sdot *= beta;
+        if (t < R)
+          for (int i = seg; i < L; i += 16) yt[k + 1 + i] -= sdot * v[i * q];
+      }
+      if (t < R)
+        for (int i = seg; i < q; i += 16) V[i * R + t] = yt[i];
     }
-    for (int i = lane; i < q; i += 64) V[size_t(i) * R + t] = yt[i];
   }
+  if (timers) {
+    __syncthreads();
+    if (tid == 0) timers[4] = wall_clock64();
+  }
+}
+
+// ---------------------------------------------- register-tiled SPD inverse ----
+// For n <= 128 the whole matrix lives in registers: 512 threads, thread t owns
+// rows tr + 16 a (a < 8) and columns tc + 32 b (b < 4), tr = t / 32, tc = t % 32.
+// The pivot column is broadcast through a small LDS vector that is only read
+// while the registers are updated (no store-to-load stalls).  Columns are
+// extracted with predicated stores from constant register indices so that the
+// tile is never demoted to scratch memory.
+constexpr int kRegT = 512, kRegMax = 128;
+
+
+// In-place inverse of an SPD matrix, n <= 128, by the symmetric sweep operator
+// (Goodnight 1979): sweeping pivot k maps a_kk -> -1/a_kk, a_ik -> a_ik/a_kk,
+// a_ij -> a_ij - a_ik a_kj / a_kk; after all pivots the matrix is -G^{-1}.  It
+// stays symmetric, so each step needs only column k broadcast; the pivots are
+// the Cholesky pivots squared (a non-positive one flags a non-SPD Gram).
+__global__ __launch_bounds__(kRegT) void k_spd_inverse_reg(double* G, int n, int lda, int* info) {
+  __shared__ double colk[kRegMax];
+  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
+  double A[8][4];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = tr + 16 * a, k = tc + 32 * b;
+      A[a][b] = (i < n && k < n) ? G[i * lda + k] : 0.0;
+    }
+  int bad = 0;
+  for (int k = 0; k < n; ++k) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)  // predicated stores: the tile stays in registers
+      if (tc + 32 * b == k)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) colk[tr + 16 * a] = A[a][b];
+    __syncthreads();
+    const double dk = colk[k];
+    if (!(dk > 0.0) && bad == 0) bad = k + 1;
+    const double rd = 1.0 / dk;
+    double cj[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) cj[b] = colk[tc + 32 * b];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int i = tr + 16 * a;
+      const double ci = colk[i];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = tc + 32 * b;
+        double v;
+        if (i == k)
+          v = j == k ? -rd : cj[b] * rd;
+        else if (j == k)
+          v = ci * rd;
+        else
+          v = A[a][b] - ci * cj[b] * rd;
+        A[a][b] = v;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *info = bad;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = tr + 16 * a, k = tc + 32 * b;
+      if (i < n && k < n) G[i * lda + k] = -A[a][b];
+    }
 }
 
 // -------------------------------------------------------------- sign fix ----
@@ -436,8 +719,29 @@ int max_lds_bytes() {
 tsk_status cholesky(double* G, int64_t n, int64_t lda, int* info, hipStream_t st) {
   size_t bytes = size_t(n) * n * 8;
   int use_lds = bytes <= size_t(max_lds_bytes()) - 1024 ? 1 : 0;
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(kCholT), use_lds ? bytes : 0, st, G, n, lda, info,
-                     use_lds);
+  if (use_lds)
+    hipLaunchKernelGGL(k_cholesky<true>, dim3(1), dim3(kCholT), bytes, st, G, int(n), int(lda),
+                       info);
+  else
+    hipLaunchKernelGGL(k_cholesky<false>, dim3(1), dim3(kCholT), 0, st, G, int(n), int(lda), info);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+bool spd_inverse_fits(int64_t n) { return size_t(n) * n * 8 + 1024 <= size_t(max_lds_bytes()); }
+
+tsk_status spd_inverse(double* G, int64_t n, int64_t lda, int* info, hipStream_t st) {
+  if (n <= kRegMax) {
+    hipLaunchKernelGGL(k_spd_inverse_reg, dim3(1), dim3(kRegT), 0, st, G, int(n), int(lda), info);
+    TSK_LAUNCHED();
+    return TSK_OK;
+  }
+  if (!spd_inverse_fits(n)) {
+    set_error("SPD inverse of order %lld exceeds the LDS budget", (long long)n);
+    return TSK_EUNSUPPORTED;
+  }
+  hipLaunchKernelGGL(k_spd_inverse, dim3(1), dim3(kGjT), size_t(n) * n * 8, st, G, int(n),
+                     int(lda), info);
   TSK_LAUNCHED();
   return TSK_OK;
 }
@@ -445,33 +749,54 @@ tsk_status cholesky(double* G, int64_t n, int64_t lda, int* info, hipStream_t st
 tsk_status chol_solve_rows(const double* L, int64_t n, int64_t ldl, double* X, int64_t rows,
                            int64_t ldx, bool forward_only, hipStream_t st) {
   if (rows == 0 || n == 0) return TSK_OK;
-  int64_t budget = (max_lds_bytes() - 1024) / 8;
-  int64_t rb = budget / n;
+  const size_t budget = size_t(max_lds_bytes()) - 1024;
+  const size_t lds_rows = (size_t(n) * n + size_t(kRowT) * (n + 1)) * 8;
+  if (lds_rows <= budget) {
+    hipLaunchKernelGGL(k_chol_solve_rows_lds, dim3(ceil_div(rows, kRowT)), dim3(kRowT), lds_rows,
+                       st, L, int(n), int(ldl), X, int(rows), int(ldx), forward_only ? 1 : 0);
+    TSK_LAUNCHED();
+    return TSK_OK;
+  }
+  int64_t rb = int64_t(budget / 8) / n;
   if (rb > 64) rb = 64;
   if (rb < 1) {
     set_error("triangular solve of order %lld exceeds the LDS budget", (long long)n);
     return TSK_EUNSUPPORTED;
   }
   hipLaunchKernelGGL(k_chol_solve_rows, dim3(ceil_div(rows, rb)), dim3(kSolveT),
-                     size_t(rb * n * 8), st, L, n, ldl, X, rows, ldx, rb, forward_only ? 1 : 0);
+                     size_t(rb * n * 8), st, L, int(n), int(ldl), X, int(rows), int(ldx), int(rb),
+                     forward_only ? 1 : 0);
   TSK_LAUNCHED();
   return TSK_OK;
 }
 
 tsk_status sym_eig_top(double* M, int64_t q, int64_t R, double* lam, double* V, Ws& ws,
                        hipStream_t st) {
-  double* scratch = ws.take<double>(size_t(R) * q * 5);
+  double* scratch = ws.take<double>(size_t(5) * R * q);
   int8_t* pivs = ws.take<int8_t>(size_t(R) * q);
   if (ws.measuring()) return TSK_OK;
-  size_t small = size_t(5) * q * 8;
-  size_t full = size_t(q) * q * 8 + small;
-  int use_lds = full + 2048 <= size_t(max_lds_bytes()) ? 1 : 0;
-  if (!use_lds && small + 2048 > size_t(max_lds_bytes())) {
+  const size_t budget = size_t(max_lds_bytes()) - 1024;
+  const size_t sbytes = size_t(5) * q * 8;
+  const size_t vbytes = size_t(5) * R * q * 8 + size_t(R) * q;
+  const size_t mbytes = size_t(q) * q * 8;
+  if (sbytes > budget) {
     set_error("eigenproblem of order %lld exceeds the LDS budget", (long long)q);
     return TSK_EUNSUPPORTED;
   }
-  hipLaunchKernelGGL(k_sym_eig_top, dim3(1), dim3(kEigT), use_lds ? full : small, st, M, int(q),
-                     int(R), lam, V, scratch, pivs, use_lds);
+  const bool m_lds = sbytes + mbytes + vbytes <= budget;
+  const bool v_lds = sbytes + (m_lds ? mbytes : 0) + vbytes <= budget;
+  const size_t lds = sbytes + (m_lds ? mbytes : 0) + (v_lds ? vbytes : 0);
+  ProfScope prof("eig", st);
+  auto* nt = static_cast<uint64_t*>(nullptr);
+  if (m_lds)
+    hipLaunchKernelGGL((k_sym_eig_top<kEigT, true, true>), dim3(1), dim3(kEigT), lds, st, M,
+                       int(q), int(R), lam, V, scratch, pivs, nt);
+  else if (v_lds)
+    hipLaunchKernelGGL((k_sym_eig_top<kEigT, false, true>), dim3(1), dim3(kEigT), lds, st, M,
+                       int(q), int(R), lam, V, scratch, pivs, nt);
+  else
+    hipLaunchKernelGGL((k_sym_eig_top<kEigT, false, false>), dim3(1), dim3(kEigT), lds, st, M,
+                       int(q), int(R), lam, V, scratch, pivs, nt);
   TSK_LAUNCHED();
   return TSK_OK;
 }

@@ -63,7 +63,7 @@ struct Job {
   void* part_val;
 };
 
-constexpr int kMaxJobs = 4;
+constexpr int kMaxJobs = 8;
 
 struct JobSet {
   int njobs;
@@ -434,6 +434,7 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
       js.job[k].part_val = f64 ? (void*)ws.take<double>(nnz) : (void*)ws.take<float>(nnz);
     }
     if (!ws.measuring()) {
+      ProfScope prof("sketch_pass", st);
       size_t hist_bytes = size_t(ttot) * sizeof(int32_t);
       size_t tile_bytes = size_t(tc) * (f64 ? 8 : 4);
       if (nnz > 0) {

@@ -2,7 +2,9 @@
 // theorems; Sec. 2.2 for the roles of A^(n) and C_(n)^T):
 //
 //   [Z^T Z ; Y^T Z]      one MFMA Gram launch in the operands' precision
-//   X^T = (Y^T Z)(Z^T Z)^{-1}     FP64 Cholesky + row-block triangular solves
+//   X^T = (Y^T Z)(Z^T Z)^{-1}     FP64: Gauss-Jordan inverse of the r x r Gram in
+//                                 LDS and an FP64 MFMA product when r fits, else
+//                                 Cholesky + row-block triangular solves
 //   A   = leading R right singular vectors of X
 //         r <= s: eigenvectors U of X X^T (r x r), A = X^T U Lambda^{-1/2}
 //         r >  s: eigenvectors of X^T X (s x s)
@@ -26,14 +28,28 @@ tsk_status rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t 
   double* lam = ws.take<double>(R);
   double* U = small_r ? ws.take<double>(size_t(r) * R) : nullptr;
   double* X = small_r ? nullptr : ws.take<double>(size_t(r) * s);
+  const bool gj = spd_inverse_fits(r);
+  double* Ht = gj ? ws.take<double>(size_t(s) * r) : nullptr;  // Y^T Z kept for the product
   const bool run = !ws.measuring();
-  TSK_TRY(gemm_tn(prec, r + s, r, m, Z, r, r, Y, s, Z, r, GH, r, ws, st));
-  if (run) TSK_TRY(cholesky(G, r, r, info, st));
-  if (run) TSK_TRY(chol_solve_rows(G, r, r, Xt, s, r, false, st));
+  {
+    ProfScope prof(run ? "gram" : "", st);
+    TSK_TRY(gemm_tn(prec, r + s, r, m, Z, r, r, Y, s, Z, r, GH, r, ws, st));
+  }
+  if (gj) {
+    // G^{-1} in place (Gauss-Jordan), then X^T = (Y^T Z) G^{-1} on the matrix cores
+    ProfScope prof(run ? "solve_la" : "", st);
+    if (run) TSK_HIP(hipMemcpyAsync(Ht, Xt, size_t(s) * r * 8, hipMemcpyDeviceToDevice, st));
+    if (run) TSK_TRY(spd_inverse(G, r, r, info, st));
+    TSK_TRY(gemm_nn_f64(s, r, r, Ht, r, G, r, Xt, r, ws, st));
+  } else {
+    ProfScope prof(run ? "solve_la" : "", st);
+    if (run) TSK_TRY(cholesky(G, r, r, info, st));
+    if (run) TSK_TRY(chol_solve_rows(G, r, r, Xt, s, r, false, st));
+  }
   if (small_r) {
     TSK_TRY(gemm_tn(TSK_PREC_F64, r, r, s, Xt, r, r, nullptr, 0, Xt, r, Mq, r, ws, st));
     TSK_TRY(sym_eig_top(Mq, r, R, lam, U, ws, st));
-    if (run) TSK_TRY(gemm_small(s, R, r, 1.0, Xt, r, 1, U, R, 1, 0.0, A, R, st));
+    TSK_TRY(gemm_nn_f64(s, R, r, Xt, r, U, R, A, R, ws, st));
     if (run) TSK_TRY(scale_columns_inv_sqrt(A, s, R, lam, st));
   } else {
     if (run) TSK_TRY(transpose_f64(Xt, s, r, X, st));

@@ -116,46 +116,56 @@ __global__ void k_twiddles(int64_t m, double2* tw) {
 }
 
 // ---- inverse hash (bucket -> rows), stable: rows increasing in a bucket ----
-__global__ void k_inverse_hash(const int32_t* h, int64_t s, int64_t m, int32_t* ptr,
-                               int32_t* items, int32_t* cursor_g) {
-  // single wave; cursor in global scratch (m + 1 ints)
+// One wave; bucket counters in LDS (m + 1 ints).  Counting uses LDS integer
+// atomics (exact); placement is stable: lanes of a round are ranked within
+// their bucket by ballots over the bucket bits, rounds go in row order.
+__global__ __launch_bounds__(64) void k_inverse_hash(const int32_t* h, int s, int m, int32_t* ptr,
+                                                     int32_t* items) {
+  extern __shared__ int32_t cur[];  // m + 1
   const int lane = threadIdx.x;
-  for (int64_t b = lane; b <= m; b += 64) cursor_g[b] = 0;
+  for (int b = lane; b <= m; b += 64) cur[b] = 0;
   __syncthreads();
-  for (int64_t i = lane; i < s; i += 64) atomicAdd(&cursor_g[h[i] + 1], 1);  // exact counts
+  for (int i = lane; i < s; i += 64) atomicAdd(&cur[h[i] + 1], 1);
   __syncthreads();
-  if (lane == 0) {
-    int32_t run = 0;
-    for (int64_t b = 0; b <= m; ++b) {
-      run += cursor_g[b];
-      cursor_g[b] = run;  // inclusive of the shifted counts = exclusive start of bucket b
-      ptr[b] = run;
-    }
+  // inclusive scan of cur[0..m] (shifted counts) = bucket starts; lane owns a chunk
+  const int chunk = (m + 1 + 63) / 64;
+  const int b0 = lane * chunk, b1 = b0 + chunk < m + 1 ? b0 + chunk : m + 1;
+  int32_t run = 0;
+  for (int b = b0; b < b1; ++b) run += cur[b];
+  int32_t incl = run;
+  for (int off = 1; off < 64; off <<= 1) {
+    int32_t o = __shfl_up(incl, off);
+    if (lane >= off) incl += o;
+  }
+  int32_t base = incl - run;
+  for (int b = b0; b < b1; ++b) {
+    base += cur[b];
+    cur[b] = base;
+    ptr[b] = base;
   }
   __syncthreads();
   int bits = 1;
-  while ((int64_t(1) << bits) < m) ++bits;
+  while ((1 << bits) < m) ++bits;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  for (int64_t i0 = 0; i0 < s; i0 += 64) {
-    int64_t i = i0 + lane;
-    bool valid = i < s;
-    uint32_t key = valid ? uint32_t(h[i]) : 0u;
+  for (int i0 = 0; i0 < s; i0 += 64) {
+    const int i = i0 + lane;
+    const bool valid = i < s;
+    const uint32_t key = valid ? uint32_t(h[i]) : 0u;
     uint64_t mt = __ballot(valid);
     for (int bt = 0; bt < bits; ++bt) {
-      bool bit = (key >> bt) & 1u;
-      uint64_t bal = __ballot(bit);
+      const bool bit = (key >> bt) & 1u;
+      const uint64_t bal = __ballot(bit);
       mt &= bit ? bal : ~bal;
     }
-    int rank = __popcll(mt & lt);
-    int base = 0;
+    const int rank = __popcll(mt & lt);
+    int bs = 0;
     if (valid && rank == 0) {
-      base = cursor_g[key];
-      cursor_g[key] = base + __popcll(mt);
+      bs = cur[key];
+      cur[key] = bs + __popcll(mt);
     }
-    int leader = valid ? __ffsll((unsigned long long)mt) - 1 : lane;
-    base = __shfl(base, leader);
-    if (valid) items[base + rank] = int32_t(i);
-    __syncthreads();
+    const int leader = valid ? __ffsll((unsigned long long)mt) - 1 : lane;
+    bs = __shfl(bs, leader);
+    if (valid) items[bs + rank] = i;
   }
 }
 
@@ -277,10 +287,14 @@ __global__ void k_conv_adjoint(SpecJob sj, int64_t m, int64_t r, Radices rd, con
 
 tsk_status build_inverse_hash(const int32_t* h, int64_t s, int64_t m, CsrTable csr, Ws& ws,
                               hipStream_t st) {
-  int32_t* cursor = ws.take<int32_t>(m + 1);
+  (void)ws;
   if (ws.measuring()) return TSK_OK;
-  hipLaunchKernelGGL(k_inverse_hash, dim3(1), dim3(64), 0, st, h, s, m, csr.ptr, csr.items,
-                     cursor);
+  if (m + 1 > 40000) {
+    set_error("TensorSketch size m = %lld above the inverse-hash LDS limit", (long long)m);
+    return TSK_EUNSUPPORTED;
+  }
+  hipLaunchKernelGGL(k_inverse_hash, dim3(1), dim3(64), size_t(m + 1) * 4, st, h, int(s), int(m),
+                     csr.ptr, csr.items);
   TSK_LAUNCHED();
   return TSK_OK;
 }
@@ -359,6 +373,7 @@ tsk_status ts_lhs(const LhsMode* modes, int nmodes, int64_t m, int prec, void* Z
   double* spec = ws.take<double>(2 * m * totR);
   double* tw = ws.take<double>(2 * m);
   if (ws.measuring()) return TSK_OK;
+  ProfScope prof("ts_lhs", st);
   TSK_TRY(ts_lhs_spectra(modes, nmodes, m, CS, spec, tw, ws, st));
   return ts_compose(modes, nmodes, m, spec, tw, prec, Z, st);
 }
