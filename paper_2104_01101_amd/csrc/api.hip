@@ -280,16 +280,20 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
         release();
       }
   }
-  {
+  if (ts) {  // sketched right-hand sides of every mode: one pass over the entries
     std::vector<PassJob> jobs;
-    if (ts)
-      for (int n = 0; n < N; ++n)
-        jobs.push_back(PassJob{0, n, m, &h[n * N], &sg[n * N], 0, Yt[n]});
-    if (o.init == TSK_INIT_RRF)
-      for (int n = 1; n < N; ++n)
-        jobs.push_back(PassJob{1, n, rrf[n].k2, nullptr, nullptr, stream_key(o.seed, kRRF, n),
-                               rrf[n].Wt});
-    if (!jobs.empty()) TSK_TRY(sketch_pass(T, jobs.data(), int(jobs.size()), ws, st));
+    for (int n = 0; n < N; ++n) jobs.push_back(PassJob{0, n, m, &h[n * N], &sg[n * N], 0, Yt[n]});
+    ProfScope prof(run ? "sketch_pass" : "", st);
+    TSK_TRY(sketch_pass(T, jobs.data(), int(jobs.size()), ws, st));
+    release();
+  }
+  if (o.init == TSK_INIT_RRF) {  // range-finder CountSketches of modes 2..N: one more pass
+    std::vector<PassJob> jobs;
+    for (int n = 1; n < N; ++n)
+      jobs.push_back(PassJob{1, n, rrf[n].k2, nullptr, nullptr, stream_key(o.seed, kRRF, n),
+                             rrf[n].Wt});
+    ProfScope prof(run ? "rrf" : "", st);
+    TSK_TRY(sketch_pass(T, jobs.data(), int(jobs.size()), ws, st));
     release();
   }
   if (ts && run)

@@ -15,15 +15,15 @@
 //            histogram, exact)
 //   scan     exclusive prefix over (tile, chunk) -> where each chunk's entries
 //            of each tile go
-//   scatter  stable partition of (fine cell, signed value) by tile; inside a
-//            wavefront the lanes that hit the same tile are matched with
-//            ballots over the tile id bits, and the four waves of a workgroup
-//            claim their ranges in wave order, so the partition keeps input
-//            order
-//   accum    one workgroup per tile: zero the tile in LDS, add the tile's
-//            entries in input order (lanes hitting the same cell are matched
-//            by ballots over the cell bits and applied rank by rank, waves in
-//            order), write the whole tile (zeros included) once, coalesced.
+//   scatter  stable partition of (16-bit fine cell, signed value) by tile;
+//            inside a wavefront the lanes that hit the same tile are matched
+//            with ballots over the tile id bits, and the four waves of a
+//            workgroup claim their ranges in wave order once per batch, so the
+//            partition keeps input order
+//   accum    one single-wave workgroup per tile: zero the tile in LDS, add the
+//            tile's entries in input order (lanes hitting the same cell are
+//            matched by ballots over the cell bits and applied rank by rank),
+//            write the whole tile (zeros included) once, coalesced.
 // Every cell is therefore the left-to-right sum of its contributions in input
 // order, independent of scheduling.
 
@@ -59,11 +59,11 @@ struct Job {
   int64_t ntiles;
   int64_t tile0;
   void* out;
-  uint32_t* part_fine;
+  uint16_t* part_fine;
   void* part_val;
 };
 
-constexpr int kMaxJobs = 8;
+constexpr int kMaxJobs = 4;  // jobs per pass; more run as further passes
 
 struct JobSet {
   int njobs;
@@ -72,7 +72,7 @@ struct JobSet {
   Job job[kMaxJobs];
 };
 
-__device__ inline void coords_of(const Coords& c, int64_t e, int64_t* i) {
+__device__ inline void coords_of(const Coords& c, int64_t e, int32_t* i) {
   if (c.layout == TSK_COO) {
 #pragma unroll
     for (int k = 0; k < TSK_MAX_ORDER; ++k)
@@ -82,14 +82,14 @@ __device__ inline void coords_of(const Coords& c, int64_t e, int64_t* i) {
 #pragma unroll
     for (int k = TSK_MAX_ORDER - 1; k >= 0; --k)
       if (k < c.N) {
-        i[k] = r % c.dims[k];
+        i[k] = int32_t(r % c.dims[k]);
         r /= c.dims[k];
       }
   }
 }
 
-__device__ inline int64_t pick(const int64_t* i, int k) {
-  int64_t r = 0;
+__device__ inline int32_t pick(const int32_t* i, int k) {
+  int32_t r = 0;
 #pragma unroll
   for (int t = 0; t < TSK_MAX_ORDER; ++t)
     if (t == k) r = i[t];
@@ -102,7 +102,7 @@ __device__ inline T value_of(const Coords& c, int64_t e) {
 }
 
 // row and sign of an entry for a job
-__device__ inline void row_sign(const Job& j, const Coords& c, const int64_t* i, int64_t& row,
+__device__ inline void row_sign(const Job& j, const Coords& c, const int32_t* i, int64_t& row,
                                 int& sg) {
   if (j.type == 0) {
     int64_t H = 0;
@@ -170,28 +170,35 @@ __device__ inline uint64_t lanemask_lt() {
 }
 
 // --------------------------------------------------------------- count ----
+// Per chunk, per tile: number of entries.  Each thread keeps four entries in
+// flight; counting uses LDS integer atomics (exact, order-independent).
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_count(Coords c, JobSet js, int64_t nnz,
-                                                  int64_t chunk, int32_t* counts,
-                                                  int ttot) {
+                                                  int64_t chunk, int32_t* counts, int ttot) {
   extern __shared__ int hist[];
   for (int t = threadIdx.x; t < ttot; t += kBlock) hist[t] = 0;
   __syncthreads();
-  int64_t lo = blockIdx.x * chunk, hi = lo + chunk < nnz ? lo + chunk : nnz;
-  int64_t ii[TSK_MAX_ORDER];
-  for (int64_t e = lo + threadIdx.x; e < hi; e += kBlock) {
-    coords_of(c, e, ii);
+  const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < nnz ? lo + chunk : nnz;
+  for (int64_t e0 = lo + threadIdx.x; e0 < hi; e0 += 4 * kBlock) {
+    int32_t ii[4][TSK_MAX_ORDER];
 #pragma unroll
-    for (int q = 0; q < kMaxJobs; ++q) {
-      if (q >= js.njobs) continue;
-      const Job& j = js.job[q];
-      int64_t row;
-      int sg;
-      row_sign(j, c, ii, row, sg);
-      int tile;
-      uint32_t fine;
-      tile_of(j, js.tc, row, pick(ii, j.col_mode), tile, fine);
-      atomicAdd(&hist[j.tile0 + tile], 1);  // integer count: exact
+    for (int u = 0; u < 4; ++u)
+      if (e0 + u * kBlock < hi) coords_of(c, e0 + u * kBlock, ii[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (e0 + u * kBlock >= hi) continue;
+#pragma unroll
+      for (int q = 0; q < kMaxJobs; ++q) {
+        if (q >= js.njobs) continue;
+        const Job& j = js.job[q];
+        int64_t row;
+        int sg;
+        row_sign(j, c, ii[u], row, sg);
+        int tile;
+        uint32_t fine;
+        tile_of(j, js.tc, row, pick(ii[u], j.col_mode), tile, fine);
+        atomicAdd(&hist[j.tile0 + tile], 1);  // integer count: exact
+      }
     }
   }
   __syncthreads();
@@ -200,17 +207,31 @@ __global__ __launch_bounds__(kBlock) void k_count(Coords c, JobSet js, int64_t n
 }
 
 // ---------------------------------------------------------------- scan ----
-// counts[c][t] -> exclusive prefix over chunks (in place); totals[t]
-__global__ void k_scan_chunks(int32_t* counts, int32_t* totals, int nchunks, int ttot) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ttot) return;
+// counts[c][t] -> exclusive prefix over chunks (in place); totals[t].  Eight
+// threads per tile, each owning a contiguous range of chunks.
+constexpr int kScanSeg = 8;
+__global__ __launch_bounds__(256) void k_scan_chunks(int32_t* counts, int32_t* totals,
+                                                     int nchunks, int ttot) {
+  __shared__ int32_t segsum[256];
+  const int tl = threadIdx.x / kScanSeg, sg = threadIdx.x % kScanSeg;
+  const int t = blockIdx.x * (256 / kScanSeg) + tl;
+  const int per = (nchunks + kScanSeg - 1) / kScanSeg;
+  const int c0 = sg * per, c1 = c0 + per < nchunks ? c0 + per : nchunks;
+  int32_t sum = 0;
+  if (t < ttot)
+    for (int cc = c0; cc < c1; ++cc) sum += counts[size_t(cc) * ttot + t];
+  segsum[threadIdx.x] = sum;
+  __syncthreads();
   int32_t run = 0;
-  for (int c = 0; c < nchunks; ++c) {
-    int32_t v = counts[size_t(c) * ttot + t];
-    counts[size_t(c) * ttot + t] = run;
-    run += v;
+  for (int q = 0; q < sg; ++q) run += segsum[tl * kScanSeg + q];
+  if (t < ttot) {
+    for (int cc = c0; cc < c1; ++cc) {
+      const int32_t v = counts[size_t(cc) * ttot + t];
+      counts[size_t(cc) * ttot + t] = run;
+      run += v;
+    }
+    if (sg == kScanSeg - 1) totals[t] = run;
   }
-  totals[t] = run;
 }
 
 // exclusive prefix of tile totals inside each job -> begin[t]; single block
@@ -239,6 +260,12 @@ __global__ void k_scan_tiles(const int32_t* totals, int32_t* begin, JobSet js) {
 }
 
 // ------------------------------------------------------------- scatter ----
+// Stable partition of (fine cell, signed value) by tile.  A batch is
+// kBlock * kRounds consecutive entries; wave w owns the w-th quarter of the
+// batch and hashes and ranks its kRounds rounds of 64 entries in parallel with
+// the other waves; the ranges in the tiles are then claimed wave by wave (one
+// barrier per wave per batch), which keeps input order inside every tile.
+constexpr int kRounds = 4;
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_scatter(Coords c, JobSet js, int64_t nnz,
                                                     int64_t chunk, const int32_t* offs,
@@ -247,60 +274,66 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Coords c, JobSet js, int64_t
   const int32_t* my = offs + size_t(blockIdx.x) * ttot;
   for (int t = threadIdx.x; t < ttot; t += kBlock) cursor[t] = begin[t] + my[t];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int64_t lo = blockIdx.x * chunk, hi = lo + chunk < nnz ? lo + chunk : nnz;
-  int64_t ii[TSK_MAX_ORDER];
-  for (int64_t r0 = lo; r0 < hi; r0 += kBlock) {
-    int64_t e = r0 + threadIdx.x;
-    bool valid = e < hi;
-    uint64_t active = __ballot(valid);
-    T v = T(0);
-    if (valid) {
-      coords_of(c, e, ii);
-      v = value_of<T>(c, e);
-    }
-    // hash, tile and in-wave rank of this entry for every job (all waves in
-    // parallel); only the claim of the tiles' ranges below is serialised.
-    int gt[kMaxJobs], rank[kMaxJobs], cnt[kMaxJobs], leader[kMaxJobs];
-    uint32_t fine[kMaxJobs];
-    bool neg[kMaxJobs];
+  const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < nnz ? lo + chunk : nnz;
+  for (int64_t b0 = lo; b0 < hi; b0 += kBlock * kRounds) {
+    int gt[kRounds][kMaxJobs], rank[kRounds][kMaxJobs], cnt[kRounds][kMaxJobs],
+        leader[kRounds][kMaxJobs];
+    uint32_t fine[kRounds][kMaxJobs];
+    bool neg[kRounds][kMaxJobs];
+    bool valid[kRounds];
+    T v[kRounds];
 #pragma unroll
-    for (int q = 0; q < kMaxJobs; ++q) {
-      if (q >= js.njobs) continue;
-      const Job& j = js.job[q];
-      int tile = 0, sg = 1;
-      uint32_t f = 0;
-      if (valid) {
-        int64_t row;
-        row_sign(j, c, ii, row, sg);
-        tile_of(j, js.tc, row, pick(ii, j.col_mode), tile, f);
+    for (int u = 0; u < kRounds; ++u) {
+      const int64_t e = b0 + (wave * kRounds + u) * 64 + lane;
+      valid[u] = e < hi;
+      int32_t ii[TSK_MAX_ORDER];
+      v[u] = T(0);
+      if (valid[u]) {
+        coords_of(c, e, ii);
+        v[u] = value_of<T>(c, e);
       }
-      uint64_t mt = match_lanes(uint32_t(tile), j.tile_bits, active);
-      gt[q] = int(j.tile0) + tile;
-      fine[q] = f;
-      neg[q] = sg < 0;
-      rank[q] = __popcll(mt & lanemask_lt());
-      cnt[q] = __popcll(mt);
-      leader[q] = valid ? __ffsll((unsigned long long)mt) - 1 : lane;
+      const uint64_t active = __ballot(valid[u]);
+#pragma unroll
+      for (int q = 0; q < kMaxJobs; ++q) {
+        if (q >= js.njobs) continue;
+        const Job& j = js.job[q];
+        int tile = 0, sgn = 1;
+        uint32_t f = 0;
+        if (valid[u]) {
+          int64_t row;
+          row_sign(j, c, ii, row, sgn);
+          tile_of(j, js.tc, row, pick(ii, j.col_mode), tile, f);
+        }
+        const uint64_t mt = match_lanes(uint32_t(tile), j.tile_bits, active);
+        gt[u][q] = int(j.tile0) + tile;
+        fine[u][q] = f;
+        neg[u][q] = sgn < 0;
+        rank[u][q] = __popcll(mt & lanemask_lt());
+        cnt[u][q] = __popcll(mt);
+        leader[u][q] = valid[u] ? __ffsll((unsigned long long)mt) - 1 : lane;
+      }
     }
-    __syncthreads();  // cursor initialised / previous round claimed
+    __syncthreads();  // cursors initialised / previous batch claimed
     for (int w = 0; w < kBlock / 64; ++w) {
       if (wave == w) {
 #pragma unroll
-        for (int q = 0; q < kMaxJobs; ++q) {
-          if (q >= js.njobs) continue;
-          const Job& j = js.job[q];
-          int base = 0;
-          if (valid && rank[q] == 0) {
-            base = cursor[gt[q]];
-            cursor[gt[q]] = base + cnt[q];
+        for (int u = 0; u < kRounds; ++u)
+#pragma unroll
+          for (int q = 0; q < kMaxJobs; ++q) {
+            if (q >= js.njobs) continue;
+            const Job& j = js.job[q];
+            int base = 0;
+            if (valid[u] && rank[u][q] == 0) {
+              base = cursor[gt[u][q]];
+              cursor[gt[u][q]] = base + cnt[u][q];
+            }
+            base = __shfl(base, leader[u][q]);
+            if (valid[u]) {
+              const int pos = base + rank[u][q];
+              j.part_fine[pos] = uint16_t(fine[u][q]);
+              static_cast<T*>(j.part_val)[pos] = neg[u][q] ? -v[u] : v[u];
+            }
           }
-          base = __shfl(base, leader[q]);
-          if (valid) {
-            int pos = base + rank[q];
-            j.part_fine[pos] = fine[q];
-            static_cast<T*>(j.part_val)[pos] = neg[q] ? -v : v;
-          }
-        }
       }
       __syncthreads();
     }
@@ -308,42 +341,50 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Coords c, JobSet js, int64_t
 }
 
 // --------------------------------------------------------------- accum ----
+// One single-wave workgroup per tile: no barriers.  Rounds of 64 consecutive
+// entries of the tile (input order); lanes that hit the same cell are matched
+// with ballots over the cell bits and applied rank by rank, so every cell is
+// the in-order sum of its entries.  The tile is then written once, coalesced.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_accum(JobSet js, const int32_t* begin,
-                                                  const int32_t* totals, int ttot) {
+__global__ __launch_bounds__(64) void k_accum(JobSet js, const int32_t* begin,
+                                              const int32_t* totals, int ttot) {
   extern __shared__ unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);
-  int gt = blockIdx.x;
+  const int gt = blockIdx.x;
   int q = 0;
   while (q + 1 < js.njobs && gt >= js.job[q + 1].tile0) ++q;
   const Job& j = js.job[q];
-  int64_t t = gt - j.tile0;
+  const int64_t t = gt - j.tile0;
   int64_t start, len;
   tile_range(j, js.tc, t, start, len);
-  for (int64_t i = threadIdx.x; i < len; i += kBlock) tile[i] = T(0);
-  const int wave = threadIdx.x >> 6;
-  int32_t b = begin[gt], n = totals[gt];
-  const uint32_t* pf = j.part_fine + b;
+  const int lane = threadIdx.x;
+  for (int i = lane; i < len; i += 64) tile[i] = T(0);
+  const int32_t b = begin[gt], n = totals[gt];
+  const uint16_t* pf = j.part_fine + b;
   const T* pv = static_cast<const T*>(j.part_val) + b;
-  for (int32_t r0 = 0; r0 < n; r0 += kBlock) {
-    int32_t e = r0 + threadIdx.x;
-    bool valid = e < n;
-    uint32_t fine = valid ? pf[e] : 0u;
-    T v = valid ? pv[e] : T(0);
-    uint64_t active = __ballot(valid);
-    uint64_t mt = match_lanes(fine, js.fine_bits, active);
-    int rank = valid ? __popcll(mt & lanemask_lt()) : 64;
-    __syncthreads();  // zeroing / previous round done
-    for (int w = 0; w < kBlock / 64; ++w) {
-      if (wave == w) {
-        for (int k = 0; __ballot(rank == k) != 0ull; ++k)
-          if (rank == k) tile[fine] += v;
-      }
-      __syncthreads();
+  for (int32_t r0 = 0; r0 < n; r0 += 64 * kRounds) {
+    uint32_t f[kRounds];
+    T v[kRounds];
+#pragma unroll
+    for (int u = 0; u < kRounds; ++u) {  // loads first
+      const int32_t e = r0 + u * 64 + lane;
+      f[u] = e < n ? uint32_t(pf[e]) : 0u;
+      v[u] = e < n ? pv[e] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kRounds; ++u) {
+      const int32_t e = r0 + u * 64 + lane;
+      const bool valid = e < n;
+      const uint64_t active = __ballot(valid);
+      if (active == 0ull) break;
+      const uint64_t mt = match_lanes(f[u], js.fine_bits, active);
+      const int rank = valid ? __popcll(mt & lanemask_lt()) : 64;
+      for (int k = 0; __ballot(rank == k) != 0ull; ++k)
+        if (rank == k) tile[f[u]] += v[u];
     }
   }
   T* out = static_cast<T*>(j.out) + start;
-  for (int64_t i = threadIdx.x; i < len; i += kBlock) out[i] = tile[i];
+  for (int i = lane; i < len; i += 64) out[i] = tile[i];
 }
 
 int bits_for(int64_t n) {
@@ -360,7 +401,7 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
                        hipStream_t st) {
   const int64_t nnz = T.nnz;
   const bool f64 = T.dtype == TSK_F64;
-  const int64_t tc = f64 ? 8192 : 16384;  // 64 KiB of LDS per tile
+  const int64_t tc = f64 ? 4096 : 8192;  // 32 KiB of LDS per tile; cell index fits 16 bits
   const int kMaxTiles = 16384;            // 64 KiB LDS histogram / cursors
 
   Coords c{};
@@ -418,23 +459,22 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
       ttot += j.ntiles;
       js.job[js.njobs++] = j;
     }
-    // chunks of the entry stream
-    int64_t nchunks = ceil_div(nnz, 4096);
+    // chunks of the entry stream: about two per compute unit, whole batches
+    int64_t nchunks = ceil_div(nnz, kBlock * kRounds);
     if (nchunks > 512) nchunks = 512;
     if (nchunks < 1) nchunks = 1;
     int64_t chunk = ceil_div(nnz, nchunks);
-    chunk = ceil_div(chunk, kBlock) * kBlock;
+    chunk = ceil_div(chunk, kBlock * kRounds) * kBlock * kRounds;
     nchunks = nnz > 0 ? ceil_div(nnz, chunk) : 1;
 
     int32_t* counts = ws.take<int32_t>(size_t(nchunks) * ttot);
     int32_t* totals = ws.take<int32_t>(ttot);
     int32_t* begin = ws.take<int32_t>(ttot);
     for (int k = 0; k < js.njobs; ++k) {
-      js.job[k].part_fine = ws.take<uint32_t>(nnz);
+      js.job[k].part_fine = ws.take<uint16_t>(nnz);
       js.job[k].part_val = f64 ? (void*)ws.take<double>(nnz) : (void*)ws.take<float>(nnz);
     }
     if (!ws.measuring()) {
-      ProfScope prof("sketch_pass", st);
       size_t hist_bytes = size_t(ttot) * sizeof(int32_t);
       size_t tile_bytes = size_t(tc) * (f64 ? 8 : 4);
       if (nnz > 0) {
@@ -445,8 +485,8 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
           hipLaunchKernelGGL(k_count<float>, dim3(nchunks), dim3(kBlock), hist_bytes, st, c, js,
                              nnz, chunk, counts, int(ttot));
         TSK_LAUNCHED();
-        hipLaunchKernelGGL(k_scan_chunks, dim3(ceil_div(ttot, 256)), dim3(256), 0, st, counts,
-                           totals, int(nchunks), int(ttot));
+        hipLaunchKernelGGL(k_scan_chunks, dim3(ceil_div(ttot, 256 / kScanSeg)), dim3(256), 0, st,
+                           counts, totals, int(nchunks), int(ttot));
         TSK_LAUNCHED();
       } else {
         TSK_HIP(hipMemsetAsync(totals, 0, size_t(ttot) * 4, st));
@@ -463,10 +503,10 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
         TSK_LAUNCHED();
       }
       if (f64)
-        hipLaunchKernelGGL(k_accum<double>, dim3(ttot), dim3(kBlock), tile_bytes, st, js, begin,
+        hipLaunchKernelGGL(k_accum<double>, dim3(ttot), dim3(64), tile_bytes, st, js, begin,
                            totals, int(ttot));
       else
-        hipLaunchKernelGGL(k_accum<float>, dim3(ttot), dim3(kBlock), tile_bytes, st, js, begin,
+        hipLaunchKernelGGL(k_accum<float>, dim3(ttot), dim3(64), tile_bytes, st, js, begin,
                            totals, int(ttot));
       TSK_LAUNCHED();
     }
