@@ -9,78 +9,98 @@
 // factor of the composite range-finder sketch, Sec. 5) -- giving
 // (T_(n) Omega^T)^T.
 //
-// No floating-point atomics.  The output Y_job (rows x ncols, row-major) is cut
-// into tiles of <= TC consecutive cells that fit in LDS.  Four kernels:
-//   count    per chunk of entries, per tile: number of entries (LDS integer
-//            histogram, exact)
-//   scan     exclusive prefix over (tile, chunk) -> where each chunk's entries
-//            of each tile go
-//   scatter  stable partition of (16-bit fine cell, signed value) by tile;
-//            inside a wavefront the lanes that hit the same tile are matched
-//            with ballots over the tile id bits, and the four waves of a
-//            workgroup claim their ranges in wave order once per batch, so the
-//            partition keeps input order
-//   accum    one single-wave workgroup per tile: zero the tile in LDS, add the
-//            tile's entries in input order (lanes hitting the same cell are
-//            matched by ballots over the cell bits and applied rank by rank),
-//            write the whole tile (zeros included) once, coalesced.
+// No atomics on values.  The output Y_job (rows x ncols, row-major) is cut
+// into bins of TC consecutive cells (32 KiB, one LDS tile).  Three kernels:
+//
+//   partition  one workgroup per chunk of E consecutive entries.  The chunk is
+//              read once (coalesced) and kept in registers; for every job the
+//              workgroup hashes it (hash tables staged in LDS), stable-sorts
+//              the (cell-in-bin, signed value) records by bin in LDS -- wave w
+//              owns a contiguous E/8 slice, counts per (wave, bin), one block
+//              scan, then every wave places its slice in order -- and writes
+//              the sorted chunk contiguously, plus the bin offsets inside the
+//              chunk.
+//   transpose  the [chunk][bin] offset table becomes [bin][chunk], so a bin
+//              reads the start of its run in every chunk contiguously.
+//   tiles      four consecutive bins per workgroup (one wave each, so the
+//              four waves share L1 lines of neighbouring runs), consecutive
+//              workgroups of one XCD on consecutive bins.  A wave walks its
+//              bin's runs in chunk order, 64 chunks per window (lane -> run by
+//              binary search over the window's prefix), adds each record to
+//              its LDS tile in sequence (lanes hitting the same cell are
+//              matched with ballots and applied rank by rank), then writes the
+//              whole tile once, zeros included.
+//
 // Every cell is therefore the left-to-right sum of its contributions in input
 // order, independent of scheduling.
 
 #include "common.h"
 #include "kernels.h"
 
+#include <algorithm>
+#include <vector>
+
 namespace tsk {
 
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kWaves = 8;              // partition: 512 threads
+constexpr int kMaxJobs = 4;            // jobs per pass; more run as further passes
+constexpr int kLds = 160 * 1024;       // LDS per workgroup
+constexpr int kTileBytes = 32 * 1024;  // one bin
 
 struct Coords {
   int N;
   int layout;
-  int dtype;
   int64_t dims[TSK_MAX_ORDER];
   const int32_t* idx[TSK_MAX_ORDER];
   const void* vals;
 };
 
 struct Job {
-  int type;  // 0 TensorSketch, 1 range-finder CountSketch
+  int type;      // 0 TensorSketch, 1 range-finder CountSketch
   int col_mode;
-  int tile_bits;
-  int pad_;
-  int64_t rows, ncols;
+  int bin_bits;  // bits of a bin index inside the slab
+  int tab_lds;   // TensorSketch tables staged in LDS (packed 15-bit hash + sign)
+  int64_t rows, ncols, cells;
   const int32_t* h[TSK_MAX_ORDER];
   const int8_t* sg[TSK_MAX_ORDER];
+  int32_t tab_off[TSK_MAX_ORDER];  // LDS offset of mode k's packed table
+  int32_t tab_len;                 // packed table entries in LDS
+  int32_t pad_;
+  uint16_t* ptab;                  // packed tables in global memory (16-byte padded)
   uint64_t key;
-  int64_t rpt;   // rows per tile (ncols <= TC), else 0
-  int64_t cbpr;  // column blocks per row (ncols > TC)
-  int64_t ntiles;
-  int64_t tile0;
+  int64_t bin_lo;  // first bin of this slab of the output
+  int32_t nbins;   // bins of this slab
+  int32_t bin0;    // first bin of this job among the group's bins
   void* out;
-  uint16_t* part_fine;
-  void* part_val;
+  uint16_t* rec_fine;  // [nchunks * E] cell inside the bin
+  void* rec_val;       // [nchunks * E] signed value
+  uint16_t* meta;      // [nchunks][nbins + 1] run starts inside each chunk
+  uint16_t* meta_t;    // [nbins + 1][nchp]
 };
-
-constexpr int kMaxJobs = 4;  // jobs per pass; more run as further passes
 
 struct JobSet {
   int njobs;
-  int fine_bits;
-  int64_t tc;
+  int tc_bits;
+  int bmax;     // LDS cursor rows are bmax wide
+  int tab_max;  // packed table entries reserved in LDS
+  int nchunks;
+  int nchp;     // row stride of meta_t: nchunks rounded up to 8
+  int btot;     // bins over all jobs
   Job job[kMaxJobs];
 };
 
+template <int NC>
 __device__ inline void coords_of(const Coords& c, int64_t e, int32_t* i) {
   if (c.layout == TSK_COO) {
 #pragma unroll
-    for (int k = 0; k < TSK_MAX_ORDER; ++k)
+    for (int k = 0; k < NC; ++k)
       if (k < c.N) i[k] = c.idx[k][e];
   } else {
     int64_t r = e;
 #pragma unroll
-    for (int k = TSK_MAX_ORDER - 1; k >= 0; --k)
+    for (int k = NC - 1; k >= 0; --k)
       if (k < c.N) {
         i[k] = int32_t(r % c.dims[k]);
         r /= c.dims[k];
@@ -88,68 +108,82 @@ __device__ inline void coords_of(const Coords& c, int64_t e, int32_t* i) {
   }
 }
 
+template <int NC>
 __device__ inline int32_t pick(const int32_t* i, int k) {
   int32_t r = 0;
 #pragma unroll
-  for (int t = 0; t < TSK_MAX_ORDER; ++t)
+  for (int t = 0; t < NC; ++t)
     if (t == k) r = i[t];
   return r;
 }
 
-template <class T>
-__device__ inline T value_of(const Coords& c, int64_t e) {
-  return static_cast<const T*>(c.vals)[e];
+// A job's fields held in registers for the partition loops.
+template <int NC>
+struct JobRegs {
+  int col_mode;
+  int bin_bits;
+  int nbins;
+  int64_t rows, ncols, bin_lo;
+  uint64_t key;
+  int32_t tab_off[NC];
+  const int32_t* h[NC];
+  const int8_t* sg[NC];
+};
+
+template <int NC>
+__device__ inline JobRegs<NC> job_regs(const Job& j) {
+  JobRegs<NC> r;
+  r.col_mode = j.col_mode;
+  r.bin_bits = j.bin_bits;
+  r.nbins = j.nbins;
+  r.rows = j.rows;
+  r.ncols = j.ncols;
+  r.bin_lo = j.bin_lo;
+  r.key = j.key;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    r.tab_off[k] = j.tab_off[k];
+    r.h[k] = j.h[k];
+    r.sg[k] = j.sg[k];
+  }
+  return r;
 }
 
-// row and sign of an entry for a job
-__device__ inline void row_sign(const Job& j, const Coords& c, const int32_t* i, int64_t& row,
-                                int& sg) {
-  if (j.type == 0) {
+// row and sign of an entry for a job: PATH 0 TensorSketch with LDS tables,
+// 1 TensorSketch with global tables, 2 range-finder CountSketch
+template <int NC, int PATH>
+__device__ inline void row_sign(const JobRegs<NC>& j, int N, const int64_t* dims,
+                                const int32_t* i, const uint16_t* tab, int64_t& row, bool& neg) {
+  if (PATH != 2) {
     int64_t H = 0;
-    int s = 1;
+    bool ng = false;
 #pragma unroll
-    for (int k = 0; k < TSK_MAX_ORDER; ++k) {
-      if (k >= c.N || k == j.col_mode) continue;
-      H += j.h[k][i[k]];
-      s *= j.sg[k][i[k]];
+    for (int k = 0; k < NC; ++k) {
+      if (k >= N || k == j.col_mode) continue;
+      if (PATH == 0) {
+        const uint32_t p = tab[j.tab_off[k] + i[k]];
+        H += p & 0x7fffu;
+        ng ^= (p >> 15) != 0;
+      } else {
+        H += j.h[k][i[k]];
+        ng ^= j.sg[k][i[k]] < 0;
+      }
     }
-    row = H % j.rows;
-    sg = s;
+#pragma unroll
+    for (int k = 0; k < NC - 1; ++k)
+      if (H >= j.rows) H -= j.rows;  // H < (N-1) m
+    row = H;
+    neg = ng;
   } else {
     int64_t lin = 0;
 #pragma unroll
-    for (int k = 0; k < TSK_MAX_ORDER; ++k) {
-      if (k >= c.N || k == j.col_mode) continue;
-      lin = lin * c.dims[k] + i[k];
+    for (int k = 0; k < NC; ++k) {
+      if (k >= N || k == j.col_mode) continue;
+      lin = lin * dims[k] + i[k];
     }
-    uint64_t x = draw(j.key, uint64_t(lin));
-    row = bucket_of(x, uint64_t(j.rows));
-    sg = sign_of(x);
-  }
-}
-
-__device__ inline void tile_of(const Job& j, int64_t tc, int64_t row, int64_t col, int& tile,
-                               uint32_t& fine) {
-  if (j.rpt > 0) {
-    tile = int(row / j.rpt);
-    fine = uint32_t((row % j.rpt) * j.ncols + col);
-  } else {
-    tile = int(row * j.cbpr + col / tc);
-    fine = uint32_t(col % tc);
-  }
-}
-
-__device__ inline void tile_range(const Job& j, int64_t tc, int64_t t, int64_t& start,
-                                  int64_t& len) {
-  if (j.rpt > 0) {
-    start = t * j.rpt * j.ncols;
-    int64_t r = j.rows - t * j.rpt;
-    len = (r < j.rpt ? r : j.rpt) * j.ncols;
-  } else {
-    int64_t row = t / j.cbpr, cb = t % j.cbpr;
-    start = row * j.ncols + cb * tc;
-    int64_t l = j.ncols - cb * tc;
-    len = l < tc ? l : tc;
+    const uint64_t x = draw(j.key, uint64_t(lin));
+    row = int64_t(bucket_of(x, uint64_t(j.rows)));
+    neg = sign_of(x) < 0;
   }
 }
 
@@ -157,233 +191,351 @@ __device__ inline void tile_range(const Job& j, int64_t tc, int64_t t, int64_t& 
 __device__ inline uint64_t match_lanes(uint32_t key, int bits, uint64_t active) {
   uint64_t m = active;
   for (int b = 0; b < bits; ++b) {
-    bool bit = (key >> b) & 1u;
-    uint64_t bal = __ballot(bit);
+    const bool bit = (key >> b) & 1u;
+    const uint64_t bal = __ballot(bit);
     m &= bit ? bal : ~bal;
   }
   return m;
 }
 
-__device__ inline uint64_t lanemask_lt() {
-  int lane = threadIdx.x & 63;
+// same, with at most MAXB key bits (unrolled; bits beyond `bits` skipped)
+template <int MAXB>
+__device__ inline uint64_t match_lanes_n(uint32_t key, int bits, uint64_t active) {
+  uint64_t m = active;
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    if (b >= bits) break;
+    const bool bit = (key >> b) & 1u;
+    const uint64_t bal = __ballot(bit);
+    m &= bit ? bal : ~bal;
+  }
+  return m;
+}
+
+__device__ inline uint64_t lanemask_lt(int lane) {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// --------------------------------------------------------------- count ----
-// Per chunk, per tile: number of entries.  Each thread keeps four entries in
-// flight; counting uses LDS integer atomics (exact, order-independent).
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_count(Coords c, JobSet js, int64_t nnz,
-                                                  int64_t chunk, int32_t* counts, int ttot) {
-  extern __shared__ int hist[];
-  for (int t = threadIdx.x; t < ttot; t += kBlock) hist[t] = 0;
-  __syncthreads();
-  const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < nnz ? lo + chunk : nnz;
-  for (int64_t e0 = lo + threadIdx.x; e0 < hi; e0 += 4 * kBlock) {
-    int32_t ii[4][TSK_MAX_ORDER];
+constexpr uint32_t kSkip = 0xffffffffu;
+
+// packed bin / sign / cell-in-bin of every round's entry for one job
+template <int NC, int RW, int PATH>
+__device__ inline void hash_rounds(const JobRegs<NC>& j, int N, const int64_t* dims,
+                                   const int32_t (*ii)[NC], const uint16_t* tab, int tc_bits,
+                                   uint32_t* pk) {
+  const uint32_t cmask = (1u << tc_bits) - 1u;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (e0 + u * kBlock < hi) coords_of(c, e0 + u * kBlock, ii[u]);
+  for (int u = 0; u < RW; ++u) {
+    pk[u] = kSkip;
+    if (ii[u][0] < 0) continue;
+    int64_t row;
+    bool neg;
+    row_sign<NC, PATH>(j, N, dims, ii[u], tab, row, neg);
+    const int64_t cell = row * j.ncols + pick<NC>(ii[u], j.col_mode);
+    const int64_t bin = (cell >> tc_bits) - j.bin_lo;
+    if (bin >= 0 && bin < j.nbins)
+      pk[u] = (uint32_t(bin) << 16) | (neg ? 0x8000u : 0u) | (uint32_t(cell) & cmask);
+  }
+}
+
+// ----------------------------------------------------------- partition ----
+// Cursors are 16-bit counters packed in pairs into 32-bit LDS words, so that
+// integer LDS atomics can update them: counts use atomic adds (exact, order
+// independent); placement uses one atomic add with return per (round, bin) by
+// the round's first lane of that bin -- a wave owns its cursor row and LDS
+// executes one wave's operations in order, so the claimed ranges follow the
+// input order.
+__device__ inline uint32_t cursor_add(uint32_t* row, uint32_t bin, uint32_t n) {
+  const uint32_t sh = (bin & 1u) * 16u;
+  return (atomicAdd(row + (bin >> 1), n << sh) >> sh) & 0xffffu;
+}
+
+template <class T, int NC, int RW, int PATH>
+__global__ __launch_bounds__(512) void k_partition(Coords c, JobSet js, int64_t nnz) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  constexpr int E = 512 * RW;
+  T* s_val = reinterpret_cast<T*>(lds);
+  uint16_t* s_fine = reinterpret_cast<uint16_t*>(lds + size_t(E) * sizeof(T));
+  const int bw = (js.bmax + 1) >> 1;  // 32-bit words per cursor row
+  uint32_t* cur = reinterpret_cast<uint32_t*>(s_fine + E);
+  uint16_t* tab = reinterpret_cast<uint16_t*>(cur + kWaves * bw);
+  int32_t* scr = reinterpret_cast<int32_t*>(tab + ((js.tab_max + 7) & ~7));
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t chunk = blockIdx.x;
+  const int64_t ebase = chunk * E + wave * (RW * 64) + lane;
+  const int N = c.N;
+  int64_t dims[NC];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (e0 + u * kBlock >= hi) continue;
+  for (int k = 0; k < NC; ++k) dims[k] = k < N ? c.dims[k] : 1;
+
+  int32_t ii[RW][NC];
+  T v[RW];
 #pragma unroll
-      for (int q = 0; q < kMaxJobs; ++q) {
-        if (q >= js.njobs) continue;
-        const Job& j = js.job[q];
-        int64_t row;
-        int sg;
-        row_sign(j, c, ii[u], row, sg);
-        int tile;
-        uint32_t fine;
-        tile_of(j, js.tc, row, pick(ii[u], j.col_mode), tile, fine);
-        atomicAdd(&hist[j.tile0 + tile], 1);  // integer count: exact
+  for (int u = 0; u < RW; ++u) {  // all loads issued before any use
+    const int64_t e = ebase + u * 64;
+    v[u] = T(0);
+    ii[u][0] = -1;
+    if (e < nnz) {
+      coords_of<NC>(c, e, ii[u]);
+      v[u] = static_cast<const T*>(c.vals)[e];
+    }
+  }
+  const int njobs = js.njobs, tc_bits = js.tc_bits;
+  for (int q = 0; q < njobs; ++q) {
+    const JobRegs<NC> j = job_regs<NC>(js.job[q]);
+    if (PATH == 0) {  // packed tables: 16-byte copies
+      const uint4* src = reinterpret_cast<const uint4*>(js.job[q].ptab);
+      uint4* dst = reinterpret_cast<uint4*>(tab);
+      const int n16 = (js.job[q].tab_len + 7) >> 3;
+#pragma unroll 4
+      for (int i = tid; i < n16; i += 512) dst[i] = src[i];
+    }
+    uint32_t* mycur = cur + wave * bw;
+    const int nw = (j.nbins + 1) >> 1;
+    for (int b = lane; b < nw; b += 64) mycur[b] = 0;
+    __syncthreads();
+
+    // hash and count per (wave, bin)
+    uint32_t pk[RW];  // bin << 16 | negative << 15 | cell in bin
+    hash_rounds<NC, RW, PATH>(j, N, dims, ii, tab, tc_bits, pk);
+#pragma unroll
+    for (int u = 0; u < RW; ++u)
+      if (pk[u] != kSkip) {
+        const uint32_t bin = pk[u] >> 16;
+        atomicAdd(mycur + (bin >> 1), 1u << ((bin & 1u) * 16u));
       }
-    }
-  }
-  __syncthreads();
-  int32_t* out = counts + size_t(blockIdx.x) * ttot;
-  for (int t = threadIdx.x; t < ttot; t += kBlock) out[t] = hist[t];
-}
+    __syncthreads();
 
-// ---------------------------------------------------------------- scan ----
-// counts[c][t] -> exclusive prefix over chunks (in place); totals[t].  Eight
-// threads per tile, each owning a contiguous range of chunks.
-constexpr int kScanSeg = 8;
-__global__ __launch_bounds__(256) void k_scan_chunks(int32_t* counts, int32_t* totals,
-                                                     int nchunks, int ttot) {
-  __shared__ int32_t segsum[256];
-  const int tl = threadIdx.x / kScanSeg, sg = threadIdx.x % kScanSeg;
-  const int t = blockIdx.x * (256 / kScanSeg) + tl;
-  const int per = (nchunks + kScanSeg - 1) / kScanSeg;
-  const int c0 = sg * per, c1 = c0 + per < nchunks ? c0 + per : nchunks;
-  int32_t sum = 0;
-  if (t < ttot)
-    for (int cc = c0; cc < c1; ++cc) sum += counts[size_t(cc) * ttot + t];
-  segsum[threadIdx.x] = sum;
-  __syncthreads();
-  int32_t run = 0;
-  for (int q = 0; q < sg; ++q) run += segsum[tl * kScanSeg + q];
-  if (t < ttot) {
-    for (int cc = c0; cc < c1; ++cc) {
-      const int32_t v = counts[size_t(cc) * ttot + t];
-      counts[size_t(cc) * ttot + t] = run;
-      run += v;
-    }
-    if (sg == kScanSeg - 1) totals[t] = run;
-  }
-}
-
-// exclusive prefix of tile totals inside each job -> begin[t]; single block
-__global__ void k_scan_tiles(const int32_t* totals, int32_t* begin, JobSet js) {
-  __shared__ int32_t part[1024];
-  for (int q = 0; q < js.njobs; ++q) {
-    int64_t t0 = js.job[q].tile0, nt = js.job[q].ntiles;
-    int32_t carry = 0;
-    for (int64_t base = 0; base < nt; base += 1024) {
-      int64_t t = base + threadIdx.x;
-      int32_t v = t < nt ? totals[t0 + t] : 0;
-      part[threadIdx.x] = v;
+    // scan: cursor(w, b) = start of bin b + entries of bin b in waves < w
+    {
+      const uint16_t* c16 = reinterpret_cast<const uint16_t*>(cur);
+      uint16_t* w16 = reinterpret_cast<uint16_t*>(cur);
+      const int rs = 2 * bw;  // u16 row stride
+      const int G = (j.nbins + 511) / 512;
+      const int b0 = tid * G;
+      int32_t tsum = 0;
+      for (int g = 0; g < G; ++g) {
+        const int b = b0 + g;
+        if (b < j.nbins)
+#pragma unroll
+          for (int w = 0; w < kWaves; ++w) tsum += c16[w * rs + b];
+      }
+      int32_t incl = tsum;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+      }
+      if (lane == 63) scr[wave] = incl;
       __syncthreads();
-      for (int off = 1; off < 1024; off <<= 1) {
-        int32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += add;
-        __syncthreads();
-      }
-      if (t < nt) begin[t0 + t] = carry + part[threadIdx.x] - v;
-      int32_t blocksum = part[1023];
-      __syncthreads();
-      carry += blocksum;
-    }
-  }
-}
-
-// ------------------------------------------------------------- scatter ----
-// Stable partition of (fine cell, signed value) by tile.  A batch is
-// kBlock * kRounds consecutive entries; wave w owns the w-th quarter of the
-// batch and hashes and ranks its kRounds rounds of 64 entries in parallel with
-// the other waves; the ranges in the tiles are then claimed wave by wave (one
-// barrier per wave per batch), which keeps input order inside every tile.
-constexpr int kRounds = 4;
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_scatter(Coords c, JobSet js, int64_t nnz,
-                                                    int64_t chunk, const int32_t* offs,
-                                                    const int32_t* begin, int ttot) {
-  extern __shared__ int cursor[];
-  const int32_t* my = offs + size_t(blockIdx.x) * ttot;
-  for (int t = threadIdx.x; t < ttot; t += kBlock) cursor[t] = begin[t] + my[t];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < nnz ? lo + chunk : nnz;
-  for (int64_t b0 = lo; b0 < hi; b0 += kBlock * kRounds) {
-    int gt[kRounds][kMaxJobs], rank[kRounds][kMaxJobs], cnt[kRounds][kMaxJobs],
-        leader[kRounds][kMaxJobs];
-    uint32_t fine[kRounds][kMaxJobs];
-    bool neg[kRounds][kMaxJobs];
-    bool valid[kRounds];
-    T v[kRounds];
+      int32_t run = incl - tsum;
+      for (int w = 0; w < wave; ++w) run += scr[w];
+      uint16_t* meta = js.job[q].meta + chunk * (j.nbins + 1);
+      for (int g = 0; g < G; ++g) {
+        const int b = b0 + g;
+        if (b >= j.nbins) break;
+        meta[b] = uint16_t(run);
 #pragma unroll
-    for (int u = 0; u < kRounds; ++u) {
-      const int64_t e = b0 + (wave * kRounds + u) * 64 + lane;
-      valid[u] = e < hi;
-      int32_t ii[TSK_MAX_ORDER];
-      v[u] = T(0);
-      if (valid[u]) {
-        coords_of(c, e, ii);
-        v[u] = value_of<T>(c, e);
-      }
-      const uint64_t active = __ballot(valid[u]);
-#pragma unroll
-      for (int q = 0; q < kMaxJobs; ++q) {
-        if (q >= js.njobs) continue;
-        const Job& j = js.job[q];
-        int tile = 0, sgn = 1;
-        uint32_t f = 0;
-        if (valid[u]) {
-          int64_t row;
-          row_sign(j, c, ii, row, sgn);
-          tile_of(j, js.tc, row, pick(ii, j.col_mode), tile, f);
+        for (int w = 0; w < kWaves; ++w) {
+          const int32_t t = c16[w * rs + b];
+          w16[w * rs + b] = uint16_t(run);
+          run += t;
         }
-        const uint64_t mt = match_lanes(uint32_t(tile), j.tile_bits, active);
-        gt[u][q] = int(j.tile0) + tile;
-        fine[u][q] = f;
-        neg[u][q] = sgn < 0;
-        rank[u][q] = __popcll(mt & lanemask_lt());
-        cnt[u][q] = __popcll(mt);
-        leader[u][q] = valid[u] ? __ffsll((unsigned long long)mt) - 1 : lane;
+      }
+      if (b0 < j.nbins && b0 + G >= j.nbins) {
+        meta[j.nbins] = uint16_t(run);
+        scr[kWaves] = run;
       }
     }
-    __syncthreads();  // cursors initialised / previous batch claimed
-    for (int w = 0; w < kBlock / 64; ++w) {
-      if (wave == w) {
+    __syncthreads();
+
+    // stable placement: claims for all rounds first, then the stores
+    uint32_t rk[RW];  // rank | leader << 8, or kSkip
 #pragma unroll
-        for (int u = 0; u < kRounds; ++u)
-#pragma unroll
-          for (int q = 0; q < kMaxJobs; ++q) {
-            if (q >= js.njobs) continue;
-            const Job& j = js.job[q];
-            int base = 0;
-            if (valid[u] && rank[u][q] == 0) {
-              base = cursor[gt[u][q]];
-              cursor[gt[u][q]] = base + cnt[u][q];
-            }
-            base = __shfl(base, leader[u][q]);
-            if (valid[u]) {
-              const int pos = base + rank[u][q];
-              j.part_fine[pos] = uint16_t(fine[u][q]);
-              static_cast<T*>(j.part_val)[pos] = neg[u][q] ? -v[u] : v[u];
-            }
-          }
-      }
-      __syncthreads();
+    for (int u = 0; u < RW; ++u) {
+      const bool valid = pk[u] != kSkip;
+      const uint64_t act = __ballot(valid);
+      const uint64_t mt = match_lanes_n<16>(pk[u] >> 16, j.bin_bits, act);
+      const uint32_t rank = __popcll(mt & lanemask_lt(lane));
+      const uint32_t lead = valid ? uint32_t(__ffsll((unsigned long long)mt) - 1) : uint32_t(lane);
+      uint32_t base = 0;
+      if (valid && rank == 0) base = cursor_add(mycur, pk[u] >> 16, uint32_t(__popcll(mt)));
+      rk[u] = valid ? (rank | (lead << 8) | (base << 16)) : kSkip;
     }
+#pragma unroll
+    for (int u = 0; u < RW; ++u) {
+      const uint32_t base = uint32_t(__shfl(int(rk[u] >> 16), int((rk[u] >> 8) & 0xffu)));
+      if (rk[u] != kSkip) {
+        const uint32_t pos = base + (rk[u] & 0xffu);
+        s_fine[pos] = uint16_t(pk[u] & 0x7fffu);
+        s_val[pos] = (pk[u] & 0x8000u) ? -v[u] : v[u];
+      }
+    }
+    __syncthreads();
+
+    const int32_t total = scr[kWaves];
+    uint16_t* rf = js.job[q].rec_fine + chunk * E;
+    T* rv = static_cast<T*>(js.job[q].rec_val) + chunk * E;
+    for (int i = tid; i < total; i += 512) {
+      rf[i] = s_fine[i];
+      rv[i] = s_val[i];
+    }
+    __syncthreads();  // LDS is reused by the next job
   }
 }
 
-// --------------------------------------------------------------- accum ----
-// One single-wave workgroup per tile: no barriers.  Rounds of 64 consecutive
-// entries of the tile (input order); lanes that hit the same cell are matched
-// with ballots over the cell bits and applied rank by rank, so every cell is
-// the in-order sum of its entries.  The tile is then written once, coalesced.
-template <class T>
-__global__ __launch_bounds__(64) void k_accum(JobSet js, const int32_t* begin,
-                                              const int32_t* totals, int ttot) {
-  extern __shared__ unsigned char smem_raw[];
-  T* tile = reinterpret_cast<T*>(smem_raw);
-  const int gt = blockIdx.x;
+// packed 15-bit hash | sign << 15 of the other modes of a TensorSketch job,
+// concatenated in mode order; one job per blockIdx.y
+__global__ __launch_bounds__(256) void k_pack_tables(JobSet js, Coords c) {
+  const Job& j = js.job[blockIdx.y];
+  if (j.type != 0 || !j.tab_lds) return;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  for (int k = 0; k < c.N; ++k) {
+    if (k == j.col_mode) continue;
+    const int i = t - j.tab_off[k];
+    if (i >= 0 && i < c.dims[k]) j.ptab[t] = uint16_t(j.h[k][i] | (j.sg[k][i] < 0 ? 0x8000 : 0));
+  }
+}
+
+// [chunk][bin] -> [bin][chunk], one job per blockIdx.z
+__global__ __launch_bounds__(256) void k_meta_transpose(JobSet js) {
+  __shared__ uint16_t t[64][65];
+  const Job& j = js.job[blockIdx.z];
+  const int nb1 = j.nbins + 1, nch = js.nchunks;
+  const int b0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  if (b0 >= nb1 || c0 >= nch) return;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4)
+    if (c0 + r < nch && b0 + tx < nb1) t[r][tx] = j.meta[size_t(c0 + r) * nb1 + b0 + tx];
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4)
+    if (b0 + r < nb1 && c0 + tx < nch) j.meta_t[size_t(b0 + r) * js.nchp + c0 + tx] = t[tx][r];
+}
+
+// ---------------------------------------------------------------- tiles ----
+constexpr int kWin = 256;   // chunks per window: 4 per lane
+constexpr int kSub = 2048;  // records per sub-window (record -> run map in LDS)
+constexpr int kWaveScratch = kSub * 2 + kWin * 8;
+
+template <class T, int K>
+__global__ __launch_bounds__(256) void k_tiles(JobSet js, int E, int ngroups_pad) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  constexpr int TC = kTileBytes / sizeof(T);
+  constexpr int FB = sizeof(T) == 8 ? 12 : 13;  // log2(TC)
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // XCD-aware: workgroups g, g + 8, g + 16, ... run on one XCD and take
+  // consecutive groups of bins
+  const int g = blockIdx.x;
+  const int grp = (g % 8) * (ngroups_pad / 8) + g / 8;
+  const int bt = grp * 4 + wave;
+  if (bt >= js.btot) return;  // waves are independent: no barriers below
   int q = 0;
-  while (q + 1 < js.njobs && gt >= js.job[q + 1].tile0) ++q;
+  while (q + 1 < js.njobs && bt >= js.job[q + 1].bin0) ++q;
   const Job& j = js.job[q];
-  const int64_t t = gt - j.tile0;
-  int64_t start, len;
-  tile_range(j, js.tc, t, start, len);
-  const int lane = threadIdx.x;
-  for (int i = lane; i < len; i += 64) tile[i] = T(0);
-  const int32_t b = begin[gt], n = totals[gt];
-  const uint16_t* pf = j.part_fine + b;
-  const T* pv = static_cast<const T*>(j.part_val) + b;
-  for (int32_t r0 = 0; r0 < n; r0 += 64 * kRounds) {
-    uint32_t f[kRounds];
-    T v[kRounds];
+  const int b = bt - j.bin0;
+  T* tile = reinterpret_cast<T*>(lds) + wave * TC;
+  unsigned char* wsc = lds + 4 * kTileBytes + wave * kWaveScratch;
+  uint16_t* map = reinterpret_cast<uint16_t*>(wsc);      // run index + 1 per record
+  uint32_t* wex = reinterpret_cast<uint32_t*>(wsc + kSub * 2);  // run start in the window
+  uint32_t* wad = wex + kWin;                                 // run start address
+  for (int i = lane; i < TC; i += 64) tile[i] = T(0);
+
+  const int nch = js.nchunks;
+  const uint16_t* St = j.meta_t + size_t(b) * js.nchp;
+  const uint16_t* Sn = St + js.nchp;
+  const uint16_t* rf = j.rec_fine;
+  const T* rv = static_cast<const T*>(j.rec_val);
+  for (int c0 = 0; c0 < nch; c0 += kWin) {
+    // runs of chunks c0 + 4 lane .. + 3 (rows are padded to 8 entries)
+    const int cl = c0 + 4 * lane;
+    uint32_t s4[4] = {0, 0, 0, 0}, n4[4] = {0, 0, 0, 0};
+    if (cl < nch) {
+      const uint2 a = *reinterpret_cast<const uint2*>(St + cl);
+      const uint2 z = *reinterpret_cast<const uint2*>(Sn + cl);
+      s4[0] = a.x & 0xffffu;
+      s4[1] = a.x >> 16;
+      s4[2] = a.y & 0xffffu;
+      s4[3] = a.y >> 16;
+      const uint32_t e4[4] = {z.x & 0xffffu, z.x >> 16, z.y & 0xffffu, z.y >> 16};
 #pragma unroll
-    for (int u = 0; u < kRounds; ++u) {  // loads first
-      const int32_t e = r0 + u * 64 + lane;
-      f[u] = e < n ? uint32_t(pf[e]) : 0u;
-      v[u] = e < n ? pv[e] : T(0);
+      for (int h = 0; h < 4; ++h) n4[h] = cl + h < nch ? e4[h] - s4[h] : 0u;
     }
+    const uint32_t lsum = n4[0] + n4[1] + n4[2] + n4[3];
+    uint32_t incl = lsum;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(incl, off);
+      if (lane >= off) incl += y;
+    }
+    const int32_t total = int32_t(__shfl(incl, 63));
+    uint32_t ex4[4];
+    {
+      uint32_t run = incl - lsum;
 #pragma unroll
-    for (int u = 0; u < kRounds; ++u) {
-      const int32_t e = r0 + u * 64 + lane;
-      const bool valid = e < n;
-      const uint64_t active = __ballot(valid);
-      if (active == 0ull) break;
-      const uint64_t mt = match_lanes(f[u], js.fine_bits, active);
-      const int rank = valid ? __popcll(mt & lanemask_lt()) : 64;
-      for (int k = 0; __ballot(rank == k) != 0ull; ++k)
-        if (rank == k) tile[f[u]] += v[u];
+      for (int h = 0; h < 4; ++h) {
+        ex4[h] = run;
+        wex[4 * lane + h] = run;
+        wad[4 * lane + h] = uint32_t(cl + h) * uint32_t(E) + s4[h];
+        run += n4[h];
+      }
+    }
+    for (int32_t x0 = 0; x0 < total; x0 += kSub) {
+      const int n = total - x0 < kSub ? total - x0 : kSub;
+      uint32_t* map32 = reinterpret_cast<uint32_t*>(map);
+      for (int w = lane; w < (n + 1) >> 1; w += 64) map32[w] = 0;
+      // every run of this sub-window marks its first record in it
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+        if (n4[h] > 0 && ex4[h] < uint32_t(x0 + n) && ex4[h] + n4[h] > uint32_t(x0)) {
+          const uint32_t p = ex4[h] > uint32_t(x0) ? ex4[h] - uint32_t(x0) : 0u;
+          map[p] = uint16_t(4 * lane + h + 1);
+        }
+      // inclusive max-scan of the marks: each record gets its run
+      {
+        const int P = (n + 63) >> 6;
+        const int p0 = lane * P, p1 = p0 + P < n ? p0 + P : n;
+        uint32_t mx = 0;
+        for (int p = p0; p < p1; ++p) mx = mx > map[p] ? mx : map[p];
+        uint32_t carry = mx;
+        for (int off = 1; off < 64; off <<= 1) {
+          const uint32_t y = __shfl_up(carry, off);
+          if (lane >= off) carry = carry > y ? carry : y;
+        }
+        uint32_t run = __shfl_up(carry, 1);
+        if (lane == 0) run = 0;
+        for (int p = p0; p < p1; ++p) {
+          const uint32_t v = map[p];
+          run = run > v ? run : v;
+          map[p] = uint16_t(run);
+        }
+      }
+      for (int r0 = 0; r0 < n; r0 += 64 * K) {
+        uint32_t f[K];
+        T val[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {  // branch-free: out-of-range lanes reload the last record
+          const int x = r0 + u * 64 + lane;
+          const int xc = x < n ? x : n - 1;
+          const int ci = int(map[xc]) - 1;
+          const uint32_t a = wad[ci] + (uint32_t(x0 + xc) - wex[ci]);
+          f[u] = rf[a];
+          val[u] = rv[a];
+        }
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+          const bool valid = r0 + u * 64 + lane < n;
+          const uint64_t act = __ballot(valid);
+          if (act == 0ull) break;
+          const uint64_t mt = match_lanes_n<FB>(f[u], FB, act);
+          const int rank = valid ? __popcll(mt & lanemask_lt(lane)) : 64;
+          for (int k = 0; __ballot(rank == k) != 0ull; ++k)
+            if (rank == k) tile[f[u]] += val[u];
+        }
+      }
     }
   }
-  T* out = static_cast<T*>(j.out) + start;
+  const int64_t first = (j.bin_lo + b) * int64_t(TC);
+  const int64_t rem = j.cells - first;
+  const int len = rem < TC ? int(rem) : TC;
+  T* out = static_cast<T*>(j.out) + first;
   for (int i = lane; i < len; i += 64) out[i] = tile[i];
 }
 
@@ -393,125 +545,156 @@ int bits_for(int64_t n) {
   return b;
 }
 
+int path_of(const Job& j) { return j.type == 1 ? 2 : j.tab_lds ? 0 : 1; }
+
+template <class T, int NC, int RW>
+void launch_partition(int path, int nchunks, size_t lds, hipStream_t st, const Coords& c,
+                      const JobSet& js, int64_t nnz) {
+  if (path == 0)
+    hipLaunchKernelGGL((k_partition<T, NC, RW, 0>), dim3(nchunks), dim3(512), lds, st, c, js, nnz);
+  else if (path == 1)
+    hipLaunchKernelGGL((k_partition<T, NC, RW, 1>), dim3(nchunks), dim3(512), lds, st, c, js, nnz);
+  else
+    hipLaunchKernelGGL((k_partition<T, NC, RW, 2>), dim3(nchunks), dim3(512), lds, st, c, js, nnz);
+}
+
 }  // namespace
 
-// One pass over the entries for a group of jobs whose tiles fit the LDS
-// histogram.  `specs` describe the jobs; outputs are overwritten.
+// Jobs are expanded into slabs of bins whose LDS cursors fit; up to four slabs
+// share one read of the entries.  Groups run one after the other on the
+// stream and reuse the same scratch.
 tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws& ws,
                        hipStream_t st) {
   const int64_t nnz = T.nnz;
   const bool f64 = T.dtype == TSK_F64;
-  const int64_t tc = f64 ? 4096 : 8192;  // 32 KiB of LDS per tile; cell index fits 16 bits
-  const int kMaxTiles = 16384;            // 64 KiB LDS histogram / cursors
+  const int vb = f64 ? 8 : 4;
+  const int64_t tc = kTileBytes / vb;
+  const bool wide = T.order > 4;  // coordinates kept per round: 3, 4 or 8
+  const int RW = wide ? 8 : T.order == 4 ? 12 : 16;
+  const int E = 512 * RW;
+  const int64_t nchunks = nnz > 0 ? ceil_div(nnz, E) : 0;
+  if ((nchunks + 1) * int64_t(E) >= (int64_t(1) << 31)) {
+    set_error("the sketch pass supports fewer than 2^31 - %d entries", E);
+    return TSK_EUNSUPPORTED;
+  }
+  const int64_t fixed = int64_t(E) * (vb + 2) + 128;  // staging + scan scratch
 
   Coords c{};
   c.N = T.order;
   c.layout = T.layout;
-  c.dtype = T.dtype;
   for (int k = 0; k < T.order; ++k) {
     c.dims[k] = T.dims[k];
     c.idx[k] = T.idx[k];
   }
   c.vals = T.values;
 
-  // group jobs so that each group's tiles fit; groups run one after the other
-  // on the stream and reuse the same scratch
+  std::vector<Job> all;
+  for (int q = 0; q < njobs; ++q) {
+    const PassJob& p = specs[q];
+    Job j{};
+    j.type = p.type;
+    j.col_mode = p.col_mode;
+    j.rows = p.rows;
+    j.ncols = T.dims[p.col_mode];
+    j.cells = j.rows * j.ncols;
+    for (int k = 0; k < T.order; ++k) {
+      j.h[k] = p.h ? p.h[k] : nullptr;
+      j.sg[k] = p.sg ? p.sg[k] : nullptr;
+    }
+    j.key = p.key;
+    j.out = p.out;
+    int64_t tab = 0;
+    if (p.type == 0)
+      for (int k = 0; k < T.order; ++k)
+        if (k != p.col_mode) {
+          j.tab_off[k] = int32_t(tab);
+          tab += T.dims[k];
+        }
+    j.tab_lds = p.type == 0 && p.rows <= 32768 && fixed + 2 * (tab + 8) + 16 * 64 <= kLds;
+    j.tab_len = j.tab_lds ? int32_t(tab) : 0;
+    const int64_t room = (kLds - fixed - 2 * (int64_t(j.tab_len) + 8)) / (2 * kWaves);
+    const int64_t bmax = std::min<int64_t>(room, 32768);
+    const int64_t nb = ceil_div(j.cells, tc);
+    for (int64_t lo = 0; lo < nb; lo += bmax) {
+      Job s = j;
+      s.bin_lo = lo;
+      s.nbins = int32_t(std::min(bmax, nb - lo));
+      s.bin_bits = bits_for(s.nbins);
+      all.push_back(s);
+    }
+  }
+
   const size_t mark = ws.off;
   size_t peak = mark;
-  int g0 = 0;
-  while (g0 < njobs) {
+  for (size_t g0 = 0; g0 < all.size();) {  // groups of up to four slabs of one hash path
     ws.off = mark;
     JobSet js{};
-    js.tc = tc;
-    js.fine_bits = bits_for(tc);
-    int64_t ttot = 0;
-    int q = g0;
-    for (; q < njobs; ++q) {
-      const PassJob& p = specs[q];
-      Job j{};
-      j.type = p.type;
-      j.col_mode = p.col_mode;
-      j.rows = p.rows;
-      j.ncols = T.dims[p.col_mode];
-      for (int k = 0; k < T.order; ++k) {
-        j.h[k] = p.h ? p.h[k] : nullptr;
-        j.sg[k] = p.sg ? p.sg[k] : nullptr;
-      }
-      j.key = p.key;
-      if (j.ncols <= tc) {
-        j.rpt = tc / j.ncols;
-        j.cbpr = 0;
-        j.ntiles = ceil_div(j.rows, j.rpt);
-      } else {
-        j.rpt = 0;
-        j.cbpr = ceil_div(j.ncols, tc);
-        j.ntiles = j.rows * j.cbpr;
-      }
-      if (j.ntiles > kMaxTiles) {
-        set_error("sketch output of %lld x %lld cells exceeds the tile budget",
-                  (long long)j.rows, (long long)j.ncols);
-        return TSK_EUNSUPPORTED;
-      }
-      if (ttot + j.ntiles > kMaxTiles || js.njobs == kMaxJobs) break;
-      j.tile_bits = bits_for(j.ntiles);
-      j.tile0 = ttot;
-      j.out = p.out;
-      ttot += j.ntiles;
+    js.tc_bits = bits_for(tc);
+    js.nchunks = int(nchunks);
+    js.nchp = int(ceil_div(nchunks, 8) * 8);
+    const int path = path_of(all[g0]);
+    int bins = 0;
+    size_t q = g0;
+    for (; q < all.size() && js.njobs < kMaxJobs && path_of(all[q]) == path; ++q) {
+      Job j = all[q];
+      j.bin0 = bins;
+      bins += j.nbins;
+      js.bmax = std::max(js.bmax, j.nbins);
+      js.tab_max = std::max(js.tab_max, j.tab_len);
+      j.rec_fine = ws.take<uint16_t>(size_t(nchunks) * E);
+      j.rec_val = ws.take<char>(size_t(nchunks) * E * vb);
+      j.meta = ws.take<uint16_t>(size_t(nchunks) * (j.nbins + 1));
+      j.meta_t = ws.take<uint16_t>(size_t(js.nchp) * (j.nbins + 2));
+      j.ptab = j.tab_lds ? ws.take<uint16_t>(size_t(ceil_div(j.tab_len, 8) * 8)) : nullptr;
       js.job[js.njobs++] = j;
     }
-    // chunks of the entry stream: about two per compute unit, whole batches
-    int64_t nchunks = ceil_div(nnz, kBlock * kRounds);
-    if (nchunks > 512) nchunks = 512;
-    if (nchunks < 1) nchunks = 1;
-    int64_t chunk = ceil_div(nnz, nchunks);
-    chunk = ceil_div(chunk, kBlock * kRounds) * kBlock * kRounds;
-    nchunks = nnz > 0 ? ceil_div(nnz, chunk) : 1;
-
-    int32_t* counts = ws.take<int32_t>(size_t(nchunks) * ttot);
-    int32_t* totals = ws.take<int32_t>(ttot);
-    int32_t* begin = ws.take<int32_t>(ttot);
-    for (int k = 0; k < js.njobs; ++k) {
-      js.job[k].part_fine = ws.take<uint16_t>(nnz);
-      js.job[k].part_val = f64 ? (void*)ws.take<double>(nnz) : (void*)ws.take<float>(nnz);
-    }
-    if (!ws.measuring()) {
-      size_t hist_bytes = size_t(ttot) * sizeof(int32_t);
-      size_t tile_bytes = size_t(tc) * (f64 ? 8 : 4);
-      if (nnz > 0) {
-        if (f64)
-          hipLaunchKernelGGL(k_count<double>, dim3(nchunks), dim3(kBlock), hist_bytes, st, c, js,
-                             nnz, chunk, counts, int(ttot));
-        else
-          hipLaunchKernelGGL(k_count<float>, dim3(nchunks), dim3(kBlock), hist_bytes, st, c, js,
-                             nnz, chunk, counts, int(ttot));
-        TSK_LAUNCHED();
-        hipLaunchKernelGGL(k_scan_chunks, dim3(ceil_div(ttot, 256 / kScanSeg)), dim3(256), 0, st,
-                           counts, totals, int(nchunks), int(ttot));
-        TSK_LAUNCHED();
-      } else {
-        TSK_HIP(hipMemsetAsync(totals, 0, size_t(ttot) * 4, st));
-      }
-      hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, totals, begin, js);
-      TSK_LAUNCHED();
-      if (nnz > 0) {
-        if (f64)
-          hipLaunchKernelGGL(k_scatter<double>, dim3(nchunks), dim3(kBlock), hist_bytes, st, c,
-                             js, nnz, chunk, counts, begin, int(ttot));
-        else
-          hipLaunchKernelGGL(k_scatter<float>, dim3(nchunks), dim3(kBlock), hist_bytes, st, c,
-                             js, nnz, chunk, counts, begin, int(ttot));
-        TSK_LAUNCHED();
-      }
-      if (f64)
-        hipLaunchKernelGGL(k_accum<double>, dim3(ttot), dim3(64), tile_bytes, st, js, begin,
-                           totals, int(ttot));
-      else
-        hipLaunchKernelGGL(k_accum<float>, dim3(ttot), dim3(64), tile_bytes, st, js, begin,
-                           totals, int(ttot));
-      TSK_LAUNCHED();
-    }
     g0 = q;
+    js.btot = bins;
     peak = std::max(peak, ws.off);
+    if (ws.measuring()) continue;
+
+    if (nchunks > 0) {
+      if (js.tab_max > 0) {
+        hipLaunchKernelGGL(k_pack_tables, dim3(unsigned(ceil_div(js.tab_max, 256)), unsigned(js.njobs)),
+                           dim3(256), 0, st, js, c);
+        TSK_LAUNCHED();
+      }
+      const size_t lds =
+          size_t(fixed + 2 * int64_t(kWaves) * js.bmax + 2 * int64_t(ceil_div(js.tab_max, 8) * 8));
+      if (f64) {
+        if (wide)
+          launch_partition<double, 8, 8>(path, int(nchunks), lds, st, c, js, nnz);
+        else if (T.order == 4)
+          launch_partition<double, 4, 12>(path, int(nchunks), lds, st, c, js, nnz);
+        else
+          launch_partition<double, 3, 16>(path, int(nchunks), lds, st, c, js, nnz);
+      } else {
+        if (wide)
+          launch_partition<float, 8, 8>(path, int(nchunks), lds, st, c, js, nnz);
+        else if (T.order == 4)
+          launch_partition<float, 4, 12>(path, int(nchunks), lds, st, c, js, nnz);
+        else
+          launch_partition<float, 3, 16>(path, int(nchunks), lds, st, c, js, nnz);
+      }
+      TSK_LAUNCHED();
+      int maxb1 = 0;
+      for (int q = 0; q < js.njobs; ++q) maxb1 = std::max(maxb1, js.job[q].nbins + 1);
+      hipLaunchKernelGGL(k_meta_transpose,
+                         dim3(unsigned(ceil_div(maxb1, 64)), unsigned(ceil_div(nchunks, 64)),
+                              unsigned(js.njobs)),
+                         dim3(256), 0, st, js);
+      TSK_LAUNCHED();
+    }
+    const size_t tiles_lds = 4 * kTileBytes + 4 * kWaveScratch;
+    const int ngroups = int(ceil_div(js.btot, 4));
+    const int ngroups_pad = int(ceil_div(ngroups, 8) * 8);
+    if (f64)
+      hipLaunchKernelGGL((k_tiles<double, 8>), dim3(ngroups_pad), dim3(256), tiles_lds, st, js, E,
+                         ngroups_pad);
+    else
+      hipLaunchKernelGGL((k_tiles<float, 8>), dim3(ngroups_pad), dim3(256), tiles_lds, st, js, E,
+                         ngroups_pad);
+    TSK_LAUNCHED();
   }
   ws.off = peak;
   return TSK_OK;
