@@ -1,25 +1,34 @@
 #!/usr/bin/env python3
 """Throughput of sketched Tucker-ALS (Alg. 4) on one MI355X.
 
-Workload (default): the sparse 3-way configuration -- 2000^3, 1e6 distinct
-uniform coordinates, values = Tucker rank-(10,10,10) Gaussian signal + N(0,1),
-FP32; TensorSketch with m = 16 * 10^2 = 1600, range-finder initialisation,
-10 sweeps, FP32 operands (FP64 factorisations).  Inputs are synthetic and
-seeded (seed 0) and resident in HBM before timing.
+Workload (default): sparse 3-way 2000^3 tensor, 1e6 distinct uniform
+coordinates, values = Tucker rank-(10,10,10) Gaussian signal + N(0,1), FP32;
+TensorSketch with m = 16 * 10^2 = 1600, range-finder initialisation, 10 sweeps,
+FP32 operands (FP64 factorisations).  Inputs are synthetic and seeded (seed 0)
+and resident in HBM before timing.
 
 One step = one complete call: TensorSketch maps, the sketch pass of every mode
-(prep), range-finder init of modes 2..3, 10 sweeps of the three sketched
+(preparation), range-finder init of modes 2..3, 10 sweeps of the three sketched
 rank-constrained subproblems, and the relative residual after every sweep.
 value = completed sweeps per second of the whole job (10 * steps / time).
 
-Prints one JSON line (keys per the benchmark contract) with a `roofline` object
-for the dominant kernel group -- timed live with HIP events on the library's
-stream over the timed region -- and a `cpu_baseline` object timing the FP64
-oracle on a bounded sample of the same workload.
+Prints one JSON line (keys per the benchmark contract) with
+  roofline              the launch group that takes the most time, timed live
+                        with HIP events on the library's stream over the timed
+                        region, against its bound (HBM, matrix cores or vector
+                        ALU) with its algorithmic bytes or flops;
+  sketch_pass_roofline  the same for the nnz sketch pass (HBM-bound);
+  cpu_baseline          the FP64 oracle timed on a bounded sample of the same
+                        workload on the host cores.
+HBM traffic per launch comes from rocprofv3 FETCH_SIZE / WRITE_SIZE summaries
+committed under profiles/ and is reported only while the kernel source they
+were taken from is unchanged (else null).
 """
 import argparse
 import ctypes
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -27,10 +36,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP32_MFMA_TFLOPS = 157.3       # dense FP32 matrix
-BF16_MFMA_TFLOPS = 2500.0
-FP64_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}  # dense matrix-core peaks
+FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+
+# source files whose kernels make up each launch group (for the traffic check)
+GROUP_SOURCES = {
+    "sketch_pass": ["sketch_pass.hip"], "rrf_pass": ["sketch_pass.hip"],
+    "ts_lhs": ["ts_lhs.hip"], "gram": ["gemm.hip"], "solve_la": ["linalg.hip", "gemm.hip"],
+    "eig": ["linalg.hip"], "fit": ["fit.hip"], "rrf": ["linalg.hip", "gemm.hip", "api.hip"],
+}
+GROUPS = ["sketch_pass", "rrf_pass", "rrf", "ts_lhs", "gram", "solve_la", "eig", "fit"]
 
 
 def parse():
@@ -38,52 +54,126 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
+                    help="c2 (default, the benchmark workload) or c4 (sketch-pass study)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true",
-                    help="also print per-group times of one extra profiled step")
+                    help="also print per-group times of the last warm-up step (stderr)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy kernel (counter scale)")
     return ap.parse_args()
 
 
-def make_workload():
+def workload(name):
     import workloads
-    w = workloads.c2()
-    return w
+    return workloads.c2() if name == "c2" else workloads.c4()
 
 
-def groups_bytes_flops(w, name):
-    """Algorithmic work of one launch group of `name` (per launch)."""
-    s = w.dims[0]
-    R = w.ranks[0]
-    N = 3
-    m = w.m
+def group_work(w):
+    """Algorithmic work of one job per launch group: name -> (bound, amount, peak, unit).
+    bytes for HBM-bound groups, flops otherwise."""
+    N = len(w.dims)
+    s, R, m, sweeps = w.dims[0], w.ranks[0], w.m, w.sweeps
     nnz = w.val.shape[0]
-    if name == "sketch_pass":
-        k1 = int(-(-((m / R ** 2) ** 0.5 * R) // 1))
-        k2 = R * R + k1
-        coo = nnz * (N * 4 + 4)
-        out = N * m * s * 4 + (N - 1) * k2 * s * 4
-        return coo + out, 0.0
-    if name == "gram":
-        r = R * R
-        return 0.0, 2.0 * m * r * (r + s)
-    return 0.0, 0.0
+    r = R ** (N - 1)
+    q = min(r, s)
+    k1 = math.ceil(math.sqrt(m / r) * R - 1e-9)
+    k2 = R * R + k1
+    vb = 4  # FP32 tensor values and FP32 operands
+    subs = N * sweeps
+    pk = PEAK_TFLOPS[w.prec]
+    eig = lambda n: 4.0 / 3.0 * n ** 3 + 2.0 * n * n * R
+    return {
+        # COO stream (N int32 indices + value) read once, every Y^(n) written once
+        "sketch_pass": ("hbm", nnz * (4 * N + vb) + N * m * s * vb, HBM_PEAK_GBS, "GB/s"),
+        "rrf_pass": ("hbm", nnz * (4 * N + vb) + (N - 1) * k2 * s * vb, HBM_PEAK_GBS, "GB/s"),
+        # B = W G (s x k2 x k1) and the Gram of B, per initialised mode
+        "rrf": ("mfma", (N - 1) * (2.0 * s * k2 * k1 + 2.0 * s * k1 * k1),
+                PEAK_TFLOPS["f64"], "TFLOP/s"),
+        # CountSketches read, Z written
+        "ts_lhs": ("hbm", subs * ((N - 1) * s * R * 8 + m * r * vb), HBM_PEAK_GBS, "GB/s"),
+        # G = Z^T Z and Z^T Y
+        "gram": ("mfma", subs * 2.0 * m * r * (r + s), pk, "TFLOP/s"),
+        # Gram inverse, X = H G^-1, X X^T, A = X^T U, W = X A (FP64)
+        "solve_la": ("mfma", subs * (r ** 3 + 4.0 * s * r * q + 4.0 * s * r * R),
+                     PEAK_TFLOPS["f64"], "TFLOP/s"),
+        # tridiagonalisation + back-transformation of R vectors (FP64 vector ALU)
+        "eig": ("alu", subs * eig(q) + (N - 1) * eig(k1), FP64_VECTOR_TFLOPS, "TFLOP/s"),
+        # per entry: core contraction R^3 + R^2 + R multiply-adds (FP64)
+        "fit": ("alu", sweeps * nnz * 2.0 * (R ** 3 + R ** 2 + R), FP64_VECTOR_TFLOPS, "TFLOP/s"),
+    }
+
+
+def source_digest(group):
+    h = hashlib.sha256()
+    for f in GROUP_SOURCES.get(group, []):
+        with open(os.path.join(ROOT, "paper_2104_01101_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic(group, wname):
+    """HBM bytes per launch from a committed counter summary, if still current."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{group}_{wname}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256_16") != source_digest(group):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline(name, work, ms_total, launches, steps, wname):
+    bound, amount, peak, unit = work[name]
+    secs = ms_total / 1e3
+    per_launch = amount * steps / max(1, launches)
+    if unit == "GB/s":
+        achieved = amount * steps / secs / 1e9
+    else:
+        achieved = amount * steps / secs / 1e12
+    t = traffic(name, wname)
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": t, "kernel": name,
+            "algorithmic_per_launch": per_launch, "avg_launch_ms": ms_total / max(1, launches),
+            "launches": launches}
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.ones(n, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
     import paper_2104_01101_amd as tsk
     from paper_2104_01101_amd import _lib as L
 
     dev = torch.device("cuda:0")
-    w = make_workload()
+    w = workload(args.workload)
     T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(dev), torch.from_numpy(w.val).to(dev), w.dims)
-    plan = tsk.TuckerPlan(T, w.ranks, w.m, w.sweeps, sketch="ts", init="rrf", prec="f32",
+    plan = tsk.TuckerPlan(T, w.ranks, w.m, w.sweeps, sketch="ts", init="rrf", prec=w.prec,
                           seed=0, record_fit=True)
     lib = L.lib()
     lib.tsk_profile_enable.argtypes = [ctypes.c_char_p]
@@ -97,22 +187,23 @@ def main():
         return ms.value, n.value
 
     # warm-up; the last warm-up step is profiled per group to find the dominant one
-    names = ["sketch_pass", "rrf", "ts_lhs", "gram", "solve_la", "eig", "fit"]
-    for i in range(max(1, args.warmup)):
-        if i == max(1, args.warmup) - 1:
+    nw = max(1, args.warmup)
+    for i in range(nw):
+        if i == nw - 1:
             L.check(lib.tsk_profile_enable(b"*"))
         plan.run()
-    per_group = {n: read(n) for n in names}
+    per_group = {n: read(n) for n in GROUPS}
     L.check(lib.tsk_profile_enable(b""))
     dominant = max(per_group, key=lambda n: per_group[n][0])
     if args.breakdown:
-        tot = read(None)
         print(json.dumps({"breakdown_ms_per_step": {n: round(v[0], 4) for n, v in per_group.items()},
-                          "launch_groups": {n: v[1] for n, v in per_group.items()},
-                          "profiled_total_ms": round(tot[0], 4)}), file=sys.stderr)
+                          "launch_groups": {n: v[1] for n, v in per_group.items()}}),
+              file=sys.stderr)
 
-    # timed region: the dominant group's launches are timed with events on the stream
-    L.check(lib.tsk_profile_enable(dominant.encode()))
+    # timed region: the dominant group's and the sketch pass's launches are
+    # timed with events on the library's stream
+    timed = dominant if dominant == "sketch_pass" else f"{dominant},sketch_pass"
+    L.check(lib.tsk_profile_enable(timed.encode()))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fits = None
@@ -120,31 +211,14 @@ def main():
         _, _, fits = plan.run()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    dom_ms, dom_n = read(dominant)
+    dom = read(dominant)
+    sp = read("sketch_pass")
     L.check(lib.tsk_profile_enable(b""))
 
-    sweeps_total = w.sweeps * args.steps
-    value = sweeps_total / elapsed
-    byts, flops = groups_bytes_flops(w, dominant)
-    avg_s = dom_ms / 1e3 / max(1, dom_n)
-    if byts > 0:
-        roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "traffic": None}
-    elif flops > 0:
-        roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "traffic": None}
-    else:
-        roof = {"bound": "latency", "achieved": None, "peak": None, "unit": None,
-                "traffic": None}
-    if roof.get("achieved") is not None:
-        roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = dominant
-    roof["avg_launch_ms"] = avg_s * 1e3
-    roof["launches"] = dom_n
-
+    work = group_work(w)
     out = {
         "metric": "ALS sweeps/s + sketch-pass GB/s at fixed relative residual, FP32 vs BF16/adjoint",
-        "value": value,
+        "value": w.sweeps * args.steps / elapsed,
         "unit": "sweeps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -153,24 +227,29 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": w.prec,
         "data": "synthetic",
-        "config": {"workload": "sparse 2000^3, 1e6 nnz uniform, Tucker rank 10 + N(0,1), "
-                               "TensorSketch m=1600, RRF init, 10 sweeps",
+        "config": {"workload": ("sparse 2000^3, 1e6 nnz uniform, Tucker rank 10 + N(0,1), "
+                                "TensorSketch m=1600, RRF init, 10 sweeps, FP32 operands")
+                   if args.workload == "c2" else
+                   ("sparse 10000^3, 1e7 nnz Zipf(1.1), lognormal values, Tucker rank 16, "
+                    "TensorSketch m=2048, RRF init, 5 sweeps, FP32 operands"),
                    "dims": list(w.dims), "nnz": int(w.val.shape[0]), "ranks": list(w.ranks),
-                   "m": w.m, "sweeps": w.sweeps, "prec": "f32"},
+                   "m": w.m, "sweeps": w.sweeps, "prec": w.prec},
         "final_relative_residual": fits[-1] if fits else None,
-        "roofline": roof,
+        "roofline": roofline(dominant, work, dom[0], dom[1], args.steps, args.workload),
+        "sketch_pass_roofline": roofline("sketch_pass", work, sp[0], sp[1], args.steps,
+                                         args.workload),
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "c2":
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))
 
 
-def cpu_baseline(w):
-    """FP64 oracle on the same c2 input: preparation (maps, sketched right-hand
-    sides, range finder) and one of the 10 sweeps are timed; the job time is
-    extrapolated to prep + 10 sweeps."""
+def cpu_baseline(w, sample_sweeps=3):
+    """FP64 oracle on the same input: preparation (maps, sketched right-hand
+    sides, range finder) and `sample_sweeps` of the sweeps are timed; the job
+    time is extrapolated to preparation + all sweeps."""
     import numpy as np
     from oracle import sketch as osk, solve as osv, tucker as otk
     try:
@@ -179,7 +258,7 @@ def cpu_baseline(w):
     except Exception:
         cores = os.cpu_count()
     T = osk.Tensor(w.dims, w.idx, w.val.astype(np.float64))
-    N, m, ranks, seed = 3, w.m, w.ranks, 0
+    N, m, ranks, seed = len(w.dims), w.m, w.ranks, 0
     t0 = time.perf_counter()
     tables = {n: osk.ts_tables(w.dims, m, seed, n) for n in range(N)}
     Ys = {n: osk.ts_rhs(T, m, tables[n], n) for n in range(N)}
@@ -189,17 +268,19 @@ def cpu_baseline(w):
         factors[n] = otk.init_rrf(T, n, ranks[n], k1, k2, seed)
     t_prep = time.perf_counter() - t0
     t1 = time.perf_counter()
-    for n in range(N):
-        Z = osk.ts_lhs(factors, tables[n], m, n)
-        A, W, _ = osv.rc_solve(Z, Ys[n], ranks[n])
-        factors[n] = A
-        core = otk.W_to_core(W, ranks, n)
-    otk.relative_residual(T, core, factors)
-    t_sweep = time.perf_counter() - t1
+    for _ in range(sample_sweeps):
+        for n in range(N):
+            Z = osk.ts_lhs(factors, tables[n], m, n)
+            A, W, _ = osv.rc_solve(Z, Ys[n], ranks[n])
+            factors[n] = A
+            core = otk.W_to_core(W, ranks, n)
+        otk.relative_residual(T, core, factors)
+    t_sweep = (time.perf_counter() - t1) / sample_sweeps
     job = t_prep + w.sweeps * t_sweep
     return {"value": w.sweeps / job, "unit": "sweeps/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"full input; prep ({t_prep:.2f} s) + 1 of {w.sweeps} sweeps "
-                      f"({t_sweep:.2f} s) timed, job = prep + {w.sweeps} sweeps"}
+            "sample": f"full input; preparation ({t_prep:.2f} s) + {sample_sweeps} of "
+                      f"{w.sweeps} sweeps ({t_sweep:.2f} s each) timed, "
+                      f"job = preparation + {w.sweeps} sweeps"}
 
 
 if __name__ == "__main__":

@@ -117,8 +117,9 @@ uint64_t tsk_draw(uint64_t key, uint64_t counter);
 
 /* Launch timing for measurement.  tsk_profile_enable(name) makes the library
  * record HIP events on the launching stream around every launch group called
- * `name` ("sketch_pass", "gram", "ts_lhs", "solve_la", "eig", "fit", "rrf",
- * "leverage", "cp_core", "adjoint"; "*" = all; NULL or "" = off, the default)
+ * `name` ("sketch_pass", "rrf_pass", "gram", "ts_lhs", "solve_la", "eig", "fit", "rrf",
+ * "leverage", "cp_core", "adjoint"; a comma-separated list selects several;
+ * "*" = all; NULL or "" = off, the default)
  * and clears earlier records.  tsk_profile_read(name) waits for the recorded
  * events and returns the summed milliseconds and the number of groups (name
  * NULL = all).  Not thread-safe with respect to concurrent library calls that
@@ -212,13 +213,16 @@ tsk_status tsk_sketch_lhs_ts(int32_t order, const int64_t* dims, const int32_t* 
                              void* stream);
 
 /* Exact sketched rank-constrained solve (Sec. 4 theorems, Sec. 2.2):
- * X = argmin ||Z X - Y||_F = (Z^T Z)^{-1} Z^T Y (Cholesky, FP64), A = leading R
- * right singular vectors of X (FP64 symmetric eigen-decomposition of the
- * smaller Gram of X, re-orthonormalised, largest-magnitude entry of each
- * column positive), W = X A = C_(n)^T.
+ * X = argmin ||Z X - Y||_F = (Z^T Z)^{-1} Z^T Y in FP64 (Gram and Z^T Y on the
+ * matrix cores in the operand precision with FP32/FP64 accumulation; the SPD
+ * Gram is inverted by Gauss-Jordan sweeps when r <= 142, else Cholesky-solved),
+ * A = leading R right singular vectors of X (FP64 symmetric eigen-decomposition
+ * of the smaller Gram of X, re-orthonormalised, largest-magnitude entry of
+ * each column positive), W = X A = C_(n)^T.
  *   Z  device m x r, Y device m x s, element type by prec (as above)
  *   A  device double s x R (output);  W device double r x R (output)
- * Requires m >= r, R <= min(r, s). */
+ * Requires m >= r, R <= min(r, s).  Synchronous: waits for the stream to check
+ * the factorisation status; ENUMERIC if the Gram is not positive definite. */
 tsk_status tsk_rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s,
                         int32_t R, int32_t prec, double* A, double* W, void* ws,
                         size_t* ws_bytes, void* stream);
@@ -228,7 +232,8 @@ tsk_status tsk_rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int6
  * (seed, 2, n) at the other-mode row-major index), G (k2 x k1) i.i.d.
  * N(0, 1/k1) (stream (seed, 3, n)), B = W G, A = leading R left singular
  * vectors of B (sign rule as above).
- *   A  device double dims[n] x R (output).  Requires R <= k1. */
+ *   A  device double dims[n] x R (output).  Requires R <= k1.
+ * Synchronous: waits for the stream to check the factorisation status. */
 tsk_status tsk_rrf_init(const tsk_tensor* T, int32_t n, int32_t R, int32_t k1, int32_t k2,
                         uint64_t seed, double* A, void* ws, size_t* ws_bytes,
                         void* stream);

@@ -292,7 +292,7 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
     for (int n = 1; n < N; ++n)
       jobs.push_back(PassJob{1, n, rrf[n].k2, nullptr, nullptr, stream_key(o.seed, kRRF, n),
                              rrf[n].Wt});
-    ProfScope prof(run ? "rrf" : "", st);
+    ProfScope prof(run ? "rrf_pass" : "", st);
     TSK_TRY(sketch_pass(T, jobs.data(), int(jobs.size()), ws, st));
     release();
   }

@@ -3,6 +3,7 @@
 // that name, so the elapsed times are the kernels' own durations on the
 // stream they run on.  Disabled by default (no events, no overhead).
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -17,9 +18,21 @@ struct Rec {
   hipEvent_t a, b;
 };
 std::mutex g_mu;
-std::string g_filter;  // "" = disabled, "*" = every name
+std::string g_filter;  // "" = disabled, "*" = every name, else comma-separated names
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
+
+bool selected(const char* name) {
+  if (g_filter == "*") return true;
+  const std::string n(name);
+  size_t p = 0;
+  while (p <= g_filter.size()) {
+    const size_t q = std::min(g_filter.find(',', p), g_filter.size());
+    if (g_filter.compare(p, q - p, n) == 0 && q - p == n.size()) return true;
+    p = q + 1;
+  }
+  return false;
+}
 
 hipEvent_t get_event() {
   if (!g_pool.empty()) {
@@ -35,7 +48,7 @@ hipEvent_t get_event() {
 
 ProfScope::ProfScope(const char* name, hipStream_t st) : st_(st), idx_(-1) {
   std::lock_guard<std::mutex> lk(g_mu);
-  if (!name || !*name || g_filter.empty() || (g_filter != "*" && g_filter != name)) return;
+  if (!name || !*name || g_filter.empty() || !selected(name)) return;
   hipEvent_t a = get_event(), b = get_event();
   if (!a || !b) return;
   if (hipEventRecord(a, st) != hipSuccess) return;
@@ -55,8 +68,8 @@ using namespace tsk;
 
 extern "C" {
 
-// Enable timing of the launch groups called `name` ("*" for all, NULL or ""
-// to disable); clears previous records.
+// Enable timing of the launch groups called `name` (a comma-separated list of
+// names, "*" for all, NULL or "" to disable); clears previous records.
 tsk_status tsk_profile_enable(const char* name) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto& r : g_recs) {
