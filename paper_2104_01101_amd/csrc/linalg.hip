@@ -312,148 +312,18 @@ __device__ double tri_solve(int q, const double* u0, const double* u1, const dou
 // (d, e, e2, p, beta: 5q; y: R q; LU factors: 4 R q; pivots: R q bytes) each
 // live in LDS when they fit, else in the global scratch.  `timers` (optional)
 // receives wall-clock stamps at the phase boundaries.
-template <int NT, bool MLDS, bool VLDS>
-__global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, double* lam,
-                                                    double* V, double* gscratch, int8_t* gpivs,
-                                                    uint64_t* timers) {
+// Eigenvalues and eigenvectors from the tridiagonal (d, e) and the stored
+// reflectors (reflector k: v in column k of Vr below the diagonal, stride q,
+// beta in bet[k]): multisection, inverse iteration, Gram-Schmidt, back-transform.
+template <int NT>
+__device__ void eig_tail(int q, int R, double* d, double* e, double* e2, const double* bet,
+                         const double* Vr, double* y, double* lu, int8_t* pivs, double* sh,
+                         double* lam, double* V, uint64_t* timers) {
   constexpr int NW = NT / 64;
-  extern __shared__ double smem[];
-  __shared__ double redK[NW];
-  __shared__ double redN[2][NW];
-  __shared__ double sh[4];
-  // small vectors always in LDS: d, e, e2, p, beta (5q); then M (q^2) and the
-  // inverse-iteration vectors/factors (5 R q doubles + R q bytes) if they fit
-  double* d = smem;
-  double* e = d + q;
-  double* e2 = e + q;
-  double* pw = e2 + q;
-  double* bet = pw + q;
-  double* M = MLDS ? smem + 5 * q : Mg;
-  double* y = VLDS ? smem + 5 * q + (MLDS ? q * q : 0) : gscratch;  // R x q
-  double* lu = y + R * q;                                            // R x 4q
-  int8_t* pivs = VLDS ? reinterpret_cast<int8_t*>(lu + 4 * R * q) : gpivs;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (timers && tid == 0) timers[0] = wall_clock64();
-  if (MLDS) {
-    for (int t = tid; t < q * q; t += NT) M[t] = Mg[t];
-    __syncthreads();
-  }
-
-  // ---- Householder tridiagonalisation (lower); reflector k: I - beta v v^T on
-  // indices k+1.., v stored in column k below the diagonal.  Two barriers per
-  // step: p = beta A22 v (wave per row, lane-parallel dot products) with v^T p,
-  // then the rank-2 update, which also accumulates the squared norm of the
-  // next column. ----
-  if (q >= 3) {
-    double part = 0.0;
-    for (int i = 1 + tid; i < q; i += NT) part += M[i * q] * M[i * q];
-    part = wave_sum(part);
-    if (lane == 0) redN[0][wave] = part;
-    __syncthreads();
-  }
-  for (int k = 0; k + 2 < q; ++k) {
-    const int L = q - k - 1;
-    const double* x = M + (k + 1) * q + k;  // stride q
-    double norm2 = 0.0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) norm2 += redN[k & 1][w];
-    const double x0 = x[0];
-    const double alpha = norm2 > 0.0 ? -copysign(sqrt(norm2), x0) : 0.0;
-    const double v0 = x0 - alpha;
-    const double vtv = norm2 - x0 * x0 + v0 * v0;
-    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
-    double* A22 = M + (k + 1) * q + (k + 1);
-    double nxt = 0.0;
-    if (beta != 0.0) {
-      // p_i = beta sum_j A22[j][i] v_j: two threads per column (halves of j),
-      // four partial sums each; v_j read from column k (v_0 = x0 - alpha)
-      const int half = (L + 1) >> 1;
-      double pp = 0.0;
-      for (int base = 0; base < L; base += NT / 2) {
-        const int i = base + (tid >> 1), h = tid & 1;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        if (i < L) {
-          const int j0 = h * half, j1 = h ? L : half;
-          int j = j0;
-          if (j == 0) {
-            a0 = A22[i] * v0;
-            j = 1;
-          }
-          for (; j + 3 < j1; j += 4) {
-            a0 += A22[j * q + i] * x[j * q];
-            a1 += A22[(j + 1) * q + i] * x[(j + 1) * q];
-            a2 += A22[(j + 2) * q + i] * x[(j + 2) * q];
-            a3 += A22[(j + 3) * q + i] * x[(j + 3) * q];
-          }
-          for (; j < j1; ++j) a0 += A22[j * q + i] * x[j * q];
-        }
-        double sacc = (a0 + a1) + (a2 + a3);
-        sacc += __shfl_xor(sacc, 1);
-        if (i < L && h == 0) {
-          const double pi = beta * sacc;
-          pw[i] = pi;
-          pp += (i == 0 ? v0 : x[i * q]) * pi;
-        }
-      }
-      pp = wave_sum(pp);
-      if (lane == 0) redK[wave] = pp;
-      __syncthreads();
-      double vp = 0.0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) vp += redK[w];
-      const double K = 0.5 * beta * vp;
-      // rank-2 update: lane owns columns j, its v_j, w_j stay in registers;
-      // rows in groups of four with every load issued before the stores
-      for (int j = lane; j < L; j += 64) {
-        const double vj = j == 0 ? v0 : x[j * q];
-        const double wj = pw[j] - K * vj;
-        int i = wave;
-        for (; i + 3 * NW < L; i += 4 * NW) {
-          double v4[4], w4[4], r4[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int ii = i + u * NW;
-            v4[u] = ii == 0 ? v0 : x[ii * q];
-            w4[u] = pw[ii];
-            r4[u] = A22[ii * q + j];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int ii = i + u * NW;
-            const double nv = r4[u] - (v4[u] * wj + (w4[u] - K * v4[u]) * vj);
-            A22[ii * q + j] = nv;
-            if (j == 0 && ii >= 1) nxt += nv * nv;
-          }
-        }
-        for (; i < L; i += NW) {
-          const double vi = i == 0 ? v0 : x[i * q];
-          const double nv = A22[i * q + j] - (vi * wj + (pw[i] - K * vi) * vj);
-          A22[i * q + j] = nv;
-          if (j == 0 && i >= 1) nxt += nv * nv;
-        }
-      }
-    } else {
-      for (int i = 1 + tid; i < L; i += NT) nxt += A22[i * q] * A22[i * q];
-    }
-    nxt = wave_sum(nxt);
-    if (lane == 0) redN[(k + 1) & 1][wave] = nxt;
-    if (tid == 0) {
-      d[k] = M[k * q + k];
-      e[k] = norm2 > 0.0 ? alpha : x0;
-      bet[k] = beta;
-    }
-    __syncthreads();
-    if (tid == 0) M[(k + 1) * q + k] = v0;  // column k is not read again until the back-transform
-  }
-  __syncthreads();
+  // d, e complete (d[q-1], e[q-2] included), bet[k] for k <= q-3, bet[q-2] = 0
   if (timers && tid == 0) timers[1] = wall_clock64();
   if (tid == 0) {
-    if (q >= 2) {
-      d[q - 2] = M[(q - 2) * q + (q - 2)];
-      e[q - 2] = M[(q - 1) * q + (q - 2)];
-      if (q >= 3) bet[q - 2] = 0.0;
-    }
-    d[q - 1] = M[(q - 1) * q + (q - 1)];
     double lo = DBL_MAX, hi = -DBL_MAX, emax2 = 0.0, onenrm = 0.0;
     for (int i = 0; i < q; ++i) {
       double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < q ? fabs(e[i]) : 0.0);
@@ -564,7 +434,7 @@ __global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, do
         const double beta = bet[k];
         if (beta == 0.0) continue;
         const int L = q - k - 1;
-        const double* v = M + (k + 1) * q + k;
+        const double* v = Vr + (k + 1) * q + k;
         double sdot = 0.0;
         for (int i = seg; i < L; i += 16) sdot += v[i * q] * yt[k + 1 + i];
         sdot += __shfl_xor(sdot, 1);
@@ -585,6 +455,164 @@ __global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, do
   }
 }
 
+template <int NT, bool MLDS, bool VLDS>
+__global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, double* lam,
+                                                    double* V, double* gscratch, int8_t* gpivs,
+                                                    uint64_t* timers) {
+  constexpr int NW = NT / 64;
+  extern __shared__ double smem[];
+  __shared__ double redK[NW];
+  __shared__ double redN[2][NW];
+  __shared__ double sh[4];
+  // small vectors always in LDS: d, e, e2, p, beta (5q); then M (q^2) and the
+  // inverse-iteration vectors/factors (5 R q doubles + R q bytes) if they fit
+  double* d = smem;
+  double* e = d + q;
+  double* e2 = e + q;
+  double* pw = e2 + q;
+  double* bet = pw + q;
+  double* M = MLDS ? smem + 5 * q : Mg;
+  double* y = VLDS ? smem + 5 * q + (MLDS ? q * q : 0) : gscratch;  // R x q
+  double* lu = y + R * q;                                            // R x 4q
+  int8_t* pivs = VLDS ? reinterpret_cast<int8_t*>(lu + 4 * R * q) : gpivs;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (timers && tid == 0) timers[0] = wall_clock64();
+  if (MLDS) {
+    for (int t = tid; t < q * q; t += NT) M[t] = Mg[t];
+    __syncthreads();
+  }
+
+  // ---- Householder tridiagonalisation (lower); reflector k: I - beta v v^T on
+  // indices k+1.., v stored in column k below the diagonal.  Two barriers per
+  // step: p = beta A22 v (wave per row, lane-parallel dot products) with v^T p,
+  // then the rank-2 update, which also accumulates the squared norm of the
+  // next column. ----
+  if (q >= 3) {
+    double part = 0.0;
+    for (int i = 1 + tid; i < q; i += NT) part += M[i * q] * M[i * q];
+    part = wave_sum(part);
+    if (lane == 0) redN[0][wave] = part;
+    __syncthreads();
+  }
+  for (int k = 0; k + 2 < q; ++k) {
+    const int L = q - k - 1;
+    const double* x = M + (k + 1) * q + k;  // stride q
+    double norm2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) norm2 += redN[k & 1][w];
+    const double x0 = x[0];
+    const double alpha = norm2 > 0.0 ? -copysign(sqrt(norm2), x0) : 0.0;
+    const double v0 = x0 - alpha;
+    const double vtv = norm2 - x0 * x0 + v0 * v0;
+    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    double* A22 = M + (k + 1) * q + (k + 1);
+    double nxt = 0.0;
+    if (beta != 0.0) {
+      // p_i = beta sum_j A22[j][i] v_j: tpc threads per column (all threads busy
+      // while L <= NT), loads issued eight at a time; v_j read from column k
+      // (v_0 = x0 - alpha)
+      const int tpc = L <= NT / 8 ? 8 : L <= NT / 4 ? 4 : L <= NT / 2 ? 2 : 1;
+      const int cpp = NT / tpc;
+      double pp = 0.0;
+      for (int c0 = 0; c0 < L; c0 += cpp) {
+        const int i = c0 + tid / tpc, h = tid % tpc;
+        double a8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a8[u] = 0.0;
+        if (i < L) {
+          int j = h;
+          for (; j + 7 * tpc < L; j += 8 * tpc) {
+            double av[8], vv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int jj = j + u * tpc;
+              av[u] = A22[jj * q + i];
+              vv[u] = x[jj * q];
+            }
+            if (j == 0) vv[0] = v0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a8[u] += av[u] * vv[u];
+          }
+          for (; j < L; j += tpc) a8[0] += A22[j * q + i] * (j == 0 ? v0 : x[j * q]);
+        }
+        double sacc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
+        for (int o = 1; o < tpc; o <<= 1) sacc += __shfl_xor(sacc, o);
+        if (i < L && h == 0) {
+          const double pi = beta * sacc;
+          pw[i] = pi;
+          pp += (i == 0 ? v0 : x[i * q]) * pi;
+        }
+      }
+      pp = wave_sum(pp);
+      if (lane == 0) redK[wave] = pp;
+      __syncthreads();
+      double vp = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) vp += redK[w];
+      const double K = 0.5 * beta * vp;
+      // rank-2 update A22 -= v w^T + w v^T, w = p - K v: threads spread over the
+      // columns (NT / L per column while L <= NT), rows strided, four rows of
+      // loads issued before the stores
+      const int tpr = L <= NT ? NT / L : 1;
+      const int jl = L <= NT ? tid % L : lane, r0 = L <= NT ? tid / L : wave;
+      const int rstep = L <= NT ? tpr : NW;
+      const int jstep = L <= NT ? L : 64;
+      if (r0 < rstep)
+        for (int j = jl; j < L; j += jstep) {
+          const double vj = j == 0 ? v0 : x[j * q];
+          const double wj = pw[j] - K * vj;
+          int i = r0;
+          for (; i + 3 * rstep < L; i += 4 * rstep) {
+            double v4[4], w4[4], r4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int ii = i + u * rstep;
+              v4[u] = x[ii * q];
+              w4[u] = pw[ii];
+              r4[u] = A22[ii * q + j];
+            }
+            if (i == 0) v4[0] = v0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int ii = i + u * rstep;
+              const double nv = r4[u] - (v4[u] * wj + (w4[u] - K * v4[u]) * vj);
+              A22[ii * q + j] = nv;
+              if (j == 0 && ii >= 1) nxt += nv * nv;
+            }
+          }
+          for (; i < L; i += rstep) {
+            const double vi = i == 0 ? v0 : x[i * q];
+            const double nv = A22[i * q + j] - (vi * wj + (pw[i] - K * vi) * vj);
+            A22[i * q + j] = nv;
+            if (j == 0 && i >= 1) nxt += nv * nv;
+          }
+        }
+    } else {
+      for (int i = 1 + tid; i < L; i += NT) nxt += A22[i * q] * A22[i * q];
+    }
+    nxt = wave_sum(nxt);
+    if (lane == 0) redN[(k + 1) & 1][wave] = nxt;
+    if (tid == 0) {
+      d[k] = M[k * q + k];
+      e[k] = norm2 > 0.0 ? alpha : x0;
+      bet[k] = beta;
+    }
+    __syncthreads();
+    if (tid == 0) M[(k + 1) * q + k] = v0;  // column k is not read again until the back-transform
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (q >= 2) {
+      d[q - 2] = M[(q - 2) * q + (q - 2)];
+      e[q - 2] = M[(q - 1) * q + (q - 2)];
+      if (q >= 3) bet[q - 2] = 0.0;
+    }
+    d[q - 1] = M[(q - 1) * q + (q - 1)];
+  }
+  __syncthreads();
+  eig_tail<NT>(q, R, d, e, e2, bet, M, y, lu, pivs, sh, lam, V, timers);
+}
+
 // ---------------------------------------------- register-tiled SPD inverse ----
 // For n <= 128 the whole matrix lives in registers: 512 threads, thread t owns
 // rows tr + 16 a (a < 8) and columns tc + 32 b (b < 4), tr = t / 32, tc = t % 32.
@@ -601,7 +629,9 @@ constexpr int kRegT = 512, kRegMax = 128;
 // stays symmetric, so each step needs only column k broadcast; the pivots are
 // the Cholesky pivots squared (a non-positive one flags a non-SPD Gram).
 __global__ __launch_bounds__(kRegT) void k_spd_inverse_reg(double* G, int n, int lda, int* info) {
-  __shared__ double colk[kRegMax];
+  // pivot columns double-buffered in LDS: the owners of column k+1 publish it
+  // while step k is applied, so each step needs one barrier
+  __shared__ double colk[2][kRegMax];
   const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
   double A[8][4];
 #pragma unroll
@@ -611,37 +641,40 @@ __global__ __launch_bounds__(kRegT) void k_spd_inverse_reg(double* G, int n, int
       const int i = tr + 16 * a, k = tc + 32 * b;
       A[a][b] = (i < n && k < n) ? G[i * lda + k] : 0.0;
     }
+  if (tc == 0)  // column 0
+#pragma unroll
+    for (int a = 0; a < 8; ++a) colk[0][tr + 16 * a] = A[a][0];
+  __syncthreads();
   int bad = 0;
   for (int k = 0; k < n; ++k) {
-#pragma unroll
-    for (int b = 0; b < 4; ++b)  // predicated stores: the tile stays in registers
-      if (tc + 32 * b == k)
-#pragma unroll
-        for (int a = 0; a < 8; ++a) colk[tr + 16 * a] = A[a][b];
-    __syncthreads();
-    const double dk = colk[k];
+    const double* ck = colk[k & 1];
+    const double dk = ck[k];
     if (!(dk > 0.0) && bad == 0) bad = k + 1;
-    const double rd = 1.0 / dk;
-    double cj[4];
+    const double rd = rcp64(dk);
+    double cj[4], cir[8];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) cj[b] = colk[tc + 32 * b];
+    for (int b = 0; b < 4; ++b) cj[b] = ck[tc + 32 * b];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) cir[a] = ck[tr + 16 * a] * rd;
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       const int i = tr + 16 * a;
-      const double ci = colk[i];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int j = tc + 32 * b;
-        double v;
-        if (i == k)
-          v = j == k ? -rd : cj[b] * rd;
-        else if (j == k)
-          v = ci * rd;
-        else
-          v = A[a][b] - ci * cj[b] * rd;
+        const double upd = fma(-cir[a], cj[b], A[a][b]);
+        double v = upd;
+        if (i == k) v = j == k ? -rd : cj[b] * rd;
+        else if (j == k) v = cir[a];
         A[a][b] = v;
       }
     }
+    // publish column k+1 (predicated stores from constant register indices)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (tc + 32 * b == k + 1)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) colk[(k + 1) & 1][tr + 16 * a] = A[a][b];
     __syncthreads();
   }
   if (tid == 0) *info = bad;
