@@ -164,6 +164,63 @@ __global__ __launch_bounds__(kT) void k_inner3(FitArgs a, int64_t nnz, int64_t p
   if (threadIdx.x == 0) partial[blockIdx.x] = acc, partial_direct[blockIdx.x] = acc2;
 }
 
+// Same, all three ranks equal to RR at compile time: the contraction unrolls
+// completely (no loop exits inside), so the y sums run as independent chains.
+template <int RR>
+__global__ __launch_bounds__(kT) void k_inner3x(FitArgs a, int64_t nnz, int64_t per_block,
+                                                const double* core, int core_lds,
+                                                double* partial, double* partial_direct) {
+  extern __shared__ double cs_lds[];
+  __shared__ double red[kT / 64];
+  const double* cs = core;
+  if (core_lds) {
+    for (int t = threadIdx.x; t < RR * RR * RR; t += kT) cs_lds[t] = core[t];
+    __syncthreads();
+    cs = cs_lds;
+  }
+  int64_t lo = int64_t(blockIdx.x) * per_block, hi = lo + per_block < nnz ? lo + per_block : nnz;
+  double acc = 0.0, acc2 = 0.0;
+  for (int64_t e = lo + threadIdx.x; e < hi; e += kT) {
+    int64_t i0, i1, i2;
+    if (a.layout == TSK_COO) {
+      i0 = a.idx[0][e], i1 = a.idx[1][e], i2 = a.idx[2][e];
+    } else {
+      i2 = e % a.dims[2];
+      int64_t r = e / a.dims[2];
+      i1 = r % a.dims[1];
+      i0 = r / a.dims[1];
+    }
+    double u2[RR], u1[RR], u0[RR];
+#pragma unroll
+    for (int c = 0; c < RR; ++c) {
+      u2[c] = a.A[2][i2 * RR + c];
+      u1[c] = a.A[1][i1 * RR + c];
+      u0[c] = a.A[0][i0 * RR + c];
+    }
+    double tv = 0.0;
+    for (int x = 0; x < RR; ++x) {
+      const double* cx = cs + x * RR * RR;
+      double wx = 0.0;
+#pragma unroll
+      for (int y = 0; y < RR; ++y) {
+        double sy = 0.0;
+#pragma unroll
+        for (int z = 0; z < RR; ++z) sy += cx[y * RR + z] * u2[z];
+        wx += sy * u1[y];
+      }
+      tv += wx * u0[x];
+    }
+    double v = a.dtype == TSK_F64 ? static_cast<const double*>(a.vals)[e]
+                                  : double(static_cast<const float*>(a.vals)[e]);
+    acc += v * tv;
+    acc2 += (v - tv) * (v - tv);
+  }
+  acc = block_reduce(acc, red);
+  __syncthreads();
+  acc2 = block_reduce(acc2, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc, partial_direct[blockIdx.x] = acc2;
+}
+
 // ||T~||^2 = <C x_k G_k, C>, single block; buf0/buf1 scratch of csize
 __global__ __launch_bounds__(kT) void k_model_norm2(FitArgs a, const double* core, int64_t csize,
                                                    const double* grams, double* buf0,
@@ -194,23 +251,34 @@ __global__ __launch_bounds__(kT) void k_model_norm2(FitArgs a, const double* cor
   if (threadIdx.x == 0) *out = s;
 }
 
-__global__ void k_finish(const double* pn, int nbn, const double* pi, int nbi,
-                         const double* pd, int dense, const double* model2, double* nT2_out,
-                         double* res_out) {
-  if (threadIdx.x != 0) return;
-  double nT2 = 0.0, inner = 0.0;
+// fixed-order sum of n partials by one block: contiguous strides per thread,
+// then the block reduction (deterministic)
+__device__ double block_sum_of(const double* p, int n, double* red) {
+  const int per = (n + kT - 1) / kT;
+  const int b0 = threadIdx.x * per, b1 = b0 + per < n ? b0 + per : n;
+  double s = 0.0;
+  for (int b = b0; b < b1; ++b) s += p[b];
+  s = block_reduce(s, red);
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(kT) void k_finish(const double* pn, int nbn, const double* pi, int nbi,
+                                               const double* pd, int dense, const double* model2,
+                                               double* nT2_out, double* res_out) {
+  __shared__ double red[kT / 64];
+  double nT2 = 0.0;
   if (pn) {
-    for (int b = 0; b < nbn; ++b) nT2 += pn[b];
-    *nT2_out = nT2;
+    nT2 = block_sum_of(pn, nbn, red);
   } else {
     nT2 = *nT2_out;
   }
-  for (int b = 0; b < nbi; ++b) inner += pi[b];
+  const double inner = block_sum_of(pi, nbi, red);
+  const double direct = dense ? block_sum_of(pd, nbi, red) : 0.0;
+  if (threadIdx.x != 0) return;
+  if (pn) *nT2_out = nT2;
   double r2 = nT2 - 2.0 * inner + *model2;
-  if (dense) {  // every entry stored: sum of squared differences, no cancellation
-    r2 = 0.0;
-    for (int b = 0; b < nbi; ++b) r2 += pd[b];
-  }
+  if (dense) r2 = direct;  // every entry stored: sum of squared differences, no cancellation
   *res_out = sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(nT2);
 }
 
@@ -268,7 +336,20 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
   if (T.order == 3 && rmax <= 32) {
     const int core_lds = csize * 8 <= 150000 ? 1 : 0;
     const size_t lds = core_lds ? size_t(csize) * 8 : 0;
-    if (rmax <= 8)
+    const bool eq = R[0] == R[1] && R[1] == R[2];
+    if (eq && R[0] == 5)
+      hipLaunchKernelGGL(k_inner3x<5>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
+                         core_lds, fs.partial_inner, fs.partial_direct);
+    else if (eq && R[0] == 8)
+      hipLaunchKernelGGL(k_inner3x<8>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
+                         core_lds, fs.partial_inner, fs.partial_direct);
+    else if (eq && R[0] == 10)
+      hipLaunchKernelGGL(k_inner3x<10>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
+                         core_lds, fs.partial_inner, fs.partial_direct);
+    else if (eq && R[0] == 16)
+      hipLaunchKernelGGL(k_inner3x<16>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
+                         core_lds, fs.partial_inner, fs.partial_direct);
+    else if (rmax <= 8)
       hipLaunchKernelGGL(k_inner3<8>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
                          core_lds, fs.partial_inner, fs.partial_direct);
     else if (rmax <= 16)
@@ -286,7 +367,7 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
   hipLaunchKernelGGL(k_model_norm2, dim3(1), dim3(kT), 0, st, a, core, csize, fs.grams, fs.buf0,
                      fs.buf1, fs.model2);
   TSK_LAUNCHED();
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, with_norm ? fs.partial_norm : nullptr,
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kT), 0, st, with_norm ? fs.partial_norm : nullptr,
                      fs.nblocks, fs.partial_inner, fs.nblocks, fs.partial_direct,
                      T.layout == TSK_DENSE ? 1 : 0, fs.model2, fs.nT2, res);
   TSK_LAUNCHED();

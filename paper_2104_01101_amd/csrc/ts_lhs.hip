@@ -16,7 +16,7 @@ namespace tsk {
 
 namespace {
 
-constexpr int kFftBlock = 256;
+constexpr int kFftBlock = 512;
 constexpr int kMaxRadices = 48;
 
 struct Radices {
@@ -47,6 +47,39 @@ __device__ inline double2 rot(double2 a, bool inv) {
   return inv ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
 }
 
+// One radix-RR butterfly of a Stockham stage (RR known at compile time, so the
+// operands stay in registers).
+template <int RR>
+__device__ inline void butterfly(const double2* a, double2* b, int j, int k, int nb, int Ns,
+                                 int idxD, int tstep, int wstep, const double2* tw, bool inv) {
+  double2 v[RR];
+#pragma unroll
+  for (int r = 0; r < RR; ++r) {
+    const double2 x = a[j + r * nb];
+    v[r] = r == 0 ? x : cmul(x, conj_if(tw[r * k * tstep], inv));
+  }
+  if (RR == 2) {
+    b[idxD] = cadd(v[0], v[1]);
+    b[idxD + Ns] = csub(v[0], v[1]);
+  } else if (RR == 4) {
+    const double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    const double2 s13 = cadd(v[1], v[3]), d13 = rot(csub(v[1], v[3]), inv);
+    b[idxD] = cadd(s02, s13);
+    b[idxD + Ns] = cadd(d02, d13);
+    b[idxD + 2 * Ns] = csub(s02, s13);
+    b[idxD + 3 * Ns] = csub(d02, d13);
+  } else {
+#pragma unroll
+    for (int o = 0; o < RR; ++o) {
+      double2 acc = v[0];
+#pragma unroll
+      for (int r = 1; r < RR; ++r)
+        acc = cadd(acc, cmul(v[r], conj_if(tw[((o * r) % RR) * wstep], inv)));
+      b[idxD + o * Ns] = acc;
+    }
+  }
+}
+
 // In-place-by-ping-pong FFT of a[0..m) in LDS (b is scratch of the same size).
 // Returns the buffer holding the result.  tw[t] = exp(-2 pi i t / m).
 __device__ double2* fft_lds(double2* a, double2* b, int m, const Radices& rd, const double2* tw,
@@ -60,33 +93,15 @@ __device__ double2* fft_lds(double2* a, double2* b, int m, const Radices& rd, co
     for (int j = threadIdx.x; j < nb; j += blockDim.x) {
       const int k = j % Ns;
       const int idxD = (j / Ns) * Ns * R + k;
-      if (R <= 5) {
-        double2 v[5];
-#pragma unroll
-        for (int r = 0; r < 5; ++r) {
-          if (r >= R) break;
-          double2 x = a[j + r * nb];
-          v[r] = r == 0 ? x : cmul(x, conj_if(tw[r * k * tstep], inv));
-        }
-        if (R == 2) {
-          b[idxD] = cadd(v[0], v[1]);
-          b[idxD + Ns] = csub(v[0], v[1]);
-        } else if (R == 4) {
-          double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
-          double2 s13 = cadd(v[1], v[3]), d13 = rot(csub(v[1], v[3]), inv);
-          b[idxD] = cadd(s02, s13);
-          b[idxD + Ns] = cadd(d02, d13);
-          b[idxD + 2 * Ns] = csub(s02, s13);
-          b[idxD + 3 * Ns] = csub(d02, d13);
-        } else {
-          for (int o = 0; o < R; ++o) {
-            double2 acc = v[0];
-            for (int r = 1; r < R; ++r)
-              acc = cadd(acc, cmul(v[r], conj_if(tw[((o * r) % R) * wstep], inv)));
-            b[idxD + o * Ns] = acc;
-          }
-        }
-      } else {  // prime radix > 5: direct DFT from LDS
+      if (R == 4)
+        butterfly<4>(a, b, j, k, nb, Ns, idxD, tstep, wstep, tw, inv);
+      else if (R == 2)
+        butterfly<2>(a, b, j, k, nb, Ns, idxD, tstep, wstep, tw, inv);
+      else if (R == 3)
+        butterfly<3>(a, b, j, k, nb, Ns, idxD, tstep, wstep, tw, inv);
+      else if (R == 5)
+        butterfly<5>(a, b, j, k, nb, Ns, idxD, tstep, wstep, tw, inv);
+      else  // prime radix > 5: direct DFT from LDS
         for (int o = 0; o < R; ++o) {
           double2 acc = make_double2(0.0, 0.0);
           for (int r = 0; r < R; ++r) {
@@ -96,7 +111,6 @@ __device__ double2* fft_lds(double2* a, double2* b, int m, const Radices& rd, co
           }
           b[idxD + o * Ns] = acc;
         }
-      }
     }
     __syncthreads();
     double2* t = a;
@@ -192,10 +206,22 @@ struct SpecJob {
   const double* CS[TSK_MAX_ORDER];
 };
 
-__global__ void k_spectra(SpecJob sj, int64_t m, Radices rd, const double2* tw, double2* spec) {
+// TWL: the twiddle table is staged in LDS after the two work buffers
+template <bool TWL>
+__device__ inline const double2* stage_twiddles(double2* buf, int64_t m, const double2* tw) {
+  if (!TWL) return tw;
+  double2* t = buf + 2 * m;
+  for (int64_t f = threadIdx.x; f < m; f += blockDim.x) t[f] = tw[f];
+  return t;  // visible after the caller's next barrier
+}
+
+template <bool TWL>
+__global__ __launch_bounds__(kFftBlock) void k_spectra(SpecJob sj, int64_t m, Radices rd,
+                                                       const double2* twg, double2* spec) {
   extern __shared__ double2 buf[];
   double2* a = buf;
   double2* b = buf + m;
+  const double2* tw = stage_twiddles<TWL>(buf, m, twg);
   int col = blockIdx.x;
   int q = 0;
   while (q + 1 < sj.nmodes && col >= sj.coloff[q + 1]) ++q;
@@ -210,11 +236,14 @@ __global__ void k_spectra(SpecJob sj, int64_t m, Radices rd, const double2* tw, 
 }
 
 // ---- Hadamard product of spectra and inverse FFT of two columns at once ----
-__global__ void k_compose(SpecJob sj, int64_t m, int64_t r, Radices rd, const double2* tw,
-                          const double2* spec, int prec, void* Z) {
+template <bool TWL>
+__global__ __launch_bounds__(kFftBlock) void k_compose(SpecJob sj, int64_t m, int64_t r,
+                                                       Radices rd, const double2* twg,
+                                                       const double2* spec, int prec, void* Z) {
   extern __shared__ double2 buf[];
   double2* a = buf;
   double2* b = buf + m;
+  const double2* tw = stage_twiddles<TWL>(buf, m, twg);
   int64_t ra = 2 * int64_t(blockIdx.x), rb = ra + 1;
   bool has_b = rb < r;
   // column indices of each mode for rho_a, rho_b (row-major over modes)
@@ -299,6 +328,30 @@ tsk_status build_inverse_hash(const int32_t* h, int64_t s, int64_t m, CsrTable c
   return TSK_OK;
 }
 
+static int fft_max_lds() {
+  static int v = -1;
+  if (v < 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 65536;
+  }
+  return v;
+}
+
+static bool twiddles_fit(int64_t m) { return int64_t(3) * m * 16 <= fft_max_lds(); }
+
+static void launch_spectra(int64_t cols, int64_t m, const Radices& rd, const SpecJob& sj, const double* tw,
+                    double* spec, hipStream_t st) {
+  if (twiddles_fit(m))
+    hipLaunchKernelGGL(k_spectra<true>, dim3(cols), dim3(kFftBlock), size_t(3 * m * 16), st, sj, m,
+                       rd, reinterpret_cast<const double2*>(tw), reinterpret_cast<double2*>(spec));
+  else
+    hipLaunchKernelGGL(k_spectra<false>, dim3(cols), dim3(kFftBlock), size_t(2 * m * 16), st, sj,
+                       m, rd, reinterpret_cast<const double2*>(tw),
+                       reinterpret_cast<double2*>(spec));
+}
+
 static tsk_status check_fft_lds(int64_t m) {
   static int max_lds = -1;
   if (max_lds < 0) {
@@ -339,8 +392,7 @@ tsk_status ts_lhs_spectra(const LhsMode* modes, int nmodes, int64_t m, double* C
                        md.csr.ptr, md.csr.items, m, const_cast<double*>(sj.CS[q]));
     TSK_LAUNCHED();
   }
-  hipLaunchKernelGGL(k_spectra, dim3(off), dim3(kFftBlock), size_t(2 * m * 16), st, sj, m, rd,
-                     reinterpret_cast<const double2*>(tw), reinterpret_cast<double2*>(spec));
+  launch_spectra(off, m, rd, sj, tw, spec, st);
   TSK_LAUNCHED();
   return TSK_OK;
 }
@@ -358,9 +410,14 @@ tsk_status ts_compose(const LhsMode* modes, int nmodes, int64_t m, const double*
     sj.coloff[q] = off;
     off += modes[q].R;
   }
-  hipLaunchKernelGGL(k_compose, dim3(ceil_div(r, 2)), dim3(kFftBlock), size_t(2 * m * 16), st,
-                     sj, m, r, rd, reinterpret_cast<const double2*>(tw),
-                     reinterpret_cast<const double2*>(spec), prec, Z);
+  if (twiddles_fit(m))
+    hipLaunchKernelGGL(k_compose<true>, dim3(ceil_div(r, 2)), dim3(kFftBlock),
+                       size_t(3 * m * 16), st, sj, m, r, rd, reinterpret_cast<const double2*>(tw),
+                       reinterpret_cast<const double2*>(spec), prec, Z);
+  else
+    hipLaunchKernelGGL(k_compose<false>, dim3(ceil_div(r, 2)), dim3(kFftBlock),
+                       size_t(2 * m * 16), st, sj, m, r, rd, reinterpret_cast<const double2*>(tw),
+                       reinterpret_cast<const double2*>(spec), prec, Z);
   TSK_LAUNCHED();
   return TSK_OK;
 }
@@ -388,8 +445,7 @@ tsk_status fft_columns(const double* X, int64_t m, int64_t cols, const double* t
   sj.R[0] = cols;
   sj.coloff[0] = 0;
   sj.CS[0] = X;
-  hipLaunchKernelGGL(k_spectra, dim3(cols), dim3(kFftBlock), size_t(2 * m * 16), st, sj, m, rd,
-                     reinterpret_cast<const double2*>(tw), reinterpret_cast<double2*>(spec));
+  launch_spectra(cols, m, rd, sj, tw, spec, st);
   TSK_LAUNCHED();
   return TSK_OK;
 }
