@@ -657,18 +657,26 @@ __global__ __launch_bounds__(kRegT) void k_spd_inverse_reg(double* G, int n, int
 #pragma unroll
     for (int a = 0; a < 8; ++a) cir[a] = ck[tr + 16 * a] * rd;
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int i = tr + 16 * a;
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int j = tc + 32 * b;
-        const double upd = fma(-cir[a], cj[b], A[a][b]);
-        double v = upd;
-        if (i == k) v = j == k ? -rd : cj[b] * rd;
-        else if (j == k) v = cir[a];
-        A[a][b] = v;
+      for (int b = 0; b < 4; ++b) A[a][b] = fma(-cir[a], cj[b], A[a][b]);
+    // pivot row and column: the register slot is a compile-time index, the
+    // test on it is wave-uniform, so only the owning lanes do any extra work
+    const int ka = k >> 4, kt = k & 15, kb = k >> 5, kc = k & 31;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (a == ka && tr == kt)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) A[a][b] = cj[b] * rd;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (b == kb && tc == kc) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) A[a][b] = cir[a];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+          if (a == ka && tr == kt) A[a][b] = -rd;
       }
-    }
     // publish column k+1 (predicated stores from constant register indices)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
