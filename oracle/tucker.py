@@ -119,9 +119,21 @@ def default_rrf_sizes(m, ranks, n):
 # ----------------------------------------------------------------------------
 # Sketch-Tucker-ALS (Alg. 4)
 # ----------------------------------------------------------------------------
+def rsvd_width(R, r, p=10):
+    """Columns of the Gaussian test matrix of RSVD-LRLS: O(R) read as R + p
+    (oversampling p = 10), at most r (the rank of Z^+ Y is at most r)."""
+    return min(R + p, r)
+
+
+def rsvd_omega(seed, sweep, n, s, k):
+    """Gaussian test matrix of subproblem (sweep, n): s x k, row-major draws of
+    the stream (seed, RSVD, sweep, n)."""
+    return rng.gauss(rng.stream_key(seed, rng.P_RSVD, sweep, n), np.arange(s * k)).reshape(s, k)
+
+
 def sketch_tucker_als(T, ranks, m, sweeps, seed=0, sketch_kind="ts", init="rrf",
                       rrf_k1=0, rrf_k2=0, init_factors=None, record_fit=True,
-                      identity_sketch=False):
+                      identity_sketch=False, solve_kind="exact", rsvd_p=10):
     """Sketched Tucker-ALS, Alg. 4.
 
     T        oracle.sketch.Tensor (COO or dense)
@@ -131,6 +143,9 @@ def sketch_tucker_als(T, ranks, m, sweeps, seed=0, sketch_kind="ts", init="rrf",
     init     "rrf" (Alg. 3 for n = 2..N), "random" or "user" (init_factors)
     identity_sketch  replace S^(n) by the identity (then each subproblem is
              exactly the HOOI update) -- used to pin the driver to Alg. 1.
+    solve_kind  "exact" (truncated SVD of Z^+ Y) or "rsvd" (RSVD-LRLS, Alg. 5,
+             the subproblem solver Alg. 4 calls, with a fresh Gaussian test
+             matrix of rsvd_width(R, r, rsvd_p) columns per subproblem)
 
     Returns dict(core, factors, fits, samples)."""
     N = T.order
@@ -173,7 +188,12 @@ def sketch_tucker_als(T, ranks, m, sweeps, seed=0, sketch_kind="ts", init="rrf",
                 Z = sketch.leverage_lhs(factors, idx, w, n)
                 Y = sketch.leverage_rhs_dense(Xd, idx, w, n) if Xd is not None \
                     else sketch.leverage_rhs_sparse(T, idx, w, n)
-            A, W, _ = solve.rc_solve(Z, Y, ranks[n])
+            if solve_kind == "rsvd":
+                r = Z.shape[1]
+                Om = rsvd_omega(seed, sweep, n, dims[n], rsvd_width(ranks[n], r, rsvd_p))
+                A, W = solve.rsvd_lrls(Z, Y, ranks[n], Om)
+            else:
+                A, W, _ = solve.rc_solve(Z, Y, ranks[n])
             factors[n] = A
             core = W_to_core(W, ranks, n)
         if record_fit:

@@ -430,3 +430,26 @@ def test_adjoint_matches_explicit_matrix_gradient():
     np.testing.assert_allclose(grads[0], g0, atol=1e-10)
     np.testing.assert_allclose(grads[2], g2, atol=1e-10)
     np.testing.assert_allclose(grads[1], 2 * E.T @ S @ P @ W, atol=1e-10)
+
+
+def test_rsvd_driver_equals_exact_when_test_matrix_spans():
+    """RSVD-LRLS (Alg. 5) with as many Gaussian columns as Z has (k = r): C = X Omega
+    spans the whole row space of X = Z^+ Y almost surely, so Q Q^T X = X and the
+    randomized solve returns the exact truncated SVD; the sweeps then coincide with
+    the exact solve.  With few columns on a noisy tensor they must differ."""
+    X = workloads.tucker_dense((12, 11, 10), (3, 3, 3), noise=0.05, seed=8)
+    T = sketch.Tensor.from_dense(X)
+    ranks, m = (3, 3, 3), 60
+    ex = tucker.sketch_tucker_als(T, ranks, m, 3, seed=4)
+    rs = tucker.sketch_tucker_als(T, ranks, m, 3, seed=4, solve_kind="rsvd", rsvd_p=100)
+    np.testing.assert_allclose(rs["fits"], ex["fits"], rtol=0, atol=1e-12)
+    lo = tucker.sketch_tucker_als(T, ranks, m, 3, seed=4, solve_kind="rsvd", rsvd_p=0)
+    assert abs(lo["fits"][-1] - ex["fits"][-1]) > 1e-9
+
+
+def test_rsvd_omega_stream():
+    """The test matrix is the (seed, RSVD, sweep, n) Gaussian stream, row-major."""
+    Om = tucker.rsvd_omega(7, 2, 1, 5, 3)
+    key = rng.stream_key(7, rng.P_RSVD, 2, 1)
+    np.testing.assert_array_equal(Om.reshape(-1), rng.gauss(key, np.arange(15)))
+    assert tucker.rsvd_width(10, 100) == 20 and tucker.rsvd_width(5, 9) == 9
