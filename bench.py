@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
                     help="c2 (default, the benchmark workload) or c4 (sketch-pass study)")
+    ap.add_argument("--solve", default="rsvd", choices=["rsvd", "exact"],
+                    help="subproblem solver: rsvd = RSVD-LRLS (Alg. 5, the solver Alg. 4 "
+                         "calls) or exact = truncated SVD of Z^+ Y")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true",
                     help="also print per-group times of the last warm-up step (stderr)")
@@ -69,7 +72,7 @@ def workload(name):
     return workloads.c2() if name == "c2" else workloads.c4()
 
 
-def group_work(w):
+def group_work(w, solve="exact"):
     """Algorithmic work of one job per launch group: name -> (bound, amount, peak, unit).
     bytes for HBM-bound groups, flops otherwise."""
     N = len(w.dims)
@@ -83,6 +86,16 @@ def group_work(w):
     subs = N * sweeps
     pk = PEAK_TFLOPS[w.prec]
     eig = lambda n: 4.0 / 3.0 * n ** 3 + 2.0 * n * n * R
+    kk = min(R + 10, r)  # RSVD-LRLS test-matrix columns
+    if solve == "rsvd":
+        # inverse, Om^T H^T, C^T, thin QR, B Q, D^T, D D^T (FP64)
+        la = r ** 3 + 2.0 * kk * r * s + 4.0 * kk * r * r + 4.0 * kk * kk * r \
+            + 2.0 * s * r * kk + 2.0 * kk * kk * s
+        q_eig = kk
+    else:
+        # Gram inverse, X = H G^-1, X X^T, A = X^T U, W = X A (FP64)
+        la = r ** 3 + 4.0 * s * r * q + 4.0 * s * r * R
+        q_eig = q
     return {
         # COO stream (N int32 indices + value) read once, every Y^(n) written once
         "sketch_pass": ("hbm", nnz * (4 * N + vb) + N * m * s * vb, HBM_PEAK_GBS, "GB/s"),
@@ -94,11 +107,9 @@ def group_work(w):
         "ts_lhs": ("hbm", subs * ((N - 1) * s * R * 8 + m * r * vb), HBM_PEAK_GBS, "GB/s"),
         # G = Z^T Z and Z^T Y
         "gram": ("mfma", subs * 2.0 * m * r * (r + s), pk, "TFLOP/s"),
-        # Gram inverse, X = H G^-1, X X^T, A = X^T U, W = X A (FP64)
-        "solve_la": ("mfma", subs * (r ** 3 + 4.0 * s * r * q + 4.0 * s * r * R),
-                     PEAK_TFLOPS["f64"], "TFLOP/s"),
+        "solve_la": ("mfma", subs * la, PEAK_TFLOPS["f64"], "TFLOP/s"),
         # tridiagonalisation + back-transformation of R vectors (FP64 vector ALU)
-        "eig": ("alu", subs * eig(q) + (N - 1) * eig(k1), FP64_VECTOR_TFLOPS, "TFLOP/s"),
+        "eig": ("alu", subs * eig(q_eig) + (N - 1) * eig(k1), FP64_VECTOR_TFLOPS, "TFLOP/s"),
         # per entry: core contraction R^3 + R^2 + R multiply-adds (FP64)
         "fit": ("alu", sweeps * nnz * 2.0 * (R ** 3 + R ** 2 + R), FP64_VECTOR_TFLOPS, "TFLOP/s"),
     }
@@ -174,7 +185,7 @@ def main():
     w = workload(args.workload)
     T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(dev), torch.from_numpy(w.val).to(dev), w.dims)
     plan = tsk.TuckerPlan(T, w.ranks, w.m, w.sweeps, sketch="ts", init="rrf", prec=w.prec,
-                          seed=0, record_fit=True)
+                          seed=0, record_fit=True, solve=args.solve)
     lib = L.lib()
     lib.tsk_profile_enable.argtypes = [ctypes.c_char_p]
     lib.tsk_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -215,7 +226,7 @@ def main():
     sp = read("sketch_pass")
     L.check(lib.tsk_profile_enable(b""))
 
-    work = group_work(w)
+    work = group_work(w, args.solve)
     out = {
         "metric": "ALS sweeps/s + sketch-pass GB/s at fixed relative residual, FP32 vs BF16/adjoint",
         "value": w.sweeps * args.steps / elapsed,
@@ -230,23 +241,24 @@ def main():
         "dtype": w.prec,
         "data": "synthetic",
         "config": {"workload": ("sparse 2000^3, 1e6 nnz uniform, Tucker rank 10 + N(0,1), "
-                                "TensorSketch m=1600, RRF init, 10 sweeps, FP32 operands")
+                                "TensorSketch m=1600, RRF init, 10 sweeps of Alg. 4, FP32 operands")
                    if args.workload == "c2" else
                    ("sparse 10000^3, 1e7 nnz Zipf(1.1), lognormal values, Tucker rank 16, "
                     "TensorSketch m=2048, RRF init, 5 sweeps, FP32 operands"),
                    "dims": list(w.dims), "nnz": int(w.val.shape[0]), "ranks": list(w.ranks),
-                   "m": w.m, "sweeps": w.sweeps, "prec": w.prec},
+                   "m": w.m, "sweeps": w.sweeps, "prec": w.prec,
+                   "solve": "RSVD-LRLS (Alg. 5)" if args.solve == "rsvd" else "exact truncated SVD"},
         "final_relative_residual": fits[-1] if fits else None,
         "roofline": roofline(dominant, work, dom[0], dom[1], args.steps, args.workload),
         "sketch_pass_roofline": roofline("sketch_pass", work, sp[0], sp[1], args.steps,
                                          args.workload),
     }
     if not args.no_cpu_baseline and args.workload == "c2":
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, args.solve)
     print(json.dumps(out))
 
 
-def cpu_baseline(w, sample_sweeps=3):
+def cpu_baseline(w, solve="exact", sample_sweeps=3):
     """FP64 oracle on the same input: preparation (maps, sketched right-hand
     sides, range finder) and `sample_sweeps` of the sweeps are timed; the job
     time is extrapolated to preparation + all sweeps."""
@@ -268,10 +280,15 @@ def cpu_baseline(w, sample_sweeps=3):
         factors[n] = otk.init_rrf(T, n, ranks[n], k1, k2, seed)
     t_prep = time.perf_counter() - t0
     t1 = time.perf_counter()
-    for _ in range(sample_sweeps):
+    for sweep in range(sample_sweeps):
         for n in range(N):
             Z = osk.ts_lhs(factors, tables[n], m, n)
-            A, W, _ = osv.rc_solve(Z, Ys[n], ranks[n])
+            if solve == "rsvd":
+                kk = otk.rsvd_width(ranks[n], Z.shape[1])
+                Om = otk.rsvd_omega(seed, sweep, n, w.dims[n], kk)
+                A, W = osv.rsvd_lrls(Z, Ys[n], ranks[n], Om)
+            else:
+                A, W, _ = osv.rc_solve(Z, Ys[n], ranks[n])
             factors[n] = A
             core = otk.W_to_core(W, ranks, n)
         otk.relative_residual(T, core, factors)

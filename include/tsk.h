@@ -45,7 +45,7 @@ extern "C" {
 #endif
 
 #define TSK_MAX_ORDER 8
-#define TSK_ABI_VERSION 1
+#define TSK_ABI_VERSION 2
 
 typedef enum {
   TSK_OK = 0,
@@ -64,6 +64,9 @@ typedef enum { TSK_INIT_RRF = 0, TSK_INIT_RANDOM = 1, TSK_INIT_USER = 2 } tsk_in
  * F64; F32; BF16 operands with FP32 accumulation.  Factorisations (Cholesky,
  * eigen-decomposition, re-orthonormalisation) are FP64 in every mode. */
 typedef enum { TSK_PREC_F64 = 0, TSK_PREC_F32 = 1, TSK_PREC_BF16 = 2 } tsk_prec;
+/* Subproblem solver: the exact best rank-R approximation of Z^+ Y (truncated
+ * SVD), or RSVD-LRLS (Alg. 5), the randomized solver that Alg. 4 calls. */
+typedef enum { TSK_SOLVE_EXACT = 0, TSK_SOLVE_RSVD = 1 } tsk_solve;
 
 #define TSK_FLAG_RECORD_FIT 1u /* evaluate the relative residual after every sweep */
 
@@ -98,6 +101,8 @@ typedef struct {
   void* workspace;
   size_t workspace_bytes;
   uint32_t flags; /* TSK_FLAG_* */
+  int32_t solve;  /* tsk_solve */
+  int32_t rsvd_k; /* RSVD-LRLS test-matrix columns, O(R) in Alg. 5; 0 = min(R_n + 10, r) */
 } tsk_options;
 
 /* ---------------------------------------------------------------------- */
@@ -226,6 +231,20 @@ tsk_status tsk_sketch_lhs_ts(int32_t order, const int64_t* dims, const int32_t* 
 tsk_status tsk_rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s,
                         int32_t R, int32_t prec, double* A, double* W, void* ws,
                         size_t* ws_bytes, void* stream);
+
+/* RSVD-LRLS (Alg. 5), the randomized low-rank least-squares solve of Alg. 4:
+ * B = (Z^T Z)^{-1}, C = B Z^T Y Omega, Q = qr(C) (thin, Householder),
+ * D = Q^T B Z^T Y, U S V^T = svd(D); A = V(:, :R) (re-orthonormalised, sign
+ * rule as above), W = Q U(:, :R) S(:R, :R) with the signs of A.  Omega is the
+ * caller's s x k Gaussian test matrix (the driver draws it from the stream
+ * (seed, 6, sweep, n), row-major).  All FP64 after the Gram products.
+ *   Z, Y   device, as tsk_rc_solve;  Omega device double s x k, R <= k <= min(r, 64)
+ *   A  device double s x R (output);  W device double r x R (output)
+ * Synchronous (checks the factorisation status); ENUMERIC if the Gram is not
+ * positive definite. */
+tsk_status tsk_rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s,
+                          int32_t R, int32_t prec, const double* Omega, int32_t k, double* A,
+                          double* W, void* ws, size_t* ws_bytes, void* stream);
 
 /* Init-RRF of mode n (Alg. 3 with the composite sketch of Sec. 5):
  * W = T_(n) Omega^T with the CountSketch g : [K] -> [k2], tau (stream

@@ -75,7 +75,8 @@ class Tensor:
         return t
 
 
-def _options(m, sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, record_fit):
+def _options(m, sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, record_fit, solve="exact",
+             rsvd_k=0):
     o = L._Options()
     o.sketch = L.SKETCH[sketch]
     o.m = int(m)
@@ -86,6 +87,8 @@ def _options(m, sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, record_fit):
     o.seed = int(seed)
     o.stream = L.stream_ptr()
     o.flags = L.FLAG_RECORD_FIT if record_fit else 0
+    o.solve = L.SOLVE[solve]
+    o.rsvd_k = int(rsvd_k)
     return o
 
 
@@ -94,9 +97,10 @@ class TuckerPlan:
     (keeps allocation out of timed loops)."""
 
     def __init__(self, T, ranks, m, sweeps, sketch="ts", init="rrf", prec="f32", seed=0,
-                 rrf_k1=0, rrf_k2=0, record_fit=True):
+                 rrf_k1=0, rrf_k2=0, record_fit=True, solve="exact", rsvd_k=0):
         self.T, self.ranks = T, tuple(int(r) for r in ranks)
-        self.opt = _options(m, sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, record_fit)
+        self.opt = _options(m, sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, record_fit,
+                            solve, rsvd_k)
         self.ct = T.c_struct()
         self.cr = L.i32_array(self.ranks)
         nb = ctypes.c_size_t(0)
@@ -127,17 +131,21 @@ class TuckerPlan:
 
 
 def tucker_sketch_als(T, ranks, m, sweeps, sketch="ts", init="rrf", prec="f32", seed=0,
-                      rrf_k1=0, rrf_k2=0, record_fit=True, init_factors=None):
+                      rrf_k1=0, rrf_k2=0, record_fit=True, init_factors=None, solve="exact",
+                      rsvd_k=0):
     """Sketch-Tucker-ALS (Alg. 4).  Returns (core, factors, fits) -- FP64 device
-    tensors and the per-sweep relative residuals."""
-    plan = TuckerPlan(T, ranks, m, sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, record_fit)
+    tensors and the per-sweep relative residuals.  solve = "exact" (truncated
+    SVD of Z^+ Y) or "rsvd" (RSVD-LRLS, Alg. 5, rsvd_k test-matrix columns,
+    0 = min(R + 10, r))."""
+    plan = TuckerPlan(T, ranks, m, sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, record_fit,
+                      solve, rsvd_k)
     return plan.run(init_factors)
 
 
 def cp_via_tucker(T, cp_rank, tucker_ranks, m, tucker_sweeps, cp_sweeps, sketch="lev",
-                  init="rrf", prec="f32", seed=0, rrf_k1=0, rrf_k2=0):
+                  init="rrf", prec="f32", seed=0, rrf_k1=0, rrf_k2=0, solve="exact", rsvd_k=0):
     """CP-Sketch-Tucker (Alg. 6).  Returns (cp_factors, cp relative residual)."""
-    o = _options(m, tucker_sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, False)
+    o = _options(m, tucker_sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, False, solve, rsvd_k)
     ct = T.c_struct()
     tr = L.i32_array(tucker_ranks)
     nb = ctypes.c_size_t(0)
@@ -203,6 +211,24 @@ def rc_solve(Z, Y, R, prec=None):
     keep = L.query_and_alloc(L.lib().tsk_rc_solve,
                              (L.ptr(Z.contiguous()), L.ptr(Y.contiguous()), m, r, s, int(R),
                               L.PREC[prec], L.ptr(A), L.ptr(W)), (L.stream_ptr(),), Z.device)
+    del keep
+    return A, W
+
+
+def rsvd_solve(Z, Y, R, Omega, prec=None):
+    """RSVD-LRLS (Alg. 5) with the given s x k Gaussian test matrix ->
+    (A s x R, W r x R), FP64."""
+    if prec is None:
+        prec = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16"}[Z.dtype]
+    m, r = Z.shape
+    s = Y.shape[1]
+    Om = Omega.to(torch.float64).contiguous()
+    A = torch.empty((s, R), dtype=torch.float64, device=Z.device)
+    W = torch.empty((r, R), dtype=torch.float64, device=Z.device)
+    keep = L.query_and_alloc(L.lib().tsk_rsvd_solve,
+                             (L.ptr(Z.contiguous()), L.ptr(Y.contiguous()), m, r, s, int(R),
+                              L.PREC[prec], L.ptr(Om), int(Om.shape[1]), L.ptr(A), L.ptr(W)),
+                             (L.stream_ptr(),), Z.device)
     del keep
     return A, W
 

@@ -16,6 +16,7 @@ DENSE, COO = 0, 1
 SKETCH = {"ts": 0, "lev": 1}
 INIT = {"rrf": 0, "random": 1, "user": 2}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
+SOLVE = {"exact": 0, "rsvd": 1}
 FLAG_RECORD_FIT = 1
 
 
@@ -38,7 +39,8 @@ class _Options(ctypes.Structure):
                 ("sweeps", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("solve", ctypes.c_int32),
+                ("rsvd_k", ctypes.c_int32)]
 
 
 _lib = None
@@ -67,6 +69,8 @@ def lib():
             "tsk_sketch_rhs_ts": (i32, [T, i32, i64, vp, vp, vp, vp, sz, vp]),
             "tsk_sketch_lhs_ts": (i32, [i32, vp, vp, i32, i64, vp, vp, vp, i32, vp, vp, sz, vp]),
             "tsk_rc_solve": (i32, [vp, vp, i64, i64, i64, i32, i32, vp, vp, vp, sz, vp]),
+            "tsk_rsvd_solve": (i32, [vp, vp, i64, i64, i64, i32, i32, vp, i32, vp, vp, vp, sz,
+                                     vp]),
             "tsk_rrf_init": (i32, [T, i32, i32, i32, i32, u64, vp, vp, sz, vp]),
             "tsk_leverage_sample": (i32, [i32, vp, vp, i32, i64, u64, i32, vp, vp, vp, vp, sz, vp]),
             "tsk_sketch_lev": (i32, [T, vp, i32, i64, vp, vp, vp, i32, vp, vp, vp]),

@@ -174,6 +174,11 @@ struct TuckerArgs {
   int* info_dev = nullptr;
 };
 
+// columns of the RSVD-LRLS test matrix: O(R) in Alg. 5, R + 10 by default
+int64_t rsvd_width(int32_t rsvd_k, int64_t R, int64_t r) {
+  return rsvd_k > 0 ? rsvd_k : std::min<int64_t>(R + 10, r);
+}
+
 tsk_status validate_options(const TensorView& T, const int64_t* R, const tsk_options* opt) {
   TSK_REQUIRE(opt, "options are NULL");
   TSK_REQUIRE(opt->sketch == TSK_SKETCH_TS || opt->sketch == TSK_SKETCH_LEV, "unknown sketch %d",
@@ -183,8 +188,18 @@ tsk_status validate_options(const TensorView& T, const int64_t* R, const tsk_opt
   TSK_REQUIRE(opt->prec >= TSK_PREC_F64 && opt->prec <= TSK_PREC_BF16, "unknown precision %d",
               opt->prec);
   TSK_REQUIRE(opt->sweeps >= 0, "sweeps = %d < 0", opt->sweeps);
+  TSK_REQUIRE(opt->solve == TSK_SOLVE_EXACT || opt->solve == TSK_SOLVE_RSVD, "unknown solve %d",
+              opt->solve);
+  TSK_REQUIRE(opt->rsvd_k >= 0, "rsvd_k = %d < 0", opt->rsvd_k);
   for (int n = 0; n < T.order; ++n) {
     int64_t r = prod_except(R, T.order, n);
+    if (opt->solve == TSK_SOLVE_RSVD) {
+      const int64_t k = rsvd_width(opt->rsvd_k, R[n], r);
+      TSK_REQUIRE(k >= R[n] && k <= r && k <= 64,
+                  "RSVD-LRLS test matrix of %lld columns for mode %d needs R_n <= k <= "
+                  "min(prod_{k != n} R_k, 64)",
+                  (long long)k, n);
+    }
     TSK_REQUIRE(opt->m >= r,
                 "sketch size m = %lld is smaller than prod_{k != %d} R_k = %lld (the sketched "
                 "problem would not have a unique solution)",
@@ -249,6 +264,14 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
     }
   void* Z = ws.take<char>(size_t(m) * rmax * prec_bytes(prec));
   double* W = ws.take<double>(rmax * Rmax);
+  const bool rsvd = o.solve == TSK_SOLVE_RSVD;
+  double* Om = nullptr;
+  if (rsvd) {
+    int64_t kmax = 0;
+    for (int n = 0; n < N; ++n)
+      kmax = std::max(kmax, rsvd_width(o.rsvd_k, a.R[n], prod_except(a.R, N, n)));
+    Om = ws.take<double>(size_t(smax) * kmax);
+  }
   int32_t* lev_idx = nullptr;
   double* lev_w = nullptr;
   void* Ylev = nullptr;
@@ -342,8 +365,15 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
           TSK_TRY(leverage_rows(T, a.R, n, m, lev_idx, lev_w, a.factors, prec, Z, Ylev, st));
         Y = Ylev;
       }
-      TSK_TRY(rc_solve(Z, Y, m, r, T.dims[n], int(a.R[n]), prec, a.factors[n], W, a.info_dev, ws,
-                       st));
+      if (rsvd) {  // RSVD-LRLS (Alg. 5) with the test matrix of stream (seed, RSVD, sweep, n)
+        const int64_t k = rsvd_width(o.rsvd_k, a.R[n], r);
+        if (run) TSK_TRY(launch_gauss(stream_key(o.seed, kRSVD, sweep, n), T.dims[n] * k, 1.0, Om, st));
+        TSK_TRY(rsvd_solve(Z, Y, m, r, T.dims[n], int(a.R[n]), prec, Om, k, a.factors[n], W,
+                           a.info_dev, ws, st));
+      } else {
+        TSK_TRY(rc_solve(Z, Y, m, r, T.dims[n], int(a.R[n]), prec, a.factors[n], W, a.info_dev,
+                         ws, st));
+      }
       release();
     }
     if (run && a.core)
@@ -534,6 +564,35 @@ tsk_status tsk_rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int6
   }
   return TSK_OK;
 }
+
+tsk_status tsk_rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s,
+                          int32_t R, int32_t prec, const double* Omega, int32_t k, double* A,
+                          double* W, void* ws, size_t* ws_bytes, void* stream) {
+  clear_error();
+  TSK_REQUIRE(Z && Y && Omega && (ws == nullptr || (A && W)), "NULL argument");
+  TSK_REQUIRE(m >= r && r >= 1 && s >= 1 && R >= 1 && R <= r && R <= s,
+              "invalid sizes m=%lld r=%lld s=%lld R=%d", (long long)m, (long long)r,
+              (long long)s, R);
+  TSK_REQUIRE(k >= R && k <= r && k <= 64, "test matrix width k = %d needs R <= k <= min(r, 64)",
+              k);
+  TSK_REQUIRE(prec >= TSK_PREC_F64 && prec <= TSK_PREC_BF16, "unknown precision");
+  int* info = nullptr;
+  TSK_TRY(with_workspace(ws, ws_bytes, [&](Ws& w) -> tsk_status {
+    info = w.take<int>(4);
+    if (!w.measuring()) TSK_HIP(hipMemsetAsync(info, 0, 4 * sizeof(int), as_stream(stream)));
+    return rsvd_solve(Z, Y, m, r, s, R, prec, Omega, k, A, W, info, w, as_stream(stream));
+  }));
+  if (!ws) return TSK_OK;
+  TSK_HIP(hipStreamSynchronize(as_stream(stream)));
+  int hinfo[2];
+  TSK_HIP(hipMemcpy(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost));
+  if (hinfo[0] || hinfo[1]) {
+    set_error("numerical breakdown in the randomized solve (info %d %d)", hinfo[0], hinfo[1]);
+    return TSK_ENUMERIC;
+  }
+  return TSK_OK;
+}
+
 
 tsk_status tsk_rrf_init(const tsk_tensor* T, int32_t n, int32_t R, int32_t k1, int32_t k2,
                         uint64_t seed, double* A, void* ws, size_t* ws_bytes, void* stream) {

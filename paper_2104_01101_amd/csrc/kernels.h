@@ -110,11 +110,18 @@ tsk_status scale_columns_inv_sqrt(double* A, int64_t rows, int64_t R, const doub
                                   hipStream_t st);
 tsk_status transpose_f64(const double* A, int64_t rows, int64_t cols, double* At,
                          hipStream_t st);
+// Thin Householder QR: Ct (k x r) holds the columns of C (r x k) as rows; Qt
+// (k x r) receives the columns of Q as rows.  k <= 64.
+tsk_status qr_rows(const double* Ct, int64_t k, int64_t r, double* Qt, Ws& ws, hipStream_t st);
 // A (rows x R) <- A chol(A^T A)^{-T} (one CholeskyQR pass, FP64)
 tsk_status cholqr(double* A, int64_t rows, int64_t R, int* info, Ws& ws, hipStream_t st);
 
-// ---- exact rank-constrained solve (solve.cpp) ----
+// ---- rank-constrained solves (solve.hip) ----
 tsk_status rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s, int R,
                     int prec, double* A, double* W, int* info, Ws& ws, hipStream_t st);
+// RSVD-LRLS (Alg. 5) with the s x k Gaussian test matrix Om (device).
+tsk_status rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s, int R,
+                      int prec, const double* Om, int64_t k, double* A, double* W, int* info,
+                      Ws& ws, hipStream_t st);
 
 }  // namespace tsk

@@ -613,6 +613,97 @@ __global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, do
   eig_tail<NT>(q, R, d, e, e2, bet, M, y, lu, pivs, sh, lam, V, timers);
 }
 
+// ----------------------------------------------------- thin Householder QR ----
+// Q of the thin QR factorisation of C (r x k, k <= 64), given and returned by
+// rows of the transposes: Ct (k x r) with row j = column j of C, Qt (k x r)
+// with row j = column j of Q.  One wavefront (column steps are short; no block
+// barriers).  Reflector j: I - beta v v^T on indices j.., v_j = c_j - alpha,
+// alpha = -sign(c_j) ||c_{j..}||; the dot products of v with the remaining
+// columns are accumulated eight at a time and reduced together.  Q is formed
+// by applying the reflectors backwards to the first k columns of the identity.
+// Work arrays (copy of Ct and Q) live in LDS when they fit, else in gwork.
+constexpr int kQrMaxK = 64;
+
+template <bool LDSW>
+__global__ __launch_bounds__(64) void k_qr_rows(const double* Ct, int k, int r, double* Qt,
+                                                double* gwork) {
+  extern __shared__ double qsm[];
+  __shared__ double betas[kQrMaxK];
+  double* V = LDSW ? qsm : gwork;          // k x r: reduced columns, reflector j in row j
+  double* Q = LDSW ? qsm + k * r : Qt;     // k x r: rows of Q
+  const int lane = threadIdx.x;
+  for (int t = lane; t < k * r; t += 64) V[t] = Ct[t];
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    double* vj = V + j * r;
+    double sig = 0.0;
+    for (int i = j + 1 + lane; i < r; i += 64) sig += vj[i] * vj[i];
+    sig = wave_sum(sig);
+    const double x0 = vj[j];
+    const double nrm = sqrt(x0 * x0 + sig);
+    const double alpha = nrm > 0.0 ? -copysign(nrm, x0) : 0.0;
+    const double v0 = x0 - alpha;
+    const double vtv = sig + v0 * v0;
+    const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    __syncthreads();
+    if (lane == 0) {
+      vj[j] = v0;
+      betas[j] = beta;
+    }
+    __syncthreads();
+    for (int l0 = j + 1; l0 < k; l0 += 8) {
+      double acc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+      for (int i = j + lane; i < r; i += 64) {
+        const double vi = vj[i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (l0 + u < k) acc[u] += vi * V[(l0 + u) * r + i];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = beta * wave_sum(acc[u]);
+      for (int i = j + lane; i < r; i += 64) {
+        const double vi = vj[i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (l0 + u < k) V[(l0 + u) * r + i] -= acc[u] * vi;
+      }
+    }
+    __syncthreads();
+  }
+  // Q = H_0 ... H_{k-1} [I_k; 0]: rows l < j of Q vanish on indices >= j, so
+  // H_j only changes rows l >= j
+  for (int t = lane; t < k * r; t += 64) Q[t] = (t % r == t / r) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = k - 1; j >= 0; --j) {
+    const double* vj = V + j * r;
+    const double beta = betas[j];
+    for (int l0 = j; l0 < k; l0 += 8) {
+      double acc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+      for (int i = j + lane; i < r; i += 64) {
+        const double vi = vj[i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (l0 + u < k) acc[u] += vi * Q[(l0 + u) * r + i];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = beta * wave_sum(acc[u]);
+      for (int i = j + lane; i < r; i += 64) {
+        const double vi = vj[i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (l0 + u < k) Q[(l0 + u) * r + i] -= acc[u] * vi;
+      }
+    }
+    __syncthreads();
+  }
+  if (LDSW)
+    for (int t = lane; t < k * r; t += 64) Qt[t] = Q[t];
+}
+
 // ---------------------------------------------- register-tiled SPD inverse ----
 // For n <= 128 the whole matrix lives in registers: 512 threads, thread t owns
 // rows tr + 16 a (a < 8) and columns tc + 32 b (b < 4), tr = t / 32, tc = t % 32.
@@ -838,6 +929,24 @@ tsk_status sym_eig_top(double* M, int64_t q, int64_t R, double* lam, double* V, 
   else
     hipLaunchKernelGGL((k_sym_eig_top<kEigT, false, false>), dim3(1), dim3(kEigT), lds, st, M,
                        int(q), int(R), lam, V, scratch, pivs, nt);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+tsk_status qr_rows(const double* Ct, int64_t k, int64_t r, double* Qt, Ws& ws, hipStream_t st) {
+  if (k > kQrMaxK || k > r) {
+    set_error("thin QR of %lld columns of length %lld is not supported", (long long)k,
+              (long long)r);
+    return TSK_EUNSUPPORTED;
+  }
+  const size_t lds = size_t(2) * k * r * 8;
+  const bool fits = lds + 1024 <= size_t(max_lds_bytes());
+  double* work = fits ? nullptr : ws.take<double>(size_t(k) * r);
+  if (ws.measuring()) return TSK_OK;
+  if (fits)
+    hipLaunchKernelGGL(k_qr_rows<true>, dim3(1), dim3(64), lds, st, Ct, int(k), int(r), Qt, work);
+  else
+    hipLaunchKernelGGL(k_qr_rows<false>, dim3(1), dim3(64), 0, st, Ct, int(k), int(r), Qt, work);
   TSK_LAUNCHED();
   return TSK_OK;
 }

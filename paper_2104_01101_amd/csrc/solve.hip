@@ -62,4 +62,70 @@ tsk_status rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t 
   return TSK_OK;
 }
 
+
+// RSVD-LRLS (Alg. 5), the randomized low-rank least-squares solve that Alg. 4
+// calls for each subproblem, with the s x k Gaussian test matrix Om:
+//
+//   [Z^T Z ; Y^T Z]                 one MFMA Gram launch (as the exact solve)
+//   B = (Z^T Z)^{-1}                Gauss-Jordan when r fits, else Cholesky solves
+//   C^T = (Om^T H^T) B              H = Z^T Y;  C = B Z^T Y Om  (r x k)
+//   Q = thin Householder QR of C
+//   D^T = H^T (B Q)                 D = Q^T B Z^T Y  (k x s)
+//   U, S: leading R eigenpairs of D D^T (k x k);  A = D^T U S^{-1} = V(:, :R)
+//   A <- CholeskyQR(A), sign rule
+//   W = Q (D A)                     = Q U S with the signs of A
+tsk_status rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s, int R,
+                      int prec, const double* Om, int64_t k, double* A, double* W, int* info,
+                      Ws& ws, hipStream_t st) {
+  double* GH = ws.take<double>(size_t(r + s) * r);
+  double* G = GH;
+  const double* Ht = GH + size_t(r) * r;  // s x r: Y^T Z = H^T
+  double* C0t = ws.take<double>(size_t(k) * r);
+  double* Ct = ws.take<double>(size_t(k) * r);
+  double* Qt = ws.take<double>(size_t(k) * r);
+  double* Pt = ws.take<double>(size_t(k) * r);
+  double* P = ws.take<double>(size_t(r) * k);
+  double* Dt = ws.take<double>(size_t(s) * k);
+  double* Mk = ws.take<double>(size_t(k) * k);
+  double* lam = ws.take<double>(R);
+  double* U = ws.take<double>(size_t(k) * R);
+  double* DA = ws.take<double>(size_t(k) * R);
+  const bool gj = spd_inverse_fits(r);
+  const bool run = !ws.measuring();
+  {
+    ProfScope prof(run ? "gram" : "", st);
+    TSK_TRY(gemm_tn(prec, r + s, r, m, Z, r, r, Y, s, Z, r, GH, r, ws, st));
+  }
+  {
+    ProfScope prof(run ? "solve_la" : "", st);
+    TSK_TRY(gemm_tn(TSK_PREC_F64, k, r, s, Om, k, k, nullptr, 0, Ht, r, C0t, r, ws, st));
+    if (gj) {
+      if (run) TSK_TRY(spd_inverse(G, r, r, info, st));
+      TSK_TRY(gemm_nn_f64(k, r, r, C0t, r, G, r, Ct, r, ws, st));
+    } else {
+      if (run) TSK_TRY(cholesky(G, r, r, info, st));
+      if (run) TSK_HIP(hipMemcpyAsync(Ct, C0t, size_t(k) * r * 8, hipMemcpyDeviceToDevice, st));
+      if (run) TSK_TRY(chol_solve_rows(G, r, r, Ct, k, r, false, st));
+    }
+    TSK_TRY(qr_rows(Ct, k, r, Qt, ws, st));
+    if (gj) {
+      TSK_TRY(gemm_nn_f64(k, r, r, Qt, r, G, r, Pt, r, ws, st));
+    } else {
+      if (run) TSK_HIP(hipMemcpyAsync(Pt, Qt, size_t(k) * r * 8, hipMemcpyDeviceToDevice, st));
+      if (run) TSK_TRY(chol_solve_rows(G, r, r, Pt, k, r, false, st));
+    }
+    if (run) TSK_TRY(transpose_f64(Pt, k, r, P, st));
+    TSK_TRY(gemm_nn_f64(s, k, r, Ht, r, P, k, Dt, k, ws, st));
+    TSK_TRY(gemm_tn(TSK_PREC_F64, k, k, s, Dt, k, k, nullptr, 0, Dt, k, Mk, k, ws, st));
+  }
+  TSK_TRY(sym_eig_top(Mk, k, R, lam, U, ws, st));
+  TSK_TRY(gemm_nn_f64(s, R, k, Dt, k, U, R, A, R, ws, st));
+  if (run) TSK_TRY(scale_columns_inv_sqrt(A, s, R, lam, st));
+  TSK_TRY(cholqr(A, s, R, info + 1, ws, st));
+  if (run) TSK_TRY(sign_fix_columns(A, s, R, st));
+  TSK_TRY(gemm_tn(TSK_PREC_F64, k, R, s, Dt, k, k, nullptr, 0, A, R, DA, R, ws, st));
+  TSK_TRY(gemm_tn(TSK_PREC_F64, r, R, k, Qt, r, r, nullptr, 0, DA, R, W, R, ws, st));
+  return TSK_OK;
+}
+
 }  // namespace tsk

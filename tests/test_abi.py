@@ -30,8 +30,10 @@ def test_header_symbols_exported():
 
 
 def test_abi_version():
+    """Version 2: the options struct gained the subproblem solver (solve, rsvd_k)."""
     L = _lib()
-    assert L.lib().tsk_abi_version() == 1
+    assert L.lib().tsk_abi_version() == 2
+    assert L._Options.solve.offset == 76 and L._Options.rsvd_k.offset == 80
 
 
 def test_generator_matches_oracle_spec():
@@ -56,9 +58,10 @@ def _tensor(L, dims, layout=0, dtype=1, nnz=0):
     return t
 
 
-def _opts(L, m, sketch=0):
+def _opts(L, m, sketch=0, solve=0, rsvd_k=0):
     o = L._Options()
     o.m, o.sketch, o.sweeps, o.prec = m, sketch, 1, 0
+    o.solve, o.rsvd_k = solve, rsvd_k
     return o
 
 
@@ -94,3 +97,21 @@ def test_workspace_query_sizes_grow_with_problem():
                                           ctypes.byref(o), ctypes.byref(nb)) == 0
         sizes.append(nb.value)
     assert sizes[0] < sizes[1] < sizes[2]
+
+
+@pytest.mark.parametrize("solve,rsvd_k,expect", [
+    (2, 0, -1),      # unknown solver
+    (1, -1, -1),     # negative width
+    (1, 2, -1),      # k < R
+    (1, 10, -1),     # k > r = 9
+    (1, 0, 0),       # default width min(R + 10, r)
+    (1, 9, 0),
+])
+def test_rsvd_option_validation(solve, rsvd_k, expect):
+    L = _lib()
+    t = _tensor(L, (10, 10, 10))
+    o = _opts(L, 50, 0, solve, rsvd_k)
+    nb = ctypes.c_size_t(0)
+    st = L.lib().tsk_workspace_size(ctypes.byref(t), L.i32_array((3, 3, 3)), ctypes.byref(o),
+                                    ctypes.byref(nb))
+    assert st == expect

@@ -267,3 +267,50 @@ def test_adjoint_matches_oracle_and_fd(tsk):
                   tsk.sketched_residual(dims, ranks, n, m, h, s, fm, cg, Yg).item()) / (2 * hstep)
             g = fa[k].grad[i, c].item()
             assert abs(fd - g) <= 1e-7 * max(1.0, abs(fd))
+
+
+# ------------------------------------------------------------ RSVD-LRLS ----
+@pytest.mark.parametrize("m,r,s,R,k", [(300, 100, 400, 10, 20), (80, 25, 40, 5, 15),
+                                       (400, 144, 150, 12, 22)])
+def test_rsvd_solve_fp64_vs_oracle(tsk, m, r, s, R, k):
+    """RSVD-LRLS (Alg. 5) with the same Gaussian test matrix: FP64 library vs
+    the oracle (r = 144 exercises the Cholesky branch of the Gram solve)."""
+    rs = np.random.default_rng(m + r)
+    Z = rs.standard_normal((m, r))
+    Y = rs.standard_normal((m, s))
+    Om = rs.standard_normal((s, k))
+    A, W = tsk.rsvd_solve(torch.from_numpy(Z).to(DEV), torch.from_numpy(Y).to(DEV), R,
+                          torch.from_numpy(Om).to(DEV))
+    Ao, Wo = osv.rsvd_lrls(Z, Y, R, Om)
+    np.testing.assert_allclose(A.cpu().numpy(), Ao, atol=1e-9)
+    np.testing.assert_allclose(W.cpu().numpy(), Wo, atol=1e-9 * np.abs(Wo).max())
+
+
+def test_rsvd_solve_rank_deficient(tsk):
+    """Z^+ Y of rank 3 < k: the test matrix product C is rank deficient; the
+    Householder QR still returns an orthonormal Q and the leading 3 triplets are
+    exact."""
+    rs = np.random.default_rng(5)
+    m, r, s, R, k = 200, 36, 60, 3, 13
+    Z = rs.standard_normal((m, r))
+    X = rs.standard_normal((r, R)) @ rs.standard_normal((R, s))
+    Y = Z @ X
+    Om = rs.standard_normal((s, k))
+    A, W = tsk.rsvd_solve(torch.from_numpy(Z).to(DEV), torch.from_numpy(Y).to(DEV), R,
+                          torch.from_numpy(Om).to(DEV))
+    np.testing.assert_allclose(W.cpu().numpy() @ A.cpu().numpy().T, X, atol=1e-9 * np.abs(X).max())
+
+
+def test_rsvd_solve_fp32_operands(tsk):
+    rs = np.random.default_rng(9)
+    m, r, s, R, k = 1600, 100, 2000, 10, 20
+    Z = rs.standard_normal((m, r)).astype(np.float32)
+    Y = rs.standard_normal((m, s)).astype(np.float32)
+    Om = rs.standard_normal((s, k))
+    A, W = tsk.rsvd_solve(torch.from_numpy(Z).to(DEV), torch.from_numpy(Y).to(DEV), R,
+                          torch.from_numpy(Om).to(DEV))
+    Ao, Wo = osv.rsvd_lrls(Z.astype(np.float64), Y.astype(np.float64), R, Om)
+    # compare the rank-R solutions (subspace and scale), FP32 operand rounding
+    Xg = W.cpu().numpy() @ A.cpu().numpy().T
+    Xo = Wo @ Ao.T
+    assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) < 1e-4

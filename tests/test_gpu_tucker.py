@@ -121,3 +121,39 @@ def test_cp_via_tucker_fp64(tsk):
     assert abs(fit - ref["fit"]) < 1e-8
     for F, Fo in zip(facs, ref["factors"]):
         np.testing.assert_allclose(F.cpu().numpy(), Fo, atol=1e-6 * np.abs(Fo).max())
+
+
+# -------------------------------------------- RSVD-LRLS subproblem solver ----
+def test_c1_rsvd_fp64_parity(tsk):
+    """configs[0] with the paper's subproblem solver (Alg. 4 calls RSVD-LRLS,
+    Alg. 5): same Gaussian test matrices on both sides, relative residuals after
+    every sweep within 1e-10, factors within 1e-8."""
+    w = workloads.c1()
+    T = _dense(tsk, w.dense)
+    core, factors, fits = tsk.tucker_sketch_als(T, w.ranks, w.m, w.sweeps, prec="f64", seed=0,
+                                                solve="rsvd")
+    ref = otk.sketch_tucker_als(osk.Tensor.from_dense(w.dense), w.ranks, w.m, w.sweeps, seed=0,
+                                solve_kind="rsvd")
+    np.testing.assert_allclose(fits, ref["fits"], rtol=0, atol=1e-10)
+    for F, Fo in zip(factors, ref["factors"]):
+        np.testing.assert_allclose(F.cpu().numpy(), Fo, atol=1e-8)
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f64", 1e-10)])
+def test_sparse_small_rsvd_parity(tsk, prec, tol):
+    dims, R = (300, 300, 300), 6
+    idx, val = workloads.sparse_tucker(dims, 50_000, (R, R, R), seed=1)
+    val = val.astype(np.float32 if prec == "f32" else np.float64)
+    T = _coo(tsk, dims, idx, val)
+    m = 16 * R * R
+    _, _, fits = tsk.tucker_sketch_als(T, (R, R, R), m, 4, prec=prec, seed=1, solve="rsvd")
+    ref = otk.sketch_tucker_als(osk.Tensor(dims, idx, val.astype(np.float64)), (R, R, R), m, 4,
+                                seed=1, solve_kind="rsvd")
+    np.testing.assert_allclose(fits, ref["fits"], rtol=0, atol=tol)
+
+
+def test_rsvd_exact_low_rank_recovered(tsk):
+    X = workloads.tucker_dense((30, 28, 26), (4, 4, 4), noise=0.0, seed=3)
+    _, _, fits = tsk.tucker_sketch_als(_dense(tsk, X), (4, 4, 4), 8 * 16, 1, prec="f64",
+                                       solve="rsvd")
+    assert fits[-1] < 1e-12
