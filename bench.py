@@ -54,8 +54,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
-                    help="c2 (default, the benchmark workload) or c4 (sketch-pass study)")
+    ap.add_argument("--workload", default="sparse2000", choices=["sparse2000", "zipf10k"],
+                    help="sparse2000 (default, the benchmark workload) or zipf10k (sketch-pass study)")
     ap.add_argument("--solve", default="rsvd", choices=["rsvd", "exact"],
                     help="subproblem solver: rsvd = RSVD-LRLS (Alg. 5, the solver Alg. 4 "
                          "calls) or exact = truncated SVD of Z^+ Y")
@@ -69,7 +69,7 @@ def parse():
 
 def workload(name):
     import workloads
-    return workloads.c2() if name == "c2" else workloads.c4()
+    return workloads.sparse2000() if name == "sparse2000" else workloads.zipf10k()
 
 
 def group_work(w, solve="exact"):
@@ -242,7 +242,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": ("sparse 2000^3, 1e6 nnz uniform, Tucker rank 10 + N(0,1), "
                                 "TensorSketch m=1600, RRF init, 10 sweeps of Alg. 4, FP32 operands")
-                   if args.workload == "c2" else
+                   if args.workload == "sparse2000" else
                    ("sparse 10000^3, 1e7 nnz Zipf(1.1), lognormal values, Tucker rank 16, "
                     "TensorSketch m=2048, RRF init, 5 sweeps, FP32 operands"),
                    "dims": list(w.dims), "nnz": int(w.val.shape[0]), "ranks": list(w.ranks),
@@ -253,7 +253,7 @@ def main():
         "sketch_pass_roofline": roofline("sketch_pass", work, sp[0], sp[1], args.steps,
                                          args.workload),
     }
-    if not args.no_cpu_baseline and args.workload == "c2":
+    if not args.no_cpu_baseline and args.workload == "sparse2000":
         out["cpu_baseline"] = cpu_baseline(w, args.solve)
     print(json.dumps(out))
 

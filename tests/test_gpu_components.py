@@ -166,7 +166,7 @@ def test_rc_solve_low_precision(tsk, prec, tol):
 
 # ---------------------------------------------------------------- a9 ----
 def test_rrf_init_matches_oracle(tsk):
-    w = workloads.c1()
+    w = workloads.dense40()
     T = _gpu_tensor(tsk, w.dims, dense=w.dense)
     To = osk.Tensor.from_dense(w.dense)
     for n in (1, 2):

@@ -32,9 +32,9 @@ def _coo(tsk, dims, idx, val):
 
 
 def test_c1_fp64_parity(tsk):
-    """configs[0]: dense 40^3 FP64, Tucker rank 5 + 1% noise, TensorSketch m = 200,
+    """Small dense case: 40^3 FP64, Tucker rank 5 + 1% noise, TensorSketch m = 200,
     RRF init, 5 sweeps."""
-    w = workloads.c1()
+    w = workloads.dense40()
     T = _dense(tsk, w.dense)
     core, factors, fits = tsk.tucker_sketch_als(T, w.ranks, w.m, w.sweeps, prec="f64", seed=0)
     ref = otk.sketch_tucker_als(osk.Tensor.from_dense(w.dense), w.ranks, w.m, w.sweeps, seed=0)
@@ -45,7 +45,7 @@ def test_c1_fp64_parity(tsk):
 
 
 def test_c1_deterministic(tsk):
-    w = workloads.c1()
+    w = workloads.dense40()
     T = _dense(tsk, w.dense)
     a = tsk.tucker_sketch_als(T, w.ranks, w.m, 3, prec="f64", seed=4)
     b = tsk.tucker_sketch_als(T, w.ranks, w.m, 3, prec="f64", seed=4)
@@ -55,7 +55,7 @@ def test_c1_deterministic(tsk):
 
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f64", 1e-10)])
 def test_sparse_small_parity(tsk, prec, tol):
-    """configs[1] shape family at reduced size: sparse 300^3, 50k distinct uniform
+    """Sparse workload family at reduced size: sparse 300^3, 50k distinct uniform
     coordinates, Tucker signal + N(0,1), TensorSketch m = 16 R^2."""
     dims, R = (300, 300, 300), 6
     idx, val = workloads.sparse_tucker(dims, 50_000, (R, R, R), seed=1)
@@ -75,7 +75,7 @@ def test_exact_low_rank_recovered(tsk):
 
 
 def test_random_init_parity(tsk):
-    w = workloads.c1()
+    w = workloads.dense40()
     _, _, fits = tsk.tucker_sketch_als(_dense(tsk, w.dense), w.ranks, w.m, 3, init="random",
                                       prec="f64", seed=2)
     ref = otk.sketch_tucker_als(osk.Tensor.from_dense(w.dense), w.ranks, w.m, 3, seed=2,
@@ -84,7 +84,7 @@ def test_random_init_parity(tsk):
 
 
 def test_leverage_dense_order4_fp64(tsk):
-    """configs[2] shape family at reduced size: dense 24^4, rank 3, leverage m = 4000
+    """Order-4 dense family at reduced size: dense 24^4, rank 3, leverage m = 4000
     scaled to 400 rows."""
     X = workloads.tucker_dense((24, 24, 24, 24), (3, 3, 3, 3), noise=0.01, seed=2)
     ranks, m = (3, 3, 3, 3), 400
@@ -109,7 +109,7 @@ def test_leverage_bf16_vs_f32(tsk):
 
 
 def test_cp_via_tucker_fp64(tsk):
-    """configs[4] shape family at reduced size: dense 40^3, CP rank 4 with
+    """Collinear CP family at reduced size: dense 40^3, CP rank 4 with
     collinearity 0.9 + 1% noise; Tucker rank 6 by leverage sampling; CP-ALS on the
     core."""
     X, _ = workloads.cp_collinear((40, 40, 40), 4, 0.9, 0.01, seed=3, dtype=np.float64)
@@ -125,10 +125,10 @@ def test_cp_via_tucker_fp64(tsk):
 
 # -------------------------------------------- RSVD-LRLS subproblem solver ----
 def test_c1_rsvd_fp64_parity(tsk):
-    """configs[0] with the paper's subproblem solver (Alg. 4 calls RSVD-LRLS,
+    """The small dense case with the paper's subproblem solver (Alg. 4 calls RSVD-LRLS,
     Alg. 5): same Gaussian test matrices on both sides, relative residuals after
     every sweep within 1e-10, factors within 1e-8."""
-    w = workloads.c1()
+    w = workloads.dense40()
     T = _dense(tsk, w.dense)
     core, factors, fits = tsk.tucker_sketch_als(T, w.ranks, w.m, w.sweeps, prec="f64", seed=0,
                                                 solve="rsvd")

@@ -332,7 +332,7 @@ def test_rrf_recovers_exact_column_space():
 def test_sketched_fit_close_to_hooi():
     """Fit of sketched Tucker-ALS is at least HOOI's and close to it (Sec. 4
     theorems; Sec. 7 reports < 8.5% relative fitness gap at K = 16)."""
-    w = workloads.c1()
+    w = workloads.dense40()
     T = sketch.Tensor.from_dense(w.dense)
     out = tucker.sketch_tucker_als(T, w.ranks, 16 * 25, 5, seed=0)
     h = tucker.hooi(w.dense, w.ranks, 5)

@@ -137,47 +137,47 @@ def cp_collinear(dims, rank, collinearity=0.9, noise=0.01, seed=0, dtype=np.floa
 # ----------------------------------------------------------------------------
 # named configurations
 # ----------------------------------------------------------------------------
-def c1(seed=0, s=40, R=5, K=8):
+def dense40(seed=0, s=40, R=5, K=8):
     """Dense 3-way s^3 FP64, Tucker rank (R,R,R) with Gaussian core and QR
     factors, 1% noise; TensorSketch m = K R^2, RRF init, 5 sweeps, FP64."""
     X = tucker_dense((s, s, s), (R, R, R), 0.01, seed, True, np.float64)
-    return Workload(name="c1", dims=X.shape, dense=X, idx=None, val=None,
+    return Workload(name="dense40", dims=X.shape, dense=X, idx=None, val=None,
                     ranks=(R, R, R), m=K * R * R, sweeps=5, sketch="ts",
                     prec="f64", init="rrf")
 
 
-def c2(seed=0, s=2000, nnz=1_000_000, R=10, K=16, sweeps=10):
+def sparse2000(seed=0, s=2000, nnz=1_000_000, R=10, K=16, sweeps=10):
     """Sparse 3-way s^3 FP32 with nnz distinct uniform coordinates, value =
     Gaussian Tucker rank-(R,R,R) signal + N(0,1); TensorSketch m = K R^2."""
     idx, val = sparse_tucker((s, s, s), nnz, (R, R, R), seed)
-    return Workload(name="c2", dims=(s, s, s), dense=None, idx=idx, val=val,
+    return Workload(name="sparse2000", dims=(s, s, s), dense=None, idx=idx, val=val,
                     ranks=(R, R, R), m=K * R * R, sweeps=sweeps, sketch="ts",
                     prec="f32", init="rrf")
 
 
-def c3(seed=0, s=200, R=10, m=4000, sweeps=5, prec="f32"):
+def dense4d200(seed=0, s=200, R=10, m=4000, sweeps=5, prec="f32"):
     """Dense 4-way s^4 FP32 Tucker rank-(R,..,R) signal + 1% noise; leverage-score
     sampling with m rows per subproblem."""
     X = tucker_dense((s,) * 4, (R,) * 4, 0.01, seed, True, np.float32)
-    return Workload(name="c3", dims=X.shape, dense=X, idx=None, val=None,
+    return Workload(name="dense4d200", dims=X.shape, dense=X, idx=None, val=None,
                     ranks=(R,) * 4, m=m, sweeps=sweeps, sketch="lev", prec=prec,
                     init="rrf")
 
 
-def c4(seed=0, s=10_000, nnz=10_000_000, R=16, K=8):
+def zipf10k(seed=0, s=10_000, nnz=10_000_000, R=16, K=8):
     """Sparse 3-way s^3 FP32, nnz distinct coordinates with Zipf(1.1) indices,
     lognormal(0,1) values; Tucker rank (R,R,R), TensorSketch m = K R^2."""
     idx, val, draws = sparse_zipf((s, s, s), nnz, 1.1, seed)
-    return Workload(name="c4", dims=(s, s, s), dense=None, idx=idx, val=val,
+    return Workload(name="zipf10k", dims=(s, s, s), dense=None, idx=idx, val=val,
                     ranks=(R, R, R), m=K * R * R, sweeps=5, sketch="ts",
                     prec="f32", init="rrf", draws=draws)
 
 
-def c5(seed=0, s=500, cp_rank=20, R=30, K=16, prec="bf16"):
+def cp500(seed=0, s=500, cp_rank=20, R=30, K=16, prec="bf16"):
     """Dense 3-way s^3 FP32 CP rank-20 signal (pairwise collinearity 0.9) + 1%
     noise; sketched Tucker (leverage, m = K R^2) to rank (R,R,R), then CP-ALS of
     rank cp_rank on the core (5 Tucker + 25 CP sweeps)."""
     X, fac = cp_collinear((s, s, s), cp_rank, 0.9, 0.01, seed, np.float32)
-    return Workload(name="c5", dims=X.shape, dense=X, idx=None, val=None,
+    return Workload(name="cp500", dims=X.shape, dense=X, idx=None, val=None,
                     ranks=(R, R, R), m=K * R * R, sweeps=5, sketch="lev",
                     prec=prec, init="rrf", cp_rank=cp_rank, cp_sweeps=25)
