@@ -15,9 +15,11 @@
 // stays on the device without host round trips.
 
 #include <cfloat>
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
+#include "wave.h"
 
 namespace tsk {
 
@@ -26,8 +28,8 @@ namespace {
 // ------------------------------------------------------------ reductions ----
 template <int NT>
 __device__ double block_sum(double v, double* red) {
-  // fixed-order: wave shuffles then waves in order (deterministic)
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  // fixed-order: wave sum then waves in order (deterministic)
+  v = wave_allsum(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) red[wave] = v;
@@ -37,9 +39,21 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-__device__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+__device__ double wave_sum(double v) { return wave_allsum(v); }
+
+// f(integral_constant<int, I>) for I = B, B+1, ..., E-1 (or downwards when
+// DOWN): loop bodies whose register-array indices must be constants.
+template <int B, int E, bool DOWN = false, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    if constexpr (DOWN) {
+      f(std::integral_constant<int, E - 1>{});
+      static_for<B, E - 1, true>(f);
+    } else {
+      f(std::integral_constant<int, B>{});
+      static_for<B + 1, E, false>(f);
+    }
+  }
 }
 
 // -------------------------------------------------------------- cholesky ----
@@ -704,6 +718,86 @@ __global__ __launch_bounds__(64) void k_qr_rows(const double* Ct, int k, int r, 
     for (int t = lane; t < k * r; t += 64) Qt[t] = Q[t];
 }
 
+// Register-resident variant for r <= 128 and k <= KM <= 24: lane l holds rows
+// l and l + 64 of every column and the step loops are unrolled, so the tile
+// is indexed by constants.  Reflector j takes a single wave reduction:
+// w_c = sum_{i >= j} c_ij c_ic for c >= j gives ||c_{j..}||^2 (c = j) and,
+// since v = c_{j..} - alpha e_j, every v^T c_c = w_c - alpha c_jc; with
+// alpha = -sign(c_jj) ||c_{j..}||, v^T v = -2 alpha v_j (no cancellation).
+constexpr int kQrRegRows = 128, kQrRegMaxK = 24;
+
+__host__ __device__ constexpr int round4(int n) { return (n + 3) / 4 * 4; }
+
+template <int KM>
+__global__ __launch_bounds__(64) void k_qr_reg(const double* Ct, int k, int r, double* Qt) {
+  const int lane = threadIdx.x;
+  double X[2][KM];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int c = 0; c < KM; ++c) {
+      const int i = lane + 64 * p;
+      X[p][c] = (i < r && c < k) ? Ct[c * r + i] : 0.0;
+    }
+  double beta[KM];
+  static_for<0, KM>([&](auto JC) {
+    constexpr int J = decltype(JC)::value;
+    constexpr int N = round4(KM - J);
+    beta[J] = 0.0;
+    if (J >= k) return;
+    const double xm0 = lane >= J ? X[0][J] : 0.0;  // rows >= 64 are always below J
+    double pr[N], w[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+      pr[u] = (J + u < KM) ? fma(xm0, X[0][(J + u) % KM], X[1][J] * X[1][(J + u) % KM]) : 0.0;
+    wave_sums<N>(pr, w);
+    const double xj = read_lane(X[0][J], J);
+    const double nrm = sqrt(w[0]);
+    const double alpha = nrm > 0.0 ? -copysign(nrm, xj) : 0.0;
+    const double vj = xj - alpha;
+    const double b = nrm > 0.0 ? -1.0 / (alpha * vj) : 0.0;  // 2 / v^T v
+    beta[J] = b;
+    X[0][J] = lane > J ? X[0][J] : (lane == J ? vj : 0.0);
+#pragma unroll
+    for (int u = 1; u < KM - J; ++u) {
+      const double g = b * fma(-alpha, read_lane(X[0][J + u], J), w[u]);
+      X[0][J + u] = fma(-g, X[0][J], X[0][J + u]);
+      X[1][J + u] = fma(-g, X[1][J], X[1][J + u]);
+    }
+  });
+  // Q = H_0 ... H_{k-1} [I_k; 0]; H_j leaves columns < j of the partial
+  // product untouched (they are still unit vectors e_c, c < j)
+  double Q[2][KM];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int c = 0; c < KM; ++c) Q[p][c] = (lane + 64 * p == c && c < k) ? 1.0 : 0.0;
+  static_for<0, KM, true>([&](auto JC) {
+    constexpr int J = decltype(JC)::value;
+    constexpr int N = round4(KM - J);
+    if (J >= k) return;
+    double pr[N], w[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+      pr[u] = (J + u < KM) ? fma(X[0][J], Q[0][(J + u) % KM], X[1][J] * Q[1][(J + u) % KM])
+                           : 0.0;
+    wave_sums<N>(pr, w);
+#pragma unroll
+    for (int u = 0; u < KM - J; ++u) {
+      const double g = beta[J] * w[u];
+      Q[0][J + u] = fma(-g, X[0][J], Q[0][J + u]);
+      Q[1][J + u] = fma(-g, X[1][J], Q[1][J + u]);
+    }
+  });
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int c = 0; c < KM; ++c) {
+      const int i = lane + 64 * p;
+      if (i < r && c < k) Qt[c * r + i] = Q[p][c];
+    }
+}
+
 // ---------------------------------------------- register-tiled SPD inverse ----
 // For n <= 128 the whole matrix lives in registers: 512 threads, thread t owns
 // rows tr + 16 a (a < 8) and columns tc + 32 b (b < 4), tr = t / 32, tc = t % 32.
@@ -938,6 +1032,17 @@ tsk_status qr_rows(const double* Ct, int64_t k, int64_t r, double* Qt, Ws& ws, h
     set_error("thin QR of %lld columns of length %lld is not supported", (long long)k,
               (long long)r);
     return TSK_EUNSUPPORTED;
+  }
+  if (r <= kQrRegRows && k <= kQrRegMaxK) {
+    if (ws.measuring()) return TSK_OK;
+    if (k <= 8)
+      hipLaunchKernelGGL(k_qr_reg<8>, dim3(1), dim3(64), 0, st, Ct, int(k), int(r), Qt);
+    else if (k <= 16)
+      hipLaunchKernelGGL(k_qr_reg<16>, dim3(1), dim3(64), 0, st, Ct, int(k), int(r), Qt);
+    else
+      hipLaunchKernelGGL(k_qr_reg<24>, dim3(1), dim3(64), 0, st, Ct, int(k), int(r), Qt);
+    TSK_LAUNCHED();
+    return TSK_OK;
   }
   const size_t lds = size_t(2) * k * r * 8;
   const bool fits = lds + 1024 <= size_t(max_lds_bytes());
