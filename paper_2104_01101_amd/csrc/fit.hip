@@ -164,23 +164,23 @@ __global__ __launch_bounds__(kT) void k_inner3(FitArgs a, int64_t nnz, int64_t p
   if (threadIdx.x == 0) partial[blockIdx.x] = acc, partial_direct[blockIdx.x] = acc2;
 }
 
-// Same, all three ranks equal to RR at compile time: the contraction unrolls
-// completely (no loop exits inside), so the y sums run as independent chains.
+// Same, all three ranks equal to RR at compile time.  The core is the same
+// for every lane, so it is read with scalar loads into SGPRs, which the FP64
+// FMAs take as their scalar operand: no LDS traffic for it.  The x and y
+// loops stay rolled so that an iteration loads only its RR core values (the
+// whole core would not fit the SGPRs), and the multipliers indexed by x and y
+// come from a thread-private LDS column rather than a dynamically indexed
+// register array.
 template <int RR>
 __global__ __launch_bounds__(kT) void k_inner3x(FitArgs a, int64_t nnz, int64_t per_block,
-                                                const double* core, int core_lds,
+                                                const double* __restrict__ core,
                                                 double* partial, double* partial_direct) {
-  extern __shared__ double cs_lds[];
   __shared__ double red[kT / 64];
-  const double* cs = core;
-  if (core_lds) {
-    for (int t = threadIdx.x; t < RR * RR * RR; t += kT) cs_lds[t] = core[t];
-    __syncthreads();
-    cs = cs_lds;
-  }
+  __shared__ double us[2][RR][kT];  // u0 and u1 of this thread's entry
+  const int tid = threadIdx.x;
   int64_t lo = int64_t(blockIdx.x) * per_block, hi = lo + per_block < nnz ? lo + per_block : nnz;
   double acc = 0.0, acc2 = 0.0;
-  for (int64_t e = lo + threadIdx.x; e < hi; e += kT) {
+  for (int64_t e = lo + tid; e < hi; e += kT) {
     int64_t i0, i1, i2;
     if (a.layout == TSK_COO) {
       i0 = a.idx[0][e], i1 = a.idx[1][e], i2 = a.idx[2][e];
@@ -190,25 +190,32 @@ __global__ __launch_bounds__(kT) void k_inner3x(FitArgs a, int64_t nnz, int64_t 
       i1 = r % a.dims[1];
       i0 = r / a.dims[1];
     }
-    double u2[RR], u1[RR], u0[RR];
+    double u2[RR];
 #pragma unroll
     for (int c = 0; c < RR; ++c) {
       u2[c] = a.A[2][i2 * RR + c];
-      u1[c] = a.A[1][i1 * RR + c];
-      u0[c] = a.A[0][i0 * RR + c];
+      us[0][c][tid] = a.A[0][i0 * RR + c];
+      us[1][c][tid] = a.A[1][i1 * RR + c];
     }
     double tv = 0.0;
+#pragma unroll 1
     for (int x = 0; x < RR; ++x) {
-      const double* cx = cs + x * RR * RR;
+      const double* gx = core + x * RR * RR;
       double wx = 0.0;
-#pragma unroll
+#pragma unroll 2
       for (int y = 0; y < RR; ++y) {
-        double sy = 0.0;
+        // even and odd z as two chains (shorter dependent FMA sequences)
+        const double* g = gx + y * RR;
+        double se = 0.0, so = 0.0;
 #pragma unroll
-        for (int z = 0; z < RR; ++z) sy += cx[y * RR + z] * u2[z];
-        wx += sy * u1[y];
+        for (int z = 0; z + 1 < RR; z += 2) {
+          se = fma(g[z], u2[z], se);
+          so = fma(g[z + 1], u2[z + 1], so);
+        }
+        if (RR & 1) se = fma(g[RR - 1], u2[RR - 1], se);
+        wx = fma(se + so, us[1][y][tid], wx);
       }
-      tv += wx * u0[x];
+      tv = fma(wx, us[0][x][tid], tv);
     }
     double v = a.dtype == TSK_F64 ? static_cast<const double*>(a.vals)[e]
                                   : double(static_cast<const float*>(a.vals)[e]);
@@ -338,17 +345,17 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
     const size_t lds = core_lds ? size_t(csize) * 8 : 0;
     const bool eq = R[0] == R[1] && R[1] == R[2];
     if (eq && R[0] == 5)
-      hipLaunchKernelGGL(k_inner3x<5>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
-                         core_lds, fs.partial_inner, fs.partial_direct);
+      hipLaunchKernelGGL(k_inner3x<5>, dim3(fs.nblocks), dim3(kT), 0, st, a, T.nnz, per, core,
+                         fs.partial_inner, fs.partial_direct);
     else if (eq && R[0] == 8)
-      hipLaunchKernelGGL(k_inner3x<8>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
-                         core_lds, fs.partial_inner, fs.partial_direct);
+      hipLaunchKernelGGL(k_inner3x<8>, dim3(fs.nblocks), dim3(kT), 0, st, a, T.nnz, per, core,
+                         fs.partial_inner, fs.partial_direct);
     else if (eq && R[0] == 10)
-      hipLaunchKernelGGL(k_inner3x<10>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
-                         core_lds, fs.partial_inner, fs.partial_direct);
+      hipLaunchKernelGGL(k_inner3x<10>, dim3(fs.nblocks), dim3(kT), 0, st, a, T.nnz, per, core,
+                         fs.partial_inner, fs.partial_direct);
     else if (eq && R[0] == 16)
-      hipLaunchKernelGGL(k_inner3x<16>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
-                         core_lds, fs.partial_inner, fs.partial_direct);
+      hipLaunchKernelGGL(k_inner3x<16>, dim3(fs.nblocks), dim3(kT), 0, st, a, T.nnz, per, core,
+                         fs.partial_inner, fs.partial_direct);
     else if (rmax <= 8)
       hipLaunchKernelGGL(k_inner3<8>, dim3(fs.nblocks), dim3(kT), lds, st, a, T.nnz, per, core,
                          core_lds, fs.partial_inner, fs.partial_direct);

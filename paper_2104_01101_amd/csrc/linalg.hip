@@ -627,6 +627,276 @@ __global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, do
   eig_tail<NT>(q, R, d, e, e2, bet, M, y, lu, pivs, sh, lam, V, timers);
 }
 
+// ------------------------------------------ small symmetric eigenproblems ----
+// Leading R eigenpairs of a symmetric q x q matrix with q <= QM <= 32, in one
+// wavefront (no block barriers), same method as k_sym_eig_top:
+//   * Householder tridiagonalisation with row `lane` of the matrix in
+//     registers; v and w = p - K v are broadcast through LDS, and only the
+//     trailing block (rows and columns > j) is updated at step j;
+//   * eigenvalues by multisection of the Sturm count: 64 / R lanes per
+//     eigenvalue, four interleaved count chains per lane, until the bracket is
+//     below 1e-13 relative (inverse iteration needs no more; the scale of the
+//     vectors is set by normalisation, not by the eigenvalue);
+//   * eigenvectors of the tridiagonal by inverse iteration, one lane each, LU
+//     factors in LDS with the lane index fastest (no bank conflicts);
+//   * Gram-Schmidt only between vectors whose eigenvalues lie within
+//     1e-3 ||T||_1 of each other (elsewhere inverse iteration already gives
+//     orthogonal vectors), then back-transformation through the reflectors,
+//     four vectors per batched wave reduction.
+constexpr int kEigSmallMax = 32;
+
+template <int QM>
+__device__ inline void sturm4(const double (&d)[QM], const double (&e2)[QM], int q,
+                              const double (&x)[4], double pivmin, int (&c)[4]) {
+  double t[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    t[k] = d[0] - x[k];
+    c[k] = t[k] < 0.0;
+  }
+  // predicated rather than exited early, so that the loop unrolls and the
+  // register arrays keep constant indices
+#pragma unroll
+  for (int i = 1; i < QM; ++i) {
+    if (i < q) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (fabs(t[k]) <= pivmin) t[k] = -pivmin;
+        t[k] = fma(-e2[i - 1], rcp64(t[k]), d[i] - x[k]);
+        c[k] += t[k] < 0.0;
+      }
+    }
+  }
+}
+
+template <int QM>
+__global__ __launch_bounds__(64) void k_sym_eig_small(const double* Mg, int q, int R,
+                                                      double* lam, double* Vout) {
+  constexpr int YS = 65;  // row stride of the eigenvector block (odd: no bank conflicts)
+  __shared__ double vsh[64], wsh[64];
+  __shared__ double dsh[QM], esh[QM], bsh[QM], lsh[QM];
+  __shared__ double lu[4][QM][64];  // u0 (reciprocal pivots), u1, u2, multipliers
+  __shared__ int8_t pv[QM][64];
+  __shared__ double ysh[QM * YS];   // y_t(i) at i * YS + t
+  const int lane = threadIdx.x;
+
+  // ---- tridiagonalisation ----
+  double m[QM], vr[QM];
+#pragma unroll
+  for (int c = 0; c < QM; ++c) m[c] = (lane < q && c < q) ? Mg[lane * q + c] : 0.0;
+  static_for<0, QM>([&](auto JC) {
+    constexpr int J = decltype(JC)::value;
+    vr[J] = 0.0;
+    if (lane == 0) bsh[J] = 0.0;
+    if (J + 2 >= q) return;
+    const double xl = lane > J ? m[J] : 0.0;
+    const double nrm = sqrt(wave_allsum(xl * xl));
+    const double x0 = read_lane(m[J], J + 1);
+    const double alpha = nrm > 0.0 ? -copysign(nrm, x0) : 0.0;
+    const double v0 = x0 - alpha;
+    const double beta = nrm > 0.0 ? -1.0 / (alpha * v0) : 0.0;  // 2 / v^T v
+    const double vl = lane > J + 1 ? m[J] : (lane == J + 1 ? v0 : 0.0);
+    vr[J] = vl;
+    if (lane == 0) {
+      esh[J] = alpha;
+      bsh[J] = beta;
+    }
+    vsh[lane] = vl;
+    __syncthreads();
+    double p = 0.0;
+#pragma unroll
+    for (int c = J + 1; c < QM; ++c) p = fma(m[c], vsh[c], p);
+    p *= beta;
+    const double K = 0.5 * beta * wave_allsum(vl * p);
+    const double wl = fma(-K, vl, p);
+    wsh[lane] = wl;
+    __syncthreads();
+#pragma unroll
+    for (int c = J + 1; c < QM; ++c) m[c] = fma(-vl, wsh[c], fma(-wl, vsh[c], m[c]));
+    __syncthreads();
+  });
+  // diagonal (never changed after its own step) and the last subdiagonal entry
+  static_for<0, QM>([&](auto JC) {
+    constexpr int J = decltype(JC)::value;
+    const double dj = read_lane(m[J], J);
+    const double ej = J + 1 < QM ? read_lane(m[J], (J + 1) % QM) : 0.0;
+    if (lane == 0 && J < q) dsh[J] = dj;
+    if (lane == 0 && J + 2 == q) esh[J] = ej;
+  });
+  __syncthreads();
+
+  // ---- eigenvalues ----
+  double d[QM], e2[QM];
+  double glo = DBL_MAX, ghi = -DBL_MAX, onenrm = 0.0, emax2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < QM; ++i) {
+    d[i] = i < q ? dsh[i] : 0.0;
+    const double ei = i + 1 < q ? esh[i] : 0.0;
+    e2[i] = ei * ei;
+    emax2 = fmax(emax2, e2[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < QM; ++i)
+    if (i < q) {
+      const double r = (i > 0 ? fabs(esh[i - 1]) : 0.0) + (i + 1 < q ? fabs(esh[i]) : 0.0);
+      glo = fmin(glo, d[i] - r);
+      ghi = fmax(ghi, d[i] + r);
+      onenrm = fmax(onenrm, fabs(d[i]) + r);
+    }
+  {
+    const double pad = 2.0 * DBL_EPSILON * fmax(fabs(glo), fabs(ghi)) + DBL_MIN;
+    glo -= pad;
+    ghi += pad;
+  }
+  const double pivmin = DBL_MIN * fmax(1.0, emax2);
+  {
+    const int G = 64 / R, P = 4 * G;
+    const int gi = lane / G, gl = lane - gi * G;
+    const bool act = gi < R;
+    const int tgt = q - 1 - (act ? gi : 0);
+    const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << (act ? gi * G : 0);
+    double lo = glo, hi = ghi;
+    for (int it = 0; it < 64; ++it) {
+      const double width = hi - lo;
+      const bool conv = !(width > 1e-13 * fmax(fabs(lo), fabs(hi)) + pivmin);
+      if (__ballot(act && !conv) == 0ull) break;
+      double x[4];
+      int c[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = lo + width * double(4 * gl + k + 1) / double(P + 1);
+      sturm4<QM>(d, e2, q, x, pivmin, c);
+      int f = 4;
+#pragma unroll
+      for (int k = 3; k >= 0; --k)
+        if (c[k] > tgt) f = k;
+      const uint64_t hm = __ballot(act && f < 4) & gmask;
+      const int L = hm ? __ffsll((unsigned long long)hm) - 1 : lane;
+      const int fL = __shfl(f, L);
+      if (act && !conv) {
+        const int idx = hm ? 4 * (L - gi * G) + fL : P;  // first point above the target
+        const double nhi = idx < P ? lo + width * double(idx + 1) / double(P + 1) : hi;
+        const double nlo = idx > 0 ? lo + width * double(idx) / double(P + 1) : lo;
+        lo = nlo;
+        hi = nhi;
+      }
+    }
+    if (act && gl == 0) lsh[gi] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+
+  // ---- inverse iteration, lane t for eigenvalue t; vectors and factors in
+  // LDS with the lane index fastest, loops rolled (q is a run-time bound) ----
+  const double tiny = DBL_EPSILON * fmax(onenrm, DBL_MIN);
+  if (lane < R) {
+    const double mu = lsh[lane];
+    double* u0 = &lu[0][0][lane];
+    double* u1 = &lu[1][0][lane];
+    double* u2 = &lu[2][0][lane];
+    double* ml = &lu[3][0][lane];
+    int8_t* pl = &pv[0][lane];
+    double* y = ysh + lane;
+    double p = dsh[0] - mu, qq = q > 1 ? esh[0] : 0.0, rr = 0.0;
+    for (int i = 0; i + 1 < q; ++i) {
+      const double c = esh[i], a1 = dsh[i + 1] - mu, b1 = i + 2 < q ? esh[i + 1] : 0.0;
+      if (fabs(p) >= fabs(c)) {
+        const double pvv = p == 0.0 ? tiny : p;
+        const double mlt = c / pvv;
+        u0[i * 64] = 1.0 / pvv, u1[i * 64] = qq, u2[i * 64] = rr, pl[i * 64] = 0;
+        ml[i * 64] = mlt;
+        p = a1 - mlt * qq;
+        qq = b1 - mlt * rr;
+      } else {
+        const double mlt = p / c;
+        u0[i * 64] = 1.0 / c, u1[i * 64] = a1, u2[i * 64] = b1, pl[i * 64] = 1;
+        ml[i * 64] = mlt;
+        p = qq - mlt * a1;
+        qq = rr - mlt * b1;
+      }
+      rr = 0.0;
+    }
+    u0[(q - 1) * 64] = 1.0 / (p == 0.0 ? tiny : p);
+    u1[(q - 1) * 64] = 0.0;
+    u2[(q - 1) * 64] = 0.0;
+    for (int i = 0; i < q; ++i) {
+      const uint32_t h = uint32_t(i) * 2654435761u + uint32_t(lane + 1) * 40503u;
+      y[i * YS] = 1.0 + double((h >> 8) & 1023u) / 2048.0;
+    }
+    double scale = 1.0;
+    for (int itr = 0; itr < 3; ++itr) {
+      // forward: row interchanges and multipliers
+      double prev = y[0] * scale;
+#pragma unroll 4
+      for (int i = 0; i + 1 < q; ++i) {
+        double nx = y[(i + 1) * YS] * scale;
+        if (pl[i * 64]) {
+          const double t = prev;
+          prev = nx;
+          nx = t;
+        }
+        y[i * YS] = prev;
+        prev = nx - ml[i * 64] * prev;
+      }
+      y[(q - 1) * YS] = prev;
+      // backward: upper triangular with two superdiagonals
+      double n2 = 0.0, x1 = 0.0, x2 = 0.0;
+#pragma unroll 4
+      for (int i = q - 1; i >= 0; --i) {
+        const double xi = (y[i * YS] - u1[i * 64] * x1 - u2[i * 64] * x2) * u0[i * 64];
+        y[i * YS] = xi;
+        n2 += xi * xi;
+        x2 = x1;
+        x1 = xi;
+      }
+      scale = 1.0 / sqrt(n2);
+    }
+    for (int i = 0; i < q; ++i) y[i * YS] *= scale;
+  }
+  __syncthreads();
+
+  // ---- lane i holds element i of every vector from here on ----
+  double yl[QM];
+#pragma unroll
+  for (int t = 0; t < QM; ++t) yl[t] = (t < R && lane < q) ? ysh[lane * YS + t] : 0.0;
+  const double ortol = 1e-3 * onenrm;
+  static_for<1, QM>([&](auto TC) {
+    constexpr int T = decltype(TC)::value;
+    if (T >= R) return;
+    bool touched = false;
+    static_for<0, T>([&](auto UC) {
+      constexpr int U = decltype(UC)::value;
+      bool near = true;  // eigenvalues U..T chained within ortol (same cluster)
+#pragma unroll
+      for (int w = U; w < T; ++w) near = near && (lsh[w] - lsh[w + 1] <= ortol);
+      if (!near) return;
+      const double dot = wave_allsum(yl[U] * yl[T]);
+      yl[T] = fma(-dot, yl[U], yl[T]);
+      touched = true;
+    });
+    if (touched) yl[T] *= 1.0 / sqrt(wave_allsum(yl[T] * yl[T]));
+  });
+  // back-transform y <- H_0 ... H_{q-3} y
+  static_for<0, QM, true>([&](auto JC) {
+    constexpr int J = decltype(JC)::value;
+    if (J + 2 >= q) return;
+    const double beta = bsh[J];
+    static_for<0, QM / 4>([&](auto CC) {
+      constexpr int C0 = 4 * decltype(CC)::value;
+      if (C0 >= R) return;
+      double pr[4], w[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pr[u] = vr[J] * yl[C0 + u];
+      wave_sums<4>(pr, w);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) yl[C0 + u] = fma(-beta * w[u], vr[J], yl[C0 + u]);
+    });
+  });
+  if (lane < q)
+#pragma unroll
+    for (int t = 0; t < QM; ++t)
+      if (t < R) Vout[lane * R + t] = yl[t];
+  if (lane < R) lam[lane] = lsh[lane];
+}
+
 // ----------------------------------------------------- thin Householder QR ----
 // Q of the thin QR factorisation of C (r x k, k <= 64), given and returned by
 // rows of the transposes: Ct (k x r) with row j = column j of C, Qt (k x r)
@@ -799,84 +1069,123 @@ __global__ __launch_bounds__(64) void k_qr_reg(const double* Ct, int k, int r, d
 }
 
 // ---------------------------------------------- register-tiled SPD inverse ----
-// For n <= 128 the whole matrix lives in registers: 512 threads, thread t owns
-// rows tr + 16 a (a < 8) and columns tc + 32 b (b < 4), tr = t / 32, tc = t % 32.
-// The pivot column is broadcast through a small LDS vector that is only read
-// while the registers are updated (no store-to-load stalls).  Columns are
-// extracted with predicated stores from constant register indices so that the
-// tile is never demoted to scratch memory.
-constexpr int kRegT = 512, kRegMax = 128;
-
-
 // In-place inverse of an SPD matrix, n <= 128, by the symmetric sweep operator
-// (Goodnight 1979): sweeping pivot k maps a_kk -> -1/a_kk, a_ik -> a_ik/a_kk,
-// a_ij -> a_ij - a_ik a_kj / a_kk; after all pivots the matrix is -G^{-1}.  It
-// stays symmetric, so each step needs only column k broadcast; the pivots are
-// the Cholesky pivots squared (a non-positive one flags a non-SPD Gram).
-__global__ __launch_bounds__(kRegT) void k_spd_inverse_reg(double* G, int n, int lda, int* info) {
-  // pivot columns double-buffered in LDS: the owners of column k+1 publish it
-  // while step k is applied, so each step needs one barrier
-  __shared__ double colk[2][kRegMax];
-  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
-  double A[8][4];
+// (Goodnight 1979): sweeping a pivot set P maps A_PP -> -A_PP^{-1},
+// A_iP -> A_iP A_PP^{-1}, A_Pj -> A_PP^{-1} A_Pj and A_ij -> A_ij - A_iP
+// A_PP^{-1} A_Pj; sweeps of disjoint sets commute, and after every index has
+// been swept the matrix is -G^{-1}.  Pivots are taken two at a time: the 2 x 2
+// block is inverted through its Schur complement (the Cholesky pivots of the
+// pair, so a non-positive one flags a non-SPD Gram), which halves the number
+// of dependent steps and barriers.  256 threads; thread (tr, tc) = (t / 16,
+// t % 16) owns rows tr + 16 a and columns tc + 16 b (a, b < NB) in registers.
+// Indices >= n are padded with the identity, which the sweep leaves untouched,
+// so an odd n needs no special last step.  The two pivot columns of the next
+// step are published through LDS (double-buffered: one barrier per step).
+//
+// Only the pivot rows are fixed up: a swept column is never read again (the
+// next pivot columns are unswept, and every entry a later step reads from a
+// swept index lies in that index's row), so the rows, hence the lower triangle
+// in sweep order, stay exact; the result is mirrored from it through LDS.
+constexpr int kPairT = 256, kRegMax = 128;
+
+template <int NB>
+constexpr size_t spd_pair_lds() {
+  return size_t(16 * NB) * (16 * NB + 1) * 8;
+}
+
+template <int NB>
+__global__ __launch_bounds__(kPairT) void k_spd_inverse_pair(double* G, int n, int lda,
+                                                             int* info) {
+  constexpr int NP = 16 * NB, SP = NP + 1;
+  extern __shared__ double S[];  // NP x SP staging of the result
+  __shared__ double col[2][2][NP];
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+  double A[NB][NB];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < NB; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = tr + 16 * a, k = tc + 32 * b;
-      A[a][b] = (i < n && k < n) ? G[i * lda + k] : 0.0;
+    for (int b = 0; b < NB; ++b) {
+      const int i = tr + 16 * a, j = tc + 16 * b;
+      A[a][b] = (i < n && j < n) ? G[i * lda + j] : (i == j ? 1.0 : 0.0);
     }
-  if (tc == 0)  // column 0
+  if (tc < 2)  // columns 0 and 1
 #pragma unroll
-    for (int a = 0; a < 8; ++a) colk[0][tr + 16 * a] = A[a][0];
+    for (int a = 0; a < NB; ++a) col[0][tc][tr + 16 * a] = A[a][0];
   __syncthreads();
   int bad = 0;
-  for (int k = 0; k < n; ++k) {
-    const double* ck = colk[k & 1];
-    const double dk = ck[k];
-    if (!(dk > 0.0) && bad == 0) bad = k + 1;
-    const double rd = rcp64(dk);
-    double cj[4], cir[8];
+  const int steps = (n + 1) / 2;
+  // the pivot rows and the next pivot columns lie in register block p / 16,
+  // a constant of the outer (unrolled) loop, so the tile is never indexed
+  // dynamically
+  static_for<0, NB>([&](auto KC) {
+    constexpr int KB = decltype(KC)::value;
+    const int t1 = min(steps, 8 * (KB + 1));
+    for (int t = 8 * KB; t < t1; ++t) {
+      const int p = 2 * t, kt = p & 15;
+      const double* cp = col[t & 1][0];
+      const double* cq = col[t & 1][1];
+      const double dpp = cp[p], dpq = cp[p + 1], dqq = cq[p + 1];
+      const double r1 = rcp64(dpp);
+      const double l = dpq * r1;
+      const double sch = fma(-l, dpq, dqq);
+      const double r2 = rcp64(sch);
+      if (bad == 0) bad = !(dpp > 0.0) ? p + 1 : (!(sch > 0.0) ? p + 2 : 0);
+      // E = A_PP^{-1}
+      const double eqq = r2, epq = -l * r2, epp = fma(l * r2, l, r1);
+      double mp[NB], mq[NB], xp[NB], xq[NB];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) cj[b] = ck[tc + 32 * b];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) cir[a] = ck[tr + 16 * a] * rd;
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) A[a][b] = fma(-cir[a], cj[b], A[a][b]);
-    // pivot row and column: the register slot is a compile-time index, the
-    // test on it is wave-uniform, so only the owning lanes do any extra work
-    const int ka = k >> 4, kt = k & 15, kb = k >> 5, kc = k & 31;
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-      if (a == ka && tr == kt)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) A[a][b] = cj[b] * rd;
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      if (b == kb && tc == kc) {
-#pragma unroll
-        for (int a = 0; a < 8; ++a) A[a][b] = cir[a];
-#pragma unroll
-        for (int a = 0; a < 8; ++a)
-          if (a == ka && tr == kt) A[a][b] = -rd;
+      for (int a = 0; a < NB; ++a) {
+        const double ap = cp[tr + 16 * a], aq = cq[tr + 16 * a];
+        mp[a] = fma(ap, epp, aq * epq);  // (A_iP E)_p
+        mq[a] = fma(ap, epq, aq * eqq);
       }
-    // publish column k+1 (predicated stores from constant register indices)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-      if (tc + 32 * b == k + 1)
+      for (int b = 0; b < NB; ++b) {
+        xp[b] = cp[tc + 16 * b];  // A_pj = A_jp
+        xq[b] = cq[tc + 16 * b];
+      }
 #pragma unroll
-        for (int a = 0; a < 8; ++a) colk[(k + 1) & 1][tr + 16 * a] = A[a][b];
-    __syncthreads();
-  }
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) A[a][b] = fma(-mp[a], xp[b], fma(-mq[a], xq[b], A[a][b]));
+      // rows p, q (lanes tr = kt, kt + 1, which share a wave) -> E A_Pj, and
+      // the 2 x 2 block itself -> -E
+      if ((tr >> 1) == (kt >> 1)) {
+        const bool rowq = tr & 1;
+        const double f0 = rowq ? epq : epp, f1 = rowq ? eqq : epq;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) A[KB][b] = fma(f0, xp[b], f1 * xq[b]);
+        if (tc == kt) A[KB][KB] = -f0;
+        if (tc == kt + 1) A[KB][KB] = -f1;
+      }
+      // publish columns p + 2 and p + 3 (block KB, or KB + 1 after the last
+      // pair of this block)
+      const int nt = (p + 2) & 15;
+      if ((tc >> 1) == (nt >> 1)) {
+        double* dst = col[(t + 1) & 1][tc & 1];
+        if (nt != 0) {
+#pragma unroll
+          for (int a = 0; a < NB; ++a) dst[tr + 16 * a] = A[a][KB];
+        } else if (KB + 1 < NB) {
+#pragma unroll
+          for (int a = 0; a < NB; ++a) dst[tr + 16 * a] = A[a][(KB + 1) % NB];
+        }
+      }
+      __syncthreads();
+    }
+  });
   if (tid == 0) *info = bad;
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < NB; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = tr + 16 * a, k = tc + 32 * b;
-      if (i < n && k < n) G[i * lda + k] = -A[a][b];
+    for (int b = 0; b < NB; ++b) S[(tr + 16 * a) * SP + tc + 16 * b] = A[a][b];
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = tr + 16 * a, j = tc + 16 * b;
+      if (i < n && j < n) G[i * lda + j] = -(i >= j ? A[a][b] : S[j * SP + i]);
     }
 }
 
@@ -957,8 +1266,17 @@ tsk_status cholesky(double* G, int64_t n, int64_t lda, int* info, hipStream_t st
 bool spd_inverse_fits(int64_t n) { return size_t(n) * n * 8 + 1024 <= size_t(max_lds_bytes()); }
 
 tsk_status spd_inverse(double* G, int64_t n, int64_t lda, int* info, hipStream_t st) {
-  if (n <= kRegMax) {
-    hipLaunchKernelGGL(k_spd_inverse_reg, dim3(1), dim3(kRegT), 0, st, G, int(n), int(lda), info);
+  const size_t pair_lds = n <= 64 ? spd_pair_lds<4>() : n <= 112 ? spd_pair_lds<7>() : spd_pair_lds<8>();
+  if (n <= kRegMax && pair_lds + 8192 <= size_t(max_lds_bytes())) {
+    if (n <= 64)
+      hipLaunchKernelGGL(k_spd_inverse_pair<4>, dim3(1), dim3(kPairT), spd_pair_lds<4>(), st, G,
+                         int(n), int(lda), info);
+    else if (n <= 112)
+      hipLaunchKernelGGL(k_spd_inverse_pair<7>, dim3(1), dim3(kPairT), spd_pair_lds<7>(), st, G,
+                         int(n), int(lda), info);
+    else
+      hipLaunchKernelGGL(k_spd_inverse_pair<8>, dim3(1), dim3(kPairT), spd_pair_lds<8>(), st, G,
+                         int(n), int(lda), info);
     TSK_LAUNCHED();
     return TSK_OK;
   }
@@ -998,6 +1316,18 @@ tsk_status chol_solve_rows(const double* L, int64_t n, int64_t ldl, double* X, i
 
 tsk_status sym_eig_top(double* M, int64_t q, int64_t R, double* lam, double* V, Ws& ws,
                        hipStream_t st) {
+  if (q <= kEigSmallMax && R >= 1 && R <= q) {
+    if (ws.measuring()) return TSK_OK;
+    ProfScope prof("eig", st);
+    if (q <= 16)
+      hipLaunchKernelGGL(k_sym_eig_small<16>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V);
+    else if (q <= 24)
+      hipLaunchKernelGGL(k_sym_eig_small<24>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V);
+    else
+      hipLaunchKernelGGL(k_sym_eig_small<32>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V);
+    TSK_LAUNCHED();
+    return TSK_OK;
+  }
   double* scratch = ws.take<double>(size_t(5) * R * q);
   int8_t* pivs = ws.take<int8_t>(size_t(R) * q);
   if (ws.measuring()) return TSK_OK;
