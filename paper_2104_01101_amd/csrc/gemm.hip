@@ -14,6 +14,8 @@
 // from one vector read.  Split-K partials are FP64 and are summed by a
 // separate kernel in a fixed order (deterministic).
 
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -160,6 +162,58 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn(int64_t M, int64_t N, int6
       }
 }
 
+// Skinny FP64 products (one side of C at most 64): a workgroup of 8 waves
+// computes one 16 x 16 tile of C over the whole contraction, each wave a
+// contiguous slice of K with v_mfma_f64_16x16x4 (lane l feeds A(m0 + l%16,
+// k) and B(k, n0 + l%16), k = k0 + l/16), operands loaded straight into
+// registers 64 k at a time so that a wave has 32 loads in flight; the 8
+// partial tiles are summed in LDS in wave order (deterministic, no split-K
+// launch and no separate reduction).
+constexpr int kSkW = 8, kSkT = 64 * kSkW, kSkChunk = 64;
+
+template <bool A_MK>
+__global__ __launch_bounds__(kSkT) void k_gemm_skinny(int64_t M, int64_t N, int64_t K,
+                                                      const double* A1, int64_t lda1, int64_t M1,
+                                                      const double* A2, int64_t lda2,
+                                                      const double* B, int64_t ldb, double* C,
+                                                      int64_t ldc) {
+  __shared__ double red[kSkW][16][17];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t m0 = int64_t(blockIdx.x) * 16, n0 = int64_t(blockIdx.y) * 16;
+  const int64_t i = m0 + li, j = n0 + li;
+  const int64_t kper = ((K + kSkW * 4 - 1) / (kSkW * 4)) * 4;
+  const int64_t kb = wave * kper, ke = kb + kper < K ? kb + kper : K;
+  const bool iv = i < M, jv = j < N;
+  const double* arow = A_MK ? A1 + i * lda1 : nullptr;
+  doublex4 acc = {0, 0, 0, 0};
+  for (int64_t k0 = kb; k0 < ke; k0 += kSkChunk) {
+    double a[kSkChunk / 4], b[kSkChunk / 4];
+#pragma unroll
+    for (int u = 0; u < kSkChunk / 4; ++u) {
+      const int64_t k = k0 + 4 * u + g;
+      const bool kv = k < ke;
+      a[u] = 0.0;
+      b[u] = 0.0;
+      if (kv && iv) a[u] = A_MK ? arow[k] : load_a(A1, lda1, M1, A2, lda2, k, i);
+      if (kv && jv) b[u] = B[k * ldb + j];
+    }
+#pragma unroll
+    for (int u = 0; u < kSkChunk / 4; ++u)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[wave][g + 4 * v][li] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kSkW; ++w) s += red[w][r][c];
+    if (m0 + r < M && n0 + c < N) C[(m0 + r) * ldc + n0 + c] = s;
+  }
+}
+
 __global__ void k_reduce_splits(const double* part, int64_t M, int64_t N, int splits,
                                 double* C, int64_t ldc) {
   int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -193,19 +247,37 @@ __global__ void k_to_f64(const void* src, int bytes, int64_t n, double* dst) {
     dst[t] = double(bf16_bits_to_f32(static_cast<const uint16_t*>(src)[t]));
 }
 
+// Split-K plan: at least ~512 workgroups when the output has few tiles, at
+// least four BK blocks of the contraction per split.
+template <class E>
+void split_plan(int64_t M, int64_t N, int64_t K, int64_t& splits, int64_t& kchunk) {
+  constexpr int BK = Cfg<E>::BK;
+  const int64_t tm = ceil_div(M, kBM), tn = ceil_div(N, kBN);
+  const int64_t kblocks = ceil_div(K, BK);
+  splits = ceil_div(512, tm * tn);
+  const int64_t maxs = kblocks / 4;
+  if (splits > maxs) splits = maxs;
+  if (splits < 1) splits = 1;
+  kchunk = ceil_div(kblocks, splits) * BK;
+  splits = K > 0 ? ceil_div(K, kchunk) : 1;
+}
+
 template <class E, bool A_MK>
 tsk_status gemm_tn_t(int64_t M, int64_t N, int64_t K, const void* A1, int64_t lda1, int64_t M1,
                      const void* A2, int64_t lda2, const void* B, int64_t ldb, double* C,
                      int64_t ldc, Ws& ws, hipStream_t st) {
-  constexpr int BK = Cfg<E>::BK;
+  if (std::is_same<E, double>::value && (M <= 64 || N <= 64) && K > 0) {
+    if (ws.measuring() || M == 0 || N == 0) return TSK_OK;
+    hipLaunchKernelGGL((k_gemm_skinny<A_MK>), dim3(ceil_div(M, 16), ceil_div(N, 16)), dim3(kSkT),
+                       0, st, M, N, K, static_cast<const double*>(A1), lda1, M1,
+                       static_cast<const double*>(A2), lda2, static_cast<const double*>(B), ldb,
+                       C, ldc);
+    TSK_LAUNCHED();
+    return TSK_OK;
+  }
   int64_t tm = ceil_div(M, kBM), tn = ceil_div(N, kBN);
-  int64_t kblocks = ceil_div(K, BK);
-  int64_t splits = ceil_div(512, tm * tn);
-  int64_t maxs = kblocks / 4;
-  if (splits > maxs) splits = maxs;
-  if (splits < 1) splits = 1;
-  int64_t kchunk = ceil_div(kblocks, splits) * BK;
-  splits = K > 0 ? ceil_div(K, kchunk) : 1;
+  int64_t splits, kchunk;
+  split_plan<E>(M, N, K, splits, kchunk);
   double* part = splits > 1 ? ws.take<double>(splits * M * N) : nullptr;
   if (ws.measuring()) return TSK_OK;
   if (M == 0 || N == 0) return TSK_OK;

@@ -104,7 +104,17 @@ tsk_status sym_eig_top(double* M, int64_t q, int64_t R, double* lam, double* V, 
 tsk_status spd_inverse(double* G, int64_t n, int64_t lda, int* info, hipStream_t st);
 bool spd_inverse_fits(int64_t n);
 // Make the entry of largest magnitude of every column of A (rows x R) positive.
-tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, hipStream_t st);
+// sgn (optional, R entries) receives the sign applied to each column
+tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, hipStream_t st,
+                            double* sgn = nullptr);
+// Range basis of the randomized solve: C = B C0 (r x k), Q = qr(C), P = B Q
+// (r x k row-major); r <= 128, k <= 24 (range_basis_fits).
+bool range_basis_fits(int64_t r, int64_t k);
+tsk_status range_basis(const double* C0, const double* B, int64_t r, int64_t k, double* Q,
+                       double* P, hipStream_t st);
+// W = Q U diag(lam * sgn), Q given as r x k (q_rows) or as Q^T (k x r), U (k x R)
+tsk_status rsvd_w(const double* Qm, bool q_rows, const double* U, const double* lam,
+                  const double* sgn, int64_t k, int64_t r, int64_t R, double* W, hipStream_t st);
 // A (rows x R): A <- A * diag(scale) with scale[c] = 1/sqrt(lam[c])
 tsk_status scale_columns_inv_sqrt(double* A, int64_t rows, int64_t R, const double* lam,
                                   hipStream_t st);

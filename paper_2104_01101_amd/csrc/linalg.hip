@@ -633,10 +633,11 @@ __global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, do
 //   * Householder tridiagonalisation with row `lane` of the matrix in
 //     registers; v and w = p - K v are broadcast through LDS, and only the
 //     trailing block (rows and columns > j) is updated at step j;
-//   * eigenvalues by multisection of the Sturm count: 64 / R lanes per
-//     eigenvalue, four interleaved count chains per lane, until the bracket is
-//     below 1e-13 relative (inverse iteration needs no more; the scale of the
-//     vectors is set by normalisation, not by the eigenvalue);
+//   * eigenvalues by multisection of the Sturm count: a first round of 256
+//     points shared by all, then 64 / R lanes per eigenvalue, four interleaved
+//     count chains per lane, until the bracket is below 1e-11 relative (enough
+//     for inverse iteration); the returned eigenvalue is the Rayleigh quotient
+//     of the computed eigenvector of the tridiagonal;
 //   * eigenvectors of the tridiagonal by inverse iteration, one lane each, LU
 //     factors in LDS with the lane index fastest (no bank conflicts);
 //   * Gram-Schmidt only between vectors whose eigenvalues lie within
@@ -671,14 +672,18 @@ __device__ inline void sturm4(const double (&d)[QM], const double (&e2)[QM], int
 
 template <int QM>
 __global__ __launch_bounds__(64) void k_sym_eig_small(const double* Mg, int q, int R,
-                                                      double* lam, double* Vout) {
+                                                      double* lam, double* Vout,
+                                                      uint64_t* timers) {
   constexpr int YS = 65;  // row stride of the eigenvector block (odd: no bank conflicts)
   __shared__ double vsh[64], wsh[64];
   __shared__ double dsh[QM], esh[QM], bsh[QM], lsh[QM];
   __shared__ double lu[4][QM][64];  // u0 (reciprocal pivots), u1, u2, multipliers
   __shared__ int8_t pv[QM][64];
   __shared__ double ysh[QM * YS];   // y_t(i) at i * YS + t
+  __shared__ int cst[QM];           // first index of the eigenvalue cluster of t
+  __shared__ int cnt[256];          // Sturm counts of the first multisection round
   const int lane = threadIdx.x;
+  if (timers && lane == 0) timers[0] = wall_clock64();
 
   // ---- tridiagonalisation ----
   double m[QM], vr[QM];
@@ -715,6 +720,7 @@ __global__ __launch_bounds__(64) void k_sym_eig_small(const double* Mg, int q, i
     for (int c = J + 1; c < QM; ++c) m[c] = fma(-vl, wsh[c], fma(-wl, vsh[c], m[c]));
     __syncthreads();
   });
+  if (timers && lane == 0) timers[1] = wall_clock64();
   // diagonal (never changed after its own step) and the last subdiagonal entry
   static_for<0, QM>([&](auto JC) {
     constexpr int J = decltype(JC)::value;
@@ -755,10 +761,30 @@ __global__ __launch_bounds__(64) void k_sym_eig_small(const double* Mg, int q, i
     const bool act = gi < R;
     const int tgt = q - 1 - (act ? gi : 0);
     const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << (act ? gi * G : 0);
+    // first round shared by all eigenvalues: 256 points over the Gershgorin
+    // interval, counts (non-decreasing in the point index) through LDS
     double lo = glo, hi = ghi;
+    {
+      double x[4];
+      int c[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = glo + (ghi - glo) * double(4 * lane + k + 1) / 257.0;
+      sturm4<QM>(d, e2, q, x, pivmin, c);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) cnt[4 * lane + k] = c[k];
+      __syncthreads();
+      int a = 0, b = 256;  // first point with count > tgt
+      while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (cnt[mid] > tgt) b = mid;
+        else a = mid + 1;
+      }
+      if (a < 256) hi = glo + (ghi - glo) * double(a + 1) / 257.0;
+      if (a > 0) lo = glo + (ghi - glo) * double(a) / 257.0;
+    }
     for (int it = 0; it < 64; ++it) {
       const double width = hi - lo;
-      const bool conv = !(width > 1e-13 * fmax(fabs(lo), fabs(hi)) + pivmin);
+      const bool conv = !(width > 1e-11 * fmax(fabs(lo), fabs(hi)) + pivmin);
       if (__ballot(act && !conv) == 0ull) break;
       double x[4];
       int c[4];
@@ -783,6 +809,7 @@ __global__ __launch_bounds__(64) void k_sym_eig_small(const double* Mg, int q, i
     if (act && gl == 0) lsh[gi] = 0.5 * (lo + hi);
   }
   __syncthreads();
+  if (timers && lane == 0) timers[2] = wall_clock64();
 
   // ---- inverse iteration, lane t for eigenvalue t; vectors and factors in
   // LDS with the lane index fastest, loops rolled (q is a run-time bound) ----
@@ -849,45 +876,61 @@ __global__ __launch_bounds__(64) void k_sym_eig_small(const double* Mg, int q, i
       }
       scale = 1.0 / sqrt(n2);
     }
-    for (int i = 0; i < q; ++i) y[i * YS] *= scale;
+    double rq = 0.0;
+    for (int i = 0; i < q; ++i) {
+      const double yi = y[i * YS] * scale;
+      y[i * YS] = yi;
+      double ty = dsh[i] * yi;
+      if (i > 0) ty = fma(esh[i - 1], y[(i - 1) * YS], ty);
+      if (i + 1 < q) ty = fma(esh[i], y[(i + 1) * YS] * scale, ty);
+      rq = fma(yi, ty, rq);
+    }
+    lsh[lane] = rq;
+  }
+  if (lane == 0) {  // clusters: runs of eigenvalues closer than ortol
+    const double ortol = 1e-3 * onenrm;
+    int st = 0;
+    for (int t = 0; t < R; ++t) {
+      if (t > 0 && lsh[t - 1] - lsh[t] > ortol) st = t;
+      cst[t] = st;
+    }
   }
   __syncthreads();
+  if (timers && lane == 0) timers[3] = wall_clock64();
 
   // ---- lane i holds element i of every vector from here on ----
   double yl[QM];
 #pragma unroll
   for (int t = 0; t < QM; ++t) yl[t] = (t < R && lane < q) ? ysh[lane * YS + t] : 0.0;
-  const double ortol = 1e-3 * onenrm;
   static_for<1, QM>([&](auto TC) {
     constexpr int T = decltype(TC)::value;
     if (T >= R) return;
-    bool touched = false;
+    const int first = cst[T];
+    if (first == T) return;
     static_for<0, T>([&](auto UC) {
       constexpr int U = decltype(UC)::value;
-      bool near = true;  // eigenvalues U..T chained within ortol (same cluster)
-#pragma unroll
-      for (int w = U; w < T; ++w) near = near && (lsh[w] - lsh[w + 1] <= ortol);
-      if (!near) return;
+      if (U < first) return;
       const double dot = wave_allsum(yl[U] * yl[T]);
       yl[T] = fma(-dot, yl[U], yl[T]);
-      touched = true;
     });
-    if (touched) yl[T] *= 1.0 / sqrt(wave_allsum(yl[T] * yl[T]));
+    yl[T] *= 1.0 / sqrt(wave_allsum(yl[T] * yl[T]));
   });
+  if (timers && lane == 0) timers[4] = wall_clock64();
   // back-transform y <- H_0 ... H_{q-3} y
   static_for<0, QM, true>([&](auto JC) {
     constexpr int J = decltype(JC)::value;
     if (J + 2 >= q) return;
     const double beta = bsh[J];
-    static_for<0, QM / 4>([&](auto CC) {
-      constexpr int C0 = 4 * decltype(CC)::value;
+    constexpr int CH = QM >= 24 ? 12 : 8;
+    static_for<0, QM / CH>([&](auto CC) {
+      constexpr int C0 = CH * decltype(CC)::value;
       if (C0 >= R) return;
-      double pr[4], w[4];
+      double pr[CH], w[CH];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) pr[u] = vr[J] * yl[C0 + u];
-      wave_sums<4>(pr, w);
+      for (int u = 0; u < CH; ++u) pr[u] = vr[J] * yl[C0 + u];
+      wave_sums<CH>(pr, w);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) yl[C0 + u] = fma(-beta * w[u], vr[J], yl[C0 + u]);
+      for (int u = 0; u < CH; ++u) yl[C0 + u] = fma(-beta * w[u], vr[J], yl[C0 + u]);
     });
   });
   if (lane < q)
@@ -895,6 +938,7 @@ __global__ __launch_bounds__(64) void k_sym_eig_small(const double* Mg, int q, i
     for (int t = 0; t < QM; ++t)
       if (t < R) Vout[lane * R + t] = yl[t];
   if (lane < R) lam[lane] = lsh[lane];
+  if (timers && lane == 0) timers[5] = wall_clock64();
 }
 
 // ----------------------------------------------------- thin Householder QR ----
@@ -998,17 +1042,11 @@ constexpr int kQrRegRows = 128, kQrRegMaxK = 24;
 
 __host__ __device__ constexpr int round4(int n) { return (n + 3) / 4 * 4; }
 
+// Q of the thin QR of the k columns held in X (lane l: rows l, l + 64),
+// returned in Q with the same layout; one wavefront.
 template <int KM>
-__global__ __launch_bounds__(64) void k_qr_reg(const double* Ct, int k, int r, double* Qt) {
-  const int lane = threadIdx.x;
-  double X[2][KM];
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int c = 0; c < KM; ++c) {
-      const int i = lane + 64 * p;
-      X[p][c] = (i < r && c < k) ? Ct[c * r + i] : 0.0;
-    }
+__device__ __forceinline__ void qr_reg_wave(double (&X)[2][KM], int k, double (&Q)[2][KM]) {
+  const int lane = threadIdx.x & 63;
   double beta[KM];
   static_for<0, KM>([&](auto JC) {
     constexpr int J = decltype(JC)::value;
@@ -1037,7 +1075,6 @@ __global__ __launch_bounds__(64) void k_qr_reg(const double* Ct, int k, int r, d
   });
   // Q = H_0 ... H_{k-1} [I_k; 0]; H_j leaves columns < j of the partial
   // product untouched (they are still unit vectors e_c, c < j)
-  double Q[2][KM];
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -1059,6 +1096,20 @@ __global__ __launch_bounds__(64) void k_qr_reg(const double* Ct, int k, int r, d
       Q[1][J + u] = fma(-g, X[1][J], Q[1][J + u]);
     }
   });
+}
+
+template <int KM>
+__global__ __launch_bounds__(64) void k_qr_reg(const double* Ct, int k, int r, double* Qt) {
+  const int lane = threadIdx.x;
+  double X[2][KM], Q[2][KM];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int c = 0; c < KM; ++c) {
+      const int i = lane + 64 * p;
+      X[p][c] = (i < r && c < k) ? Ct[c * r + i] : 0.0;
+    }
+  qr_reg_wave<KM>(X, k, Q);
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -1066,6 +1117,83 @@ __global__ __launch_bounds__(64) void k_qr_reg(const double* Ct, int k, int r, d
       const int i = lane + 64 * p;
       if (i < r && c < k) Qt[c * r + i] = Q[p][c];
     }
+}
+
+// Range basis of the randomized solve (Alg. 5), for r <= 128 and k <= KM:
+// with B = (Z^T Z)^{-1} and C0 = Z^T Y Omega given, C = B C0, Q = qr(C) and
+// P = B Q, all r x k row-major.  256 threads: B, C0/C and Q are staged
+// in LDS; the two products use every thread, the QR wave 0 (register
+// Householder, as k_qr_reg).
+constexpr int kRbT = 256;
+
+template <int KM>
+__global__ __launch_bounds__(kRbT) void k_range_basis(const double* C0, const double* B, int r,
+                                                      int k, double* Qout, double* Pout) {
+  extern __shared__ double rb[];
+  const int lb = r + 1;            // odd row stride: rows of B spread over the banks
+  double* Bs = rb;                 // r x lb
+  double* Cs = rb + r * lb;        // r x KM: C, then Q
+  double* Ts = Cs + r * KM;        // r x KM: C0
+  const int tid = threadIdx.x;
+  for (int t = tid; t < r * r; t += kRbT) Bs[(t / r) * lb + t % r] = B[t];
+  for (int t = tid; t < r * KM; t += kRbT) {
+    const int i = t / KM, c = t % KM;
+    Ts[t] = c < k ? C0[i * k + c] : 0.0;
+  }
+  __syncthreads();
+  // C = B C0: thread (i, h) forms columns [h KM/2, (h + 1) KM/2) of row i;
+  // the C0 values it needs are the same for all lanes of a half (broadcast)
+  constexpr int HC = KM / 2;
+  const int ri = tid % 128, rh = tid / 128;
+  if (ri < r) {
+    double acc[HC];
+#pragma unroll
+    for (int c = 0; c < HC; ++c) acc[c] = 0.0;
+    for (int j = 0; j < r; ++j) {
+      const double b = Bs[ri * lb + j];
+#pragma unroll
+      for (int c = 0; c < HC; ++c) acc[c] = fma(b, Ts[j * KM + rh * HC + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < HC; ++c) Cs[ri * KM + rh * HC + c] = acc[c];
+  }
+  __syncthreads();
+  if (tid < 64) {
+    double X[2][KM], Q[2][KM];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int c = 0; c < KM; ++c) {
+        const int i = tid + 64 * p;
+        X[p][c] = i < r ? Cs[i * KM + c] : 0.0;
+      }
+    qr_reg_wave<KM>(X, k, Q);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int c = 0; c < KM; ++c) {
+        const int i = tid + 64 * p;
+        if (i < r) {
+          Cs[i * KM + c] = Q[p][c];
+          if (c < k) Qout[i * k + c] = Q[p][c];
+        }
+      }
+  }
+  __syncthreads();
+  // P = B Q, same split
+  if (ri < r) {
+    double acc[HC];
+#pragma unroll
+    for (int c = 0; c < HC; ++c) acc[c] = 0.0;
+    for (int j = 0; j < r; ++j) {
+      const double b = Bs[ri * lb + j];
+#pragma unroll
+      for (int c = 0; c < HC; ++c) acc[c] = fma(b, Cs[j * KM + rh * HC + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < HC; ++c)
+      if (rh * HC + c < k) Pout[ri * k + rh * HC + c] = acc[c];
+  }
 }
 
 // ---------------------------------------------- register-tiled SPD inverse ----
@@ -1190,7 +1318,7 @@ __global__ __launch_bounds__(kPairT) void k_spd_inverse_pair(double* G, int n, i
 }
 
 // -------------------------------------------------------------- sign fix ----
-__global__ void k_sign_fix(double* A, int64_t rows, int64_t R) {
+__global__ void k_sign_fix(double* A, int64_t rows, int64_t R, double* sgn) {
   __shared__ double bv[256];
   __shared__ int64_t bi[256];
   const int64_t c = blockIdx.x;
@@ -1213,9 +1341,23 @@ __global__ void k_sign_fix(double* A, int64_t rows, int64_t R) {
     __syncthreads();
   }
   const bool flip = A[bi[0] * R + c] < 0.0;
+  if (sgn && threadIdx.x == 0) sgn[c] = flip ? -1.0 : 1.0;
   __syncthreads();
   if (flip)
     for (int64_t i = threadIdx.x; i < rows; i += 256) A[i * R + c] = -A[i * R + c];
+}
+
+// W (r x R) = Q U diag(lam * sgn) with Q given by rows of Q^T (k x r) and U
+// (k x R) already scaled by lam^{-1/2}: Q times the left singular vectors
+// times the singular values, in the column signs chosen for the right ones.
+__global__ void k_rsvd_w(const double* Qm, bool q_rows, const double* U, const double* lam,
+                         const double* sgn, int k, int r, int R, double* W) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= r * R) return;
+  const int i = t / R, c = t % R;
+  double s = 0.0;
+  for (int j = 0; j < k; ++j) s = fma(q_rows ? Qm[i * k + j] : Qm[j * r + i], U[j * R + c], s);
+  W[t] = s * lam[c] * sgn[c];
 }
 
 __global__ void k_scale_inv_sqrt(double* A, int64_t rows, int64_t R, const double* lam) {
@@ -1316,15 +1458,19 @@ tsk_status chol_solve_rows(const double* L, int64_t n, int64_t ldl, double* X, i
 
 tsk_status sym_eig_top(double* M, int64_t q, int64_t R, double* lam, double* V, Ws& ws,
                        hipStream_t st) {
+  auto* nt = static_cast<uint64_t*>(nullptr);
   if (q <= kEigSmallMax && R >= 1 && R <= q) {
     if (ws.measuring()) return TSK_OK;
     ProfScope prof("eig", st);
     if (q <= 16)
-      hipLaunchKernelGGL(k_sym_eig_small<16>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V);
+      hipLaunchKernelGGL(k_sym_eig_small<16>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V,
+                         nt);
     else if (q <= 24)
-      hipLaunchKernelGGL(k_sym_eig_small<24>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V);
+      hipLaunchKernelGGL(k_sym_eig_small<24>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V,
+                         nt);
     else
-      hipLaunchKernelGGL(k_sym_eig_small<32>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V);
+      hipLaunchKernelGGL(k_sym_eig_small<32>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V,
+                         nt);
     TSK_LAUNCHED();
     return TSK_OK;
   }
@@ -1343,7 +1489,6 @@ tsk_status sym_eig_top(double* M, int64_t q, int64_t R, double* lam, double* V, 
   const bool v_lds = sbytes + (m_lds ? mbytes : 0) + vbytes <= budget;
   const size_t lds = sbytes + (m_lds ? mbytes : 0) + (v_lds ? vbytes : 0);
   ProfScope prof("eig", st);
-  auto* nt = static_cast<uint64_t*>(nullptr);
   if (m_lds)
     hipLaunchKernelGGL((k_sym_eig_top<kEigT, true, true>), dim3(1), dim3(kEigT), lds, st, M,
                        int(q), int(R), lam, V, scratch, pivs, nt);
@@ -1386,8 +1531,43 @@ tsk_status qr_rows(const double* Ct, int64_t k, int64_t r, double* Qt, Ws& ws, h
   return TSK_OK;
 }
 
-tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, hipStream_t st) {
-  hipLaunchKernelGGL(k_sign_fix, dim3(R), dim3(256), 0, st, A, rows, R);
+bool range_basis_fits(int64_t r, int64_t k) {
+  const size_t lds = (size_t(r) * (r + 1) + 2 * size_t(r) * kQrRegMaxK) * 8;
+  return r <= kQrRegRows && k <= kQrRegMaxK && k <= r && lds + 1024 <= size_t(max_lds_bytes());
+}
+
+tsk_status range_basis(const double* C0, const double* B, int64_t r, int64_t k, double* Q,
+                       double* P, hipStream_t st) {
+  if (!range_basis_fits(r, k)) {
+    set_error("range basis with r = %lld, k = %lld is not supported", (long long)r,
+              (long long)k);
+    return TSK_EUNSUPPORTED;
+  }
+  const int KM = k <= 8 ? 8 : (k <= 16 ? 16 : 24);
+  const size_t lds = (size_t(r) * (r + 1) + 2 * size_t(r) * KM) * 8;
+  if (KM == 8)
+    hipLaunchKernelGGL(k_range_basis<8>, dim3(1), dim3(kRbT), lds, st, C0, B, int(r), int(k), Q,
+                       P);
+  else if (KM == 16)
+    hipLaunchKernelGGL(k_range_basis<16>, dim3(1), dim3(kRbT), lds, st, C0, B, int(r), int(k),
+                       Q, P);
+  else
+    hipLaunchKernelGGL(k_range_basis<24>, dim3(1), dim3(kRbT), lds, st, C0, B, int(r), int(k),
+                       Q, P);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, hipStream_t st, double* sgn) {
+  hipLaunchKernelGGL(k_sign_fix, dim3(R), dim3(256), 0, st, A, rows, R, sgn);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+tsk_status rsvd_w(const double* Qm, bool q_rows, const double* U, const double* lam,
+                  const double* sgn, int64_t k, int64_t r, int64_t R, double* W, hipStream_t st) {
+  hipLaunchKernelGGL(k_rsvd_w, dim3(ceil_div(r * R, 256)), dim3(256), 0, st, Qm, q_rows, U, lam,
+                     sgn, int(k), int(r), int(R), W);
   TSK_LAUNCHED();
   return TSK_OK;
 }

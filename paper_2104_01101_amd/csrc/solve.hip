@@ -89,12 +89,32 @@ tsk_status rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_
   double* Mk = ws.take<double>(size_t(k) * k);
   double* lam = ws.take<double>(R);
   double* U = ws.take<double>(size_t(k) * R);
-  double* DA = ws.take<double>(size_t(k) * R);
+  double* sgn = ws.take<double>(R);
   const bool gj = spd_inverse_fits(r);
   const bool run = !ws.measuring();
   {
     ProfScope prof(run ? "gram" : "", st);
     TSK_TRY(gemm_tn(prec, r + s, r, m, Z, r, r, Y, s, Z, r, GH, r, ws, st));
+  }
+  if (gj && range_basis_fits(r, k)) {
+    // fused chain: C0 = H Omega, B = G^{-1}, then C = B C0, Q = qr(C),
+    // P = B Q in one launch; D^T = H^T P and the Gram D D^T
+    double* Q = Qt;  // r x k here
+    double* C0 = C0t;
+    {
+      ProfScope prof(run ? "solve_la" : "", st);
+      TSK_TRY(gemm_tn(TSK_PREC_F64, r, k, s, Ht, r, r, nullptr, 0, Om, k, C0, k, ws, st));
+      if (run) TSK_TRY(spd_inverse(G, r, r, info, st));
+      if (run) TSK_TRY(range_basis(C0, G, r, k, Q, P, st));
+      TSK_TRY(gemm_nn_f64(s, k, r, Ht, r, P, k, Dt, k, ws, st));
+      TSK_TRY(gemm_tn(TSK_PREC_F64, k, k, s, Dt, k, k, nullptr, 0, Dt, k, Mk, k, ws, st));
+    }
+    TSK_TRY(sym_eig_top(Mk, k, R, lam, U, ws, st));
+    if (run) TSK_TRY(scale_columns_inv_sqrt(U, k, R, lam, st));
+    TSK_TRY(gemm_nn_f64(s, R, k, Dt, k, U, R, A, R, ws, st));
+    if (run) TSK_TRY(sign_fix_columns(A, s, R, st, sgn));
+    if (run) TSK_TRY(rsvd_w(Q, true, U, lam, sgn, k, r, R, W, st));
+    return TSK_OK;
   }
   {
     ProfScope prof(run ? "solve_la" : "", st);
@@ -118,13 +138,15 @@ tsk_status rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_
     TSK_TRY(gemm_nn_f64(s, k, r, Ht, r, P, k, Dt, k, ws, st));
     TSK_TRY(gemm_tn(TSK_PREC_F64, k, k, s, Dt, k, k, nullptr, 0, Dt, k, Mk, k, ws, st));
   }
+  // SVD of D = Q^T B Z^T Y (k x s) from the eigenpairs of D D^T = Dt^T Dt:
+  // right singular vectors A = D^T U Sigma^{-1} = Dt (U lam^{-1/2}), left
+  // factor W = Q U Sigma, both in the column signs that make the largest
+  // entry of each column of A positive
   TSK_TRY(sym_eig_top(Mk, k, R, lam, U, ws, st));
+  if (run) TSK_TRY(scale_columns_inv_sqrt(U, k, R, lam, st));
   TSK_TRY(gemm_nn_f64(s, R, k, Dt, k, U, R, A, R, ws, st));
-  if (run) TSK_TRY(scale_columns_inv_sqrt(A, s, R, lam, st));
-  TSK_TRY(cholqr(A, s, R, info + 1, ws, st));
-  if (run) TSK_TRY(sign_fix_columns(A, s, R, st));
-  TSK_TRY(gemm_tn(TSK_PREC_F64, k, R, s, Dt, k, k, nullptr, 0, A, R, DA, R, ws, st));
-  TSK_TRY(gemm_tn(TSK_PREC_F64, r, R, k, Qt, r, r, nullptr, 0, DA, R, W, R, ws, st));
+  if (run) TSK_TRY(sign_fix_columns(A, s, R, st, sgn));
+  if (run) TSK_TRY(rsvd_w(Qt, false, U, lam, sgn, k, r, R, W, st));
   return TSK_OK;
 }
 
