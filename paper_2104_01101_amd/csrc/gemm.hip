@@ -214,6 +214,119 @@ __global__ __launch_bounds__(kSkT) void k_gemm_skinny(int64_t M, int64_t N, int6
   }
 }
 
+// FP32 operands, both K-major (A = [A1 | A2] as K x M, B as K x N), 64 x 64
+// tiles, 4 waves (2 x 2, 32 x 32 each), K slabs of 64 double-buffered in LDS
+// in [k][m] layout (row stride 80 floats: the four k rows that one MFMA
+// operand read touches fall in different bank halves), float4 global loads;
+// the next slab is fetched into registers while the current one feeds the
+// MFMAs.  Requires M1, lda1, lda2, ldb multiples of 4 and 16-byte aligned
+// bases (k_gemm_tn covers the rest).
+constexpr int kF4K = 64, kF4LD = 80;
+
+__device__ inline float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+
+__global__ __launch_bounds__(kThreads) void k_gemm_tn_f32v(int64_t M, int64_t N, int64_t K,
+                                                          const float* A1, int64_t lda1,
+                                                          int64_t M1, const float* A2,
+                                                          int64_t lda2, const float* B,
+                                                          int64_t ldb, int64_t kchunk, double* C,
+                                                          int64_t ldc, int64_t split_stride) {
+  __shared__ __attribute__((aligned(16))) float As[2][kF4K * kF4LD];
+  __shared__ __attribute__((aligned(16))) float Bs[2][kF4K * kF4LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t i0 = int64_t(blockIdx.x) * kBM, j0 = int64_t(blockIdx.y) * kBN;
+  const int64_t kbeg = int64_t(blockIdx.z) * kchunk;
+  const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
+  const int g = lane >> 4, li = lane & 15;
+  // loader: thread covers column quad cq (4 consecutive m or n) of rows
+  // kr + 16 u, u < 4
+  const int cq = (tid & 15) * 4, kr = tid >> 4;
+  const int64_t ia = i0 + cq, jb = j0 + cq;
+  const bool a_in = ia + 3 < M, b_in = jb + 3 < N;
+  const float* abase = ia < M1 ? A1 + ia : A2 + (ia - M1);
+  const int64_t alda = ia < M1 ? lda1 : lda2;
+  float4 ra[4], rb[4];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + kr + 16 * u;
+      const bool kv = k < kend;
+      if (kv && a_in) {
+        ra[u] = ld4(abase + k * alda);
+      } else {
+        float t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t i = ia + e;
+          t[e] = (kv && i < M) ? (i < M1 ? A1[k * lda1 + i] : A2[k * lda2 + (i - M1)]) : 0.f;
+        }
+        ra[u] = make_float4(t[0], t[1], t[2], t[3]);
+      }
+      if (kv && b_in) {
+        rb[u] = ld4(B + k * ldb + jb);
+      } else {
+        float t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = (kv && jb + e < N) ? B[k * ldb + jb + e] : 0.f;
+        rb[u] = make_float4(t[0], t[1], t[2], t[3]);
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      *reinterpret_cast<float4*>(&As[buf][(kr + 16 * u) * kF4LD + cq]) = ra[u];
+      *reinterpret_cast<float4*>(&Bs[buf][(kr + 16 * u) * kF4LD + cq]) = rb[u];
+    }
+  };
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0, 0, 0, 0};
+  int buf = 0;
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kF4K) {
+    const bool more = k0 + kF4K < kend;
+    if (more) fetch(k0 + kF4K);
+    const float* as = As[buf];
+    const float* bs = Bs[buf];
+#pragma unroll
+    for (int t = 0; t < kF4K / 4; ++t) {
+      const int kk = 4 * t + g;
+      float av[2], bv[2];
+#pragma unroll
+      for (int sm = 0; sm < 2; ++sm) av[sm] = as[kk * kF4LD + wm * 32 + sm * 16 + li];
+#pragma unroll
+      for (int sn = 0; sn < 2; ++sn) bv[sn] = bs[kk * kF4LD + wn * 32 + sn * 16 + li];
+#pragma unroll
+      for (int sm = 0; sm < 2; ++sm)
+#pragma unroll
+        for (int sn = 0; sn < 2; ++sn)
+          acc[sm][sn] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[sm], bv[sn], acc[sm][sn], 0, 0, 0);
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  double* Cz = C + int64_t(blockIdx.z) * split_stride;
+#pragma unroll
+  for (int sm = 0; sm < 2; ++sm)
+#pragma unroll
+    for (int sn = 0; sn < 2; ++sn)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = i0 + wm * 32 + sm * 16 + 4 * g + v;
+        const int64_t j = j0 + wn * 32 + sn * 16 + li;
+        if (i < M && j < N) Cz[i * ldc + j] = double(acc[sm][sn][v]);
+      }
+}
+
 __global__ void k_reduce_splits(const double* part, int64_t M, int64_t N, int splits,
                                 double* C, int64_t ldc) {
   int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -286,6 +399,28 @@ tsk_status gemm_tn_t(int64_t M, int64_t N, int64_t K, const void* A1, int64_t ld
     return TSK_OK;
   }
   dim3 grid(tm, tn, splits);
+  if (std::is_same<E, float>::value && !A_MK) {
+    const bool vec = M1 % 4 == 0 && lda1 % 4 == 0 && lda2 % 4 == 0 && ldb % 4 == 0 &&
+                     reinterpret_cast<uintptr_t>(A1) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(A2) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(B) % 16 == 0;
+    if (vec) {
+      const int64_t kch = ceil_div(kchunk, kF4K) * kF4K;
+      const int64_t spl = ceil_div(K, kch);
+      double* dst = spl > 1 ? part : C;
+      hipLaunchKernelGGL(k_gemm_tn_f32v, dim3(tm, tn, spl), dim3(kThreads), 0, st, M, N, K,
+                         static_cast<const float*>(A1), lda1, M1,
+                         static_cast<const float*>(A2), lda2, static_cast<const float*>(B), ldb,
+                         kch, dst, spl > 1 ? N : ldc, spl > 1 ? M * N : int64_t(0));
+      TSK_LAUNCHED();
+      if (spl > 1) {
+        hipLaunchKernelGGL(k_reduce_splits, dim3(ceil_div(M * N, 256)), dim3(256), 0, st, part, M,
+                           N, int(spl), C, ldc);
+        TSK_LAUNCHED();
+      }
+      return TSK_OK;
+    }
+  }
   if (splits == 1) {
     hipLaunchKernelGGL((k_gemm_tn<E, A_MK>), grid, dim3(kThreads), 0, st, M, N, K,
                        static_cast<const E*>(A1), lda1, M1, static_cast<const E*>(A2), lda2,

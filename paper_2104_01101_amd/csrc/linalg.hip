@@ -1135,7 +1135,10 @@ __global__ __launch_bounds__(kRbT) void k_range_basis(const double* C0, const do
   double* Cs = rb + r * lb;        // r x KM: C, then Q
   double* Ts = Cs + r * KM;        // r x KM: C0
   const int tid = threadIdx.x;
+  // staging: unrolled so that many loads are in flight before the stores
+#pragma unroll 8
   for (int t = tid; t < r * r; t += kRbT) Bs[(t / r) * lb + t % r] = B[t];
+#pragma unroll 4
   for (int t = tid; t < r * KM; t += kRbT) {
     const int i = t / KM, c = t % KM;
     Ts[t] = c < k ? C0[i * k + c] : 0.0;

@@ -204,18 +204,31 @@ struct SpecJob {
   int64_t R[TSK_MAX_ORDER];
   int64_t coloff[TSK_MAX_ORDER];  // first column index of mode q in the spectra array
   const double* CS[TSK_MAX_ORDER];
+  // gathered in the spectra kernel itself (CS not materialised)
+  const double* A[TSK_MAX_ORDER];
+  const int8_t* sg[TSK_MAX_ORDER];
+  const int32_t* ptr[TSK_MAX_ORDER];
+  const int32_t* items[TSK_MAX_ORDER];
 };
 
-// TWL: the twiddle table is staged in LDS after the two work buffers
+// TWL: the twiddle table lives in LDS after the two work buffers and is
+// computed there (the same expression as k_twiddles, so the same values);
+// otherwise the global table is read
 template <bool TWL>
 __device__ inline const double2* stage_twiddles(double2* buf, int64_t m, const double2* tw) {
   if (!TWL) return tw;
   double2* t = buf + 2 * m;
-  for (int64_t f = threadIdx.x; f < m; f += blockDim.x) t[f] = tw[f];
+  for (int64_t f = threadIdx.x; f < m; f += blockDim.x) {
+    double sn, cs;
+    sincospi(-2.0 * double(f) / double(m), &sn, &cs);
+    t[f] = make_double2(cs, sn);
+  }
   return t;  // visible after the caller's next barrier
 }
 
-template <bool TWL>
+// GATHER: CountSketch column c of mode q formed here, bucket by bucket in the
+// order of k_cs_gather (same sums), instead of being read from sj.CS
+template <bool TWL, bool GATHER>
 __global__ __launch_bounds__(kFftBlock) void k_spectra(SpecJob sj, int64_t m, Radices rd,
                                                        const double2* twg, double2* spec) {
   extern __shared__ double2 buf[];
@@ -226,9 +239,25 @@ __global__ __launch_bounds__(kFftBlock) void k_spectra(SpecJob sj, int64_t m, Ra
   int q = 0;
   while (q + 1 < sj.nmodes && col >= sj.coloff[q + 1]) ++q;
   int64_t c = col - sj.coloff[q];
-  const double* CS = sj.CS[q];
   int64_t R = sj.R[q];
-  for (int64_t f = threadIdx.x; f < m; f += blockDim.x) a[f] = make_double2(CS[f * R + c], 0.0);
+  if (GATHER) {
+    const double* A = sj.A[q];
+    const int8_t* sg = sj.sg[q];
+    const int32_t* ptr = sj.ptr[q];
+    const int32_t* items = sj.items[q];
+    for (int64_t f = threadIdx.x; f < m; f += blockDim.x) {
+      double acc = 0.0;
+      for (int32_t p = ptr[f]; p < ptr[f + 1]; ++p) {
+        const int32_t i = items[p];
+        const double v = A[int64_t(i) * R + c];
+        acc += sg[i] > 0 ? v : -v;
+      }
+      a[f] = make_double2(acc, 0.0);
+    }
+  } else {
+    const double* CS = sj.CS[q];
+    for (int64_t f = threadIdx.x; f < m; f += blockDim.x) a[f] = make_double2(CS[f * R + c], 0.0);
+  }
   __syncthreads();
   double2* out = fft_lds(a, b, int(m), rd, tw, false);
   double2* dst = spec + int64_t(col) * m;
@@ -344,11 +373,12 @@ static bool twiddles_fit(int64_t m) { return int64_t(3) * m * 16 <= fft_max_lds(
 static void launch_spectra(int64_t cols, int64_t m, const Radices& rd, const SpecJob& sj, const double* tw,
                     double* spec, hipStream_t st) {
   if (twiddles_fit(m))
-    hipLaunchKernelGGL(k_spectra<true>, dim3(cols), dim3(kFftBlock), size_t(3 * m * 16), st, sj, m,
-                       rd, reinterpret_cast<const double2*>(tw), reinterpret_cast<double2*>(spec));
+    hipLaunchKernelGGL((k_spectra<true, false>), dim3(cols), dim3(kFftBlock), size_t(3 * m * 16),
+                       st, sj, m, rd, reinterpret_cast<const double2*>(tw),
+                       reinterpret_cast<double2*>(spec));
   else
-    hipLaunchKernelGGL(k_spectra<false>, dim3(cols), dim3(kFftBlock), size_t(2 * m * 16), st, sj,
-                       m, rd, reinterpret_cast<const double2*>(tw),
+    hipLaunchKernelGGL((k_spectra<false, false>), dim3(cols), dim3(kFftBlock),
+                       size_t(2 * m * 16), st, sj, m, rd, reinterpret_cast<const double2*>(tw),
                        reinterpret_cast<double2*>(spec));
 }
 
@@ -431,8 +461,31 @@ tsk_status ts_lhs(const LhsMode* modes, int nmodes, int64_t m, int prec, void* Z
   double* tw = ws.take<double>(2 * m);
   if (ws.measuring()) return TSK_OK;
   ProfScope prof("ts_lhs", st);
-  TSK_TRY(ts_lhs_spectra(modes, nmodes, m, CS, spec, tw, ws, st));
-  return ts_compose(modes, nmodes, m, spec, tw, prec, Z, st);
+  TSK_TRY(check_fft_lds(m));
+  if (!twiddles_fit(m)) {
+    TSK_TRY(ts_lhs_spectra(modes, nmodes, m, CS, spec, tw, ws, st));
+    return ts_compose(modes, nmodes, m, spec, tw, prec, Z, st);
+  }
+  // two launches: spectra with the CountSketch gather and the twiddles in
+  // the kernel, then the composition (twiddles in the kernel)
+  Radices rd = factor_length(m);
+  SpecJob sj{};
+  sj.nmodes = nmodes;
+  int64_t off = 0;
+  for (int q = 0; q < nmodes; ++q) {
+    sj.R[q] = modes[q].R;
+    sj.coloff[q] = off;
+    sj.A[q] = modes[q].A;
+    sj.sg[q] = modes[q].sg;
+    sj.ptr[q] = modes[q].csr.ptr;
+    sj.items[q] = modes[q].csr.items;
+    off += modes[q].R;
+  }
+  hipLaunchKernelGGL((k_spectra<true, true>), dim3(off), dim3(kFftBlock), size_t(3 * m * 16), st,
+                     sj, m, rd, static_cast<const double2*>(nullptr),
+                     reinterpret_cast<double2*>(spec));
+  TSK_LAUNCHED();
+  return ts_compose(modes, nmodes, m, spec, nullptr, prec, Z, st);
 }
 
 // FFT of the columns of a real m x cols row-major matrix (twiddles already set)
