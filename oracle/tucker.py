@@ -133,7 +133,7 @@ def rsvd_omega(seed, sweep, n, s, k):
 
 def sketch_tucker_als(T, ranks, m, sweeps, seed=0, sketch_kind="ts", init="rrf",
                       rrf_k1=0, rrf_k2=0, init_factors=None, record_fit=True,
-                      identity_sketch=False, solve_kind="exact", rsvd_p=10):
+                      identity_sketch=False, solve_kind="exact", rsvd_p=10, first_sweep=0):
     """Sketched Tucker-ALS, Alg. 4.
 
     T        oracle.sketch.Tensor (COO or dense)
@@ -146,6 +146,9 @@ def sketch_tucker_als(T, ranks, m, sweeps, seed=0, sketch_kind="ts", init="rrf",
     solve_kind  "exact" (truncated SVD of Z^+ Y) or "rsvd" (RSVD-LRLS, Alg. 5,
              the subproblem solver Alg. 4 calls, with a fresh Gaussian test
              matrix of rsvd_width(R, r, rsvd_p) columns per subproblem)
+    first_sweep  index of the first sweep in the per-sweep random streams
+             (leverage samples, RSVD test matrices), so that a run can resume
+             at that sweep from given factors (init="user")
 
     Returns dict(core, factors, fits, samples)."""
     N = T.order
@@ -174,7 +177,7 @@ def sketch_tucker_als(T, ranks, m, sweeps, seed=0, sketch_kind="ts", init="rrf",
             tables[n] = sketch.ts_tables(dims, m, seed, n)
             Ys[n] = sketch.ts_rhs(T, m, tables[n], n)
     fits, samples = [], []
-    for sweep in range(sweeps):
+    for sweep in range(first_sweep, first_sweep + sweeps):
         for n in range(N):
             if identity_sketch:
                 P = kron_chain([factors[k] for k in range(N) if k != n])

@@ -31,7 +31,7 @@ def _coo(tsk, dims, idx, val):
     return tsk.Tensor.coo(torch.from_numpy(idx).to(DEV), torch.from_numpy(val).to(DEV), dims)
 
 
-def test_c1_fp64_parity(tsk):
+def test_dense40_fp64_parity(tsk):
     """Small dense case: 40^3 FP64, Tucker rank 5 + 1% noise, TensorSketch m = 200,
     RRF init, 5 sweeps."""
     w = workloads.dense40()
@@ -44,7 +44,7 @@ def test_c1_fp64_parity(tsk):
     np.testing.assert_allclose(core.cpu().numpy(), ref["core"], atol=1e-8 * np.abs(ref["core"]).max())
 
 
-def test_c1_deterministic(tsk):
+def test_dense40_deterministic(tsk):
     w = workloads.dense40()
     T = _dense(tsk, w.dense)
     a = tsk.tucker_sketch_als(T, w.ranks, w.m, 3, prec="f64", seed=4)
@@ -124,7 +124,7 @@ def test_cp_via_tucker_fp64(tsk):
 
 
 # -------------------------------------------- RSVD-LRLS subproblem solver ----
-def test_c1_rsvd_fp64_parity(tsk):
+def test_dense40_rsvd_fp64_parity(tsk):
     """The small dense case with the paper's subproblem solver (Alg. 4 calls RSVD-LRLS,
     Alg. 5): same Gaussian test matrices on both sides, relative residuals after
     every sweep within 1e-10, factors within 1e-8."""

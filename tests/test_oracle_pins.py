@@ -453,3 +453,21 @@ def test_rsvd_omega_stream():
     key = rng.stream_key(7, rng.P_RSVD, 2, 1)
     np.testing.assert_array_equal(Om.reshape(-1), rng.gauss(key, np.arange(15)))
     assert tucker.rsvd_width(10, 100) == 20 and tucker.rsvd_width(5, 9) == 9
+
+
+def test_driver_resumes_at_a_sweep():
+    """Two sweeps in one run equal one sweep followed by a run resumed at sweep 1
+    from its factors (the per-sweep streams are keyed by the absolute sweep)."""
+    X = workloads.tucker_dense((14, 13, 12), (3, 3, 3), 0.05, seed=4)
+    T = sketch.Tensor.from_dense(X)
+    for kind, solve_kind in (("ts", "rsvd"), ("lev", "exact")):
+        full = tucker.sketch_tucker_als(T, (3, 3, 3), 60, 2, seed=5, sketch_kind=kind,
+                                        solve_kind=solve_kind)
+        one = tucker.sketch_tucker_als(T, (3, 3, 3), 60, 1, seed=5, sketch_kind=kind,
+                                       solve_kind=solve_kind)
+        rest = tucker.sketch_tucker_als(T, (3, 3, 3), 60, 1, seed=5, sketch_kind=kind,
+                                        solve_kind=solve_kind, init="user",
+                                        init_factors=one["factors"], first_sweep=1)
+        assert full["fits"][1] == rest["fits"][0]
+        for a, b in zip(full["factors"], rest["factors"]):
+            assert np.array_equal(a, b)
