@@ -17,6 +17,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "skinny.h"
 #include "kernels.h"
 
 namespace tsk {
@@ -162,14 +163,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn(int64_t M, int64_t N, int6
       }
 }
 
-// Skinny FP64 products (one side of C at most 64): a workgroup of 8 waves
-// computes one 16 x 16 tile of C over the whole contraction, each wave a
-// contiguous slice of K with v_mfma_f64_16x16x4 (lane l feeds A(m0 + l%16,
-// k) and B(k, n0 + l%16), k = k0 + l/16), operands loaded straight into
-// registers 64 k at a time so that a wave has 32 loads in flight; the 8
-// partial tiles are summed in LDS in wave order (deterministic, no split-K
-// launch and no separate reduction).
-constexpr int kSkW = 8, kSkT = 64 * kSkW, kSkChunk = 64;
+// Skinny FP64 products: one workgroup of 8 waves per 16 x 16 tile of C
+// (skinny_tile in skinny.h).
+constexpr int kSkW = 8, kSkT = 64 * kSkW;
 
 template <bool A_MK>
 __global__ __launch_bounds__(kSkT) void k_gemm_skinny(int64_t M, int64_t N, int64_t K,
@@ -178,40 +174,8 @@ __global__ __launch_bounds__(kSkT) void k_gemm_skinny(int64_t M, int64_t N, int6
                                                       const double* B, int64_t ldb, double* C,
                                                       int64_t ldc) {
   __shared__ double red[kSkW][16][17];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, g = lane >> 4;
-  const int64_t m0 = int64_t(blockIdx.x) * 16, n0 = int64_t(blockIdx.y) * 16;
-  const int64_t i = m0 + li, j = n0 + li;
-  const int64_t kper = ((K + kSkW * 4 - 1) / (kSkW * 4)) * 4;
-  const int64_t kb = wave * kper, ke = kb + kper < K ? kb + kper : K;
-  const bool iv = i < M, jv = j < N;
-  const double* arow = A_MK ? A1 + i * lda1 : nullptr;
-  doublex4 acc = {0, 0, 0, 0};
-  for (int64_t k0 = kb; k0 < ke; k0 += kSkChunk) {
-    double a[kSkChunk / 4], b[kSkChunk / 4];
-#pragma unroll
-    for (int u = 0; u < kSkChunk / 4; ++u) {
-      const int64_t k = k0 + 4 * u + g;
-      const bool kv = k < ke;
-      a[u] = 0.0;
-      b[u] = 0.0;
-      if (kv && iv) a[u] = A_MK ? arow[k] : load_a(A1, lda1, M1, A2, lda2, k, i);
-      if (kv && jv) b[u] = B[k * ldb + j];
-    }
-#pragma unroll
-    for (int u = 0; u < kSkChunk / 4; ++u)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v) red[wave][g + 4 * v][li] = acc[v];
-  __syncthreads();
-  if (threadIdx.x < 256) {
-    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kSkW; ++w) s += red[w][r][c];
-    if (m0 + r < M && n0 + c < N) C[(m0 + r) * ldc + n0 + c] = s;
-  }
+  skinny_tile<kSkW, A_MK>(M, N, K, A1, lda1, M1, A2, lda2, B, ldb, C, ldc, blockIdx.x, blockIdx.y,
+                          red);
 }
 
 // FP32 operands, both K-major (A = [A1 | A2] as K x M, B as K x N), 64 x 64

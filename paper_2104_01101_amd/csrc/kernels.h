@@ -107,11 +107,22 @@ bool spd_inverse_fits(int64_t n);
 // sgn (optional, R entries) receives the sign applied to each column
 tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, hipStream_t st,
                             double* sgn = nullptr);
+// C = A^T B (A: K x M, B: K x N, row-major FP64) beside the in-place SPD
+// inverse of G (n x n, n <= 128) in one launch (c0_inverse_fits)
+bool c0_inverse_fits(int64_t n);
+tsk_status c0_and_inverse(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                          const double* B, int64_t ldb, double* C, int64_t ldc, double* G,
+                          int64_t n, int64_t ldg, int* info, hipStream_t st);
 // Range basis of the randomized solve: C = B C0 (r x k), Q = qr(C), P = B Q
 // (r x k row-major); r <= 128, k <= 24 (range_basis_fits).
 bool range_basis_fits(int64_t r, int64_t k);
 tsk_status range_basis(const double* C0, const double* B, int64_t r, int64_t k, double* Q,
                        double* P, hipStream_t st);
+// A = Dt U lam^{-1/2} (s x R), sign rule on its columns, W = Q U lam^{1/2} in
+// the same signs (Q r x k row-major); k <= 64; one launch
+tsk_status rsvd_finish(const double* Dt, const double* U, const double* lam, const double* Q,
+                       int64_t s, int64_t k, int64_t r, int64_t R, double* A, double* W,
+                       hipStream_t st);
 // W = Q U diag(lam * sgn), Q given as r x k (q_rows) or as Q^T (k x r), U (k x R)
 tsk_status rsvd_w(const double* Qm, bool q_rows, const double* U, const double* lam,
                   const double* sgn, int64_t k, int64_t r, int64_t R, double* W, hipStream_t st);

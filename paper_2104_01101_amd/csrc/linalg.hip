@@ -19,6 +19,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "skinny.h"
 #include "wave.h"
 
 namespace tsk {
@@ -628,7 +629,7 @@ __global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, do
 }
 
 // ------------------------------------------ small symmetric eigenproblems ----
-// Leading R eigenpairs of a symmetric q x q matrix with q <= QM <= 32, in one
+// Leading R eigenpairs of a symmetric q x q matrix with q <= QM <= 24, in one
 // wavefront (no block barriers), same method as k_sym_eig_top:
 //   * Householder tridiagonalisation with row `lane` of the matrix in
 //     registers; v and w = p - K v are broadcast through LDS, and only the
@@ -644,7 +645,8 @@ __global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, do
 //     1e-3 ||T||_1 of each other (elsewhere inverse iteration already gives
 //     orthogonal vectors), then back-transformation through the reflectors,
 //     four vectors per batched wave reduction.
-constexpr int kEigSmallMax = 32;
+// order 24 at most: at 32 the kernel needs every VGPR and spills SGPRs
+constexpr int kEigSmallMax = 24;
 
 template <int QM>
 __device__ inline void sturm4(const double (&d)[QM], const double (&e2)[QM], int q,
@@ -657,15 +659,27 @@ __device__ inline void sturm4(const double (&d)[QM], const double (&e2)[QM], int
   }
   // predicated rather than exited early, so that the loop unrolls and the
   // register arrays keep constant indices
+  // each operation is issued for the four chains before the next one, so
+  // that the dependent steps of one chain overlap the others
 #pragma unroll
   for (int i = 1; i < QM; ++i) {
     if (i < q) {
+      double r[4], e[4], dx[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if (fabs(t[k]) <= pivmin) t[k] = -pivmin;
-        t[k] = fma(-e2[i - 1], rcp64(t[k]), d[i] - x[k]);
-        c[k] += t[k] < 0.0;
+        dx[k] = d[i] - x[k];
+        t[k] = fabs(t[k]) <= pivmin ? -pivmin : t[k];
       }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) r[k] = __builtin_amdgcn_rcp(t[k]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) e[k] = fma(-t[k], r[k], 1.0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) r[k] = fma(r[k], e[k], r[k]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t[k] = fma(-e2[i - 1], r[k], dx[k]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) c[k] += t[k] < 0.0;
     }
   }
 }
@@ -699,7 +713,9 @@ __global__ __launch_bounds__(64) void k_sym_eig_small(const double* Mg, int q, i
     const double x0 = read_lane(m[J], J + 1);
     const double alpha = nrm > 0.0 ? -copysign(nrm, x0) : 0.0;
     const double v0 = x0 - alpha;
-    const double beta = nrm > 0.0 ? -1.0 / (alpha * v0) : 0.0;  // 2 / v^T v
+    // 2 / v^T v by a true division: |alpha v0| can be tiny for nearly rank-
+    // deficient matrices, where the reciprocal-and-Newton form gives NaN
+    const double beta = nrm > 0.0 ? -1.0 / (alpha * v0) : 0.0;
     const double vl = lane > J + 1 ? m[J] : (lane == J + 1 ? v0 : 0.0);
     vr[J] = vl;
     if (lane == 0) {
@@ -825,23 +841,26 @@ __global__ __launch_bounds__(64) void k_sym_eig_small(const double* Mg, int q, i
     double p = dsh[0] - mu, qq = q > 1 ? esh[0] : 0.0, rr = 0.0;
     for (int i = 0; i + 1 < q; ++i) {
       const double c = esh[i], a1 = dsh[i + 1] - mu, b1 = i + 2 < q ? esh[i + 1] : 0.0;
+      // reciprocals with one Newton step (rcp64) are accurate enough for the
+      // factors of inverse iteration and keep the dependent chain short
       if (fabs(p) >= fabs(c)) {
-        const double pvv = p == 0.0 ? tiny : p;
-        const double mlt = c / pvv;
-        u0[i * 64] = 1.0 / pvv, u1[i * 64] = qq, u2[i * 64] = rr, pl[i * 64] = 0;
+        const double rp = rcp64(p == 0.0 ? tiny : p);
+        const double mlt = c * rp;
+        u0[i * 64] = rp, u1[i * 64] = qq, u2[i * 64] = rr, pl[i * 64] = 0;
         ml[i * 64] = mlt;
         p = a1 - mlt * qq;
         qq = b1 - mlt * rr;
       } else {
-        const double mlt = p / c;
-        u0[i * 64] = 1.0 / c, u1[i * 64] = a1, u2[i * 64] = b1, pl[i * 64] = 1;
+        const double rc = rcp64(c);
+        const double mlt = p * rc;
+        u0[i * 64] = rc, u1[i * 64] = a1, u2[i * 64] = b1, pl[i * 64] = 1;
         ml[i * 64] = mlt;
         p = qq - mlt * a1;
         qq = rr - mlt * b1;
       }
       rr = 0.0;
     }
-    u0[(q - 1) * 64] = 1.0 / (p == 0.0 ? tiny : p);
+    u0[(q - 1) * 64] = rcp64(p == 0.0 ? tiny : p);
     u1[(q - 1) * 64] = 0.0;
     u2[(q - 1) * 64] = 0.0;
     for (int i = 0; i < q; ++i) {
@@ -921,7 +940,9 @@ __global__ __launch_bounds__(64) void k_sym_eig_small(const double* Mg, int q, i
     constexpr int J = decltype(JC)::value;
     if (J + 2 >= q) return;
     const double beta = bsh[J];
-    constexpr int CH = QM >= 24 ? 12 : 8;
+    // chunk of vectors per batched reduction: a multiple of 4 dividing QM
+    constexpr int CH = QM % 12 == 0 ? 12 : (QM % 8 == 0 ? 8 : 4);
+    static_assert(QM % CH == 0 && CH % 4 == 0, "back-transform chunks must cover QM");
     static_for<0, QM / CH>([&](auto CC) {
       constexpr int C0 = CH * decltype(CC)::value;
       if (C0 >= R) return;
@@ -1063,7 +1084,8 @@ __device__ __forceinline__ void qr_reg_wave(double (&X)[2][KM], int k, double (&
     const double nrm = sqrt(w[0]);
     const double alpha = nrm > 0.0 ? -copysign(nrm, xj) : 0.0;
     const double vj = xj - alpha;
-    const double b = nrm > 0.0 ? -1.0 / (alpha * vj) : 0.0;  // 2 / v^T v
+    // 2 / v^T v by a true division (tiny |alpha v_j| on nearly dependent columns)
+    const double b = nrm > 0.0 ? -1.0 / (alpha * vj) : 0.0;
     beta[J] = b;
     X[0][J] = lane > J ? X[0][J] : (lane == J ? vj : 0.0);
 #pragma unroll
@@ -1224,11 +1246,11 @@ constexpr size_t spd_pair_lds() {
   return size_t(16 * NB) * (16 * NB + 1) * 8;
 }
 
+// S: NP x (NP + 1) doubles of LDS for the result staging
 template <int NB>
-__global__ __launch_bounds__(kPairT) void k_spd_inverse_pair(double* G, int n, int lda,
-                                                             int* info) {
+__device__ __forceinline__ void spd_inverse_pair_body(double* G, int n, int lda, int* info,
+                                                      double* S) {
   constexpr int NP = 16 * NB, SP = NP + 1;
-  extern __shared__ double S[];  // NP x SP staging of the result
   __shared__ double col[2][2][NP];
   const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
   double A[NB][NB];
@@ -1320,6 +1342,33 @@ __global__ __launch_bounds__(kPairT) void k_spd_inverse_pair(double* G, int n, i
     }
 }
 
+template <int NB>
+__global__ __launch_bounds__(kPairT) void k_spd_inverse_pair(double* G, int n, int lda,
+                                                             int* info) {
+  extern __shared__ double S[];
+  spd_inverse_pair_body<NB>(G, n, lda, info, S);
+}
+
+// C0 = A^T B (A K x M, B K x N, skinny tiles of 4 waves) in blocks [0, tiles)
+// and the SPD inverse of G in the last block: the two products of the
+// randomized solve that do not depend on each other share one launch, and
+// the tiles run on other CUs while the one-workgroup inverse runs.
+template <int NB>
+__global__ __launch_bounds__(kPairT) void k_c0_inverse(int64_t M, int64_t N, int64_t K,
+                                                       const double* A, int64_t lda,
+                                                       const double* B, int64_t ldb, double* C,
+                                                       int64_t ldc, int tiles_m, int tiles,
+                                                       double* G, int n, int ldg, int* info) {
+  extern __shared__ double S[];
+  if (int(blockIdx.x) < tiles) {
+    auto* red = reinterpret_cast<double (*)[16][17]>(S);
+    skinny_tile<kPairT / 64, false>(M, N, K, A, lda, M, A, lda, B, ldb, C, ldc,
+                                    blockIdx.x % tiles_m, blockIdx.x / tiles_m, red);
+  } else {
+    spd_inverse_pair_body<NB>(G, n, ldg, info, S);
+  }
+}
+
 // -------------------------------------------------------------- sign fix ----
 __global__ void k_sign_fix(double* A, int64_t rows, int64_t R, double* sgn) {
   __shared__ double bv[256];
@@ -1363,6 +1412,67 @@ __global__ void k_rsvd_w(const double* Qm, bool q_rows, const double* U, const d
   W[t] = s * lam[c] * sgn[c];
 }
 
+// Last steps of the randomized solve in one launch, one workgroup per column
+// c of A: u = U(:, c) lam_c^{-1/2}; A(:, c) = D^T u (each row a dot product
+// of length k, the row read in pairs when k is even); the sign that makes the
+// largest-magnitude entry positive (lowest index on ties, as k_sign_fix);
+// A(:, c) in that sign; and W(:, c) = Q U(:, c) lam_c^{1/2} in the same sign.
+// Q is r x k, Dt is s x k; k <= 64.
+constexpr int kFinT = 256;
+
+__global__ __launch_bounds__(kFinT) void k_rsvd_finish(const double* Dt, const double* U,
+                                                       const double* lam, const double* Q,
+                                                       int s, int k, int r, int R, double* A,
+                                                       double* W) {
+  __shared__ double us[64];
+  __shared__ double bv[kFinT];
+  __shared__ int bi[kFinT];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const double lc = lam[c];
+  if (tid < k) us[tid] = U[tid * R + c] / sqrt(lc);
+  __syncthreads();
+  double best = -1.0;
+  int bidx = 0;
+  const bool pairs = (k & 1) == 0;
+  for (int i = tid; i < s; i += kFinT) {
+    const double* d = Dt + size_t(i) * k;
+    double a0 = 0.0, a1 = 0.0;
+    if (pairs) {
+      const double2* d2 = reinterpret_cast<const double2*>(d);
+      for (int j = 0; j < k / 2; ++j) {
+        const double2 v = d2[j];
+        a0 = fma(v.x, us[2 * j], a0);
+        a1 = fma(v.y, us[2 * j + 1], a1);
+      }
+    } else {
+      for (int j = 0; j < k; ++j) a0 = fma(d[j], us[j], a0);
+    }
+    const double a = a0 + a1;
+    A[size_t(i) * R + c] = a;
+    if (fabs(a) > best) best = fabs(a), bidx = i;  // first maximum within the stride
+  }
+  bv[tid] = best;
+  bi[tid] = bidx;
+  __syncthreads();
+  for (int off = kFinT / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      const double o = bv[tid + off];
+      const int oi = bi[tid + off];
+      if (o > bv[tid] || (o == bv[tid] && oi < bi[tid])) bv[tid] = o, bi[tid] = oi;
+    }
+    __syncthreads();
+  }
+  const bool flip = A[size_t(bi[0]) * R + c] < 0.0;
+  if (flip)
+    for (int i = tid; i < s; i += kFinT) A[size_t(i) * R + c] = -A[size_t(i) * R + c];
+  const double ws = flip ? -sqrt(lc) : sqrt(lc);
+  for (int i = tid; i < r; i += kFinT) {
+    double w = 0.0;
+    for (int j = 0; j < k; ++j) w = fma(Q[i * k + j], U[j * R + c], w);
+    W[i * R + c] = w * ws;
+  }
+}
+
 __global__ void k_scale_inv_sqrt(double* A, int64_t rows, int64_t R, const double* lam) {
   int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= rows * R) return;
@@ -1404,6 +1514,34 @@ tsk_status cholesky(double* G, int64_t n, int64_t lda, int* info, hipStream_t st
                        info);
   else
     hipLaunchKernelGGL(k_cholesky<false>, dim3(1), dim3(kCholT), 0, st, G, int(n), int(lda), info);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+bool c0_inverse_fits(int64_t n) {
+  return n <= kRegMax &&
+         (n <= 64 ? spd_pair_lds<4>() : n <= 112 ? spd_pair_lds<7>() : spd_pair_lds<8>()) + 8192 <=
+             size_t(max_lds_bytes());
+}
+
+tsk_status c0_and_inverse(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                          const double* B, int64_t ldb, double* C, int64_t ldc, double* G,
+                          int64_t n, int64_t ldg, int* info, hipStream_t st) {
+  if (!c0_inverse_fits(n)) {
+    set_error("fused product and SPD inverse of order %lld is not supported", (long long)n);
+    return TSK_EUNSUPPORTED;
+  }
+  const int tm = int(ceil_div(M, 16)), tiles = tm * int(ceil_div(N, 16));
+  const dim3 grid(tiles + 1);
+  if (n <= 64)
+    hipLaunchKernelGGL(k_c0_inverse<4>, grid, dim3(kPairT), spd_pair_lds<4>(), st, M, N, K, A,
+                       lda, B, ldb, C, ldc, tm, tiles, G, int(n), int(ldg), info);
+  else if (n <= 112)
+    hipLaunchKernelGGL(k_c0_inverse<7>, grid, dim3(kPairT), spd_pair_lds<7>(), st, M, N, K, A,
+                       lda, B, ldb, C, ldc, tm, tiles, G, int(n), int(ldg), info);
+  else
+    hipLaunchKernelGGL(k_c0_inverse<8>, grid, dim3(kPairT), spd_pair_lds<8>(), st, M, N, K, A,
+                       lda, B, ldb, C, ldc, tm, tiles, G, int(n), int(ldg), info);
   TSK_LAUNCHED();
   return TSK_OK;
 }
@@ -1468,11 +1606,11 @@ tsk_status sym_eig_top(double* M, int64_t q, int64_t R, double* lam, double* V, 
     if (q <= 16)
       hipLaunchKernelGGL(k_sym_eig_small<16>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V,
                          nt);
-    else if (q <= 24)
-      hipLaunchKernelGGL(k_sym_eig_small<24>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V,
+    else if (q <= 20)
+      hipLaunchKernelGGL(k_sym_eig_small<20>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V,
                          nt);
     else
-      hipLaunchKernelGGL(k_sym_eig_small<32>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V,
+      hipLaunchKernelGGL(k_sym_eig_small<24>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V,
                          nt);
     TSK_LAUNCHED();
     return TSK_OK;
@@ -1517,6 +1655,8 @@ tsk_status qr_rows(const double* Ct, int64_t k, int64_t r, double* Qt, Ws& ws, h
       hipLaunchKernelGGL(k_qr_reg<8>, dim3(1), dim3(64), 0, st, Ct, int(k), int(r), Qt);
     else if (k <= 16)
       hipLaunchKernelGGL(k_qr_reg<16>, dim3(1), dim3(64), 0, st, Ct, int(k), int(r), Qt);
+    else if (k <= 20)
+      hipLaunchKernelGGL(k_qr_reg<20>, dim3(1), dim3(64), 0, st, Ct, int(k), int(r), Qt);
     else
       hipLaunchKernelGGL(k_qr_reg<24>, dim3(1), dim3(64), 0, st, Ct, int(k), int(r), Qt);
     TSK_LAUNCHED();
@@ -1546,13 +1686,16 @@ tsk_status range_basis(const double* C0, const double* B, int64_t r, int64_t k, 
               (long long)k);
     return TSK_EUNSUPPORTED;
   }
-  const int KM = k <= 8 ? 8 : (k <= 16 ? 16 : 24);
+  const int KM = k <= 8 ? 8 : (k <= 16 ? 16 : (k <= 20 ? 20 : 24));
   const size_t lds = (size_t(r) * (r + 1) + 2 * size_t(r) * KM) * 8;
   if (KM == 8)
     hipLaunchKernelGGL(k_range_basis<8>, dim3(1), dim3(kRbT), lds, st, C0, B, int(r), int(k), Q,
                        P);
   else if (KM == 16)
     hipLaunchKernelGGL(k_range_basis<16>, dim3(1), dim3(kRbT), lds, st, C0, B, int(r), int(k),
+                       Q, P);
+  else if (KM == 20)
+    hipLaunchKernelGGL(k_range_basis<20>, dim3(1), dim3(kRbT), lds, st, C0, B, int(r), int(k),
                        Q, P);
   else
     hipLaunchKernelGGL(k_range_basis<24>, dim3(1), dim3(kRbT), lds, st, C0, B, int(r), int(k),
@@ -1563,6 +1706,19 @@ tsk_status range_basis(const double* C0, const double* B, int64_t r, int64_t k, 
 
 tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, hipStream_t st, double* sgn) {
   hipLaunchKernelGGL(k_sign_fix, dim3(R), dim3(256), 0, st, A, rows, R, sgn);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+tsk_status rsvd_finish(const double* Dt, const double* U, const double* lam, const double* Q,
+                       int64_t s, int64_t k, int64_t r, int64_t R, double* A, double* W,
+                       hipStream_t st) {
+  if (k > 64 || s > INT32_MAX / 64) {
+    set_error("randomized solve finish supports k <= 64 (k = %lld)", (long long)k);
+    return TSK_EUNSUPPORTED;
+  }
+  hipLaunchKernelGGL(k_rsvd_finish, dim3(R), dim3(kFinT), 0, st, Dt, U, lam, Q, int(s), int(k),
+                     int(r), int(R), A, W);
   TSK_LAUNCHED();
   return TSK_OK;
 }

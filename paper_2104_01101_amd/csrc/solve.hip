@@ -96,24 +96,20 @@ tsk_status rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_
     ProfScope prof(run ? "gram" : "", st);
     TSK_TRY(gemm_tn(prec, r + s, r, m, Z, r, r, Y, s, Z, r, GH, r, ws, st));
   }
-  if (gj && range_basis_fits(r, k)) {
-    // fused chain: C0 = H Omega, B = G^{-1}, then C = B C0, Q = qr(C),
-    // P = B Q in one launch; D^T = H^T P and the Gram D D^T
+  if (gj && range_basis_fits(r, k) && c0_inverse_fits(r)) {
+    // fused chain: C0 = H Omega beside B = G^{-1} (one launch), then C = B C0,
+    // Q = qr(C), P = B Q (one launch); D^T = H^T P and the Gram D D^T
     double* Q = Qt;  // r x k here
     double* C0 = C0t;
     {
       ProfScope prof(run ? "solve_la" : "", st);
-      TSK_TRY(gemm_tn(TSK_PREC_F64, r, k, s, Ht, r, r, nullptr, 0, Om, k, C0, k, ws, st));
-      if (run) TSK_TRY(spd_inverse(G, r, r, info, st));
+      if (run) TSK_TRY(c0_and_inverse(r, k, s, Ht, r, Om, k, C0, k, G, r, r, info, st));
       if (run) TSK_TRY(range_basis(C0, G, r, k, Q, P, st));
       TSK_TRY(gemm_nn_f64(s, k, r, Ht, r, P, k, Dt, k, ws, st));
       TSK_TRY(gemm_tn(TSK_PREC_F64, k, k, s, Dt, k, k, nullptr, 0, Dt, k, Mk, k, ws, st));
     }
     TSK_TRY(sym_eig_top(Mk, k, R, lam, U, ws, st));
-    if (run) TSK_TRY(scale_columns_inv_sqrt(U, k, R, lam, st));
-    TSK_TRY(gemm_nn_f64(s, R, k, Dt, k, U, R, A, R, ws, st));
-    if (run) TSK_TRY(sign_fix_columns(A, s, R, st, sgn));
-    if (run) TSK_TRY(rsvd_w(Q, true, U, lam, sgn, k, r, R, W, st));
+    if (run) TSK_TRY(rsvd_finish(Dt, U, lam, Q, s, k, r, R, A, W, st));
     return TSK_OK;
   }
   {

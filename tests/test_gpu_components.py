@@ -136,7 +136,8 @@ def test_sketch_lhs_matches_convolution(tsk, dims, ranks, m, n):
 
 # ---------------------------------------------------------------- a6, a7 ----
 @pytest.mark.parametrize("m,r,s,R", [(200, 25, 40, 5), (1600, 100, 2000, 10), (400, 30, 20, 4),
-                                     (333, 64, 65, 7), (4000, 100, 200, 10), (90, 90, 1, 1)])
+                                     (333, 64, 65, 7), (4000, 100, 200, 10), (90, 90, 1, 1),
+                                     (700, 121, 150, 6), (800, 128, 150, 8)])
 def test_rc_solve_fp64(tsk, m, r, s, R):
     rs = np.random.default_rng(r * s)
     Z = rs.standard_normal((m, r)) / np.sqrt(m)
@@ -271,10 +272,13 @@ def test_adjoint_matches_oracle_and_fd(tsk):
 
 # ------------------------------------------------------------ RSVD-LRLS ----
 @pytest.mark.parametrize("m,r,s,R,k", [(300, 100, 400, 10, 20), (80, 25, 40, 5, 15),
-                                       (400, 144, 150, 12, 22)])
+                                       (400, 144, 150, 12, 22), (150, 36, 50, 12, 20),
+                                       (200, 40, 60, 26, 30), (500, 120, 90, 7, 13)])
 def test_rsvd_solve_fp64_vs_oracle(tsk, m, r, s, R, k):
     """RSVD-LRLS (Alg. 5) with the same Gaussian test matrix: FP64 library vs
-    the oracle (r = 144 exercises the Cholesky branch of the Gram solve)."""
+    the oracle.  r = 144 exercises the Cholesky branch of the Gram solve,
+    k = 30 the unfused chain and the order-32 eigensolver with R = 26 vectors,
+    r = 120 the largest register SPD inverse."""
     rs = np.random.default_rng(m + r)
     Z = rs.standard_normal((m, r))
     Y = rs.standard_normal((m, s))
