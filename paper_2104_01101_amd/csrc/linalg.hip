@@ -636,9 +636,11 @@ __global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, do
 //     trailing block (rows and columns > j) is updated at step j;
 //   * eigenvalues by multisection of the Sturm count: a first round of 256
 //     points shared by all, then 64 / R lanes per eigenvalue, four interleaved
-//     count chains per lane, until the bracket is below 1e-11 relative (enough
-//     for inverse iteration); the returned eigenvalue is the Rayleigh quotient
-//     of the computed eigenvector of the tridiagonal;
+//     count chains per lane, until the bracket is below 1e-9 relative (three
+//     inverse iterations then converge to working precision unless the gap is
+//     under ~1e-4 relative, and those eigenvalues are orthogonalised as a
+//     cluster); the returned eigenvalue is the Rayleigh quotient of the
+//     computed eigenvector of the tridiagonal;
 //   * eigenvectors of the tridiagonal by inverse iteration, one lane each, LU
 //     factors in LDS with the lane index fastest (no bank conflicts);
 //   * Gram-Schmidt only between vectors whose eigenvalues lie within
@@ -800,7 +802,7 @@ __global__ __launch_bounds__(64) void k_sym_eig_small(const double* Mg, int q, i
     }
     for (int it = 0; it < 64; ++it) {
       const double width = hi - lo;
-      const bool conv = !(width > 1e-11 * fmax(fabs(lo), fabs(hi)) + pivmin);
+      const bool conv = !(width > 1e-9 * fmax(fabs(lo), fabs(hi)) + pivmin);
       if (__ballot(act && !conv) == 0ull) break;
       double x[4];
       int c[4];
@@ -941,6 +943,7 @@ __global__ __launch_bounds__(64) void k_sym_eig_small(const double* Mg, int q, i
     if (J + 2 >= q) return;
     const double beta = bsh[J];
     // chunk of vectors per batched reduction: a multiple of 4 dividing QM
+    // (one wide chunk measured slower than several narrow ones)
     constexpr int CH = QM % 12 == 0 ? 12 : (QM % 8 == 0 ? 8 : 4);
     static_assert(QM % CH == 0 && CH % 4 == 0, "back-transform chunks must cover QM");
     static_for<0, QM / CH>([&](auto CC) {
