@@ -45,8 +45,11 @@ GROUP_SOURCES = {
     "sketch_pass": ["sketch_pass.hip"], "rrf_pass": ["sketch_pass.hip"],
     "ts_lhs": ["ts_lhs.hip"], "gram": ["gemm.hip"], "solve_la": ["linalg.hip", "gemm.hip"],
     "eig": ["linalg.hip"], "fit": ["fit.hip"], "rrf": ["linalg.hip", "gemm.hip", "api.hip"],
+    "leverage": ["leverage.hip"], "fiber_index": ["fibers.hip"], "fiber_rows": ["fibers.hip"],
 }
-GROUPS = ["sketch_pass", "rrf_pass", "rrf", "ts_lhs", "gram", "solve_la", "eig", "fit"]
+GROUPS = ["sketch_pass", "rrf_pass", "rrf", "ts_lhs", "gram", "solve_la", "eig", "fit",
+          "leverage", "fiber_index", "fiber_rows"]
+WORKLOADS = ["sparse2000", "zipf10k", "sparse2000lev"]
 
 
 def parse():
@@ -54,8 +57,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sparse2000", choices=["sparse2000", "zipf10k"],
-                    help="sparse2000 (default, the benchmark workload) or zipf10k (sketch-pass study)")
+    ap.add_argument("--workload", default="sparse2000", choices=WORKLOADS,
+                    help="sparse2000 (default, the benchmark workload), zipf10k (sketch-pass "
+                         "study) or sparse2000lev (the same tensor under leverage-score "
+                         "sampling through the fibre indices)")
     ap.add_argument("--solve", default="rsvd", choices=["rsvd", "exact"],
                     help="subproblem solver: rsvd = RSVD-LRLS (Alg. 5, the solver Alg. 4 "
                          "calls) or exact = truncated SVD of Z^+ Y")
@@ -69,7 +74,7 @@ def parse():
 
 def workload(name):
     import workloads
-    return workloads.sparse2000() if name == "sparse2000" else workloads.zipf10k()
+    return getattr(workloads, name)()
 
 
 def group_work(w, solve="exact"):
@@ -112,6 +117,14 @@ def group_work(w, solve="exact"):
         "eig": ("alu", subs * eig(q_eig) + (N - 1) * eig(k1), FP64_VECTOR_TFLOPS, "TFLOP/s"),
         # per entry: core contraction R^3 + R^2 + R multiply-adds (FP64)
         "fit": ("alu", sweeps * nnz * 2.0 * (R ** 3 + R ** 2 + R), FP64_VECTOR_TFLOPS, "TFLOP/s"),
+        # sampled Kronecker rows: factors read, Z written
+        "leverage": ("hbm", subs * ((N - 1) * s * R * 8 + m * r * vb), HBM_PEAK_GBS, "GB/s"),
+        # per mode: keys built (indices read, keys written), then sorted pairs written once
+        "fiber_index": ("hbm", N * nnz * (4 * N + 8 + 12), HBM_PEAK_GBS, "GB/s"),
+        # sampled fibres: Y written, the fibres' keys and values read (expected length
+        # nnz / prod_{k != n} s_k), sample indices and weights read
+        "fiber_rows": ("hbm", subs * (m * s * vb + m * (nnz / s ** (N - 1)) * 12
+                                      + m * (4 * (N - 1) + 8)), HBM_PEAK_GBS, "GB/s"),
     }
 
 
@@ -184,8 +197,9 @@ def main():
     dev = torch.device("cuda:0")
     w = workload(args.workload)
     T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(dev), torch.from_numpy(w.val).to(dev), w.dims)
-    plan = tsk.TuckerPlan(T, w.ranks, w.m, w.sweeps, sketch="ts", init="rrf", prec=w.prec,
+    plan = tsk.TuckerPlan(T, w.ranks, w.m, w.sweeps, sketch=w.sketch, init="rrf", prec=w.prec,
                           seed=0, record_fit=True, solve=args.solve)
+    second = "sketch_pass" if w.sketch == "ts" else "fiber_rows"
     lib = L.lib()
     lib.tsk_profile_enable.argtypes = [ctypes.c_char_p]
     lib.tsk_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -211,9 +225,9 @@ def main():
                           "launch_groups": {n: v[1] for n, v in per_group.items()}}),
               file=sys.stderr)
 
-    # timed region: the dominant group's and the sketch pass's launches are
-    # timed with events on the library's stream
-    timed = dominant if dominant == "sketch_pass" else f"{dominant},sketch_pass"
+    # timed region: the dominant group's and the sketch pass's (leverage:
+    # the fibre gather's) launches are timed with events on the library's stream
+    timed = dominant if dominant == second else f"{dominant},{second}"
     L.check(lib.tsk_profile_enable(timed.encode()))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -223,7 +237,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     dom = read(dominant)
-    sp = read("sketch_pass")
+    sp = read(second)
     L.check(lib.tsk_profile_enable(b""))
 
     work = group_work(w, args.solve)
@@ -240,20 +254,25 @@ def main():
         "vs_baseline": None,
         "dtype": w.prec,
         "data": "synthetic",
-        "config": {"workload": ("sparse 2000^3, 1e6 nnz uniform, Tucker rank 10 + N(0,1), "
-                                "TensorSketch m=1600, RRF init, 10 sweeps of Alg. 4, FP32 operands")
-                   if args.workload == "sparse2000" else
-                   ("sparse 10000^3, 1e7 nnz Zipf(1.1), lognormal values, Tucker rank 16, "
-                    "TensorSketch m=2048, RRF init, 5 sweeps, FP32 operands"),
+        "config": {"workload": {
+                       "sparse2000": "sparse 2000^3, 1e6 nnz uniform, Tucker rank 10 + N(0,1), "
+                                     "TensorSketch m=1600, RRF init, 10 sweeps of Alg. 4, "
+                                     "FP32 operands",
+                       "sparse2000lev": "sparse 2000^3, 1e6 nnz uniform, Tucker rank 10 + "
+                                        "N(0,1), leverage-score sampling m=1600 through "
+                                        "per-mode fibre indices, RRF init, 10 sweeps of "
+                                        "Alg. 4, FP32 operands",
+                       "zipf10k": "sparse 10000^3, 1e7 nnz Zipf(1.1), lognormal values, "
+                                  "Tucker rank 16, TensorSketch m=2048, RRF init, 5 sweeps, "
+                                  "FP32 operands"}[args.workload],
                    "dims": list(w.dims), "nnz": int(w.val.shape[0]), "ranks": list(w.ranks),
                    "m": w.m, "sweeps": w.sweeps, "prec": w.prec,
                    "solve": "RSVD-LRLS (Alg. 5)" if args.solve == "rsvd" else "exact truncated SVD"},
         "final_relative_residual": fits[-1] if fits else None,
         "roofline": roofline(dominant, work, dom[0], dom[1], args.steps, args.workload),
-        "sketch_pass_roofline": roofline("sketch_pass", work, sp[0], sp[1], args.steps,
-                                         args.workload),
+        f"{second}_roofline": roofline(second, work, sp[0], sp[1], args.steps, args.workload),
     }
-    if not args.no_cpu_baseline and args.workload == "sparse2000":
+    if not args.no_cpu_baseline and args.workload in ("sparse2000", "sparse2000lev"):
         out["cpu_baseline"] = cpu_baseline(w, args.solve)
     print(json.dumps(out))
 
@@ -271,9 +290,11 @@ def cpu_baseline(w, solve="exact", sample_sweeps=3):
         cores = os.cpu_count()
     T = osk.Tensor(w.dims, w.idx, w.val.astype(np.float64))
     N, m, ranks, seed = len(w.dims), w.m, w.ranks, 0
+    ts = w.sketch == "ts"
     t0 = time.perf_counter()
-    tables = {n: osk.ts_tables(w.dims, m, seed, n) for n in range(N)}
-    Ys = {n: osk.ts_rhs(T, m, tables[n], n) for n in range(N)}
+    if ts:
+        tables = {n: osk.ts_tables(w.dims, m, seed, n) for n in range(N)}
+        Ys = {n: osk.ts_rhs(T, m, tables[n], n) for n in range(N)}
     factors = [None] * N
     for n in range(1, N):
         k1, k2 = otk.default_rrf_sizes(m, ranks, n)
@@ -282,13 +303,18 @@ def cpu_baseline(w, solve="exact", sample_sweeps=3):
     t1 = time.perf_counter()
     for sweep in range(sample_sweeps):
         for n in range(N):
-            Z = osk.ts_lhs(factors, tables[n], m, n)
+            if ts:
+                Z, Y = osk.ts_lhs(factors, tables[n], m, n), Ys[n]
+            else:
+                idx, wt = osk.leverage_sample(factors, m, seed, sweep, n)
+                Z = osk.leverage_lhs(factors, idx, wt, n)
+                Y = osk.leverage_rhs_sparse(T, idx, wt, n)
             if solve == "rsvd":
                 kk = otk.rsvd_width(ranks[n], Z.shape[1])
                 Om = otk.rsvd_omega(seed, sweep, n, w.dims[n], kk)
-                A, W = osv.rsvd_lrls(Z, Ys[n], ranks[n], Om)
+                A, W = osv.rsvd_lrls(Z, Y, ranks[n], Om)
             else:
-                A, W, _ = osv.rc_solve(Z, Ys[n], ranks[n])
+                A, W, _ = osv.rc_solve(Z, Y, ranks[n])
             factors[n] = A
             core = otk.W_to_core(W, ranks, n)
         otk.relative_residual(T, core, factors)

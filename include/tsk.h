@@ -45,7 +45,7 @@ extern "C" {
 #endif
 
 #define TSK_MAX_ORDER 8
-#define TSK_ABI_VERSION 2
+#define TSK_ABI_VERSION 3
 
 typedef enum {
   TSK_OK = 0,
@@ -146,7 +146,9 @@ tsk_status tsk_workspace_size(const tsk_tensor* T, const int32_t* ranks,
  * B~ = best rank-R_n approximation of (S P)^+ (S T_(n)^T), A^(n) = its leading
  * right singular vectors, C_(n)^T = B~ A^(n) (Sec. 2.2, Sec. 4 theorems).
  * TensorSketch maps are drawn once and S^(n) T_(n)^T is formed once for all
- * sweeps; leverage samples are redrawn for every subproblem (Sec. 6.1).
+ * sweeps; leverage samples are redrawn for every subproblem (Sec. 6.1); for a
+ * COO tensor the mode-n fibre indices (tsk_fiber_index) are built once, in
+ * the workspace, and every sampled right-hand side is gathered through them.
  *   ranks       host int32[N], 1 <= R_n < s_n
  *   core        device double[prod R_n]          (output)
  *   factors     host array of N device double*, factors[n] is s_n x R_n with
@@ -156,7 +158,7 @@ tsk_status tsk_workspace_size(const tsk_tensor* T, const int32_t* ranks,
  *               sweep (needs TSK_FLAG_RECORD_FIT)
  *   sweeps_done host int32 or NULL
  * Synchronous.  Errors: EINVAL (shapes, m < prod_{k != n} R_k, sizes),
- * EUNSUPPORTED (leverage sampling of a COO tensor), ENOMEM (workspace),
+ * EUNSUPPORTED (prod s_k > 2^64 for leverage sampling of a COO tensor), ENOMEM (workspace),
  * ENUMERIC (sketched Gram not positive definite), EHIP. */
 tsk_status tsk_tucker_sketch_als(const tsk_tensor* T, const int32_t* ranks,
                                  const tsk_options* opt, double* core,
@@ -273,10 +275,41 @@ tsk_status tsk_leverage_sample(int32_t order, const int64_t* dims, const int32_t
 /* Sampled sketch (Sec. 3.2): Z[j, :] = w_j kron_{k != n} A^(k)(idx[j][.], :),
  * Y[j, :] = w_j T(i_1, .., :, .., i_N) (the sampled mode-n fibre of a dense T).
  *   Z device m x r, Y device m x dims[n], element type by prec (outputs).
- * EUNSUPPORTED for COO tensors. */
+ * Either output may be NULL.  For a COO tensor Y must be NULL (EUNSUPPORTED):
+ * its fibres come from tsk_sketch_lev_coo. */
 tsk_status tsk_sketch_lev(const tsk_tensor* T, const int32_t* ranks, int32_t n, int64_t m,
                           const int32_t* idx, const double* w, const double* const* factors,
                           int32_t prec, void* Z, void* Y, void* stream);
+
+/* Mode-n fibre index of a COO tensor, the access structure behind the O(m s_n)
+ * sampled right-hand side of leverage-score sampling (Sec. 3.2, cost in
+ * Sec. 6.1).  Every entry e gets the key
+ *   key(e) = (row-major linear index of (i_k)_{k != n}) * s_n + i_n,
+ * and the index holds the keys in ascending order (uint64[nnz]) followed by the
+ * values in the same order (the tensor's dtype), from a stable sort, so that
+ * duplicate coordinates stay adjacent in input order.
+ *   index  device buffer of *index_bytes, 256-byte aligned (output); it stays
+ *          valid while T's coordinates and values are unchanged
+ *   ws     device scratch of *ws_bytes, 256-byte aligned (free after the call)
+ * With index == NULL or ws == NULL, only *index_bytes and *ws_bytes are set.
+ * Asynchronous on `stream`.  Errors: EINVAL (not COO, bad mode, NULL sizes,
+ * buffers too small or misaligned), EUNSUPPORTED (prod s_k > 2^64), EHIP. */
+tsk_status tsk_fiber_index(const tsk_tensor* T, int32_t n, void* index, size_t* index_bytes,
+                           void* ws, size_t* ws_bytes, void* stream);
+
+/* Sampled fibres of a COO tensor (Sec. 3.2) through its mode-n fibre index:
+ *   Y[j, i] = w_j * (sum of the values stored at the coordinate whose mode-n
+ *             index is i and whose other indices are idx[j][.]),
+ * duplicates summed in FP64 in input order, 0 where nothing is stored.
+ *   index  built by tsk_fiber_index from the same T and n (not checked)
+ *   idx    device int32 m x (N-1), modes k != n in increasing order (as from
+ *          tsk_leverage_sample); each idx[j][t] within [0, s_k)
+ *   w      device double m
+ *   Y      device m x dims[n], element type by prec (output)
+ * Asynchronous.  Errors: EINVAL, EHIP. */
+tsk_status tsk_sketch_lev_coo(const tsk_tensor* T, int32_t n, const void* index, int64_t m,
+                              const int32_t* idx, const double* w, int32_t prec, void* Y,
+                              void* stream);
 
 /* Relative residual ||T - C x_1 A^(1) ... x_N A^(N)||_F / ||T||_F (Sec. 7,
  * 1 - fitness), accumulated in FP64 as ||T||^2 - 2 <T, T~> + ||T~||^2.

@@ -15,7 +15,8 @@ import torch
 from . import _lib as L
 
 __all__ = ["Tensor", "tucker_sketch_als", "cp_via_tucker", "hash_tables", "sketch_rhs_ts",
-           "sketch_lhs_ts", "rc_solve", "rrf_init", "leverage_sample", "sketch_lev", "fit",
+           "sketch_lhs_ts", "rc_solve", "rrf_init", "leverage_sample", "sketch_lev",
+           "FiberIndex", "fiber_index", "sketch_lev_coo", "fit",
            "sketched_residual", "sketched_residual_grads", "SketchedResidual", "lib"]
 
 lib = L.lib
@@ -273,6 +274,39 @@ def sketch_lev(T, ranks, n, m, idx, w, factors, prec="f64"):
                                    L.ptr(idx), L.ptr(w), L.ptr_array(facs), L.PREC[prec],
                                    L.ptr(Z), L.ptr(Y), L.stream_ptr()))
     return Z, Y
+
+
+class FiberIndex:
+    """Mode-n fibre index of a COO tensor (device buffer owned by this object)."""
+
+    def __init__(self, T, n, keep, pointer, nbytes):
+        self.T, self.n, self._keep, self.ptr, self.nbytes = T, int(n), keep, pointer, nbytes
+
+
+def fiber_index(T, n):
+    """Build the mode-n fibre index of COO tensor T (sorted keys + values)."""
+    ct = T.c_struct()
+    ib, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    L.check(L.lib().tsk_fiber_index(ctypes.byref(ct), int(n), None, ctypes.byref(ib), None,
+                                    ctypes.byref(wb), L.stream_ptr()))
+    keep, ip, ni = L.workspace(ib.value, T.device)
+    wkeep, wp, nw = L.workspace(wb.value, T.device)
+    ib2, wb2 = ctypes.c_size_t(ni), ctypes.c_size_t(nw)
+    L.check(L.lib().tsk_fiber_index(ctypes.byref(ct), int(n), ip, ctypes.byref(ib2), wp,
+                                    ctypes.byref(wb2), L.stream_ptr()))
+    torch.cuda.current_stream().synchronize()
+    del wkeep
+    return FiberIndex(T, n, keep, ip, ni)
+
+
+def sketch_lev_coo(T, index, m, idx, w, prec="f64"):
+    """Sampled mode-n fibres of COO tensor T through its fibre index: Y (m x s_n)."""
+    n = index.n
+    Y = torch.empty((int(m), T.dims[n]), dtype=_PREC_DTYPE[prec], device=T.device)
+    ct = T.c_struct()
+    L.check(L.lib().tsk_sketch_lev_coo(ctypes.byref(ct), n, index.ptr, int(m), L.ptr(idx),
+                                       L.ptr(w), L.PREC[prec], L.ptr(Y), L.stream_ptr()))
+    return Y
 
 
 def fit(T, core, factors):

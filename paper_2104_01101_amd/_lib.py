@@ -74,6 +74,8 @@ def lib():
             "tsk_rrf_init": (i32, [T, i32, i32, i32, i32, u64, vp, vp, sz, vp]),
             "tsk_leverage_sample": (i32, [i32, vp, vp, i32, i64, u64, i32, vp, vp, vp, vp, sz, vp]),
             "tsk_sketch_lev": (i32, [T, vp, i32, i64, vp, vp, vp, i32, vp, vp, vp]),
+            "tsk_fiber_index": (i32, [T, i32, vp, sz, vp, sz, vp]),
+            "tsk_sketch_lev_coo": (i32, [T, i32, vp, i64, vp, vp, i32, vp, vp]),
             "tsk_fit": (i32, [T, vp, vp, vp, vp, vp, sz, vp]),
             "tsk_sketched_residual_fwd": (i32, [i32, vp, vp, i32, i64, vp, vp, vp, vp, vp, i32,
                                                 vp, vp, sz, vp]),

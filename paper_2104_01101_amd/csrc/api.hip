@@ -9,6 +9,7 @@
 
 #include "common.h"
 #include "cp.h"
+#include "fibers.h"
 #include "fit.h"
 #include "kernels.h"
 #include "leverage.h"
@@ -207,8 +208,8 @@ tsk_status validate_options(const TensorView& T, const int64_t* R, const tsk_opt
   }
   TSK_REQUIRE(opt->m < (int64_t(1) << 31), "sketch size too large");
   if (opt->sketch == TSK_SKETCH_LEV && T.layout == TSK_COO) {
-    set_error("leverage-score sampling of a COO tensor needs a fibre index (not built)");
-    return TSK_EUNSUPPORTED;
+    unsigned bits = 0;
+    TSK_TRY(fiber_key_bits(T, &bits));
   }
   return TSK_OK;
 }
@@ -275,10 +276,14 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
   int32_t* lev_idx = nullptr;
   double* lev_w = nullptr;
   void* Ylev = nullptr;
+  const bool fibres = !ts && T.layout == TSK_COO;
+  std::vector<FiberIndexView> fib(N);
   if (!ts) {
     lev_idx = ws.take<int32_t>(size_t(m) * (N - 1));
     lev_w = ws.take<double>(m);
     Ylev = ws.take<char>(size_t(m) * smax * prec_bytes(prec));
+    if (fibres)
+      for (int n = 0; n < N; ++n) TSK_TRY(fiber_index_alloc(T, n, fib[n], ws));
   }
   FitScratch fs{};
   if (record) TSK_TRY(fit_plan(T, a.R, fs, ws));
@@ -303,6 +308,11 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
         release();
       }
   }
+  if (fibres)  // mode-n fibre indices of a COO tensor for the sampled right-hand sides
+    for (int n = 0; n < N; ++n) {
+      TSK_TRY(fiber_index_build(T, fib[n], ws, st));
+      release();
+    }
   if (ts) {  // sketched right-hand sides of every mode: one pass over the entries
     std::vector<PassJob> jobs;
     for (int n = 0; n < N; ++n) jobs.push_back(PassJob{0, n, m, &h[n * N], &sg[n * N], 0, Yt[n]});
@@ -360,9 +370,14 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
         Y = Yp[n];
       } else {
         TSK_TRY(leverage_sample(N, T.dims, a.R, n, m, o.seed, sweep, a.factors, lev_idx, lev_w,
-                                ws, st));
-        if (run)
-          TSK_TRY(leverage_rows(T, a.R, n, m, lev_idx, lev_w, a.factors, prec, Z, Ylev, st));
+                                ws, st, prec, Z));
+        if (run) {
+          if (fibres)
+            TSK_TRY(fiber_rows(fib[n], m, lev_idx, lev_w, prec, Ylev, st));
+          else
+            TSK_TRY(leverage_rows(T, a.R, n, m, lev_idx, lev_w, a.factors, prec, nullptr, Ylev,
+                                  st));
+        }
         Y = Ylev;
       }
       if (rsvd) {  // RSVD-LRLS (Alg. 5) with the test matrix of stream (seed, RSVD, sweep, n)
@@ -649,12 +664,66 @@ tsk_status tsk_sketch_lev(const tsk_tensor* T, const int32_t* ranks, int32_t n, 
   TSK_REQUIRE(ranks && idx && w && factors && n >= 0 && n < tv.order && m >= 1,
               "invalid arguments");
   if (tv.layout == TSK_COO && Y) {
-    set_error("sampled fibres of a COO tensor need a fibre index (not built)");
+    set_error("sampled fibres of a COO tensor come from tsk_sketch_lev_coo (fibre index)");
     return TSK_EUNSUPPORTED;
   }
   int64_t R[TSK_MAX_ORDER];
   for (int k = 0; k < tv.order; ++k) R[k] = ranks[k];
   return leverage_rows(tv, R, n, m, idx, w, factors, prec, Z, Y, as_stream(stream));
+}
+
+tsk_status tsk_fiber_index(const tsk_tensor* T, int32_t n, void* index, size_t* index_bytes,
+                           void* ws, size_t* ws_bytes, void* stream) {
+  clear_error();
+  TensorView tv;
+  TSK_TRY(view_tensor(T, tv));
+  TSK_REQUIRE(tv.layout == TSK_COO, "a fibre index is built for COO tensors");
+  TSK_REQUIRE(n >= 0 && n < tv.order, "invalid mode %d", n);
+  TSK_REQUIRE(index_bytes && ws_bytes, "index_bytes and ws_bytes must not be NULL");
+  hipStream_t st = as_stream(stream);
+  FiberIndexView fx{};
+  Ws ix_probe, ws_probe;
+  TSK_TRY(fiber_index_alloc(tv, n, fx, ix_probe));
+  TSK_TRY(fiber_index_build(tv, fx, ws_probe, st));
+  const size_t need_ix = ix_probe.off + 256, need_ws = ws_probe.off + 256;
+  if (!index || !ws) {
+    *index_bytes = need_ix;
+    *ws_bytes = need_ws;
+    return TSK_OK;
+  }
+  TSK_REQUIRE(!(reinterpret_cast<uintptr_t>(index) & 255) &&
+                  !(reinterpret_cast<uintptr_t>(ws) & 255),
+              "index and workspace must be 256-byte aligned");
+  TSK_REQUIRE(*index_bytes >= need_ix && *ws_bytes >= need_ws,
+              "buffers too small: index %zu < %zu or workspace %zu < %zu", *index_bytes, need_ix,
+              *ws_bytes, need_ws);
+  Ws ix, w;
+  ix.base = static_cast<char*>(index);
+  ix.cap = *index_bytes;
+  w.base = static_cast<char*>(ws);
+  w.cap = *ws_bytes;
+  TSK_TRY(fiber_index_alloc(tv, n, fx, ix));
+  return fiber_index_build(tv, fx, w, st);
+}
+
+tsk_status tsk_sketch_lev_coo(const tsk_tensor* T, int32_t n, const void* index, int64_t m,
+                              const int32_t* idx, const double* w, int32_t prec, void* Y,
+                              void* stream) {
+  clear_error();
+  TensorView tv;
+  TSK_TRY(view_tensor(T, tv));
+  TSK_REQUIRE(tv.layout == TSK_COO, "tsk_sketch_lev_coo takes a COO tensor");
+  TSK_REQUIRE(n >= 0 && n < tv.order, "invalid mode %d", n);
+  TSK_REQUIRE(index && !(reinterpret_cast<uintptr_t>(index) & 255), "index NULL or misaligned");
+  TSK_REQUIRE(m >= 0 && m < (int64_t(1) << 31), "invalid sample count");
+  TSK_REQUIRE(m == 0 || (idx && w && Y), "invalid arguments");
+  TSK_REQUIRE(prec >= TSK_PREC_F64 && prec <= TSK_PREC_BF16, "unknown precision %d", prec);
+  FiberIndexView fx{};
+  Ws ix;
+  ix.base = static_cast<char*>(const_cast<void*>(index));
+  ix.cap = ~size_t(0);
+  TSK_TRY(fiber_index_alloc(tv, n, fx, ix));
+  return fiber_rows(fx, m, idx, w, prec, Y, as_stream(stream));
 }
 
 tsk_status tsk_fit(const tsk_tensor* T, const int32_t* ranks, const double* core,

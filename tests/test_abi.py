@@ -32,7 +32,7 @@ def test_header_symbols_exported():
 def test_abi_version():
     """Version 2: the options struct gained the subproblem solver (solve, rsvd_k)."""
     L = _lib()
-    assert L.lib().tsk_abi_version() == 2
+    assert L.lib().tsk_abi_version() == 3
     assert L._Options.solve.offset == 76 and L._Options.rsvd_k.offset == 80
 
 
@@ -69,7 +69,7 @@ def _opts(L, m, sketch=0, solve=0, rsvd_k=0):
     ((10, 10, 10), (3, 3, 3), 5, 0, 0, -1),        # m < prod of other ranks
     ((10, 10, 10), (11, 3, 3), 50, 0, 0, -1),      # rank above dimension
     ((10,), (3,), 50, 0, 0, -1),                   # order 1
-    ((10, 10, 10), (3, 3, 3), 50, 1, 1, -2),       # leverage on COO: unsupported
+    ((2**31 - 1,) * 3, (3, 3, 3), 50, 1, 1, -2),   # leverage on COO: fibre keys beyond 64 bits
     ((10, 10, 10), (3, 3, 20), 50, 0, 0, -1),      # R_n above the product of the others... and s
 ])
 def test_validation_errors(dims, ranks, m, sketch, layout, expect):
@@ -115,3 +115,28 @@ def test_rsvd_option_validation(solve, rsvd_k, expect):
     st = L.lib().tsk_workspace_size(ctypes.byref(t), L.i32_array((3, 3, 3)), ctypes.byref(o),
                                     ctypes.byref(nb))
     assert st == expect
+
+
+def test_fibre_index_query_sizes():
+    """Host-side size query of the fibre index (no device work): keys and values
+    of every entry; the leverage job on a COO tensor holds N of them."""
+    L = _lib()
+    t = _tensor(L, (100, 90, 80), dtype=0, layout=1, nnz=1000)
+    for k in range(3):
+        t.idx[k] = 8
+    ib, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.lib().tsk_fiber_index(ctypes.byref(t), 1, None, ctypes.byref(ib), None,
+                                   ctypes.byref(wb), None) == 0
+    assert 1000 * (8 + 4) <= ib.value <= 1000 * (8 + 4) + 1024
+    assert wb.value >= 1000 * 8
+    dense = _tensor(L, (10, 10, 10))
+    assert L.lib().tsk_fiber_index(ctypes.byref(dense), 0, None, ctypes.byref(ib), None,
+                                   ctypes.byref(wb), None) == -1
+    sizes = []
+    for sketch in (0, 1):
+        o = _opts(L, 200, sketch)
+        nb = ctypes.c_size_t(0)
+        assert L.lib().tsk_workspace_size(ctypes.byref(t), L.i32_array((5, 5, 5)),
+                                          ctypes.byref(o), ctypes.byref(nb)) == 0
+        sizes.append(nb.value)
+    assert sizes[1] > 3 * 1000 * 12

@@ -189,7 +189,9 @@ def test_rrf_init_sparse_fp32(tsk):
 # ---------------------------------------------------------------- a5 ----
 @pytest.mark.parametrize("dims,ranks,m,n", [((200, 200, 200, 200), (10, 10, 10, 10), 4000, 1),
                                             ((500, 500, 500), (30, 30, 30), 14400, 0),
-                                            ((40, 40, 40), (5, 5, 5), 200, 2)])
+                                            ((40, 40, 40), (5, 5, 5), 200, 2),
+                                            # cdfs beyond the LDS staging budget
+                                            ((9000, 3000, 50), (4, 4, 4), 300, 2)])
 def test_leverage_sample_bit_exact(tsk, dims, ranks, m, n):
     rs = np.random.default_rng(sum(dims))
     facs = [np.linalg.qr(rs.standard_normal((d, r)))[0] for d, r in zip(dims, ranks)]
@@ -212,6 +214,85 @@ def test_leverage_rows_match(tsk):
     io, wo = idx.cpu().numpy().astype(np.int64), w.cpu().numpy()
     np.testing.assert_array_equal(Z.cpu().numpy(), osk.leverage_lhs(facs, io, wo, n))
     np.testing.assert_allclose(Y.cpu().numpy(), osk.leverage_rhs_dense(X, io, wo, n), rtol=1e-15)
+
+
+# ------------------------------------------------- sparse fibres (f2) ----
+def _coo_with_duplicates(dims, nnz, dup, rs, dtype):
+    """nnz distinct uniform coordinates, `dup` of them stored again with fresh
+    values, all shuffled (COO: duplicates add)."""
+    idx, _ = workloads.distinct_coords(
+        dims, nnz, lambda r, c: np.stack([r.integers(0, d, c) for d in dims], 1), rs)
+    if dup and nnz:
+        idx = np.concatenate([idx, idx[rs.integers(0, nnz, dup)]])
+    val = rs.standard_normal(idx.shape[0])
+    perm = rs.permutation(idx.shape[0])
+    return idx[perm].astype(np.int32), val[perm].astype(dtype)
+
+
+def _fibre_samples(dims, n, idx, m, rs):
+    """m sampled other-mode coordinates: half taken from stored entries (non-empty
+    fibres, duplicates included), half uniform; positive weights."""
+    others = [k for k in range(len(dims)) if k != n]
+    uni = np.stack([rs.integers(0, dims[k], m) for k in others], 1)
+    if idx.shape[0]:
+        hit = idx[rs.integers(0, idx.shape[0], m)][:, others]
+        uni[: m // 2] = hit[: m // 2]
+    return uni.astype(np.int32), rs.uniform(0.5, 2.0, m)
+
+
+def _check_fibres(tsk, dims, idx, val, n, samples, w):
+    T = _gpu_tensor(tsk, dims, idx, val)
+    fx = tsk.fiber_index(T, n)
+    ig, wg = torch.from_numpy(samples).to(DEV), torch.from_numpy(w).to(DEV)
+    Yo = osk.leverage_rhs_sparse(osk.Tensor(dims, idx, val), samples.astype(np.int64), w, n)
+    Y64 = tsk.sketch_lev_coo(T, fx, samples.shape[0], ig, wg, "f64").cpu().numpy()
+    np.testing.assert_array_equal(Y64, Yo)
+    Y32 = tsk.sketch_lev_coo(T, fx, samples.shape[0], ig, wg, "f32").cpu().numpy()
+    np.testing.assert_array_equal(Y32, Yo.astype(np.float32))
+    Ybf = tsk.sketch_lev_coo(T, fx, samples.shape[0], ig, wg, "bf16").cpu()
+    assert torch.equal(Ybf, torch.from_numpy(Yo).float().bfloat16())
+    return Yo
+
+
+@pytest.mark.parametrize("dims,nnz,dup,n,m,dtype", [
+    ((30, 25, 20), 3000, 500, 1, 700, np.float64),       # several search rounds
+    ((300, 300, 300), 200_000, 20_000, 0, 2000, np.float32),
+    ((5000, 9, 7), 40_000, 1000, 0, 300, np.float64),    # s_n > 4096: two LDS chunks
+    ((12, 10, 8, 6), 4000, 300, 2, 500, np.float32),     # order 4
+    ((7, 6, 5), 40, 10, 2, 64, np.float64),              # fewer entries than one probe round
+    ((20, 20, 20), 0, 0, 1, 50, np.float64),             # empty tensor
+])
+def test_fibre_gather_bit_exact(tsk, dims, nnz, dup, n, m, dtype):
+    rs = np.random.default_rng(nnz + n)
+    idx, val = _coo_with_duplicates(dims, nnz, dup, rs, dtype)
+    samples, w = _fibre_samples(dims, n, idx, m, rs)
+    Yo = _check_fibres(tsk, dims, idx, val, n, samples, w)
+    if nnz:
+        assert np.count_nonzero(Yo) > 0
+
+
+def test_fibre_gather_every_mode_and_sampler(tsk):
+    """All modes of one tensor, samples from the library's leverage sampler."""
+    dims, ranks = (40, 30, 20), (4, 3, 2)
+    rs = np.random.default_rng(11)
+    idx, val = _coo_with_duplicates(dims, 8000, 800, rs, np.float32)
+    facs = [np.linalg.qr(rs.standard_normal((d, r)))[0] for d, r in zip(dims, ranks)]
+    fg = [torch.from_numpy(F).to(DEV) for F in facs]
+    for n in range(3):
+        ig, wg = tsk.leverage_sample(dims, ranks, n, 600, 5, 1, fg)
+        _check_fibres(tsk, dims, idx, val, n, ig.cpu().numpy(), wg.cpu().numpy())
+
+
+def test_sketch_lev_coo_rejects_dense_route(tsk):
+    dims = (10, 9, 8)
+    rs = np.random.default_rng(2)
+    idx, val = _coo_with_duplicates(dims, 100, 0, rs, np.float64)
+    T = _gpu_tensor(tsk, dims, idx, val)
+    ig = torch.zeros((4, 2), dtype=torch.int32, device=DEV)
+    wg = torch.ones(4, dtype=torch.float64, device=DEV)
+    fg = [torch.eye(d, 2, dtype=torch.float64, device=DEV) for d in dims]
+    with pytest.raises(RuntimeError, match="tsk_sketch_lev_coo"):
+        tsk.sketch_lev(T, (2, 2, 2), 0, 4, ig, wg, fg, "f64")
 
 
 # ---------------------------------------------------------------- a11 ----

@@ -14,7 +14,13 @@ repeatability of the whole job.
 
 zipf10k -- 10000^3 with 10^7 Zipf(1.1) entries: the FP32 sketch pass of one
 mode against the oracle's FP64 per-cell sums, within the bound of FP32
-summation in input order, and bitwise repeatable."""
+summation in input order, and bitwise repeatable.
+
+Leverage sampling of the COO tensors (fibre indices): the sampled fibres of
+sparse2000 and zipf10k (whose head fibres hold thousands of entries) equal the
+oracle's bit for bit in FP64, and the first three sweeps of the sparse2000
+leverage job (m = 1600 sampled fibres per subproblem, RSVD-LRLS, FP32
+operands) match the oracle within 1e-5."""
 import numpy as np
 import pytest
 import torch
@@ -36,6 +42,11 @@ def tsk():
 @pytest.fixture(scope="module")
 def sparse2000():
     return workloads.sparse2000()
+
+
+@pytest.fixture(scope="module")
+def zipf10k():
+    return workloads.zipf10k()
 
 
 def _plan(tsk, w, sweeps=None):
@@ -75,8 +86,8 @@ def _tables_np(h, s):
             for k in range(len(h)) if h[k] is not None}
 
 
-def test_zipf10k_sketch_pass_mode0(tsk):
-    w = workloads.zipf10k()
+def test_zipf10k_sketch_pass_mode0(tsk, zipf10k):
+    w = zipf10k
     n, m = 0, w.m
     T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(DEV), torch.from_numpy(w.val).to(DEV), w.dims)
     h, s = tsk.hash_tables(w.dims, n, m, 7, DEV)
@@ -92,3 +103,52 @@ def test_zipf10k_sketch_pass_mode0(tsk):
     cnt = np.bincount(key, minlength=m * w.dims[n]).reshape(m, -1)
     bound = (cnt + 2) * 2.0 ** -24 * absum
     assert np.all(np.abs(Y1.cpu().numpy().astype(np.float64) - Yo) <= bound + 1e-30)
+
+
+def _fibre_parity(tsk, w, n, seed):
+    """Sampled mode-n fibres at full size: m samples, half at the other-mode
+    coordinates of stored entries, half from the library's leverage sampler
+    with random orthonormal factors; FP64 output compared bit for bit."""
+    rs = np.random.default_rng(seed)
+    T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(DEV), torch.from_numpy(w.val).to(DEV), w.dims)
+    fx = tsk.fiber_index(T, n)
+    facs = [torch.linalg.qr(torch.randn(d, R, dtype=torch.float64,
+                                        generator=torch.Generator().manual_seed(seed + d)))[0]
+            .to(DEV) for d, R in zip(w.dims, w.ranks)]
+    ig, wg = tsk.leverage_sample(w.dims, w.ranks, n, w.m, seed, 0, facs)
+    io, wo = ig.cpu().numpy(), wg.cpu().numpy()
+    others = [k for k in range(len(w.dims)) if k != n]
+    half = w.m // 2
+    io[:half] = w.idx[rs.integers(0, w.idx.shape[0], half)][:, others]
+    key = np.ravel_multi_index(w.idx[:, others].T.astype(np.int64), [w.dims[k] for k in others])
+    u, cnt = np.unique(key, return_counts=True)
+    io[0] = np.unravel_index(u[cnt.argmax()], [w.dims[k] for k in others])  # heaviest fibre
+    ig = torch.from_numpy(io).to(DEV)
+    Y = tsk.sketch_lev_coo(T, fx, w.m, ig, wg, "f64")
+    assert torch.equal(Y, tsk.sketch_lev_coo(T, fx, w.m, ig, wg, "f64"))
+    To = osk.Tensor(w.dims, w.idx, w.val.astype(np.float64))
+    Yo = osk.leverage_rhs_sparse(To, io.astype(np.int64), wo, n)
+    np.testing.assert_array_equal(Y.cpu().numpy(), Yo)
+    return Yo
+
+
+def test_sparse2000_fibres_bit_exact(tsk, sparse2000):
+    for n in range(3):
+        Yo = _fibre_parity(tsk, sparse2000, n, 20 + n)
+        assert np.count_nonzero(Yo) >= sparse2000.m // 2
+
+
+def test_zipf10k_fibres_bit_exact(tsk, zipf10k):
+    w = zipf10k
+    Yo = _fibre_parity(tsk, w, 0, 31)
+    assert np.count_nonzero(Yo, axis=1).max() > 4096  # a fibre spanning several LDS chunks
+
+
+def test_sparse2000lev_job_vs_oracle(tsk):
+    w = workloads.sparse2000lev()
+    T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(DEV), torch.from_numpy(w.val).to(DEV), w.dims)
+    _, _, fits = tsk.tucker_sketch_als(T, w.ranks, w.m, 3, sketch="lev", init="rrf",
+                                       prec=w.prec, seed=0, solve="rsvd")
+    To = osk.Tensor(w.dims, w.idx, w.val.astype(np.float64))
+    ref = otk.sketch_tucker_als(To, w.ranks, w.m, 3, seed=0, sketch_kind="lev", solve_kind="rsvd")
+    np.testing.assert_allclose(fits, ref["fits"], rtol=0, atol=1e-5)

@@ -123,6 +123,46 @@ def test_cp_via_tucker_fp64(tsk):
         np.testing.assert_allclose(F.cpu().numpy(), Fo, atol=1e-6 * np.abs(Fo).max())
 
 
+@pytest.mark.parametrize("prec,solve,tol", [("f64", "exact", 1e-10), ("f32", "exact", 1e-5),
+                                             ("f64", "rsvd", 1e-10)])
+def test_sparse_leverage_parity(tsk, prec, solve, tol):
+    """Leverage-score sampling of a COO tensor through the per-mode fibre indices:
+    80 x 70 x 60 with 100k distinct uniform coordinates (30 % of the entries),
+    Tucker (5, 4, 3) signal + N(0, 0.1^2), m = 400 samples per subproblem, RRF
+    init, 4 sweeps, against the oracle's sampled fibres of the coalesced tensor."""
+    dims, ranks, m = (80, 70, 60), (5, 4, 3), 400
+    idx, val = workloads.sparse_tucker(dims, 100_000, ranks, seed=4, noise_std=0.1)
+    val = val.astype(np.float32 if prec == "f32" else np.float64)
+    T = _coo(tsk, dims, idx, val)
+    _, factors, fits = tsk.tucker_sketch_als(T, ranks, m, 4, sketch="lev", prec=prec, seed=3,
+                                             solve=solve)
+    ref = otk.sketch_tucker_als(osk.Tensor(dims, idx, val.astype(np.float64)), ranks, m, 4,
+                                seed=3, sketch_kind="lev", solve_kind=solve)
+    np.testing.assert_allclose(fits, ref["fits"], rtol=0, atol=tol)
+    if prec == "f64":
+        for F, Fo in zip(factors, ref["factors"]):
+            np.testing.assert_allclose(F.cpu().numpy(), Fo, atol=1e-8)
+
+
+def test_sparse_leverage_dense_equivalent(tsk):
+    """The same small tensor stored densely and as COO (every entry, shuffled)
+    gives the same leverage run: the fibre index changes the access, not the sketch.
+    Random init (independent of T) keeps the range finder's layout-dependent
+    summation order out of the comparison, so the factors agree bit for bit."""
+    X = workloads.tucker_dense((24, 22, 20), (3, 3, 3), 0.05, seed=8)
+    dims = X.shape
+    To = osk.Tensor.from_dense(X)
+    perm = np.random.default_rng(0).permutation(To.val.size)
+    idx, val = To.idx[perm].astype(np.int32), To.val[perm].copy()
+    a = tsk.tucker_sketch_als(_dense(tsk, X), (3, 3, 3), 200, 3, sketch="lev", init="random",
+                              prec="f64", seed=9)
+    b = tsk.tucker_sketch_als(_coo(tsk, dims, idx, val), (3, 3, 3), 200, 3, sketch="lev",
+                              init="random", prec="f64", seed=9)
+    for F, G in zip(a[1], b[1]):
+        assert torch.equal(F, G)
+    np.testing.assert_allclose(a[2], b[2], rtol=0, atol=1e-13)
+
+
 # -------------------------------------------- RSVD-LRLS subproblem solver ----
 def test_dense40_rsvd_fp64_parity(tsk):
     """The small dense case with the paper's subproblem solver (Alg. 4 calls RSVD-LRLS,
