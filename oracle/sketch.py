@@ -13,6 +13,9 @@ Everything is FP64 NumPy, written from the paper's definitions:
 * leverage scores and Kronecker-factored sampling
                                                 -- Definition (leverage scores), Definition
                                                    (importance sampling), Lemma (Kronecker leverage)
+* deterministic leverage selection (the m rows of largest score, no rescaling)
+                                                -- Sec. 3.2, the deterministic alternative to
+                                                   importance sampling
 * composite sketch S = T G of the range finder  -- Definition (composite sketch), Sec. 5
 
 Index conventions.  Tensors are row-major (last index fastest).  For mode n the
@@ -189,6 +192,41 @@ def leverage_sample(factors, m, seed, sweep, n):
         prob = prob * (ell[pos] / total)
     w = 1.0 / np.sqrt(m * prob)
     return idx, w
+
+
+def score_ranks(ell):
+    """Position of every row in the order (score descending, index ascending)."""
+    order = np.argsort(-np.asarray(ell), kind="stable")
+    rank = np.empty(order.size, dtype=np.int64)
+    rank[order] = np.arange(order.size)
+    return rank
+
+
+def leverage_select(factors, m, n):
+    """Deterministic leverage sampling (Sec. 3.2: instead of drawing rows with
+    probability proportional to their leverage scores, keep the rows with the
+    largest scores).  The rows of kron_{k != n} A^(k) are the multi-indices
+    (i_k)_{k != n}; by the Lemma on Kronecker leverage scores the score of a row
+    is pi = prod_k l^(k)_{i_k} (multiplied in increasing k).  The m rows of
+    largest pi are kept, in decreasing pi; rows of equal pi are ordered by their
+    per-mode ranks (score_ranks), compared lexicographically in increasing k.
+    No rescaling: every weight is 1.  Evaluated by brute force over all rows.
+    Returns (idx int64[m, N-1] in increasing k, w float64[m] = 1)."""
+    N = len(factors)
+    ks = other_modes(N, n)
+    ells = [leverage_scores(factors[k]) for k in ks]
+    total = int(np.prod([e.size for e in ells]))
+    if m > total:
+        raise ValueError("more rows requested than the Kronecker chain has")
+    grids = np.meshgrid(*[np.arange(e.size) for e in ells], indexing="ij")
+    flat = [g.reshape(-1) for g in grids]
+    pi = ells[0][flat[0]]
+    for t in range(1, len(ells)):
+        pi = pi * ells[t][flat[t]]
+    ranks = [score_ranks(e)[f] for e, f in zip(ells, flat)]
+    order = np.lexsort(ranks[::-1] + [-pi])[:m]
+    idx = np.stack([f[order] for f in flat], 1).astype(np.int64)
+    return idx, np.ones(m)
 
 
 def leverage_lhs(factors, idx, w, n):

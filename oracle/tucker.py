@@ -139,7 +139,8 @@ def sketch_tucker_als(T, ranks, m, sweeps, seed=0, sketch_kind="ts", init="rrf",
     T        oracle.sketch.Tensor (COO or dense)
     ranks    Tucker ranks (R_1..R_N)
     m        sketch size (rows of every sketched subproblem)
-    sketch_kind  "ts" (TensorSketch) or "lev" (leverage-score sampling)
+    sketch_kind  "ts" (TensorSketch), "lev" (leverage-score sampling) or
+             "lev_det" (deterministic leverage selection, weights 1)
     init     "rrf" (Alg. 3 for n = 2..N), "random" or "user" (init_factors)
     identity_sketch  replace S^(n) by the identity (then each subproblem is
              exactly the HOOI update) -- used to pin the driver to Alg. 1.
@@ -168,7 +169,7 @@ def sketch_tucker_als(T, ranks, m, sweeps, seed=0, sketch_kind="ts", init="rrf",
                 factors[n] = init_random(dims[n], ranks[n], n, seed)
     core = np.zeros(ranks)
 
-    Xd = T.to_dense() if (identity_sketch or sketch_kind == "lev") and \
+    Xd = T.to_dense() if (identity_sketch or sketch_kind in ("lev", "lev_det")) and \
         getattr(T, "dense", None) is not None else None
     # TensorSketch: S^(n) drawn once and Y^(n) formed once (preparation cost)
     tables, Ys = {}, {}
@@ -186,7 +187,10 @@ def sketch_tucker_als(T, ranks, m, sweeps, seed=0, sketch_kind="ts", init="rrf",
                 Z = sketch.ts_lhs(factors, tables[n], m, n)
                 Y = Ys[n]
             else:
-                idx, w = sketch.leverage_sample(factors, m, seed, sweep, n)
+                if sketch_kind == "lev_det":
+                    idx, w = sketch.leverage_select(factors, m, n)
+                else:
+                    idx, w = sketch.leverage_sample(factors, m, seed, sweep, n)
                 samples.append((sweep, n, idx, w))
                 Z = sketch.leverage_lhs(factors, idx, w, n)
                 Y = sketch.leverage_rhs_dense(Xd, idx, w, n) if Xd is not None \

@@ -213,6 +213,77 @@ def test_leverage_rows_match_explicit_kronecker():
     np.testing.assert_allclose(Ys, Y, atol=1e-14)
 
 
+def test_leverage_select_hand_worked_ties():
+    """Deterministic selection with ties, worked by hand.  Mode-0 scores
+    (1, 4, 4) from rows (1), (2), (2); mode-2 scores (9, 1) from rows (3), (1).
+    Row scores: (0,0) 9, (0,1) 1, (1,0) 36, (1,1) 4, (2,0) 36, (2,1) 4.  Per-mode
+    ranks (score descending, index ascending): mode 0 -> (2, 0, 1), mode 2 ->
+    (0, 1).  Order: 36 (1,0) before (2,0) by rank; 9 (0,0); 4 (1,1) before
+    (2,1); 1 (0,1)."""
+    facs = [np.array([[1.0], [2.0], [2.0]]), np.eye(4, 2), np.array([[3.0], [1.0]])]
+    idx, w = sketch.leverage_select(facs, 5, 1)
+    assert idx.tolist() == [[1, 0], [2, 0], [0, 0], [1, 1], [2, 1]]
+    assert np.all(w == 1.0)
+    Z = sketch.leverage_lhs(facs, idx, w, 1)
+    np.testing.assert_array_equal(Z[:, 0], [6.0, 6.0, 3.0, 2.0, 2.0])
+    # ties where rank order and index order disagree: scores (1, 4) and (4, 1);
+    # pi(0,0) = pi(1,1) = 4 with rank tuples (1, 0) and (0, 1): (1,1) comes first
+    facs = [np.array([[1.0], [2.0]]), np.eye(3, 1), np.array([[2.0], [1.0]])]
+    idx, _ = sketch.leverage_select(facs, 4, 1)
+    assert idx.tolist() == [[1, 0], [1, 1], [0, 0], [0, 1]]
+
+
+def test_leverage_select_is_top_rows_of_explicit_kronecker():
+    """The kept rows are the m rows of largest squared norm of the explicit
+    Kronecker product P = A^(0) (x) A^(2) (its leverage scores, orthonormal
+    columns), in decreasing order; the fixture has a clear gap at m."""
+    rs = np.random.default_rng(12)
+    facs = [np.linalg.qr(rs.standard_normal((s, r)))[0] for s, r in ((9, 2), (5, 3), (8, 3))]
+    P = tucker.kron_chain([facs[0], facs[2]])
+    lev = np.sum(P * P, axis=1)
+    m = 17
+    top = np.argsort(-lev, kind="stable")
+    assert lev[top[m - 1]] - lev[top[m]] > 1e-9
+    idx, _ = sketch.leverage_select(facs, m, 1)
+    rows = idx[:, 0] * 8 + idx[:, 1]
+    assert sorted(rows.tolist()) == sorted(top[:m].tolist())
+    assert np.all(np.diff(lev[rows]) <= 1e-15)
+    np.testing.assert_allclose(lev.sum(), 2 * 3, rtol=1e-13)   # sum of scores = prod R_k
+
+
+def test_leverage_select_rank_dominance_bound():
+    """A kept row's per-mode ranks satisfy prod_k (rank_k + 1) <= m: the rows
+    that dominate it in every mode all come first (pi is monotone in every
+    factor; equal pi is ordered by the ranks).  The library enumerates exactly
+    these candidates, so the bound is checked here, on ties too."""
+    rs = np.random.default_rng(3)
+    for dims, n, m in (((30, 20, 25), 0, 60), ((12, 9, 10, 8), 2, 150)):
+        facs = [np.linalg.qr(rs.standard_normal((s, 3)))[0] for s in dims]
+        facs[(n + 1) % len(dims)][3] = facs[(n + 1) % len(dims)][4]    # a tie
+        idx, _ = sketch.leverage_select(facs, m, n)
+        ks = [k for k in range(len(dims)) if k != n]
+        ranks = [sketch.score_ranks(sketch.leverage_scores(facs[k])) for k in ks]
+        bound = np.ones(m, dtype=np.int64)
+        for t in range(len(ks)):
+            bound *= ranks[t][idx[:, t]] + 1
+        assert bound.max() <= m
+
+
+def test_leverage_select_all_rows_reproduces_identity_sketch():
+    """Keeping every row (m = prod_{k != n} s_k) with weight 1 permutes the
+    rows of the full subproblem, so the driver reproduces the unsketched one."""
+    X = workloads.tucker_dense((9, 9, 9), (3, 2, 3), noise=0.2, seed=5)
+    T = sketch.Tensor.from_dense(X)
+    init = tucker.hosvd(X, (3, 2, 3))
+    a = tucker.sketch_tucker_als(T, (3, 2, 3), m=81, sweeps=2, init="user", init_factors=init,
+                                 sketch_kind="lev_det")
+    b = tucker.sketch_tucker_als(T, (3, 2, 3), m=0, sweeps=2, init="user", init_factors=init,
+                                 identity_sketch=True)
+    np.testing.assert_allclose(a["fits"], b["fits"], atol=1e-12)
+    for Fa, Fb in zip(a["factors"], b["factors"]):
+        np.testing.assert_allclose(Fa, Fb, atol=1e-10)
+
+
 # ----------------------------------------------------------------------------
 # Rank-constrained solve (Sec. 4)
 # ----------------------------------------------------------------------------
