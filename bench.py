@@ -46,10 +46,11 @@ GROUP_SOURCES = {
     "ts_lhs": ["ts_lhs.hip"], "gram": ["gemm.hip"], "solve_la": ["linalg.hip", "gemm.hip"],
     "eig": ["linalg.hip"], "fit": ["fit.hip"], "rrf": ["linalg.hip", "gemm.hip", "api.hip"],
     "leverage": ["leverage.hip"], "fiber_index": ["fibers.hip"], "fiber_rows": ["fibers.hip"],
+    "select": ["select.hip"],
 }
 GROUPS = ["sketch_pass", "rrf_pass", "rrf", "ts_lhs", "gram", "solve_la", "eig", "fit",
-          "leverage", "fiber_index", "fiber_rows"]
-WORKLOADS = ["sparse2000", "zipf10k", "sparse2000lev"]
+          "leverage", "fiber_index", "fiber_rows", "select"]
+WORKLOADS = ["sparse2000", "zipf10k", "sparse2000lev", "sparse2000det"]
 
 
 def parse():
@@ -59,8 +60,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="sparse2000", choices=WORKLOADS,
                     help="sparse2000 (default, the benchmark workload), zipf10k (sketch-pass "
-                         "study) or sparse2000lev (the same tensor under leverage-score "
-                         "sampling through the fibre indices)")
+                         "study), sparse2000lev / sparse2000det (the same tensor under "
+                         "leverage-score sampling / deterministic leverage selection, "
+                         "through the fibre indices)")
     ap.add_argument("--solve", default="rsvd", choices=["rsvd", "exact"],
                     help="subproblem solver: rsvd = RSVD-LRLS (Alg. 5, the solver Alg. 4 "
                          "calls) or exact = truncated SVD of Z^+ Y")
@@ -121,6 +123,9 @@ def group_work(w, solve="exact"):
         "leverage": ("hbm", subs * ((N - 1) * s * R * 8 + m * r * vb), HBM_PEAK_GBS, "GB/s"),
         # per mode: keys built (indices read, keys written), then sorted pairs written once
         "fiber_index": ("hbm", N * nnz * (4 * N + 8 + 12), HBM_PEAK_GBS, "GB/s"),
+        # deterministic selection: candidate products and their sort keys (about
+        # m (ln m + 1) candidates, 8-byte key + 4-byte id written, sorted, read back)
+        "select": ("hbm", subs * 3 * m * (math.log(m) + 1) * 24, HBM_PEAK_GBS, "GB/s"),
         # sampled fibres: Y written, the fibres' keys and values read (expected length
         # nnz / prod_{k != n} s_k), sample indices and weights read
         "fiber_rows": ("hbm", subs * (m * s * vb + m * (nnz / s ** (N - 1)) * 12
@@ -262,6 +267,10 @@ def main():
                                         "N(0,1), leverage-score sampling m=1600 through "
                                         "per-mode fibre indices, RRF init, 10 sweeps of "
                                         "Alg. 4, FP32 operands",
+                       "sparse2000det": "sparse 2000^3, 1e6 nnz uniform, Tucker rank 10 + "
+                                        "N(0,1), deterministic leverage selection m=1600 "
+                                        "through per-mode fibre indices, RRF init, 10 sweeps "
+                                        "of Alg. 4, FP32 operands",
                        "zipf10k": "sparse 10000^3, 1e7 nnz Zipf(1.1), lognormal values, "
                                   "Tucker rank 16, TensorSketch m=2048, RRF init, 5 sweeps, "
                                   "FP32 operands"}[args.workload],
@@ -272,7 +281,7 @@ def main():
         "roofline": roofline(dominant, work, dom[0], dom[1], args.steps, args.workload),
         f"{second}_roofline": roofline(second, work, sp[0], sp[1], args.steps, args.workload),
     }
-    if not args.no_cpu_baseline and args.workload in ("sparse2000", "sparse2000lev"):
+    if not args.no_cpu_baseline and args.workload.startswith("sparse2000"):
         out["cpu_baseline"] = cpu_baseline(w, args.solve)
     print(json.dumps(out))
 
@@ -306,7 +315,8 @@ def cpu_baseline(w, solve="exact", sample_sweeps=3):
             if ts:
                 Z, Y = osk.ts_lhs(factors, tables[n], m, n), Ys[n]
             else:
-                idx, wt = osk.leverage_sample(factors, m, seed, sweep, n)
+                idx, wt = (osk.leverage_select(factors, m, n) if w.sketch == "lev_det"
+                           else osk.leverage_sample(factors, m, seed, sweep, n))
                 Z = osk.leverage_lhs(factors, idx, wt, n)
                 Y = osk.leverage_rhs_sparse(T, idx, wt, n)
             if solve == "rsvd":

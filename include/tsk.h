@@ -45,7 +45,7 @@ extern "C" {
 #endif
 
 #define TSK_MAX_ORDER 8
-#define TSK_ABI_VERSION 3
+#define TSK_ABI_VERSION 4
 
 typedef enum {
   TSK_OK = 0,
@@ -58,7 +58,10 @@ typedef enum {
 
 typedef enum { TSK_F32 = 0, TSK_F64 = 1 } tsk_dtype;
 typedef enum { TSK_DENSE = 0, TSK_COO = 1 } tsk_layout;
-typedef enum { TSK_SKETCH_TS = 0, TSK_SKETCH_LEV = 1 } tsk_sketch;
+/* Sketch of every subproblem: TensorSketch (Sec. 3.1), leverage-score
+ * importance sampling (Sec. 3.2), or the deterministic leverage selection of
+ * Sec. 3.2 (the m rows of largest score, weights 1; needs m <= prod_{k != n} s_k). */
+typedef enum { TSK_SKETCH_TS = 0, TSK_SKETCH_LEV = 1, TSK_SKETCH_LEV_DET = 2 } tsk_sketch;
 typedef enum { TSK_INIT_RRF = 0, TSK_INIT_RANDOM = 1, TSK_INIT_USER = 2 } tsk_init;
 /* Arithmetic of the sketched operands Z, Y and of their Gram products:
  * F64; F32; BF16 operands with FP32 accumulation.  Factorisations (Cholesky,
@@ -135,7 +138,11 @@ tsk_status tsk_profile_read(const char* name, double* total_ms, int64_t* launche
 /* ---------------------------------------------------------------------- */
 /* Drivers                                                                 */
 /* ---------------------------------------------------------------------- */
-/* Workspace size of tsk_tucker_sketch_als for this tensor, ranks and options. */
+/* Workspace size of tsk_tucker_sketch_als for this tensor, ranks and options.
+ * Validation errors are reported without touching the device.  Leverage
+ * sampling of a COO tensor and deterministic selection include the scratch of
+ * a device radix sort, whose size depends on the current device: on a host
+ * without one that part of the query fails with EHIP. */
 tsk_status tsk_workspace_size(const tsk_tensor* T, const int32_t* ranks,
                               const tsk_options* opt, size_t* bytes);
 
@@ -146,7 +153,8 @@ tsk_status tsk_workspace_size(const tsk_tensor* T, const int32_t* ranks,
  * B~ = best rank-R_n approximation of (S P)^+ (S T_(n)^T), A^(n) = its leading
  * right singular vectors, C_(n)^T = B~ A^(n) (Sec. 2.2, Sec. 4 theorems).
  * TensorSketch maps are drawn once and S^(n) T_(n)^T is formed once for all
- * sweeps; leverage samples are redrawn for every subproblem (Sec. 6.1); for a
+ * sweeps; leverage samples (or the deterministic selection) are redrawn for
+ * every subproblem (Sec. 6.1); for a
  * COO tensor the mode-n fibre indices (tsk_fiber_index) are built once, in
  * the workspace, and every sampled right-hand side is gathered through them.
  *   ranks       host int32[N], 1 <= R_n < s_n
@@ -270,6 +278,21 @@ tsk_status tsk_rrf_init(const tsk_tensor* T, int32_t n, int32_t R, int32_t k1, i
 tsk_status tsk_leverage_sample(int32_t order, const int64_t* dims, const int32_t* ranks,
                                int32_t n, int64_t m, uint64_t seed, int32_t sweep,
                                const double* const* factors, int32_t* idx, double* w,
+                               void* ws, size_t* ws_bytes, void* stream);
+
+/* Deterministic leverage selection (Sec. 3.2, the alternative to importance
+ * sampling that keeps the rows of largest leverage score).  Row (i_k)_{k != n}
+ * of kron_{k != n} A^(k) has the score pi = prod_k l^(k)_{i_k} (Lemma on
+ * Kronecker leverage scores; l as in tsk_leverage_sample; the product taken in
+ * increasing k, FP64).  Rows are ordered by pi descending, equal pi by the
+ * per-mode ranks (position in score-descending, index-ascending order)
+ * compared lexicographically in increasing k; the first m are returned.  No
+ * rescaling: use weights 1 with tsk_sketch_lev / tsk_sketch_lev_coo.
+ *   idx  device int32 m x (N-1), modes k != n in increasing order (output)
+ * Requires 1 <= m <= prod_{k != n} s_k (EINVAL otherwise).  Workspace query
+ * convention as tsk_leverage_sample; asynchronous on `stream`. */
+tsk_status tsk_leverage_select(int32_t order, const int64_t* dims, const int32_t* ranks,
+                               int32_t n, int64_t m, const double* const* factors, int32_t* idx,
                                void* ws, size_t* ws_bytes, void* stream);
 
 /* Sampled sketch (Sec. 3.2): Z[j, :] = w_j kron_{k != n} A^(k)(idx[j][.], :),

@@ -15,7 +15,7 @@ import torch
 from . import _lib as L
 
 __all__ = ["Tensor", "tucker_sketch_als", "cp_via_tucker", "hash_tables", "sketch_rhs_ts",
-           "sketch_lhs_ts", "rc_solve", "rrf_init", "leverage_sample", "sketch_lev",
+           "sketch_lhs_ts", "rc_solve", "rrf_init", "leverage_sample", "leverage_select", "sketch_lev",
            "FiberIndex", "fiber_index", "sketch_lev_coo", "fit",
            "sketched_residual", "sketched_residual_grads", "SketchedResidual", "lib"]
 
@@ -257,6 +257,18 @@ def leverage_sample(dims, ranks, n, m, seed, sweep, factors):
                              (L.stream_ptr(),), dev)
     del keep
     return idx, w
+
+
+def leverage_select(dims, ranks, n, m, factors):
+    """Deterministic leverage selection -> idx int32 m x (N-1) (weights are 1)."""
+    dev = factors[0 if n else 1].device
+    idx = torch.empty((int(m), len(dims) - 1), dtype=torch.int32, device=dev)
+    facs = [None if k == n else factors[k].contiguous() for k in range(len(dims))]
+    keep = L.query_and_alloc(L.lib().tsk_leverage_select,
+                             (len(dims), L.i64_array(dims), L.i32_array(ranks), int(n), int(m),
+                              L.ptr_array(facs), L.ptr(idx)), (L.stream_ptr(),), dev)
+    del keep
+    return idx
 
 
 def sketch_lev(T, ranks, n, m, idx, w, factors, prec="f64"):

@@ -13,7 +13,7 @@ MAX_ORDER = 8
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENUMERIC = 0, -1, -2, -3, -4, -5
 F32, F64 = 0, 1
 DENSE, COO = 0, 1
-SKETCH = {"ts": 0, "lev": 1}
+SKETCH = {"ts": 0, "lev": 1, "lev_det": 2}
 INIT = {"rrf": 0, "random": 1, "user": 2}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 SOLVE = {"exact": 0, "rsvd": 1}
@@ -73,6 +73,7 @@ def lib():
                                      vp]),
             "tsk_rrf_init": (i32, [T, i32, i32, i32, i32, u64, vp, vp, sz, vp]),
             "tsk_leverage_sample": (i32, [i32, vp, vp, i32, i64, u64, i32, vp, vp, vp, vp, sz, vp]),
+            "tsk_leverage_select": (i32, [i32, vp, vp, i32, i64, vp, vp, vp, sz, vp]),
             "tsk_sketch_lev": (i32, [T, vp, i32, i64, vp, vp, vp, i32, vp, vp, vp]),
             "tsk_fiber_index": (i32, [T, i32, vp, sz, vp, sz, vp]),
             "tsk_sketch_lev_coo": (i32, [T, i32, vp, i64, vp, vp, i32, vp, vp]),

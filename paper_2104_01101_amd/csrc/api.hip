@@ -13,6 +13,7 @@
 #include "fit.h"
 #include "kernels.h"
 #include "leverage.h"
+#include "select.h"
 
 namespace tsk {
 
@@ -182,8 +183,8 @@ int64_t rsvd_width(int32_t rsvd_k, int64_t R, int64_t r) {
 
 tsk_status validate_options(const TensorView& T, const int64_t* R, const tsk_options* opt) {
   TSK_REQUIRE(opt, "options are NULL");
-  TSK_REQUIRE(opt->sketch == TSK_SKETCH_TS || opt->sketch == TSK_SKETCH_LEV, "unknown sketch %d",
-              opt->sketch);
+  TSK_REQUIRE(opt->sketch >= TSK_SKETCH_TS && opt->sketch <= TSK_SKETCH_LEV_DET,
+              "unknown sketch %d", opt->sketch);
   TSK_REQUIRE(opt->init >= TSK_INIT_RRF && opt->init <= TSK_INIT_USER, "unknown init %d",
               opt->init);
   TSK_REQUIRE(opt->prec >= TSK_PREC_F64 && opt->prec <= TSK_PREC_BF16, "unknown precision %d",
@@ -205,9 +206,17 @@ tsk_status validate_options(const TensorView& T, const int64_t* R, const tsk_opt
                 "sketch size m = %lld is smaller than prod_{k != %d} R_k = %lld (the sketched "
                 "problem would not have a unique solution)",
                 (long long)opt->m, n, (long long)r);
+    if (opt->sketch == TSK_SKETCH_LEV_DET) {
+      double rows = 1.0;
+      for (int k = 0; k < T.order; ++k)
+        if (k != n) rows *= double(T.dims[k]);
+      TSK_REQUIRE(double(opt->m) <= rows,
+                  "deterministic selection of m = %lld rows exceeds the %.0f rows of mode %d",
+                  (long long)opt->m, rows, n);
+    }
   }
   TSK_REQUIRE(opt->m < (int64_t(1) << 31), "sketch size too large");
-  if (opt->sketch == TSK_SKETCH_LEV && T.layout == TSK_COO) {
+  if (opt->sketch != TSK_SKETCH_TS && T.layout == TSK_COO) {
     unsigned bits = 0;
     TSK_TRY(fiber_key_bits(T, &bits));
   }
@@ -277,13 +286,17 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
   double* lev_w = nullptr;
   void* Ylev = nullptr;
   const bool fibres = !ts && T.layout == TSK_COO;
+  const bool det = o.sketch == TSK_SKETCH_LEV_DET;
   std::vector<FiberIndexView> fib(N);
+  std::vector<SelectPlan> sel(N);
   if (!ts) {
     lev_idx = ws.take<int32_t>(size_t(m) * (N - 1));
     lev_w = ws.take<double>(m);
     Ylev = ws.take<char>(size_t(m) * smax * prec_bytes(prec));
     if (fibres)
       for (int n = 0; n < N; ++n) TSK_TRY(fiber_index_alloc(T, n, fib[n], ws));
+    if (det)  // candidate rank tuples of every mode (independent of the data)
+      for (int n = 0; n < N; ++n) TSK_TRY(select_plan(N, T.dims, n, m, sel[n], ws, st));
   }
   FitScratch fs{};
   if (record) TSK_TRY(fit_plan(T, a.R, fs, ws));
@@ -369,9 +382,15 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
         TSK_TRY(ts_lhs(modes, N - 1, m, prec, Z, ws, st));
         Y = Yp[n];
       } else {
-        TSK_TRY(leverage_sample(N, T.dims, a.R, n, m, o.seed, sweep, a.factors, lev_idx, lev_w,
-                                ws, st, prec, Z));
+        if (det) {
+          TSK_TRY(select_rows(N, T.dims, a.R, n, sel[n], a.factors, lev_idx, lev_w, ws, st));
+        } else {
+          TSK_TRY(leverage_sample(N, T.dims, a.R, n, m, o.seed, sweep, a.factors, lev_idx,
+                                  lev_w, ws, st, prec, Z));
+        }
         if (run) {
+          if (det)
+            TSK_TRY(leverage_rows(T, a.R, n, m, lev_idx, lev_w, a.factors, prec, Z, nullptr, st));
           if (fibres)
             TSK_TRY(fiber_rows(fib[n], m, lev_idx, lev_w, prec, Ylev, st));
           else
@@ -652,6 +671,27 @@ tsk_status tsk_leverage_sample(int32_t order, const int64_t* dims, const int32_t
   return with_workspace(ws, ws_bytes, [&](Ws& wk) {
     return leverage_sample(order, dims, R, n, m, seed, sweep, factors, idx, w, wk,
                            as_stream(stream));
+  });
+}
+
+tsk_status tsk_leverage_select(int32_t order, const int64_t* dims, const int32_t* ranks,
+                               int32_t n, int64_t m, const double* const* factors, int32_t* idx,
+                               void* ws, size_t* ws_bytes, void* stream) {
+  clear_error();
+  TSK_REQUIRE(order >= 2 && order <= TSK_MAX_ORDER && dims && ranks && factors,
+              "invalid arguments");
+  TSK_REQUIRE(n >= 0 && n < order && m >= 1, "invalid mode or row count");
+  int64_t R[TSK_MAX_ORDER];
+  for (int k = 0; k < order; ++k) {
+    TSK_REQUIRE(dims[k] >= 1 && dims[k] < (int64_t(1) << 31) && ranks[k] >= 1,
+                "invalid dims or ranks");
+    R[k] = ranks[k];
+  }
+  hipStream_t st = as_stream(stream);
+  return with_workspace(ws, ws_bytes, [&](Ws& wk) -> tsk_status {
+    SelectPlan p{};
+    TSK_TRY(select_plan(order, dims, n, m, p, wk, st));
+    return select_rows(order, dims, R, n, p, factors, idx, nullptr, wk, st);
   });
 }
 

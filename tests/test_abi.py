@@ -32,7 +32,7 @@ def test_header_symbols_exported():
 def test_abi_version():
     """Version 2: the options struct gained the subproblem solver (solve, rsvd_k)."""
     L = _lib()
-    assert L.lib().tsk_abi_version() == 3
+    assert L.lib().tsk_abi_version() == 4
     assert L._Options.solve.offset == 76 and L._Options.rsvd_k.offset == 80
 
 
@@ -70,6 +70,8 @@ def _opts(L, m, sketch=0, solve=0, rsvd_k=0):
     ((10, 10, 10), (11, 3, 3), 50, 0, 0, -1),      # rank above dimension
     ((10,), (3,), 50, 0, 0, -1),                   # order 1
     ((2**31 - 1,) * 3, (3, 3, 3), 50, 1, 1, -2),   # leverage on COO: fibre keys beyond 64 bits
+    ((5, 5, 5), (2, 2, 2), 30, 2, 0, -1),          # deterministic selection: m > 25 rows
+    ((5, 5, 5), (2, 2, 2), 30, 3, 0, -1),          # unknown sketch
     ((10, 10, 10), (3, 3, 20), 50, 0, 0, -1),      # R_n above the product of the others... and s
 ])
 def test_validation_errors(dims, ranks, m, sketch, layout, expect):
@@ -140,3 +142,23 @@ def test_fibre_index_query_sizes():
                                           ctypes.byref(o), ctypes.byref(nb)) == 0
         sizes.append(nb.value)
     assert sizes[1] > 3 * 1000 * 12
+
+
+@pytest.mark.gpu
+def test_selection_workspace_query():
+    """Deterministic selection sizes its candidate set on the host: m ln m
+    rank tuples for three modes (here m = 1600 of 2000 x 2000 rows).  The radix
+    sort's scratch size depends on the device, so the query needs the GPU."""
+    L = _lib()
+    t = _tensor(L, (2000, 2000, 2000), layout=1, dtype=0, nnz=1000)
+    for k in range(3):
+        t.idx[k] = 8
+    sizes = {}
+    for sketch in (1, 2):
+        o = _opts(L, 1600, sketch)
+        nb = ctypes.c_size_t(0)
+        assert L.lib().tsk_workspace_size(ctypes.byref(t), L.i32_array((10, 10, 10)),
+                                          ctypes.byref(o), ctypes.byref(nb)) == 0
+        sizes[sketch] = nb.value
+    ncand = sum(min(2000, 1600 // (r + 1)) for r in range(1600))   # 12.6k per mode
+    assert sizes[2] - sizes[1] >= 3 * ncand * 2 * 4

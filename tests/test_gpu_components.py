@@ -216,6 +216,29 @@ def test_leverage_rows_match(tsk):
     np.testing.assert_allclose(Y.cpu().numpy(), osk.leverage_rhs_dense(X, io, wo, n), rtol=1e-15)
 
 
+# ------------------------------------- deterministic leverage selection ----
+@pytest.mark.parametrize("dims,ranks,m,n,tie", [
+    ((40, 30, 20), (4, 3, 2), 200, 0, False),
+    ((60, 50, 40, 30), (3, 3, 3, 3), 500, 1, False),     # order 4: three levels of candidates
+    ((500, 500, 500), (30, 30, 30), 14400, 0, False),    # CP-size sketch
+    ((2000, 2000, 2000), (10, 10, 10), 1600, 2, False),  # full size, 4e6 rows
+    ((30, 25, 20), (3, 3, 3), 150, 1, True),             # equal scores in two modes
+    ((6, 5, 4), (2, 2, 2), 20, 0, False),                # every row kept
+])
+def test_leverage_select_bit_exact(tsk, dims, ranks, m, n, tie):
+    rs = np.random.default_rng(sum(dims) + m)
+    facs = [np.linalg.qr(rs.standard_normal((d, r)))[0] for d, r in zip(dims, ranks)]
+    if tie:
+        for k in range(len(dims)):
+            if k != n:
+                facs[k][1] = facs[k][0]
+                facs[k][5] = -facs[k][2]
+    fg = [torch.from_numpy(F).to(DEV) for F in facs]
+    idx = tsk.leverage_select(dims, ranks, n, m, fg)
+    io, _ = osk.leverage_select(facs, m, n)
+    assert np.array_equal(idx.cpu().numpy().astype(np.int64), io)
+
+
 # ------------------------------------------------- sparse fibres (f2) ----
 def _coo_with_duplicates(dims, nnz, dup, rs, dtype):
     """nnz distinct uniform coordinates, `dup` of them stored again with fresh

@@ -163,6 +163,31 @@ def test_sparse_leverage_dense_equivalent(tsk):
     np.testing.assert_allclose(a[2], b[2], rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("sparse,solve", [(False, "exact"), (True, "exact"), (True, "rsvd")])
+def test_lev_det_parity(tsk, sparse, solve):
+    """Deterministic leverage selection (the m rows of largest Kronecker score,
+    weights 1) in the driver, FP64, against the oracle's brute-force selection:
+    dense 30 x 28 x 26 (Tucker (3,3,3) + 5 % noise) or the 80 x 70 x 60 COO tensor
+    with 100k entries; m = 16 R^2 rows per subproblem, RRF init, 3 sweeps."""
+    if sparse:
+        dims, ranks = (80, 70, 60), (5, 4, 3)
+        idx, val = workloads.sparse_tucker(dims, 100_000, ranks, seed=4, noise_std=0.1)
+        val = val.astype(np.float64)
+        T, To = _coo(tsk, dims, idx, val), osk.Tensor(dims, idx, val)
+    else:
+        ranks = (3, 3, 3)
+        X = workloads.tucker_dense((30, 28, 26), ranks, 0.05, seed=2)
+        T, To = _dense(tsk, X), osk.Tensor.from_dense(X)
+    m = 16 * max(ranks) ** 2
+    _, factors, fits = tsk.tucker_sketch_als(T, ranks, m, 3, sketch="lev_det", prec="f64",
+                                             seed=5, solve=solve)
+    ref = otk.sketch_tucker_als(To, ranks, m, 3, seed=5, sketch_kind="lev_det",
+                                solve_kind=solve)
+    np.testing.assert_allclose(fits, ref["fits"], rtol=0, atol=1e-10)
+    for F, Fo in zip(factors, ref["factors"]):
+        np.testing.assert_allclose(F.cpu().numpy(), Fo, atol=1e-8)
+
+
 # -------------------------------------------- RSVD-LRLS subproblem solver ----
 def test_dense40_rsvd_fp64_parity(tsk):
     """The small dense case with the paper's subproblem solver (Alg. 4 calls RSVD-LRLS,

@@ -163,6 +163,14 @@ def sparse2000lev(seed=0, s=2000, nnz=1_000_000, R=10, K=16, sweeps=10):
     return w
 
 
+def sparse2000det(seed=0, s=2000, nnz=1_000_000, R=10, K=16, sweeps=10):
+    """The sparse2000 tensor under deterministic leverage selection (the m = K R^2
+    rows of largest Kronecker leverage score per subproblem, weights 1)."""
+    w = sparse2000(seed, s, nnz, R, K, sweeps)
+    w["name"], w["sketch"] = "sparse2000det", "lev_det"
+    return w
+
+
 def dense4d200(seed=0, s=200, R=10, m=4000, sweeps=5, prec="f32"):
     """Dense 4-way s^4 FP32 Tucker rank-(R,..,R) signal + 1% noise; leverage-score
     sampling with m rows per subproblem."""
