@@ -53,6 +53,82 @@ GROUPS = ["sketch_pass", "rrf_pass", "rrf", "ts_lhs", "gram", "solve_la", "eig",
 WORKLOADS = ["sparse2000", "zipf10k", "sparse2000lev", "sparse2000det"]
 
 
+# The test tensors of Sec. 7 with the experiments' parameters: name -> (builder
+# of (dense | (idx, val)), s, R, description).
+PAPER_TENSORS = {
+    "t1a12": ("dense", 200, 5, "Tensor 1, s=200, R=5, alpha=1.2"),
+    "t1a16": ("dense", 200, 5, "Tensor 1, s=200, R=5, alpha=1.6"),
+    "t2": ("dense", 200, 5, "Tensor 2 (power-law spikes), s=200, R=5, alpha=1.6"),
+    "t3": ("sparse", 2000, 10, "Tensor 3, s=2000, R=10, alpha=1.2, p=0.02"),
+    "t4": ("dense", 200, 5, "Tensor 4 on Tensor 1 (10 coherent entries), s=200, R=5, alpha=1.6"),
+    "t4s": ("sparse", 2000, 10, "Tensor 4 on Tensor 3, s=2000, R=10, alpha=1.2, p=0.02"),
+}
+
+
+def paper_tensor(name, seed):
+    import workloads as W
+    return {"t1a12": lambda: W.paper_tensor1(200, 5, 1.2, seed),
+            "t1a16": lambda: W.paper_tensor1(200, 5, 1.6, seed),
+            "t2": lambda: W.paper_tensor2(200, 5, 1.6, seed),
+            "t3": lambda: W.paper_tensor3(2000, 10, 1.2, 0.02, seed),
+            "t4": lambda: W.paper_tensor4_dense(200, 5, 1.6, seed),
+            "t4s": lambda: W.paper_tensor4_sparse(2000, 10, 1.2, 0.02, seed)}[name]()
+
+
+def fitness_vs_k(args):
+    """Final fitness 1 - ||T - T~|| / ||T|| after 5 sweeps (the experiments'
+    count) for TensorSketch, leverage sampling and deterministic leverage
+    selection, RRF and random initialisation, m = K R^2, FP64 operands, on
+    `seeds` tensors of the chosen family (tensor seed = run seed).  Dense
+    tensors also get the unsketched ALS from the RRF start (every row kept)."""
+    import statistics
+    import torch
+    import paper_2104_01101_amd as tsk
+    from paper_2104_01101_amd import _lib as L
+    dev = torch.device("cuda:0")
+    layout, s, R, desc = PAPER_TENSORS[args.fitness]
+    ks = [int(k) for k in args.ks.split(",")]
+    res = {}
+    t0 = time.perf_counter()
+    for seed in range(args.seeds):
+        data = paper_tensor(args.fitness, seed)
+        if layout == "dense":
+            T = tsk.Tensor.dense(torch.from_numpy(data).to(dev))
+        else:
+            idx, val = data
+            T = tsk.Tensor.coo(torch.from_numpy(idx).to(dev), torch.from_numpy(val).to(dev),
+                               (s, s, s))
+        runs = [(kind, init, K) for K in ks for kind in ("ts", "lev", "lev_det")
+                for init in ("rrf", "random")]
+        if layout == "dense":
+            runs.append(("lev_det", "rrf", s * s // (R * R)))  # every row: unsketched ALS
+        for kind, init, K in runs:
+            try:
+                _, _, fits = tsk.tucker_sketch_als(T, (R, R, R), K * R * R, 5, sketch=kind,
+                                                   init=init, prec="f64", seed=seed,
+                                                   solve=args.solve)
+                f = 1.0 - fits[-1]
+            except L.TskError as e:  # singular sketched Gram: the sketch missed the signal
+                if e.status != L.ENUMERIC:
+                    raise
+                f = None
+            res.setdefault((kind, init, K), []).append(f)
+        del T
+        torch.cuda.empty_cache()
+    for (kind, init, K), fs in res.items():
+        f = [v for v in fs if v is not None]
+        print(json.dumps({"tensor": args.fitness, "description": desc, "method": kind,
+                          "init": init, "K": K, "m": K * R * R, "sweeps": 5,
+                          "solve": args.solve, "seeds": len(fs),
+                          "breakdowns": len(fs) - len(f),
+                          "fitness_mean": statistics.fmean(f) if f else None,
+                          "fitness_min": min(f) if f else None,
+                          "fitness_max": max(f) if f else None,
+                          "unsketched": K * R * R == s * s}))
+    print(json.dumps({"tensor": args.fitness, "runs": sum(len(v) for v in res.values()),
+                      "seconds": time.perf_counter() - t0}))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +147,12 @@ def parse():
                     help="also print per-group times of the last warm-up step (stderr)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy kernel (counter scale)")
+    ap.add_argument("--fitness", default=None, choices=sorted(PAPER_TENSORS),
+                    help="instead of the benchmark: final fitness against the sketch size "
+                         "parameter K on one of the paper's test tensors (one JSON line per "
+                         "method, initialisation and K)")
+    ap.add_argument("--ks", default="4,8,16", help="K values of --fitness (m = K R^2)")
+    ap.add_argument("--seeds", type=int, default=3, help="random seeds per point of --fitness")
     return ap.parse_args()
 
 
@@ -194,6 +276,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.fitness:
+        fitness_vs_k(args)
         return
     import torch
     import paper_2104_01101_amd as tsk

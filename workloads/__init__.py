@@ -15,6 +15,9 @@ Families (Sec. 7 of the paper builds all its tensors synthetically):
                  lognormal values
 * cp_collinear   sum of rank-1 terms with unit-norm factor columns of pairwise
                  cosine c, + noise (the CP experiments of Sec. 7)
+* paper_tensor1..4  the four test tensors of Sec. 7 as the paper defines them
+                 (Gaussian Tucker; + power-law rank-1 spikes; sparse Tucker with
+                 entries kept with probability p; + a few coherent large entries)
 * the named configurations c1..c5 (full size or scaled down)
 """
 import numpy as np
@@ -137,6 +140,101 @@ def cp_collinear(dims, rank, collinearity=0.9, noise=0.01, seed=0, dtype=np.floa
 # ----------------------------------------------------------------------------
 # named configurations
 # ----------------------------------------------------------------------------
+# ----------------------------------------------------------------------------
+# The four test tensors of Sec. 7 (order 3, s x s x s, R_true = round(alpha R))
+# ----------------------------------------------------------------------------
+def true_rank(R, alpha):
+    return int(round(alpha * R))
+
+
+def paper_tensor1(s, R, alpha, seed=0):
+    """Tensor 1 (eq. tsr_dense): T = C x_1 B1 x_2 B2 x_3 B3 with every entry of the
+    core (R_true^3) and of the factors (s x R_true) i.i.d. N(0, 1).  Dense FP64."""
+    rs = np.random.default_rng(seed)
+    Rt = true_rank(R, alpha)
+    core = rs.standard_normal((Rt, Rt, Rt))
+    fac = [rs.standard_normal((s, Rt)) for _ in range(3)]
+    return _dense_from_tucker(core, fac)
+
+
+def paper_tensor2(s, R, alpha, seed=0, n=5, C=3.0, eta=0.5):
+    """Tensor 2: Tensor 1 + sum_{i=1..n} lambda_i a1_i o a2_i o a3_i with unit-norm
+    Gaussian directions and power-law magnitudes lambda_i = C ||T||_F / i^(1+eta)
+    (n = 5, C = 3, eta = 0.5 as in the experiments).  Dense FP64."""
+    X = paper_tensor1(s, R, alpha, seed)
+    rs = np.random.default_rng(seed + 7919)
+    nrm = np.linalg.norm(X)
+    for i in range(1, n + 1):
+        a = [v / np.linalg.norm(v) for v in (rs.standard_normal(s) for _ in range(3))]
+        X = X + (C * nrm / i ** (1.0 + eta)) * np.einsum("i,j,k->ijk", *a)
+    return X
+
+
+def paper_tensor3(s, R, alpha, p, seed=0):
+    """Tensor 3 (eq. tsr_sparse): Tensor 1 with every core and factor entry kept
+    with probability p (N(0,1)) and zero otherwise, so a term of the sum is
+    nonzero with probability p^4 and the expected density is at most
+    R_true^3 p^4.  Built from the nonzero core entries: each adds the outer
+    product of its three factor columns' supports; coinciding coordinates are
+    summed.  Returns (idx int32 nnz x 3, val float64), coordinates distinct."""
+    rs = np.random.default_rng(seed)
+    Rt = true_rank(R, alpha)
+    keep = lambda shape: np.where(rs.random(shape) < p, rs.standard_normal(shape), 0.0)
+    core = keep((Rt, Rt, Rt))
+    fac = [keep((s, Rt)) for _ in range(3)]
+    keys, vals = [], []
+    for x, y, z in zip(*np.nonzero(core)):
+        cols = [np.nonzero(fac[0][:, x])[0], np.nonzero(fac[1][:, y])[0],
+                np.nonzero(fac[2][:, z])[0]]
+        if min(c.size for c in cols) == 0:
+            continue
+        v = core[x, y, z] * np.einsum("i,j,k->ijk", fac[0][cols[0], x], fac[1][cols[1], y],
+                                      fac[2][cols[2], z])
+        ii, jj, kk = np.meshgrid(*cols, indexing="ij")
+        keys.append(((ii * s + jj) * s + kk).reshape(-1))
+        vals.append(v.reshape(-1))
+    if not keys:
+        return np.zeros((0, 3), np.int32), np.zeros(0)
+    key = np.concatenate(keys)
+    u, inv = np.unique(key, return_inverse=True)
+    val = np.bincount(inv, weights=np.concatenate(vals), minlength=u.size)
+    nz = val != 0.0
+    idx = np.stack(np.unravel_index(u[nz], (s, s, s)), 1).astype(np.int32)
+    perm = rs.permutation(idx.shape[0])
+    return idx[perm], val[nz][perm]
+
+
+def coherent_spikes(dims, norm, seed=0, n=10):
+    """The N of Tensor 4: n distinct random positions, values i.i.d.
+    N(norm / sqrt(n), 1) (so E ||N||_F / norm = 1 with norm = ||T||_F)."""
+    rs = np.random.default_rng(seed + 104729)
+    lin = rs.choice(int(np.prod(dims)), size=n, replace=False)
+    idx = np.stack(np.unravel_index(lin, dims), 1).astype(np.int32)
+    return idx, rs.normal(norm / np.sqrt(n), 1.0, n)
+
+
+def paper_tensor4_dense(s, R, alpha, seed=0, n=10):
+    """Tensor 4 on Tensor 1: a dense FP64 s^3 tensor plus n coherent entries."""
+    X = paper_tensor1(s, R, alpha, seed)
+    idx, val = coherent_spikes(X.shape, np.linalg.norm(X), seed, n)
+    X[tuple(idx.T)] += val
+    return X
+
+
+def paper_tensor4_sparse(s, R, alpha, p, seed=0, n=10):
+    """Tensor 4 on Tensor 3: COO (distinct coordinates) plus n coherent entries
+    (a spike on a stored coordinate is added to its value)."""
+    idx, val = paper_tensor3(s, R, alpha, p, seed)
+    sidx, sval = coherent_spikes((s, s, s), np.linalg.norm(val), seed, n)
+    key = np.concatenate([np.ravel_multi_index(idx.T.astype(np.int64), (s, s, s)),
+                          np.ravel_multi_index(sidx.T.astype(np.int64), (s, s, s))])
+    u, inv = np.unique(key, return_inverse=True)
+    v = np.bincount(inv, weights=np.concatenate([val, sval]), minlength=u.size)
+    out = np.stack(np.unravel_index(u, (s, s, s)), 1).astype(np.int32)
+    perm = np.random.default_rng(seed + 1).permutation(u.size)
+    return out[perm], v[perm]
+
+
 def dense40(seed=0, s=40, R=5, K=8):
     """Dense 3-way s^3 FP64, Tucker rank (R,R,R) with Gaussian core and QR
     factors, 1% noise; TensorSketch m = K R^2, RRF init, 5 sweeps, FP64."""
