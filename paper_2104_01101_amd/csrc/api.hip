@@ -276,11 +276,23 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
   double* W = ws.take<double>(rmax * Rmax);
   const bool rsvd = o.solve == TSK_SOLVE_RSVD;
   double* Om = nullptr;
+  std::vector<double*> Om_all;  // every sweep's test matrices, drawn at once when they fit
   if (rsvd) {
-    int64_t kmax = 0;
-    for (int n = 0; n < N; ++n)
-      kmax = std::max(kmax, rsvd_width(o.rsvd_k, a.R[n], prod_except(a.R, N, n)));
-    Om = ws.take<double>(size_t(smax) * kmax);
+    int64_t kmax = 0, per_sweep = 0;
+    for (int n = 0; n < N; ++n) {
+      const int64_t k = rsvd_width(o.rsvd_k, a.R[n], prod_except(a.R, N, n));
+      kmax = std::max(kmax, k);
+      per_sweep += T.dims[n] * k;
+    }
+    if (int64_t(o.sweeps) * per_sweep <= (int64_t(8) << 20)) {
+      Om_all.resize(size_t(o.sweeps) * N);
+      for (int sw = 0; sw < o.sweeps; ++sw)
+        for (int n = 0; n < N; ++n)
+          Om_all[size_t(sw) * N + n] = ws.take<double>(
+              size_t(T.dims[n]) * rsvd_width(o.rsvd_k, a.R[n], prod_except(a.R, N, n)));
+    } else {
+      Om = ws.take<double>(size_t(smax) * kmax);
+    }
   }
   int32_t* lev_idx = nullptr;
   double* lev_w = nullptr;
@@ -362,6 +374,22 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
     }
   }
 
+  if (run && !Om_all.empty()) {  // Gaussian test matrices of every (sweep, n), batched
+    GaussBatch gb{};
+    for (int sw = 0; sw < o.sweeps; ++sw)
+      for (int n = 0; n < N; ++n) {
+        gb.key[gb.n] = stream_key(o.seed, kRSVD, sw, n);
+        gb.count[gb.n] =
+            T.dims[n] * rsvd_width(o.rsvd_k, a.R[n], prod_except(a.R, N, n));
+        gb.out[gb.n] = Om_all[size_t(sw) * N + n];
+        if (++gb.n == kGaussBatch) {
+          TSK_TRY(launch_gauss_batch(gb, st));
+          gb.n = 0;
+        }
+      }
+    TSK_TRY(launch_gauss_batch(gb, st));
+  }
+
   // ---- sweeps (Alg. 4) ----
   const int64_t csize = [&] {
     int64_t p = 1;
@@ -401,8 +429,10 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
       }
       if (rsvd) {  // RSVD-LRLS (Alg. 5) with the test matrix of stream (seed, RSVD, sweep, n)
         const int64_t k = rsvd_width(o.rsvd_k, a.R[n], r);
-        if (run) TSK_TRY(launch_gauss(stream_key(o.seed, kRSVD, sweep, n), T.dims[n] * k, 1.0, Om, st));
-        TSK_TRY(rsvd_solve(Z, Y, m, r, T.dims[n], int(a.R[n]), prec, Om, k, a.factors[n], W,
+        double* Om_n = Om_all.empty() ? Om : Om_all[size_t(sweep) * N + n];
+        if (run && Om_all.empty())
+          TSK_TRY(launch_gauss(stream_key(o.seed, kRSVD, sweep, n), T.dims[n] * k, 1.0, Om, st));
+        TSK_TRY(rsvd_solve(Z, Y, m, r, T.dims[n], int(a.R[n]), prec, Om_n, k, a.factors[n], W,
                            a.info_dev, ws, st));
       } else {
         TSK_TRY(rc_solve(Z, Y, m, r, T.dims[n], int(a.R[n]), prec, a.factors[n], W, a.info_dev,

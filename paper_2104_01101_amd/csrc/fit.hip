@@ -324,14 +324,21 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
     csize *= R[k];
   }
   a.vals = T.values;
-  int64_t goff = 0;
+  int64_t goff = 0, rmax_g = 0;
+  double* gp[TSK_MAX_ORDER];
   for (int k = 0; k < T.order; ++k) {
-    TSK_TRY(gemm_tn(TSK_PREC_F64, R[k], R[k], T.dims[k], factors[k], R[k], R[k], nullptr, 0,
-                    factors[k], R[k], fs.grams + goff, R[k], ws, st));
+    gp[k] = fs.grams + goff;
     goff += R[k] * R[k];
+    rmax_g = std::max<int64_t>(rmax_g, R[k]);
   }
+  if (rmax_g > 64)
+    for (int k = 0; k < T.order; ++k)
+      TSK_TRY(gemm_tn(TSK_PREC_F64, R[k], R[k], T.dims[k], factors[k], R[k], R[k], nullptr, 0,
+                      factors[k], R[k], gp[k], R[k], ws, st));
   if (ws.measuring()) return TSK_OK;
   ProfScope prof("fit", st);
+  if (rmax_g <= 64)  // the factor Grams of every mode in one launch
+    TSK_TRY(gram_batch_f64(T.order, R, T.dims, factors, gp, st));
   int64_t per = ceil_div(T.nnz, fs.nblocks);
   if (with_norm) {
     hipLaunchKernelGGL(k_norm2, dim3(fs.nblocks), dim3(kT), 0, st, a, T.nnz, per,

@@ -178,6 +178,36 @@ __global__ __launch_bounds__(kSkT) void k_gemm_skinny(int64_t M, int64_t N, int6
                           red);
 }
 
+// One- to four-tile products over a long K: 16 waves per tile, so that each
+// wave's share of K (and the chain of operand loads) is half as long.
+constexpr int kSkW16 = 16;
+template <bool A_MK>
+__global__ __launch_bounds__(64 * kSkW16) void k_gemm_skinny16(
+    int64_t M, int64_t N, int64_t K, const double* A1, int64_t lda1, int64_t M1, const double* A2,
+    int64_t lda2, const double* B, int64_t ldb, double* C, int64_t ldc) {
+  __shared__ double red[kSkW16][16][17];
+  skinny_tile<kSkW16, A_MK, 32>(M, N, K, A1, lda1, M1, A2, lda2, B, ldb, C, ldc, blockIdx.x,
+                                blockIdx.y, red);
+}
+
+// Grams A^T A of several row-major K x R matrices in one launch: blockIdx.z
+// picks the matrix, workgroups beyond its tiles leave at once.
+struct GramBatch {
+  int n;
+  int64_t R[TSK_MAX_ORDER];
+  int64_t K[TSK_MAX_ORDER];
+  const double* A[TSK_MAX_ORDER];
+  double* C[TSK_MAX_ORDER];
+};
+__global__ __launch_bounds__(kSkT) void k_gram_batch(GramBatch gb) {
+  __shared__ double red[kSkW][16][17];
+  const int p = blockIdx.z;
+  const int64_t R = gb.R[p];
+  if (int64_t(blockIdx.x) * 16 >= R || int64_t(blockIdx.y) * 16 >= R) return;  // uniform
+  skinny_tile<kSkW, false>(R, R, gb.K[p], gb.A[p], R, R, nullptr, 0, gb.A[p], R, gb.C[p], R,
+                           blockIdx.x, blockIdx.y, red);
+}
+
 // FP32 operands, both K-major (A = [A1 | A2] as K x M, B as K x N), 64 x 64
 // tiles, 4 waves (2 x 2, 32 x 32 each), K slabs of 64 double-buffered in LDS
 // in [k][m] layout (row stride 80 floats: the four k rows that one MFMA
@@ -345,6 +375,14 @@ tsk_status gemm_tn_t(int64_t M, int64_t N, int64_t K, const void* A1, int64_t ld
                      int64_t ldc, Ws& ws, hipStream_t st) {
   if (std::is_same<E, double>::value && (M <= 64 || N <= 64) && K > 0) {
     if (ws.measuring() || M == 0 || N == 0) return TSK_OK;
+    if (ceil_div(M, 16) * ceil_div(N, 16) <= 4 && K >= 1024) {
+      hipLaunchKernelGGL((k_gemm_skinny16<A_MK>), dim3(ceil_div(M, 16), ceil_div(N, 16)),
+                         dim3(64 * kSkW16), 0, st, M, N, K, static_cast<const double*>(A1), lda1,
+                         M1, static_cast<const double*>(A2), lda2,
+                         static_cast<const double*>(B), ldb, C, ldc);
+      TSK_LAUNCHED();
+      return TSK_OK;
+    }
     hipLaunchKernelGGL((k_gemm_skinny<A_MK>), dim3(ceil_div(M, 16), ceil_div(N, 16)), dim3(kSkT),
                        0, st, M, N, K, static_cast<const double*>(A1), lda1, M1,
                        static_cast<const double*>(A2), lda2, static_cast<const double*>(B), ldb,
@@ -403,6 +441,26 @@ tsk_status gemm_tn_t(int64_t M, int64_t N, int64_t K, const void* A1, int64_t ld
 }
 
 }  // namespace
+
+tsk_status gram_batch_f64(int n, const int64_t* R, const int64_t* K, const double* const* A,
+                          double* const* C, hipStream_t st) {
+  TSK_REQUIRE(n >= 1 && n <= TSK_MAX_ORDER, "gram batch of %d matrices", n);
+  GramBatch gb{};
+  gb.n = n;
+  int64_t rmax = 0;
+  for (int p = 0; p < n; ++p) {
+    TSK_REQUIRE(R[p] >= 1 && R[p] <= 64 && K[p] >= 1, "gram batch shapes");
+    gb.R[p] = R[p];
+    gb.K[p] = K[p];
+    gb.A[p] = A[p];
+    gb.C[p] = C[p];
+    rmax = R[p] > rmax ? R[p] : rmax;
+  }
+  const unsigned t = unsigned(ceil_div(rmax, 16));
+  hipLaunchKernelGGL(k_gram_batch, dim3(t, t, unsigned(n)), dim3(kSkT), 0, st, gb);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
 
 tsk_status gemm_tn(int prec, int64_t M, int64_t N, int64_t K, const void* A1, int64_t lda1,
                    int64_t M1, const void* A2, int64_t lda2, const void* B, int64_t ldb,

@@ -38,6 +38,15 @@ tsk_status launch_hash_table(uint64_t key, int64_t s, int64_t m, int32_t* h, int
                              hipStream_t st);
 // out[i] = scale * gauss(key, i), i < count (FP64)
 tsk_status launch_gauss(uint64_t key, int64_t count, double scale, double* out, hipStream_t st);
+// Several Gaussian arrays in one launch: out[b][i] = gauss(key[b], i), i < count[b]
+constexpr int kGaussBatch = 64;
+struct GaussBatch {
+  int n;
+  uint64_t key[kGaussBatch];
+  int64_t count[kGaussBatch];
+  double* out[kGaussBatch];
+};
+tsk_status launch_gauss_batch(const GaussBatch& b, hipStream_t st);
 
 // ---- TensorSketch of the Kronecker chain (ts_lhs.hip) ----
 struct CsrTable {  // inverse hash of one mode: bucket b holds items[ptr[b] .. ptr[b+1])
@@ -71,6 +80,10 @@ tsk_status ts_conv_adjoint(const LhsMode* modes, int nmodes, int64_t m, const do
 // C (M x N, FP64) = A^T B with A = [A1 | A2] (K x M1, K x (M - M1), row-major,
 // leading dims lda1/lda2) and B (K x N, ldb), all of element type `prec`.
 // `ldc` leading dimension of C.  Deterministic split-K.
+// Grams C[p] = A[p]^T A[p] (A[p] row-major K[p] x R[p], R[p] <= 64, FP64) of up to
+// TSK_MAX_ORDER matrices in one launch (skinny tiles).
+tsk_status gram_batch_f64(int n, const int64_t* R, const int64_t* K, const double* const* A,
+                          double* const* C, hipStream_t st);
 tsk_status gemm_tn(int prec, int64_t M, int64_t N, int64_t K, const void* A1, int64_t lda1,
                    int64_t M1, const void* A2, int64_t lda2, const void* B, int64_t ldb,
                    double* C, int64_t ldc, Ws& ws, hipStream_t st);

@@ -21,7 +21,23 @@ __global__ void k_gauss(uint64_t key, int64_t count, double scale, double* out) 
   if (i >= count) return;
   out[i] = scale * gauss_of(key, uint64_t(i));
 }
+__global__ void k_gauss_batch(GaussBatch b) {
+  const int q = blockIdx.y;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= b.n || i >= b.count[q]) return;
+  b.out[q][i] = gauss_of(b.key[q], uint64_t(i));
+}
 }  // namespace
+
+tsk_status launch_gauss_batch(const GaussBatch& b, hipStream_t st) {
+  int64_t cmax = 0;
+  for (int q = 0; q < b.n; ++q) cmax = b.count[q] > cmax ? b.count[q] : cmax;
+  if (b.n <= 0 || cmax <= 0) return TSK_OK;
+  hipLaunchKernelGGL(k_gauss_batch, dim3(unsigned(ceil_div(cmax, 256)), unsigned(b.n)),
+                     dim3(256), 0, st, b);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
 
 tsk_status launch_hash_table(uint64_t key, int64_t s, int64_t m, int32_t* h, int8_t* sg,
                              hipStream_t st) {

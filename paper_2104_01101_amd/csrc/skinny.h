@@ -23,8 +23,9 @@ __device__ inline double skinny_load_a(const double* A1, int64_t lda1, int64_t M
 
 constexpr int kSkChunk = 64;
 
-// red: NW x 16 x 17 doubles of LDS; threads 0 .. 64 NW - 1 of the workgroup
-template <int NW, bool A_MK>
+// red: NW x 16 x 17 doubles of LDS; threads 0 .. 64 NW - 1 of the workgroup;
+// CH: k values loaded per round (CH / 2 operand registers in flight per lane)
+template <int NW, bool A_MK, int CH = kSkChunk>
 __device__ inline void skinny_tile(int64_t M, int64_t N, int64_t K, const double* A1,
                                    int64_t lda1, int64_t M1, const double* A2, int64_t lda2,
                                    const double* B, int64_t ldb, double* C, int64_t ldc,
@@ -38,10 +39,10 @@ __device__ inline void skinny_tile(int64_t M, int64_t N, int64_t K, const double
   const bool iv = i < M, jv = j < N;
   const double* arow = A_MK ? A1 + i * lda1 : nullptr;
   skinny_doublex4 acc = {0, 0, 0, 0};
-  for (int64_t k0 = kb; k0 < ke; k0 += kSkChunk) {
-    double a[kSkChunk / 4], b[kSkChunk / 4];
+  for (int64_t k0 = kb; k0 < ke; k0 += CH) {
+    double a[CH / 4], b[CH / 4];
 #pragma unroll
-    for (int u = 0; u < kSkChunk / 4; ++u) {
+    for (int u = 0; u < CH / 4; ++u) {
       const int64_t k = k0 + 4 * u + g;
       const bool kv = k < ke;
       a[u] = 0.0;
@@ -50,7 +51,7 @@ __device__ inline void skinny_tile(int64_t M, int64_t N, int64_t K, const double
       if (kv && jv) b[u] = B[k * ldb + j];
     }
 #pragma unroll
-    for (int u = 0; u < kSkChunk / 4; ++u)
+    for (int u = 0; u < CH / 4; ++u)
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
   }
 #pragma unroll
