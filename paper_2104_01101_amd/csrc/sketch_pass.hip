@@ -10,7 +10,7 @@
 // (T_(n) Omega^T)^T.
 //
 // No atomics on values.  The output Y_job (rows x ncols, row-major) is cut
-// into bins of TC consecutive cells (32 KiB, one LDS tile).  Three kernels:
+// into bins of TC consecutive cells (8, 16 or 32 KiB, one LDS tile).  Three kernels:
 //
 //   partition  one workgroup per chunk of E consecutive entries.  The chunk is
 //              read once (coalesced) and kept in registers; for every job the
@@ -47,7 +47,7 @@ namespace {
 constexpr int kWaves = 8;              // partition: 512 threads
 constexpr int kMaxJobs = 4;            // jobs per pass; more run as further passes
 constexpr int kLds = 160 * 1024;       // LDS per workgroup
-constexpr int kTileBytes = 32 * 1024;  // one bin
+constexpr int kTileMax = 32 * 1024;  // largest bin (one LDS tile); 8 and 16 KiB also built
 
 struct Coords {
   int N;
@@ -413,14 +413,15 @@ __global__ __launch_bounds__(256) void k_meta_transpose(JobSet js) {
 
 // ---------------------------------------------------------------- tiles ----
 constexpr int kWin = 256;   // chunks per window: 4 per lane
-constexpr int kSub = 2048;  // records per sub-window (record -> run map in LDS)
+constexpr int kSub = 1024;  // records per sub-window (record -> run map in LDS)
 constexpr int kWaveScratch = kSub * 2 + kWin * 8;
 
-template <class T, int K>
+template <class T, int K, int TB>
 __global__ __launch_bounds__(256) void k_tiles(JobSet js, int E, int ngroups_pad) {
   extern __shared__ __align__(16) unsigned char lds[];
-  constexpr int TC = kTileBytes / sizeof(T);
-  constexpr int FB = sizeof(T) == 8 ? 12 : 13;  // log2(TC)
+  constexpr int TC = TB / sizeof(T);
+  constexpr int FB = TC == 8192 ? 13 : TC == 4096 ? 12 : TC == 2048 ? 11 : TC == 1024 ? 10 : 0;
+  static_assert((1 << FB) == TC, "tile cells must be a power of two");
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // XCD-aware: workgroups g, g + 8, g + 16, ... run on one XCD and take
   // consecutive groups of bins
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(256) void k_tiles(JobSet js, int E, int ngroups_pad
   const Job& j = js.job[q];
   const int b = bt - j.bin0;
   T* tile = reinterpret_cast<T*>(lds) + wave * TC;
-  unsigned char* wsc = lds + 4 * kTileBytes + wave * kWaveScratch;
+  unsigned char* wsc = lds + 4 * TB + wave * kWaveScratch;
   uint16_t* map = reinterpret_cast<uint16_t*>(wsc);      // run index + 1 per record
   uint32_t* wex = reinterpret_cast<uint32_t*>(wsc + kSub * 2);  // run start in the window
   uint32_t* wad = wex + kWin;                                 // run start address
@@ -568,11 +569,26 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
   const int64_t nnz = T.nnz;
   const bool f64 = T.dtype == TSK_F64;
   const int vb = f64 ? 8 : 4;
-  const int64_t tc = kTileBytes / vb;
   const bool wide = T.order > 4;  // coordinates kept per round: 3, 4 or 8
   const int RW = wide ? 8 : T.order == 4 ? 12 : 16;
   const int E = 512 * RW;
   const int64_t nchunks = nnz > 0 ? ceil_div(nnz, E) : 0;
+  // Tile (bin) size: halved from 32 KiB while the pass has fewer than 2048
+  // bins (too few waves for the accumulation) and the smaller bins still get
+  // at least 8 records per (chunk, bin) run on average (else the per-run
+  // bookkeeping dominates).
+  int64_t cells_all = 0;
+  for (int q = 0; q < njobs; ++q) cells_all += specs[q].rows * T.dims[specs[q].col_mode];
+  int tile_bytes = kTileMax;
+  while (tile_bytes > 8 * 1024) {
+    const int64_t bins = ceil_div(cells_all, tile_bytes / vb);
+    const double per_run =
+        double(tile_bytes / 2 / vb) * double(std::min<int64_t>(E, std::max<int64_t>(nnz, 1))) *
+        double(njobs) / double(std::max<int64_t>(cells_all, 1));
+    if (bins >= 2048 || per_run < 8.0) break;
+    tile_bytes /= 2;
+  }
+  const int64_t tc = tile_bytes / vb;
   if ((nchunks + 1) * int64_t(E) >= (int64_t(1) << 31)) {
     set_error("the sketch pass supports fewer than 2^31 - %d entries", E);
     return TSK_EUNSUPPORTED;
@@ -685,15 +701,22 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
                          dim3(256), 0, st, js);
       TSK_LAUNCHED();
     }
-    const size_t tiles_lds = 4 * kTileBytes + 4 * kWaveScratch;
+    const size_t tiles_lds = 4 * size_t(tile_bytes) + 4 * kWaveScratch;
     const int ngroups = int(ceil_div(js.btot, 4));
     const int ngroups_pad = int(ceil_div(ngroups, 8) * 8);
-    if (f64)
-      hipLaunchKernelGGL((k_tiles<double, 8>), dim3(ngroups_pad), dim3(256), tiles_lds, st, js, E,
-                         ngroups_pad);
-    else
-      hipLaunchKernelGGL((k_tiles<float, 8>), dim3(ngroups_pad), dim3(256), tiles_lds, st, js, E,
-                         ngroups_pad);
+    const dim3 tg(ngroups_pad), tb(256);
+#define TSK_TILES(TY, B)                                                                   \
+  hipLaunchKernelGGL((k_tiles<TY, 8, B>), tg, tb, tiles_lds, st, js, E, ngroups_pad)
+    if (f64) {
+      if (tile_bytes == 8 * 1024) TSK_TILES(double, 8 * 1024);
+      else if (tile_bytes == 16 * 1024) TSK_TILES(double, 16 * 1024);
+      else TSK_TILES(double, 32 * 1024);
+    } else {
+      if (tile_bytes == 8 * 1024) TSK_TILES(float, 8 * 1024);
+      else if (tile_bytes == 16 * 1024) TSK_TILES(float, 16 * 1024);
+      else TSK_TILES(float, 32 * 1024);
+    }
+#undef TSK_TILES
     TSK_LAUNCHED();
   }
   ws.off = peak;
