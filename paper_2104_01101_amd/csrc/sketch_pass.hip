@@ -570,13 +570,18 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
   const bool f64 = T.dtype == TSK_F64;
   const int vb = f64 ? 8 : 4;
   const bool wide = T.order > 4;  // coordinates kept per round: 3, 4 or 8
-  const int RW = wide ? 8 : T.order == 4 ? 12 : 16;
+  // order 3: 16 rounds (8192-entry chunks), or 8 (4096) when that still leaves
+  // fewer than two chunks per CU, so that small tensors fill the chip
+  const bool small3 = T.order == 3 && nnz < int64_t(512) * 8192;
+  const int RW = wide ? 8 : T.order == 4 ? 12 : small3 ? 8 : 16;
   const int E = 512 * RW;
   const int64_t nchunks = nnz > 0 ? ceil_div(nnz, E) : 0;
   // Tile (bin) size: halved from 32 KiB while the pass has fewer than 2048
   // bins (too few waves for the accumulation) and the smaller bins still get
-  // at least 8 records per (chunk, bin) run on average (else the per-run
-  // bookkeeping dominates).
+  // enough records per (chunk, bin) run on average, else the per-run
+  // bookkeeping dominates: 8, or 4 with the small chunks (both measured on
+  // MI355X: sparse 2000^3 with 10^6 entries, 10000^3 with 10^7).
+  const double min_run = small3 ? 4.0 : 8.0;
   int64_t cells_all = 0;
   for (int q = 0; q < njobs; ++q) cells_all += specs[q].rows * T.dims[specs[q].col_mode];
   int tile_bytes = kTileMax;
@@ -585,7 +590,7 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
     const double per_run =
         double(tile_bytes / 2 / vb) * double(std::min<int64_t>(E, std::max<int64_t>(nnz, 1))) *
         double(njobs) / double(std::max<int64_t>(cells_all, 1));
-    if (bins >= 2048 || per_run < 8.0) break;
+    if (bins >= 2048 || per_run < min_run) break;
     tile_bytes /= 2;
   }
   const int64_t tc = tile_bytes / vb;
@@ -682,6 +687,8 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
           launch_partition<double, 8, 8>(path, int(nchunks), lds, st, c, js, nnz);
         else if (T.order == 4)
           launch_partition<double, 4, 12>(path, int(nchunks), lds, st, c, js, nnz);
+        else if (RW == 8)
+          launch_partition<double, 3, 8>(path, int(nchunks), lds, st, c, js, nnz);
         else
           launch_partition<double, 3, 16>(path, int(nchunks), lds, st, c, js, nnz);
       } else {
@@ -689,6 +696,8 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
           launch_partition<float, 8, 8>(path, int(nchunks), lds, st, c, js, nnz);
         else if (T.order == 4)
           launch_partition<float, 4, 12>(path, int(nchunks), lds, st, c, js, nnz);
+        else if (RW == 8)
+          launch_partition<float, 3, 8>(path, int(nchunks), lds, st, c, js, nnz);
         else
           launch_partition<float, 3, 16>(path, int(nchunks), lds, st, c, js, nnz);
       }
