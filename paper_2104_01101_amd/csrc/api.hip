@@ -322,16 +322,32 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
 
   // ---- preparation: maps, sketched right-hand sides, range finder ----
   if (run) TSK_HIP(hipMemsetAsync(a.info_dev, 0, 4 * sizeof(int), st));
-  if (ts) {
+  if (ts) {  // maps and their inverse tables, batched when every table fits in LDS
+    bool batch = true;
+    for (int k = 0; k < N; ++k) batch = batch && table_batch_fits(T.dims[k], m);
+    TableBatch tb{};
     for (int n = 0; n < N; ++n)
       for (int k = 0; k < N; ++k) {
         if (k == n) continue;
+        if (batch) {
+          tb.key[tb.n] = stream_key(o.seed, kTS, n, k);
+          tb.s[tb.n] = T.dims[k];
+          tb.h[tb.n] = h[n * N + k];
+          tb.sg[tb.n] = sg[n * N + k];
+          tb.csr[tb.n] = csr[n * N + k];
+          if (++tb.n == kTableBatch) {
+            if (run) TSK_TRY(hash_tables_batch(tb, m, st));
+            tb.n = 0;
+          }
+          continue;
+        }
         if (run)
           TSK_TRY(launch_hash_table(stream_key(o.seed, kTS, n, k), T.dims[k], m, h[n * N + k],
                                     sg[n * N + k], st));
         TSK_TRY(build_inverse_hash(h[n * N + k], T.dims[k], m, csr[n * N + k], ws, st));
         release();
       }
+    if (run && batch) TSK_TRY(hash_tables_batch(tb, m, st));
   }
   if (fibres)  // mode-n fibre indices of a COO tensor for the sampled right-hand sides
     for (int n = 0; n < N; ++n) {

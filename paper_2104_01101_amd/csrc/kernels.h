@@ -55,6 +55,19 @@ struct CsrTable {  // inverse hash of one mode: bucket b holds items[ptr[b] .. p
 };
 tsk_status build_inverse_hash(const int32_t* h, int64_t s, int64_t m, CsrTable csr, Ws& ws,
                               hipStream_t st);
+// Hash tables h, sg (as launch_hash_table) and their inverse-hash tables for
+// several (n, k) pairs: one launch for all tables, one for all inverses.
+constexpr int kTableBatch = 16;
+struct TableBatch {
+  int n;
+  uint64_t key[kTableBatch];
+  int64_t s[kTableBatch];
+  int32_t* h[kTableBatch];
+  int8_t* sg[kTableBatch];
+  CsrTable csr[kTableBatch];
+};
+bool table_batch_fits(int64_t s, int64_t m);
+tsk_status hash_tables_batch(const TableBatch& b, int64_t m, hipStream_t st);
 // Z (m x r row-major, precision prec) = TensorSketch of kron_{k in modes} A^(k)
 struct LhsMode {
   const double* A;  // s_k x R_k

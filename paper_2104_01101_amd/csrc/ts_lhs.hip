@@ -183,6 +183,79 @@ __global__ __launch_bounds__(64) void k_inverse_hash(const int32_t* h, int s, in
   }
 }
 
+// The same table with h staged in LDS by a 256-thread workgroup (all loads in
+// flight, counts by every thread) and the ordered scan and placement by wave 0
+// out of LDS; for (m + 1 + s) * 4 bytes within 64 KiB.  One workgroup per
+// table of the batch; the hash tables themselves come from k_hash_table_batch.
+__global__ void k_hash_table_batch(TableBatch b, uint64_t m) {
+  const int q = blockIdx.y;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= b.n || i >= b.s[q]) return;
+  const uint64_t x = draw(b.key[q], uint64_t(i));
+  b.h[q][i] = int32_t(bucket_of(x, m));
+  b.sg[q][i] = int8_t(sign_of(x));
+}
+
+__global__ __launch_bounds__(256) void k_inverse_hash_lds(TableBatch tb, int m) {
+  extern __shared__ int32_t sh[];
+  const int q = blockIdx.x;
+  const int32_t* h = tb.h[q];
+  const int s = int(tb.s[q]);
+  int32_t* ptr = tb.csr[q].ptr;
+  int32_t* items = tb.csr[q].items;
+  int32_t* cur = sh;          // m + 1
+  int32_t* hs = sh + m + 1;   // s
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int b = tid; b <= m; b += 256) cur[b] = 0;
+#pragma unroll 4
+  for (int i = tid; i < s; i += 256) hs[i] = h[i];
+  __syncthreads();
+  for (int i = tid; i < s; i += 256) atomicAdd(&cur[hs[i] + 1], 1);
+  __syncthreads();
+  if (tid >= 64) return;  // one wave from here on: no more block barriers
+  const int chunk = (m + 1 + 63) / 64;
+  const int b0 = lane * chunk, b1 = b0 + chunk < m + 1 ? b0 + chunk : m + 1;
+  int32_t run = 0;
+  for (int b = b0; b < b1; ++b) run += cur[b];
+  int32_t incl = run;
+  for (int off = 1; off < 64; off <<= 1) {
+    int32_t o = __shfl_up(incl, off);
+    if (lane >= off) incl += o;
+  }
+  int32_t base = incl - run;
+  for (int b = b0; b < b1; ++b) {
+    base += cur[b];
+    cur[b] = base;
+    ptr[b] = base;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  int bits = 1;
+  while ((1 << bits) < m) ++bits;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (int i0 = 0; i0 < s; i0 += 64) {
+    const int i = i0 + lane;
+    const bool valid = i < s;
+    const uint32_t key = valid ? uint32_t(hs[i]) : 0u;
+    uint64_t mt = __ballot(valid);
+    for (int bt = 0; bt < bits; ++bt) {
+      const bool bit = (key >> bt) & 1u;
+      const uint64_t bal = __ballot(bit);
+      mt &= bit ? bal : ~bal;
+    }
+    const int rank = __popcll(mt & lt);
+    int bs = 0;
+    if (valid && rank == 0) {
+      bs = cur[key];
+      cur[key] = bs + __popcll(mt);
+    }
+    const int leader = valid ? __ffsll((unsigned long long)mt) - 1 : lane;
+    bs = __shfl(bs, leader);
+    if (valid) items[bs + rank] = i;
+  }
+}
+
 // ---- CountSketch by gather: CS[b, c] = sum_{i in bucket b} sg[i] A[i, c] ----
 __global__ void k_cs_gather(const double* A, int64_t R, const int8_t* sg, const int32_t* ptr,
                             const int32_t* items, int64_t m, double* CS) {
@@ -351,8 +424,36 @@ tsk_status build_inverse_hash(const int32_t* h, int64_t s, int64_t m, CsrTable c
     set_error("TensorSketch size m = %lld above the inverse-hash LDS limit", (long long)m);
     return TSK_EUNSUPPORTED;
   }
-  hipLaunchKernelGGL(k_inverse_hash, dim3(1), dim3(64), size_t(m + 1) * 4, st, h, int(s), int(m),
-                     csr.ptr, csr.items);
+  if (table_batch_fits(s, m)) {
+    TableBatch tb{};
+    tb.n = 1;
+    tb.s[0] = s;
+    tb.h[0] = const_cast<int32_t*>(h);
+    tb.csr[0] = csr;
+    hipLaunchKernelGGL(k_inverse_hash_lds, dim3(1), dim3(256), size_t(m + 1 + s) * 4, st, tb,
+                       int(m));
+  } else {
+    hipLaunchKernelGGL(k_inverse_hash, dim3(1), dim3(64), size_t(m + 1) * 4, st, h, int(s),
+                       int(m), csr.ptr, csr.items);
+  }
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+bool table_batch_fits(int64_t s, int64_t m) { return (m + 1 + s) * 4 <= 65536; }
+
+tsk_status hash_tables_batch(const TableBatch& b, int64_t m, hipStream_t st) {
+  if (b.n <= 0) return TSK_OK;
+  int64_t smax = 0;
+  for (int q = 0; q < b.n; ++q) {
+    TSK_REQUIRE(table_batch_fits(b.s[q], m), "inverse-hash table beyond the LDS budget");
+    smax = b.s[q] > smax ? b.s[q] : smax;
+  }
+  hipLaunchKernelGGL(k_hash_table_batch, dim3(unsigned(ceil_div(smax, 256)), unsigned(b.n)),
+                     dim3(256), 0, st, b, uint64_t(m));
+  TSK_LAUNCHED();
+  hipLaunchKernelGGL(k_inverse_hash_lds, dim3(unsigned(b.n)), dim3(256),
+                     size_t(m + 1 + smax) * 4, st, b, int(m));
   TSK_LAUNCHED();
   return TSK_OK;
 }
