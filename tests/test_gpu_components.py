@@ -284,6 +284,8 @@ def _check_fibres(tsk, dims, idx, val, n, samples, w):
     ((12, 10, 8, 6), 4000, 300, 2, 500, np.float32),     # order 4
     ((7, 6, 5), 40, 10, 2, 64, np.float64),              # fewer entries than one probe round
     ((20, 20, 20), 0, 0, 1, 50, np.float64),             # empty tensor
+    ((4096, 6, 5), 20_000, 500, 0, 100, np.float32),     # s_n = one LDS chunk exactly
+    ((5, 4097, 6), 20_000, 500, 1, 100, np.float64),     # one column past the chunk
 ])
 def test_fibre_gather_bit_exact(tsk, dims, nnz, dup, n, m, dtype):
     rs = np.random.default_rng(nnz + n)

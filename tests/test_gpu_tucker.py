@@ -144,6 +144,35 @@ def test_sparse_leverage_parity(tsk, prec, solve, tol):
             np.testing.assert_allclose(F.cpu().numpy(), Fo, atol=1e-8)
 
 
+def test_lev_det_order4_dense_parity(tsk):
+    """Deterministic selection with three other modes (candidate tuples of three
+    levels): dense 16 x 14 x 12 x 10, Tucker (3,3,2,2) + 5 % noise, m = 8 r_max.
+    At m = 4 r_max the kept rows of the last mode leave Z numerically singular
+    (condition 6e15), and both sides then solve an ill-posed problem; at 8 r_max
+    the condition number of every sketch stays below 2.3."""
+    ranks = (3, 3, 2, 2)
+    X = workloads.tucker_dense((16, 14, 12, 10), ranks, 0.05, seed=6)
+    m = 8 * 18
+    _, factors, fits = tsk.tucker_sketch_als(_dense(tsk, X), ranks, m, 3, sketch="lev_det",
+                                             prec="f64", seed=2)
+    ref = otk.sketch_tucker_als(osk.Tensor.from_dense(X), ranks, m, 3, seed=2,
+                                sketch_kind="lev_det")
+    np.testing.assert_allclose(fits, ref["fits"], rtol=0, atol=1e-10)
+
+
+def test_sparse_leverage_order4_fp32(tsk):
+    """Leverage sampling of an order-4 COO tensor (fibre keys over three other
+    modes): 30 x 25 x 20 x 15 with 40k entries, FP32 operands."""
+    dims, ranks = (30, 25, 20, 15), (3, 3, 2, 2)
+    idx, val = workloads.sparse_tucker(dims, 40_000, ranks, seed=7, noise_std=0.1)
+    T = _coo(tsk, dims, idx, val)
+    m = 16 * 18
+    _, _, fits = tsk.tucker_sketch_als(T, ranks, m, 3, sketch="lev", prec="f32", seed=4)
+    ref = otk.sketch_tucker_als(osk.Tensor(dims, idx, val.astype(np.float64)), ranks, m, 3,
+                                seed=4, sketch_kind="lev")
+    np.testing.assert_allclose(fits, ref["fits"], rtol=0, atol=1e-5)
+
+
 def test_sparse_leverage_dense_equivalent(tsk):
     """The same small tensor stored densely and as COO (every entry, shuffled)
     gives the same leverage run: the fibre index changes the access, not the sketch.
