@@ -273,8 +273,10 @@ tsk_status tsk_rrf_init(const tsk_tensor* T, int32_t n, int32_t R, int32_t k1, i
  * idx[j][t] = first i with cdf_k[i] > u cdf_k[last], cdf_k the sequential FP64
  * prefix sum of l_i = sum_c A^(k)(i,c)^2 (each square rounded before the add);
  * w[j] = 1 / sqrt(m prod_k l_{i_k} / sum l).
- *   idx device int32 m x (N-1) (modes k != n in increasing order) (output)
- *   w   device double m (output) */
+ *   ranks   host int32[N]; factors host array of N device double*, factors[k]
+ *           s_k x R_k row-major (entry n unused)
+ *   idx     device int32 m x (N-1) (modes k != n in increasing order) (output)
+ *   w       device double m (output) */
 tsk_status tsk_leverage_sample(int32_t order, const int64_t* dims, const int32_t* ranks,
                                int32_t n, int64_t m, uint64_t seed, int32_t sweep,
                                const double* const* factors, int32_t* idx, double* w,
@@ -288,7 +290,9 @@ tsk_status tsk_leverage_sample(int32_t order, const int64_t* dims, const int32_t
  * per-mode ranks (position in score-descending, index-ascending order)
  * compared lexicographically in increasing k; the first m are returned.  No
  * rescaling: use weights 1 with tsk_sketch_lev / tsk_sketch_lev_coo.
- *   idx  device int32 m x (N-1), modes k != n in increasing order (output)
+ *   ranks    host int32[N]; factors host array of N device double*, factors[k]
+ *            s_k x R_k row-major (entry n unused)
+ *   idx      device int32 m x (N-1), modes k != n in increasing order (output)
  * Requires 1 <= m <= prod_{k != n} s_k (EINVAL otherwise).  Workspace query
  * convention as tsk_leverage_sample; asynchronous on `stream`. */
 tsk_status tsk_leverage_select(int32_t order, const int64_t* dims, const int32_t* ranks,
