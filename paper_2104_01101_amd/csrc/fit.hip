@@ -270,6 +270,52 @@ __device__ double block_sum_of(const double* p, int n, double* red) {
   return s;
 }
 
+// k_model_norm2 and k_finish in one workgroup, the mode products of the
+// model norm ping-ponging between two LDS buffers of csize doubles.
+__global__ __launch_bounds__(kT) void k_finish_model(FitArgs a, const double* core, int64_t csize,
+                                                     const double* grams, const double* pn,
+                                                     int nbn, const double* pi, int nbi,
+                                                     const double* pd, int dense,
+                                                     double* nT2_out, double* res_out) {
+  extern __shared__ double lbuf[];  // 2 csize
+  __shared__ double red[kT / 64];
+  const double* in = core;
+  int64_t goff = 0;
+  for (int k = 0; k < a.N; ++k) {
+    const int64_t Rk = a.R[k];
+    int64_t inner = 1;
+    for (int l = k + 1; l < a.N; ++l) inner *= a.R[l];
+    const double* G = grams + goff;
+    double* o = lbuf + (k & 1) * csize;
+    for (int64_t t = threadIdx.x; t < csize; t += kT) {
+      int64_t rk = (t / inner) % Rk, base = t - rk * inner;
+      double s = 0.0;
+      for (int64_t c = 0; c < Rk; ++c) s += G[rk * Rk + c] * in[base + c * inner];
+      o[t] = s;
+    }
+    __syncthreads();
+    in = o;
+    goff += Rk * Rk;
+  }
+  double m2 = 0.0;
+  for (int64_t t = threadIdx.x; t < csize; t += kT) m2 += in[t] * core[t];
+  m2 = block_reduce(m2, red);
+  __syncthreads();
+  double nT2 = 0.0;
+  if (pn) {
+    nT2 = block_sum_of(pn, nbn, red);
+  } else {
+    nT2 = *nT2_out;
+  }
+  const double inner = block_sum_of(pi, nbi, red);
+  const double direct = dense ? block_sum_of(pd, nbi, red) : 0.0;
+  if (threadIdx.x != 0) return;
+  if (pn) *nT2_out = nT2;
+  double r2 = nT2 - 2.0 * inner + m2;
+  if (dense) r2 = direct;  // every entry stored: sum of squared differences, no cancellation
+  *res_out = sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(nT2);
+}
+
 __global__ __launch_bounds__(kT) void k_finish(const double* pn, int nbn, const double* pi, int nbi,
                                                const double* pd, int dense, const double* model2,
                                                double* nT2_out, double* res_out) {
@@ -378,6 +424,14 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
                        a, T.nnz, per, core, csize, core_lds, fs.partial_inner, fs.partial_direct);
   }
   TSK_LAUNCHED();
+  if (csize <= 4096) {  // model norm in LDS inside the final reduction
+    hipLaunchKernelGGL(k_finish_model, dim3(1), dim3(kT), size_t(2 * csize) * 8, st, a, core,
+                       csize, fs.grams, with_norm ? fs.partial_norm : nullptr, fs.nblocks,
+                       fs.partial_inner, fs.nblocks, fs.partial_direct,
+                       T.layout == TSK_DENSE ? 1 : 0, fs.nT2, res);
+    TSK_LAUNCHED();
+    return TSK_OK;
+  }
   hipLaunchKernelGGL(k_model_norm2, dim3(1), dim3(kT), 0, st, a, core, csize, fs.grams, fs.buf0,
                      fs.buf1, fs.model2);
   TSK_LAUNCHED();
