@@ -274,6 +274,7 @@ __global__ void k_cs_gather(const double* A, int64_t R, const int8_t* sg, const 
 // ---- forward FFT of every CountSketch column ----
 struct SpecJob {
   int nmodes;
+  int64_t s[TSK_MAX_ORDER];  // rows of A (items of the inverse hash), for the staged gather
   int64_t R[TSK_MAX_ORDER];
   int64_t coloff[TSK_MAX_ORDER];  // first column index of mode q in the spectra array
   const double* CS[TSK_MAX_ORDER];
@@ -318,14 +319,37 @@ __global__ __launch_bounds__(kFftBlock) void k_spectra(SpecJob sj, int64_t m, Ra
     const int8_t* sg = sj.sg[q];
     const int32_t* ptr = sj.ptr[q];
     const int32_t* items = sj.items[q];
-    for (int64_t f = threadIdx.x; f < m; f += blockDim.x) {
-      double acc = 0.0;
-      for (int32_t p = ptr[f]; p < ptr[f + 1]; ++p) {
+    const int64_t sq = sj.s[q];
+    if (sq <= 2 * m) {
+      // staged: the signed entries of every item into the (still unused) FFT
+      // work buffer b, all loads in flight, and the bucket starts into LDS
+      // after the twiddles; then each bucket summed in item order (the sums
+      // of the loop below, bit for bit)
+      double* val = reinterpret_cast<double*>(b);
+      int32_t* ps = reinterpret_cast<int32_t*>(buf + 3 * m);
+#pragma unroll 4
+      for (int64_t p = threadIdx.x; p < sq; p += blockDim.x) {
         const int32_t i = items[p];
         const double v = A[int64_t(i) * R + c];
-        acc += sg[i] > 0 ? v : -v;
+        val[p] = sg[i] > 0 ? v : -v;
       }
-      a[f] = make_double2(acc, 0.0);
+      for (int64_t f = threadIdx.x; f <= m; f += blockDim.x) ps[f] = ptr[f];
+      __syncthreads();
+      for (int64_t f = threadIdx.x; f < m; f += blockDim.x) {
+        double acc = 0.0;
+        for (int32_t p = ps[f]; p < ps[f + 1]; ++p) acc += val[p];
+        a[f] = make_double2(acc, 0.0);
+      }
+    } else {
+      for (int64_t f = threadIdx.x; f < m; f += blockDim.x) {
+        double acc = 0.0;
+        for (int32_t p = ptr[f]; p < ptr[f + 1]; ++p) {
+          const int32_t i = items[p];
+          const double v = A[int64_t(i) * R + c];
+          acc += sg[i] > 0 ? v : -v;
+        }
+        a[f] = make_double2(acc, 0.0);
+      }
     }
   } else {
     const double* CS = sj.CS[q];
@@ -469,7 +493,8 @@ static int fft_max_lds() {
   return v;
 }
 
-static bool twiddles_fit(int64_t m) { return int64_t(3) * m * 16 <= fft_max_lds(); }
+// a, b and the twiddles in LDS, plus the bucket starts of the staged gather
+static bool twiddles_fit(int64_t m) { return int64_t(3) * m * 16 + (m + 1) * 4 <= fft_max_lds(); }
 
 static void launch_spectra(int64_t cols, int64_t m, const Radices& rd, const SpecJob& sj, const double* tw,
                     double* spec, hipStream_t st) {
@@ -580,9 +605,12 @@ tsk_status ts_lhs(const LhsMode* modes, int nmodes, int64_t m, int prec, void* Z
     sj.sg[q] = modes[q].sg;
     sj.ptr[q] = modes[q].csr.ptr;
     sj.items[q] = modes[q].csr.items;
+    sj.s[q] = modes[q].s;
     off += modes[q].R;
   }
-  hipLaunchKernelGGL((k_spectra<true, true>), dim3(off), dim3(kFftBlock), size_t(3 * m * 16), st,
+  // a, b and the twiddles (3 m double2), then the bucket starts (m + 1 int32)
+  const size_t spec_lds = size_t(3 * m * 16) + size_t(m + 1) * 4;
+  hipLaunchKernelGGL((k_spectra<true, true>), dim3(off), dim3(kFftBlock), spec_lds, st,
                      sj, m, rd, static_cast<const double2*>(nullptr),
                      reinterpret_cast<double2*>(spec));
   TSK_LAUNCHED();
