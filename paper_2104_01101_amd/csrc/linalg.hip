@@ -1421,6 +1421,7 @@ __global__ void k_rsvd_w(const double* Qm, bool q_rows, const double* U, const d
 // largest-magnitude entry positive (lowest index on ties, as k_sign_fix);
 // A(:, c) in that sign; and W(:, c) = Q U(:, c) lam_c^{1/2} in the same sign.
 // Q is r x k, Dt is s x k; k <= 64.
+constexpr int kFinRegs = 16;  // rows per thread kept in registers by k_rsvd_finish
 constexpr int kFinT = 256;
 
 __global__ __launch_bounds__(kFinT) void k_rsvd_finish(const double* Dt, const double* U,
@@ -1430,14 +1431,15 @@ __global__ __launch_bounds__(kFinT) void k_rsvd_finish(const double* Dt, const d
   __shared__ double us[64];
   __shared__ double bv[kFinT];
   __shared__ int bi[kFinT];
+  __shared__ int bn[kFinT];
   const int c = blockIdx.x, tid = threadIdx.x;
   const double lc = lam[c];
   if (tid < k) us[tid] = U[tid * R + c] / sqrt(lc);
   __syncthreads();
   double best = -1.0;
-  int bidx = 0;
+  int bidx = 0, bneg = 0;
   const bool pairs = (k & 1) == 0;
-  for (int i = tid; i < s; i += kFinT) {
+  auto row_value = [&](int i) {
     const double* d = Dt + size_t(i) * k;
     double a0 = 0.0, a1 = 0.0;
     if (pairs) {
@@ -1451,23 +1453,40 @@ __global__ __launch_bounds__(kFinT) void k_rsvd_finish(const double* Dt, const d
       for (int j = 0; j < k; ++j) a0 = fma(d[j], us[j], a0);
     }
     const double a = a0 + a1;
-    A[size_t(i) * R + c] = a;
-    if (fabs(a) > best) best = fabs(a), bidx = i;  // first maximum within the stride
+    if (fabs(a) > best) best = fabs(a), bidx = i, bneg = a < 0.0;  // first maximum in the stride
+    return a;
+  };
+  // the first kFinRegs rows of this thread stay in registers until the sign
+  // is known; rows beyond them (s > kFinRegs kFinT) go through A twice
+  double keep[kFinRegs];
+#pragma unroll
+  for (int t = 0; t < kFinRegs; ++t) {
+    const int i = tid + t * kFinT;
+    keep[t] = i < s ? row_value(i) : 0.0;
   }
+  for (int i = tid + kFinRegs * kFinT; i < s; i += kFinT) A[size_t(i) * R + c] = row_value(i);
   bv[tid] = best;
   bi[tid] = bidx;
+  bn[tid] = bneg;
   __syncthreads();
   for (int off = kFinT / 2; off > 0; off >>= 1) {
     if (tid < off) {
       const double o = bv[tid + off];
       const int oi = bi[tid + off];
-      if (o > bv[tid] || (o == bv[tid] && oi < bi[tid])) bv[tid] = o, bi[tid] = oi;
+      if (o > bv[tid] || (o == bv[tid] && oi < bi[tid]))
+        bv[tid] = o, bi[tid] = oi, bn[tid] = bn[tid + off];
     }
     __syncthreads();
   }
-  const bool flip = A[size_t(bi[0]) * R + c] < 0.0;
+  const bool flip = bn[0] != 0;
+#pragma unroll
+  for (int t = 0; t < kFinRegs; ++t) {
+    const int i = tid + t * kFinT;
+    if (i < s) A[size_t(i) * R + c] = flip ? -keep[t] : keep[t];
+  }
   if (flip)
-    for (int i = tid; i < s; i += kFinT) A[size_t(i) * R + c] = -A[size_t(i) * R + c];
+    for (int i = tid + kFinRegs * kFinT; i < s; i += kFinT)
+      A[size_t(i) * R + c] = -A[size_t(i) * R + c];
   const double ws = flip ? -sqrt(lc) : sqrt(lc);
   for (int i = tid; i < r; i += kFinT) {
     double w = 0.0;
