@@ -142,6 +142,9 @@ def parse():
     ap.add_argument("--solve", default="rsvd", choices=["rsvd", "exact"],
                     help="subproblem solver: rsvd = RSVD-LRLS (Alg. 5, the solver Alg. 4 "
                          "calls) or exact = truncated SVD of Z^+ Y")
+    ap.add_argument("--prec", default=None, choices=["f32", "bf16", "f64"],
+                    help="operand precision of the sketched products (default: the workload's, "
+                         "FP32); bf16 = BF16 operands with FP32 accumulation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true",
                     help="also print per-group times of the last warm-up step (stderr)")
@@ -171,7 +174,8 @@ def group_work(w, solve="exact"):
     q = min(r, s)
     k1 = math.ceil(math.sqrt(m / r) * R - 1e-9)
     k2 = R * R + k1
-    vb = 4  # FP32 tensor values and FP32 operands
+    vb = 4  # FP32 tensor values (and the sketched right-hand sides of the pass)
+    vo = {"f32": 4, "bf16": 2, "f64": 8}[w.prec]  # operand bytes of Z and sampled Y
     subs = N * sweeps
     pk = PEAK_TFLOPS[w.prec]
     eig = lambda n: 4.0 / 3.0 * n ** 3 + 2.0 * n * n * R
@@ -193,7 +197,7 @@ def group_work(w, solve="exact"):
         "rrf": ("mfma", (N - 1) * (2.0 * s * k2 * k1 + 2.0 * s * k1 * k1),
                 PEAK_TFLOPS["f64"], "TFLOP/s"),
         # CountSketches read, Z written
-        "ts_lhs": ("hbm", subs * ((N - 1) * s * R * 8 + m * r * vb), HBM_PEAK_GBS, "GB/s"),
+        "ts_lhs": ("hbm", subs * ((N - 1) * s * R * 8 + m * r * vo), HBM_PEAK_GBS, "GB/s"),
         # G = Z^T Z and Z^T Y
         "gram": ("mfma", subs * 2.0 * m * r * (r + s), pk, "TFLOP/s"),
         "solve_la": ("mfma", subs * la, PEAK_TFLOPS["f64"], "TFLOP/s"),
@@ -202,7 +206,7 @@ def group_work(w, solve="exact"):
         # per entry: core contraction R^3 + R^2 + R multiply-adds (FP64)
         "fit": ("alu", sweeps * nnz * 2.0 * (R ** 3 + R ** 2 + R), FP64_VECTOR_TFLOPS, "TFLOP/s"),
         # sampled Kronecker rows: factors read, Z written
-        "leverage": ("hbm", subs * ((N - 1) * s * R * 8 + m * r * vb), HBM_PEAK_GBS, "GB/s"),
+        "leverage": ("hbm", subs * ((N - 1) * s * R * 8 + m * r * vo), HBM_PEAK_GBS, "GB/s"),
         # per mode: keys built (indices read, keys written), then sorted pairs written once
         "fiber_index": ("hbm", N * nnz * (4 * N + 8 + 12), HBM_PEAK_GBS, "GB/s"),
         # deterministic selection: candidate products and their sort keys (about
@@ -210,7 +214,7 @@ def group_work(w, solve="exact"):
         "select": ("hbm", subs * 3 * m * (math.log(m) + 1) * 24, HBM_PEAK_GBS, "GB/s"),
         # sampled fibres: Y written, the fibres' keys and values read (expected length
         # nnz / prod_{k != n} s_k), sample indices and weights read
-        "fiber_rows": ("hbm", subs * (m * s * vb + m * (nnz / s ** (N - 1)) * 12
+        "fiber_rows": ("hbm", subs * (m * s * vo + m * (nnz / s ** (N - 1)) * 12
                                       + m * (4 * (N - 1) + 8)), HBM_PEAK_GBS, "GB/s"),
     }
 
@@ -286,6 +290,8 @@ def main():
 
     dev = torch.device("cuda:0")
     w = workload(args.workload)
+    if args.prec:
+        w["prec"] = args.prec
     T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(dev), torch.from_numpy(w.val).to(dev), w.dims)
     plan = tsk.TuckerPlan(T, w.ranks, w.m, w.sweeps, sketch=w.sketch, init="rrf", prec=w.prec,
                           seed=0, record_fit=True, solve=args.solve)
@@ -358,7 +364,9 @@ def main():
                                         "of Alg. 4, FP32 operands",
                        "zipf10k": "sparse 10000^3, 1e7 nnz Zipf(1.1), lognormal values, "
                                   "Tucker rank 16, TensorSketch m=2048, RRF init, 5 sweeps, "
-                                  "FP32 operands"}[args.workload],
+                                  "FP32 operands"}[args.workload].replace(
+                       "FP32 operands", {"f32": "FP32", "bf16": "BF16 (FP32-accumulated)",
+                                         "f64": "FP64"}[w.prec] + " operands"),
                    "dims": list(w.dims), "nnz": int(w.val.shape[0]), "ranks": list(w.ranks),
                    "m": w.m, "sweeps": w.sweeps, "prec": w.prec,
                    "solve": "RSVD-LRLS (Alg. 5)" if args.solve == "rsvd" else "exact truncated SVD"},
