@@ -379,12 +379,16 @@ def test_adjoint_matches_oracle_and_fd(tsk):
 # ------------------------------------------------------------ RSVD-LRLS ----
 @pytest.mark.parametrize("m,r,s,R,k", [(300, 100, 400, 10, 20), (80, 25, 40, 5, 15),
                                        (400, 144, 150, 12, 22), (150, 36, 50, 12, 20),
-                                       (200, 40, 60, 26, 30), (500, 120, 90, 7, 13)])
+                                       (200, 40, 60, 26, 30), (500, 120, 90, 7, 13),
+                                       (400, 128, 200, 10, 24), (60, 17, 30, 3, 8),
+                                       (50, 9, 20, 1, 1), (250, 64, 100, 16, 16)])
 def test_rsvd_solve_fp64_vs_oracle(tsk, m, r, s, R, k):
     """RSVD-LRLS (Alg. 5) with the same Gaussian test matrix: FP64 library vs
     the oracle.  r = 144 exercises the Cholesky branch of the Gram solve,
     k = 30 the unfused chain and the order-32 eigensolver with R = 26 vectors,
-    r = 120 the largest register SPD inverse."""
+    r = 120 a large register SPD inverse; r = 128 with k = 24 is the largest
+    fused shape, r = 17 with k = 8 a ragged one at the smallest column block,
+    R = k = 1 the degenerate sketch of one column, R = k = 16 all vectors kept."""
     rs = np.random.default_rng(m + r)
     Z = rs.standard_normal((m, r))
     Y = rs.standard_normal((m, s))
