@@ -53,7 +53,7 @@ typedef enum {
   TSK_EUNSUPPORTED = -2, /* valid but not supported by this build */
   TSK_ENOMEM = -3,       /* workspace too small */
   TSK_EHIP = -4,         /* HIP runtime / kernel launch failure */
-  TSK_ENUMERIC = -5      /* numerical breakdown (non-SPD sketched Gram, NaN) */
+  TSK_ENUMERIC = -5      /* numerical breakdown: a pivot of the sketched Gram not positive */
 } tsk_status;
 
 typedef enum { TSK_F32 = 0, TSK_F64 = 1 } tsk_dtype;
