@@ -359,7 +359,7 @@ def main():
                                         "per-mode fibre indices, RRF init, 10 sweeps of "
                                         "Alg. 4, FP32 operands",
                        "sparse2000det": "sparse 2000^3, 1e6 nnz uniform, Tucker rank 10 + "
-                                        "N(0,1), deterministic leverage selection m=1600 "
+                                        "N(0,1), deterministic leverage selection m=2400 "
                                         "through per-mode fibre indices, RRF init, 10 sweeps "
                                         "of Alg. 4, FP32 operands",
                        "zipf10k": "sparse 10000^3, 1e7 nnz Zipf(1.1), lognormal values, "

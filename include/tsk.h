@@ -53,7 +53,7 @@ typedef enum {
   TSK_EUNSUPPORTED = -2, /* valid but not supported by this build */
   TSK_ENOMEM = -3,       /* workspace too small */
   TSK_EHIP = -4,         /* HIP runtime / kernel launch failure */
-  TSK_ENUMERIC = -5      /* numerical breakdown: a pivot of the sketched Gram not positive */
+  TSK_ENUMERIC = -5      /* numerical breakdown: a Gram pivot or a singular value not positive */
 } tsk_status;
 
 typedef enum { TSK_F32 = 0, TSK_F64 = 1 } tsk_dtype;
@@ -167,7 +167,9 @@ tsk_status tsk_workspace_size(const tsk_tensor* T, const int32_t* ranks,
  *   sweeps_done host int32 or NULL
  * Synchronous.  Errors: EINVAL (shapes, m < prod_{k != n} R_k, sizes),
  * EUNSUPPORTED (prod s_k > 2^64 for leverage sampling of a COO tensor), ENOMEM (workspace),
- * ENUMERIC (sketched Gram not positive definite), EHIP. */
+ * ENUMERIC (a sketched Gram not positive definite, or a subproblem whose sketched
+ * right-hand side has rank below R_n, e.g. an all-zero tensor: a singular value
+ * the solve divides by is zero), EHIP. */
 tsk_status tsk_tucker_sketch_als(const tsk_tensor* T, const int32_t* ranks,
                                  const tsk_options* opt, double* core,
                                  double* const* factors, double* fit_history,
@@ -237,7 +239,9 @@ tsk_status tsk_sketch_lhs_ts(int32_t order, const int64_t* dims, const int32_t* 
  *   Z  device m x r, Y device m x s, element type by prec (as above)
  *   A  device double s x R (output);  W device double r x R (output)
  * Requires m >= r, R <= min(r, s).  Synchronous: waits for the stream to check
- * the factorisation status; ENUMERIC if the Gram is not positive definite. */
+ * the factorisation status; ENUMERIC if the Gram is not positive definite or, for
+ * r <= s, if one of the R leading eigenvalues of X^T X (X = Z^+ Y) is not
+ * positive (Y of rank below R). */
 tsk_status tsk_rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s,
                         int32_t R, int32_t prec, double* A, double* W, void* ws,
                         size_t* ws_bytes, void* stream);
@@ -251,7 +255,8 @@ tsk_status tsk_rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int6
  *   Z, Y   device, as tsk_rc_solve;  Omega device double s x k, R <= k <= min(r, 64)
  *   A  device double s x R (output);  W device double r x R (output)
  * Synchronous (checks the factorisation status); ENUMERIC if the Gram is not
- * positive definite. */
+ * positive definite or one of the R leading eigenvalues of D D^T is not positive
+ * (Y of rank below R). */
 tsk_status tsk_rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s,
                           int32_t R, int32_t prec, const double* Omega, int32_t k, double* A,
                           double* W, void* ws, size_t* ws_bytes, void* stream);

@@ -157,7 +157,7 @@ tsk_status rrf_finish(const TensorView& T, int n, int64_t R, uint64_t seed, RrfB
   TSK_TRY(sym_eig_top(b.Mq, b.k1, R, b.lam, b.V, ws, st));
   if (run) {
     TSK_TRY(gemm_small(s, R, b.k1, 1.0, b.B, b.k1, 1, b.V, R, 1, 0.0, A, R, st));
-    TSK_TRY(scale_columns_inv_sqrt(A, s, R, b.lam, st));
+    TSK_TRY(scale_columns_inv_sqrt(A, s, R, b.lam, st, info));
   }
   TSK_TRY(cholqr(A, s, R, info, ws, st));
   if (run) TSK_TRY(sign_fix_columns(A, s, R, st));
@@ -490,6 +490,11 @@ tsk_status finish_sync(TuckerArgs& a, double* fit_history, int32_t* sweeps_done)
               info[1], info[2]);
     return TSK_ENUMERIC;
   }
+  if (info[3]) {
+    set_error("numerical breakdown: sketched right-hand side of rank below R (a singular value "
+              "of the subproblem is zero)");
+    return TSK_ENUMERIC;
+  }
   return TSK_OK;
 }
 
@@ -636,10 +641,11 @@ tsk_status tsk_rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int6
   });
   if (stt != TSK_OK || ws == nullptr) return stt;
   TSK_HIP(hipStreamSynchronize(as_stream(stream)));
-  int hinfo[2];
+  int hinfo[4];
   TSK_HIP(hipMemcpy(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost));
-  if (hinfo[0] || hinfo[1]) {
-    set_error("numerical breakdown in the sketched solve (info %d %d)", hinfo[0], hinfo[1]);
+  if (hinfo[0] || hinfo[1] || hinfo[3]) {
+    set_error("numerical breakdown in the sketched solve (info %d %d %d)", hinfo[0], hinfo[1],
+              hinfo[3]);
     return TSK_ENUMERIC;
   }
   return TSK_OK;
@@ -664,10 +670,11 @@ tsk_status tsk_rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, in
   }));
   if (!ws) return TSK_OK;
   TSK_HIP(hipStreamSynchronize(as_stream(stream)));
-  int hinfo[2];
+  int hinfo[4];
   TSK_HIP(hipMemcpy(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost));
-  if (hinfo[0] || hinfo[1]) {
-    set_error("numerical breakdown in the randomized solve (info %d %d)", hinfo[0], hinfo[1]);
+  if (hinfo[0] || hinfo[1] || hinfo[3]) {
+    set_error("numerical breakdown in the randomized solve (info %d %d %d)", hinfo[0], hinfo[1],
+              hinfo[3]);
     return TSK_ENUMERIC;
   }
   return TSK_OK;

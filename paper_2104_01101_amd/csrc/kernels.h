@@ -145,16 +145,18 @@ bool range_basis_fits(int64_t r, int64_t k);
 tsk_status range_basis(const double* C0, const double* B, int64_t r, int64_t k, double* Q,
                        double* P, hipStream_t st);
 // A = Dt U lam^{-1/2} (s x R), sign rule on its columns, W = Q U lam^{1/2} in
-// the same signs (Q r x k row-major); k <= 64; one launch
+// the same signs (Q r x k row-major); k <= 64; one launch; *bad = 1 when some
+// lam_c <= 0 (or NaN)
 tsk_status rsvd_finish(const double* Dt, const double* U, const double* lam, const double* Q,
                        int64_t s, int64_t k, int64_t r, int64_t R, double* A, double* W,
-                       hipStream_t st);
+                       int* bad, hipStream_t st);
 // W = Q U diag(lam * sgn), Q given as r x k (q_rows) or as Q^T (k x r), U (k x R)
 tsk_status rsvd_w(const double* Qm, bool q_rows, const double* U, const double* lam,
                   const double* sgn, int64_t k, int64_t r, int64_t R, double* W, hipStream_t st);
-// A (rows x R): A <- A * diag(scale) with scale[c] = 1/sqrt(lam[c])
+// A (rows x R): A <- A * diag(scale) with scale[c] = 1/sqrt(lam[c]); *bad = 1
+// (when bad is given) if some lam[c] <= 0 (or NaN)
 tsk_status scale_columns_inv_sqrt(double* A, int64_t rows, int64_t R, const double* lam,
-                                  hipStream_t st);
+                                  hipStream_t st, int* bad = nullptr);
 tsk_status transpose_f64(const double* A, int64_t rows, int64_t cols, double* At,
                          hipStream_t st);
 // Thin Householder QR: Ct (k x r) holds the columns of C (r x k) as rows; Qt

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kCholT) void k_cholesky(double* G, int n, int lda, 
     }
     __syncthreads();
   }
-  if (tid == 0) *info = bad;
+  if (tid == 0 && bad) *info = bad;  // sticky: the caller zeroes info once per job
   for (int i = wave; i < n; i += kCholWaves)
     for (int k = lane; k < n; k += 64) G[i * lda + k] = k <= i ? a[i * ld + k] : 0.0;
 }
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kGjT) void k_spd_inverse(double* G, int n, int lda,
     __syncthreads();
   }
   (void)prow_inv;
-  if (tid == 0) *info = bad;
+  if (tid == 0 && bad) *info = bad;  // sticky: the caller zeroes info once per job
   for (int i = wave; i < n; i += NW)
     for (int k = lane; k < n; k += 64) G[i * lda + k] = a[i * n + k];
 }
@@ -1330,7 +1330,7 @@ __device__ __forceinline__ void spd_inverse_pair_body(double* G, int n, int lda,
       __syncthreads();
     }
   });
-  if (tid == 0) *info = bad;
+  if (tid == 0 && bad) *info = bad;  // sticky: the caller zeroes info once per job
 #pragma unroll
   for (int a = 0; a < NB; ++a)
 #pragma unroll
@@ -1420,20 +1420,22 @@ __global__ void k_rsvd_w(const double* Qm, bool q_rows, const double* U, const d
 // of length k, the row read in pairs when k is even); the sign that makes the
 // largest-magnitude entry positive (lowest index on ties, as k_sign_fix);
 // A(:, c) in that sign; and W(:, c) = Q U(:, c) lam_c^{1/2} in the same sign.
-// Q is r x k, Dt is s x k; k <= 64.
+// Q is r x k, Dt is s x k; k <= 64.  *bad is set when lam_c is not positive
+// (D of rank below R: no division by its square root is meaningful).
 constexpr int kFinRegs = 16;  // rows per thread kept in registers by k_rsvd_finish
 constexpr int kFinT = 256;
 
 __global__ __launch_bounds__(kFinT) void k_rsvd_finish(const double* Dt, const double* U,
                                                        const double* lam, const double* Q,
                                                        int s, int k, int r, int R, double* A,
-                                                       double* W) {
+                                                       double* W, int* bad) {
   __shared__ double us[64];
   __shared__ double bv[kFinT];
   __shared__ int bi[kFinT];
   __shared__ int bn[kFinT];
   const int c = blockIdx.x, tid = threadIdx.x;
   const double lc = lam[c];
+  if (tid == 0 && !(lc > 0.0)) *bad = 1;
   if (tid < k) us[tid] = U[tid * R + c] / sqrt(lc);
   __syncthreads();
   double best = -1.0;
@@ -1495,8 +1497,9 @@ __global__ __launch_bounds__(kFinT) void k_rsvd_finish(const double* Dt, const d
   }
 }
 
-__global__ void k_scale_inv_sqrt(double* A, int64_t rows, int64_t R, const double* lam) {
+__global__ void k_scale_inv_sqrt(double* A, int64_t rows, int64_t R, const double* lam, int* bad) {
   int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (bad && t < R && !(lam[t] > 0.0)) *bad = 1;
   if (t >= rows * R) return;
   A[t] /= sqrt(lam[t % R]);
 }
@@ -1734,13 +1737,13 @@ tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, hipStream_t st, 
 
 tsk_status rsvd_finish(const double* Dt, const double* U, const double* lam, const double* Q,
                        int64_t s, int64_t k, int64_t r, int64_t R, double* A, double* W,
-                       hipStream_t st) {
+                       int* bad, hipStream_t st) {
   if (k > 64 || s > INT32_MAX / 64) {
     set_error("randomized solve finish supports k <= 64 (k = %lld)", (long long)k);
     return TSK_EUNSUPPORTED;
   }
   hipLaunchKernelGGL(k_rsvd_finish, dim3(R), dim3(kFinT), 0, st, Dt, U, lam, Q, int(s), int(k),
-                     int(r), int(R), A, W);
+                     int(r), int(R), A, W, bad);
   TSK_LAUNCHED();
   return TSK_OK;
 }
@@ -1754,9 +1757,9 @@ tsk_status rsvd_w(const double* Qm, bool q_rows, const double* U, const double* 
 }
 
 tsk_status scale_columns_inv_sqrt(double* A, int64_t rows, int64_t R, const double* lam,
-                                  hipStream_t st) {
+                                  hipStream_t st, int* bad) {
   hipLaunchKernelGGL(k_scale_inv_sqrt, dim3(ceil_div(rows * R, 256)), dim3(256), 0, st, A, rows,
-                     R, lam);
+                     R, lam, bad);
   TSK_LAUNCHED();
   return TSK_OK;
 }

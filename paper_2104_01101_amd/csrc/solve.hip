@@ -50,7 +50,7 @@ tsk_status rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t 
     TSK_TRY(gemm_tn(TSK_PREC_F64, r, r, s, Xt, r, r, nullptr, 0, Xt, r, Mq, r, ws, st));
     TSK_TRY(sym_eig_top(Mq, r, R, lam, U, ws, st));
     TSK_TRY(gemm_nn_f64(s, R, r, Xt, r, U, R, A, R, ws, st));
-    if (run) TSK_TRY(scale_columns_inv_sqrt(A, s, R, lam, st));
+    if (run) TSK_TRY(scale_columns_inv_sqrt(A, s, R, lam, st, info + 3));
   } else {
     if (run) TSK_TRY(transpose_f64(Xt, s, r, X, st));
     TSK_TRY(gemm_tn(TSK_PREC_F64, s, s, r, X, s, s, nullptr, 0, X, s, Mq, s, ws, st));
@@ -109,7 +109,7 @@ tsk_status rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_
       TSK_TRY(gemm_tn(TSK_PREC_F64, k, k, s, Dt, k, k, nullptr, 0, Dt, k, Mk, k, ws, st));
     }
     TSK_TRY(sym_eig_top(Mk, k, R, lam, U, ws, st));
-    if (run) TSK_TRY(rsvd_finish(Dt, U, lam, Q, s, k, r, R, A, W, st));
+    if (run) TSK_TRY(rsvd_finish(Dt, U, lam, Q, s, k, r, R, A, W, info + 3, st));
     return TSK_OK;
   }
   {
@@ -139,7 +139,7 @@ tsk_status rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_
   // factor W = Q U Sigma, both in the column signs that make the largest
   // entry of each column of A positive
   TSK_TRY(sym_eig_top(Mk, k, R, lam, U, ws, st));
-  if (run) TSK_TRY(scale_columns_inv_sqrt(U, k, R, lam, st));
+  if (run) TSK_TRY(scale_columns_inv_sqrt(U, k, R, lam, st, info + 3));
   TSK_TRY(gemm_nn_f64(s, R, k, Dt, k, U, R, A, R, ws, st));
   if (run) TSK_TRY(sign_fix_columns(A, s, R, st, sgn));
   if (run) TSK_TRY(rsvd_w(Qt, false, U, lam, sgn, k, r, R, W, st));

@@ -415,6 +415,35 @@ def test_rsvd_solve_rank_deficient(tsk):
     np.testing.assert_allclose(W.cpu().numpy() @ A.cpu().numpy().T, X, atol=1e-9 * np.abs(X).max())
 
 
+@pytest.mark.parametrize("solver", ["rsvd", "exact"])
+def test_solve_zero_rhs_is_a_breakdown(tsk, solver):
+    """An all-zero right-hand side: every singular value of the subproblem is
+    zero, so A = D^T U Sigma^{-1} is undefined; both solvers report a numerical
+    breakdown rather than non-finite factors."""
+    from paper_2104_01101_amd import _lib as L
+    rs = np.random.default_rng(11)
+    m, r, s, R, k = 200, 36, 60, 3, 13
+    Z = torch.from_numpy(rs.standard_normal((m, r))).to(DEV)
+    Y = torch.zeros((m, s), dtype=torch.float64, device=DEV)
+    with pytest.raises(L.TskError) as e:
+        if solver == "rsvd":
+            tsk.rsvd_solve(Z, Y, R, torch.from_numpy(rs.standard_normal((s, k))).to(DEV))
+        else:
+            tsk.rc_solve(Z, Y, R)
+    assert e.value.status == L.ENUMERIC
+
+
+@pytest.mark.parametrize("solve", ["rsvd", "exact"])
+def test_zero_tensor_is_a_breakdown(tsk, solve):
+    """Sketch-Tucker-ALS on an all-zero tensor from a random start: the first
+    subproblem has a zero right-hand side and the call reports a breakdown."""
+    from paper_2104_01101_amd import _lib as L
+    T = tsk.Tensor.dense(torch.zeros((30, 30, 30), dtype=torch.float64, device=DEV))
+    with pytest.raises(L.TskError) as e:
+        tsk.tucker_sketch_als(T, (4, 4, 4), 200, 2, init="random", prec="f64", solve=solve)
+    assert e.value.status == L.ENUMERIC
+
+
 def test_rsvd_solve_fp32_operands(tsk):
     rs = np.random.default_rng(9)
     m, r, s, R, k = 1600, 100, 2000, 10, 20
