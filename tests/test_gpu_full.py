@@ -20,7 +20,11 @@ Leverage sampling of the COO tensors (fibre indices): the sampled fibres of
 sparse2000 and zipf10k (whose head fibres hold thousands of entries) equal the
 oracle's bit for bit in FP64, and the first three sweeps of the sparse2000
 leverage job (m = 1600 sampled fibres per subproblem, RSVD-LRLS, FP32
-operands) match the oracle within 1e-5."""
+operands) match the oracle within 1e-5.
+
+Deterministic selection at m = 1600 meets a singular sketched Gram in its
+second subproblem (rank 97 of 100 in the oracle); the job reports it although
+every later subproblem is well-conditioned."""
 import numpy as np
 import pytest
 import torch
@@ -152,3 +156,30 @@ def test_sparse2000lev_job_vs_oracle(tsk):
     To = osk.Tensor(w.dims, w.idx, w.val.astype(np.float64))
     ref = otk.sketch_tucker_als(To, w.ranks, w.m, 3, seed=0, sketch_kind="lev", solve_kind="rsvd")
     np.testing.assert_allclose(fits, ref["fits"], rtol=0, atol=1e-5)
+
+
+def test_sparse2000det_k16_breakdown_is_reported(tsk, monkeypatch):
+    """Deterministic selection of m = 16 R^2 rows from the range-finder start:
+    in the oracle, the sketch of the second subproblem (sweep 0, mode 1) has
+    rank below r = 100, so its Gram is singular, and the next one has full
+    rank.  The whole 10-sweep job must still end with a breakdown: the flag of
+    an early singular Gram is not cleared by the factorisations after it."""
+    from oracle import solve as osv
+    from paper_2104_01101_amd import _lib as L
+    w = workloads.sparse2000det(K=16)
+    To = osk.Tensor(w.dims, w.idx, w.val.astype(np.float64))
+    seen = []
+    orig = osv.rsvd_lrls
+
+    def spy(Z, Y, R, Om):
+        seen.append(np.linalg.matrix_rank(Z))
+        return orig(Z, Y, R, Om)
+
+    monkeypatch.setattr(osv, "rsvd_lrls", spy)
+    otk.sketch_tucker_als(To, w.ranks, w.m, 1, seed=0, sketch_kind="lev_det", solve_kind="rsvd")
+    assert seen[1] < 100 and seen[2] == 100, seen
+    T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(DEV), torch.from_numpy(w.val).to(DEV), w.dims)
+    with pytest.raises(L.TskError) as e:
+        tsk.tucker_sketch_als(T, w.ranks, w.m, w.sweeps, sketch="lev_det", init="rrf",
+                              prec=w.prec, seed=0, solve="rsvd")
+    assert e.value.status == L.ENUMERIC
