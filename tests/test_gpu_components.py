@@ -433,14 +433,17 @@ def test_solve_zero_rhs_is_a_breakdown(tsk, solver):
     assert e.value.status == L.ENUMERIC
 
 
+@pytest.mark.parametrize("init", ["random", "rrf"])
 @pytest.mark.parametrize("solve", ["rsvd", "exact"])
-def test_zero_tensor_is_a_breakdown(tsk, solve):
-    """Sketch-Tucker-ALS on an all-zero tensor from a random start: the first
-    subproblem has a zero right-hand side and the call reports a breakdown."""
+def test_zero_tensor_is_a_breakdown(tsk, solve, init):
+    """Sketch-Tucker-ALS on an all-zero tensor: from a random start the first
+    subproblem has a zero right-hand side; from the range-finder start the
+    range finder's B = W G is zero already.  Either way the call reports a
+    breakdown."""
     from paper_2104_01101_amd import _lib as L
     T = tsk.Tensor.dense(torch.zeros((30, 30, 30), dtype=torch.float64, device=DEV))
     with pytest.raises(L.TskError) as e:
-        tsk.tucker_sketch_als(T, (4, 4, 4), 200, 2, init="random", prec="f64", solve=solve)
+        tsk.tucker_sketch_als(T, (4, 4, 4), 200, 2, init=init, prec="f64", solve=solve)
     assert e.value.status == L.ENUMERIC
 
 
