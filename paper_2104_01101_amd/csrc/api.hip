@@ -485,14 +485,15 @@ tsk_status finish_sync(TuckerArgs& a, double* fit_history, int32_t* sweeps_done)
     TSK_HIP(hipMemcpy(fit_history, a.fit_dev, a.opt.sweeps * sizeof(double),
                       hipMemcpyDeviceToHost));
   if (sweeps_done) *sweeps_done = a.opt.sweeps;
-  if (info[0] || info[1] || info[2]) {
-    set_error("numerical breakdown: sketched Gram not positive definite (info %d %d %d)", info[0],
-              info[1], info[2]);
-    return TSK_ENUMERIC;
-  }
-  if (info[3]) {
-    set_error("numerical breakdown: sketched right-hand side of rank below R (a singular value "
-              "of the subproblem is zero)");
+  // info: [0] a sketched Gram's pivot, [1] the QR of a solve's factor, [2] the
+  // initialisation (range finder or QR of the random start), [3] a zero
+  // singular value of a subproblem
+  if (info[0] || info[1] || info[2] || info[3]) {
+    set_error("numerical breakdown: %s%s%s%s",
+              info[0] ? "sketched Gram not positive definite; " : "",
+              info[1] ? "factor QR of a solve failed; " : "",
+              info[2] ? "initialisation failed (zero or rank-deficient range); " : "",
+              info[3] ? "sketched right-hand side of rank below R; " : "");
     return TSK_ENUMERIC;
   }
   return TSK_OK;

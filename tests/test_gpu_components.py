@@ -445,6 +445,7 @@ def test_zero_tensor_is_a_breakdown(tsk, solve, init):
     with pytest.raises(L.TskError) as e:
         tsk.tucker_sketch_als(T, (4, 4, 4), 200, 2, init=init, prec="f64", solve=solve)
     assert e.value.status == L.ENUMERIC
+    assert ("initialisation" if init == "rrf" else "rank below R") in str(e.value), e.value
 
 
 def test_rsvd_solve_fp32_operands(tsk):
