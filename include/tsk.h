@@ -267,7 +267,9 @@ tsk_status tsk_rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, in
  * N(0, 1/k1) (stream (seed, 3, n)), B = W G, A = leading R left singular
  * vectors of B (sign rule as above).
  *   A  device double dims[n] x R (output).  Requires R <= k1.
- * Synchronous: waits for the stream to check the factorisation status. */
+ * Synchronous: waits for the stream to check the factorisation status; ENUMERIC if
+ * one of the R leading eigenvalues of B^T B is not positive (a sketched range of rank
+ * below R, e.g. an all-zero tensor) or the QR of the result fails. */
 tsk_status tsk_rrf_init(const tsk_tensor* T, int32_t n, int32_t R, int32_t k1, int32_t k2,
                         uint64_t seed, double* A, void* ws, size_t* ws_bytes,
                         void* stream);
