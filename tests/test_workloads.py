@@ -60,3 +60,25 @@ def test_tensor4_coherent_entries():
     assert idx.shape[0] <= idx4.shape[0] <= idx.shape[0] + 10
     np.testing.assert_allclose(np.linalg.norm(val4) ** 2,
                                np.linalg.norm(val) ** 2 * 2, rtol=0.05)
+
+
+def test_sparse2000det_first_sweep_sketches_full_rank(monkeypatch):
+    """The deterministic-selection workload keeps m = 24 R^2 rows so that the
+    selected sketch Z of every subproblem spans all r = 100 directions (its Gram
+    is then invertible, as RSVD-LRLS requires); checked in the oracle over the
+    first sweep from the range-finder start."""
+    from oracle import sketch as osk, solve as osv, tucker as otk
+    w = W.sparse2000det()
+    assert w.m == 24 * w.ranks[0] ** 2
+    To = osk.Tensor(w.dims, w.idx, w.val.astype(np.float64))
+    ranks = []
+    orig = osv.rsvd_lrls
+
+    def spy(Z, Y, R, Om):
+        ranks.append(np.linalg.matrix_rank(Z))
+        return orig(Z, Y, R, Om)
+
+    monkeypatch.setattr(osv, "rsvd_lrls", spy)
+    otk.sketch_tucker_als(To, w.ranks, w.m, 1, seed=0, sketch_kind="lev_det", solve_kind="rsvd",
+                          record_fit=False)
+    assert ranks == [100, 100, 100]
