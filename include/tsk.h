@@ -50,7 +50,7 @@ extern "C" {
 typedef enum {
   TSK_OK = 0,
   TSK_EINVAL = -1,       /* invalid argument (message says which) */
-  TSK_EUNSUPPORTED = -2, /* valid but not supported by this build */
+  TSK_EUNSUPPORTED = -2, /* valid but not supported by this library */
   TSK_ENOMEM = -3,       /* workspace too small */
   TSK_EHIP = -4,         /* HIP runtime / kernel launch failure */
   TSK_ENUMERIC = -5      /* numerical breakdown: a Gram pivot or a singular value not positive */
