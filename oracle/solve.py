@@ -38,21 +38,19 @@ def rc_solve(Z, Y, R):
 
 
 def rsvd_lrls(Z, Y, R, Omega):
-    """RSVD-LRLS (Alg. 5): low-rank approximation of the LS solution by a
-    randomized SVD with the given Gaussian test matrix Omega (s x (R+p)).
+    """RSVD-LRLS (Alg. 5): the randomized SVD, with the given Gaussian test
+    matrix Omega (s x k, k = R + p), of the least-squares solution X = Z^+ Y.
 
-        B = (Z^T Z)^{-1};  C = B Z^T Y Omega;  Q, _ = qr(C);  D = Q^T B Z^T Y;
-        U, Sigma, V = svd(D);  return Q U[:, :R] Sigma[:R], V[:, :R]
+    The range of X is captured by an orthonormal basis Q of X Omega; the SVD of
+    the small k x s matrix Q^T X gives the approximate leading singular triplets
+    of X: X ~ (Q U) Sigma V^T.  A^(n) = V_R (sign rule) and C_(n)^T = Q U_R Sigma_R.
 
     Returns (A = V[:, :R] sign-fixed, W = Q U_R Sigma_R with matching signs)."""
     Z = np.asarray(Z, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
-    B = np.linalg.inv(Z.T @ Z)
-    ZtY = Z.T @ Y
-    C = B @ ZtY @ Omega
-    Q, _ = np.linalg.qr(C)
-    D = Q.T @ B @ ZtY
-    U, S, Vt = np.linalg.svd(D, full_matrices=False)
-    A, s = sign_fix(Vt[:R].T)
-    W = (Q @ U[:, :R]) * S[:R][None, :] * s[None, :]
+    X = np.linalg.lstsq(Z, Y, rcond=None)[0]                   # Z^+ Y, r x s
+    Q = np.linalg.qr(X @ Omega)[0]                             # basis of range(X Omega)
+    U, S, Vt = np.linalg.svd(Q.T @ X, full_matrices=False)
+    A, sgn = sign_fix(Vt[:R].T)
+    W = (Q @ U[:, :R]) * (S[:R] * sgn)[None, :]
     return A, W

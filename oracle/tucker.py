@@ -77,8 +77,9 @@ def relative_residual(T, C, factors):
 # initialisations
 # ----------------------------------------------------------------------------
 def init_rrf(T, n, R, k1, k2, seed):
-    """Init-RRF (Alg. 3) on M = T_(n) with the composite sketch S = Omega_cs^T G:
-    B = M S;  U, Sigma, V = svd(B);  return U[:, :R] (sign-fixed)."""
+    """Init-RRF (Alg. 3) of mode n: the leading R left singular vectors
+    (sign-fixed) of T_(n) sketched from the right by the composite sketch of
+    Sec. 5 (a CountSketch to k2 columns followed by a k2 x k1 Gaussian map)."""
     Wcs = sketch.rrf_countsketch(T, n, k2, seed)
     G = sketch.rrf_gaussian(n, k1, k2, seed)
     B = Wcs @ G
@@ -155,7 +156,7 @@ def sketch_tucker_als(T, ranks, m, sweeps, seed=0, sketch_kind="ts", init="rrf",
     N = T.order
     dims = T.dims
     factors = [None] * N
-    # Alg. 4: C <- 0; A^(n) <- Init-RRF(T_(n), R_n, eps) for n = 2..N
+    # Alg. 4 initialises modes 2..N (zero-based 1..N-1) before the first sweep
     if init == "user":
         factors = [np.array(A, dtype=np.float64) for A in init_factors]
     else:

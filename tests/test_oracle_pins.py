@@ -542,3 +542,120 @@ def test_driver_resumes_at_a_sweep():
         assert full["fits"][1] == rest["fits"][0]
         for a, b in zip(full["factors"], rest["factors"]):
             assert np.array_equal(a, b)
+
+
+# ----------------------------------------------------------------------------
+# HOSVD, random initialisation, COO semantics, CP fit on COO tensors
+# ----------------------------------------------------------------------------
+def _exact_tucker(dims, ranks, seed):
+    """C x_1 Q1 ... x_N QN with orthonormal Q_n and a core whose mode-n
+    unfoldings have well separated singular values (a diagonal-dominant core)."""
+    rs = np.random.default_rng(seed)
+    Qs = [np.linalg.qr(rs.standard_normal((s, R)))[0] for s, R in zip(dims, ranks)]
+    C = 0.05 * rs.standard_normal(ranks)
+    for t in range(min(ranks)):
+        C[(t,) * len(ranks)] = 10.0 * 0.5 ** t     # singular values 10, 5, 2.5, ...
+    X = C
+    for k, Q in enumerate(Qs):
+        X = np.moveaxis(np.tensordot(Q, X, axes=(1, k)), 0, k)
+    return X, Qs
+
+
+def test_hosvd_left_singular_vectors_of_unfoldings():
+    """HOSVD (Sec. 2.2, the initialisation of Alg. 1 and of the CP step of Alg. 6):
+    A^(n) spans the column space of X_(n) and its columns are the left singular
+    vectors in order of decreasing singular value.  Checked through the
+    eigen-decomposition of X_(n) X_(n)^T (a different LAPACK route), and on an
+    exact Tucker tensor whose factors are known."""
+    dims, ranks = (9, 7, 5), (3, 3, 2)
+    X, Qs = _exact_tucker(dims, ranks, 11)
+    A = tucker.hosvd(X, ranks)
+    for n in range(3):
+        assert A[n].shape == (dims[n], ranks[n])               # left, not right, vectors
+        np.testing.assert_allclose(A[n].T @ A[n], np.eye(ranks[n]), atol=1e-13)
+        # exact column space of the known factor
+        cos = np.linalg.svd(A[n].T @ Qs[n], compute_uv=False)
+        np.testing.assert_allclose(cos, 1.0, atol=1e-12)
+        # eigenvectors of X_(n) X_(n)^T, descending, sign rule applied by hand
+        M = tucker.unfold(X, n)
+        lam, V = np.linalg.eigh(M @ M.T)
+        V = V[:, ::-1][:, :ranks[n]]
+        for c in range(ranks[n]):
+            p = int(np.argmax(np.abs(V[:, c])))
+            V[:, c] *= np.sign(V[p, c])
+        np.testing.assert_allclose(A[n], V, atol=1e-10)
+        # column c carries the c-th largest singular value
+        norms = np.linalg.norm(M.T @ A[n], axis=0)
+        np.testing.assert_allclose(norms, np.sqrt(lam[::-1][:ranks[n]]), rtol=1e-12)
+        assert np.all(np.diff(norms) < 0)
+
+
+def test_hosvd_catches_transposed_or_unsorted_variants():
+    """A right-singular-vector or unsorted variant of the HOSVD fails the checks
+    above (the test would catch the plausible mistakes)."""
+    dims, ranks = (9, 7, 5), (3, 3, 2)
+    X, Qs = _exact_tucker(dims, ranks, 12)
+    M = tucker.unfold(X, 0)
+    _, _, Vt = np.linalg.svd(M, full_matrices=False)
+    assert Vt[:3].T.shape != (dims[0], ranks[0])               # right vectors: wrong shape
+    U = np.linalg.svd(M, full_matrices=False)[0][:, :3]
+    norms = np.linalg.norm(M.T @ U[:, ::-1], axis=0)
+    assert not np.all(np.diff(norms) < 0)                      # reversed order detected
+
+
+def test_init_random_orthonormal_signed_gaussian_span():
+    """Random initialisation (Gaussian then QR, reading of the paper's random
+    start): orthonormal columns, the sign rule, and the column space of the
+    (seed, INIT, n) Gaussian draw."""
+    s, R, n, seed = 23, 4, 2, 9
+    A = tucker.init_random(s, R, n, seed)
+    np.testing.assert_allclose(A.T @ A, np.eye(R), atol=1e-14)
+    for c in range(R):
+        p = int(np.argmax(np.abs(A[:, c])))
+        assert A[p, c] > 0
+        assert np.all(np.abs(A[:, c]) <= A[p, c])
+    G = rng.gauss(rng.stream_key(seed, rng.P_INIT, n), np.arange(s * R)).reshape(s, R)
+    np.testing.assert_allclose(A @ (A.T @ G), G, atol=1e-12)   # same column space
+    # Gram-Schmidt order: the first column is the normalised first Gaussian column
+    g0 = G[:, 0] / np.linalg.norm(G[:, 0])
+    assert abs(abs(A[:, 0] @ g0) - 1.0) < 1e-14
+    # different n or seed: a different draw
+    assert not np.allclose(A, tucker.init_random(s, R, n + 1, seed))
+
+
+def test_coalesced_sums_duplicates_hand_worked():
+    """COO semantics (duplicates add): a hand-worked example."""
+    idx = np.array([[1, 0, 2], [0, 1, 1], [1, 0, 2], [2, 2, 0], [0, 1, 1], [1, 0, 2]])
+    val = np.array([1.0, 2.0, 10.0, -3.0, 0.5, 100.0])
+    T = sketch.Tensor((3, 3, 3), idx, val)
+    c = T.coalesced()
+    got = {tuple(int(x) for x in i): v for i, v in zip(c.idx, c.val)}
+    assert got == {(0, 1, 1): 2.5, (1, 0, 2): 111.0, (2, 2, 0): -3.0}
+    assert T.norm2() == 2.5 ** 2 + 111.0 ** 2 + 9.0
+    D = T.to_dense()
+    assert D[1, 0, 2] == 111.0 and D[0, 1, 1] == 2.5 and np.count_nonzero(D) == 3
+
+
+def test_cp_relative_residual_coo_equals_dense():
+    """CP fit (Sec. 7): the COO formula ||T||^2 - 2<T, T~> + ||T~||^2 equals the
+    dense definition on a tensor stored with duplicate coordinates."""
+    rs = np.random.default_rng(13)
+    dims, R = (6, 5, 4), 3
+    idx = np.stack([rs.integers(0, d, 80) for d in dims], axis=1)
+    idx = np.concatenate([idx, idx[:25]])                      # 25 duplicates
+    val = rs.standard_normal(idx.shape[0])
+    Tcoo = sketch.Tensor(dims, idx, val)
+    D = np.zeros(dims)
+    for i, v in zip(idx, val):                                 # plain loop, duplicates add
+        D[tuple(i)] += v
+    Td = sketch.Tensor.from_dense(D)
+    facs = [rs.standard_normal((d, R)) for d in dims]
+    want = np.linalg.norm(D - cp.cp_reconstruct(facs)) / np.linalg.norm(D)
+    assert abs(cp.cp_relative_residual(Tcoo, facs) - want) < 1e-12
+    assert abs(cp.cp_relative_residual(Td, facs) - want) < 1e-12
+    # the exact CP tensor stored as COO with split duplicates has residual 0
+    Dx = cp.cp_reconstruct(facs)
+    full = np.stack(np.unravel_index(np.arange(Dx.size), dims), axis=1)
+    halves = sketch.Tensor(dims, np.concatenate([full, full]),
+                           np.concatenate([0.25 * Dx.reshape(-1), 0.75 * Dx.reshape(-1)]))
+    assert cp.cp_relative_residual(halves, facs) < 1e-7
