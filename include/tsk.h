@@ -45,7 +45,7 @@ extern "C" {
 #endif
 
 #define TSK_MAX_ORDER 8
-#define TSK_ABI_VERSION 4
+#define TSK_ABI_VERSION 5
 
 typedef enum {
   TSK_OK = 0,
@@ -71,7 +71,13 @@ typedef enum { TSK_PREC_F64 = 0, TSK_PREC_F32 = 1, TSK_PREC_BF16 = 2 } tsk_prec;
  * SVD), or RSVD-LRLS (Alg. 5), the randomized solver that Alg. 4 calls. */
 typedef enum { TSK_SOLVE_EXACT = 0, TSK_SOLVE_RSVD = 1 } tsk_solve;
 
-#define TSK_FLAG_RECORD_FIT 1u /* evaluate the relative residual after every sweep */
+/* Relative residual (Sec. 7 fitness, evaluation only: not a step of Alg. 4).
+ * RECORD_FIT: after every sweep; FINAL_FIT: after the last sweep only (the
+ * earlier entries of fit_history are set to NaN).  FINAL_FIT wins when both are
+ * set.  The sign rule on the factors (largest-magnitude entry of each column
+ * positive) is always applied; there is no flag for it. */
+#define TSK_FLAG_RECORD_FIT 1u
+#define TSK_FLAG_FINAL_FIT 2u
 
 /* An order-N tensor.  DENSE: `values` holds prod(dims) entries, row-major.
  * COO: `values` holds nnz entries and idx[k][e] (int32, 0-based) is the mode-k
@@ -106,6 +112,17 @@ typedef struct {
   uint32_t flags; /* TSK_FLAG_* */
   int32_t solve;  /* tsk_solve */
   int32_t rsvd_k; /* RSVD-LRLS test-matrix columns, O(R) in Alg. 5; 0 = min(R_n + 10, r) */
+  /* Absolute index of the first sweep.  The per-sweep random streams (leverage
+   * samples, RSVD test matrices) are keyed by the absolute sweep, so a run with
+   * init = USER from the factors after sweep i and first_sweep = i + 1 continues
+   * that run exactly (checkpoint / resume of the sweep loop of Alg. 4). */
+  int32_t first_sweep;
+  /* Convergence test of the sweep loop (the "until converged" of Alg. 1; Alg. 4
+   * fixes I_max = sweeps): stop after sweep i >= 1 when
+   * |residual_i - residual_{i-1}| < tol.  0 = run all sweeps.  tol > 0 needs
+   * TSK_FLAG_RECORD_FIT (and not FINAL_FIT) and synchronises the stream once per
+   * sweep. */
+  double tol;
 } tsk_options;
 
 /* ---------------------------------------------------------------------- */
@@ -126,7 +143,10 @@ uint64_t tsk_draw(uint64_t key, uint64_t counter);
 /* Launch timing for measurement.  tsk_profile_enable(name) makes the library
  * record HIP events on the launching stream around every launch group called
  * `name` ("sketch_pass", "rrf_pass", "gram", "ts_lhs", "solve_la", "eig", "fit", "rrf",
- * "leverage", "cp_core", "adjoint"; a comma-separated list selects several;
+ * "leverage", "cp_core", "adjoint"; the driver's phases "phase_prep" (maps and
+ * sketched right-hand sides), "phase_init" (initialisation), "phase_sweeps"
+ * (one per sweep, the subproblems only) and "phase_fit"; a comma-separated list
+ * selects several;
  * "*" = all; NULL or "" = off, the default)
  * and clears earlier records.  tsk_profile_read(name) waits for the recorded
  * events and returns the summed milliseconds and the number of groups (name
@@ -163,8 +183,11 @@ tsk_status tsk_workspace_size(const tsk_tensor* T, const int32_t* ranks,
  *               orthonormal columns, the entry of largest magnitude of each
  *               column positive (output; input too when init = USER)
  *   fit_history host double[sweeps] or NULL: ||T - T~||_F / ||T||_F after each
- *               sweep (needs TSK_FLAG_RECORD_FIT)
- *   sweeps_done host int32 or NULL
+ *               sweep (TSK_FLAG_RECORD_FIT) or after the last one
+ *               (TSK_FLAG_FINAL_FIT, the others NaN); index i is the i-th sweep
+ *               of this call (absolute sweep first_sweep + i)
+ *   sweeps_done host int32 or NULL: sweeps run (fewer than opt->sweeps when
+ *               opt->tol stopped the loop)
  * Synchronous.  Errors: EINVAL (shapes, m < prod_{k != n} R_k, sizes),
  * EUNSUPPORTED (prod s_k > 2^64 for leverage sampling of a COO tensor), ENOMEM (workspace),
  * ENUMERIC (a sketched Gram not positive definite, or a subproblem whose sketched
@@ -247,11 +270,16 @@ tsk_status tsk_rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int6
                         size_t* ws_bytes, void* stream);
 
 /* RSVD-LRLS (Alg. 5), the randomized low-rank least-squares solve of Alg. 4:
- * B = (Z^T Z)^{-1}, C = B Z^T Y Omega, Q = qr(C) (thin, Householder),
- * D = Q^T B Z^T Y, U S V^T = svd(D); A = V(:, :R) (re-orthonormalised, sign
- * rule as above), W = Q U(:, :R) S(:R, :R) with the signs of A.  Omega is the
- * caller's s x k Gaussian test matrix (the driver draws it from the stream
- * (seed, 6, sweep, n), row-major).  All FP64 after the Gram products.
+ * the randomized SVD, with the caller's s x k Gaussian test matrix Omega (the
+ * driver draws it from the stream (seed, 6, sweep, n), row-major), of the
+ * least-squares solution X = (Z^T Z)^{-1} Z^T Y: Q = thin Householder QR basis
+ * of X Omega, D = Q^T X (k x s), U S V^T = svd(D); A = V(:, :R) (sign rule as
+ * above), W = Q U(:, :R) S(:R, :R) with the signs of A.  The products with Y are
+ * ordered for the O(m s k) cost of Sec. 6: Y Omega and Y^T (Z B Q) when s is
+ * large against r, else Z^T Y once.  The SVD of D comes from the eigenpairs of
+ * D D^T, so the columns of A are orthonormal to O(u kappa(D)^2) (u the FP64 unit
+ * roundoff, kappa(D) = sigma_1 / sigma_R) and are not re-orthonormalised.  All
+ * FP64 after the products with Z and Y.
  *   Z, Y   device, as tsk_rc_solve;  Omega device double s x k, R <= k <= min(r, 64)
  *   A  device double s x R (output);  W device double r x R (output)
  * Synchronous (checks the factorisation status); ENUMERIC if the Gram is not

@@ -77,7 +77,7 @@ class Tensor:
 
 
 def _options(m, sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, record_fit, solve="exact",
-             rsvd_k=0):
+             rsvd_k=0, first_sweep=0, tol=0.0):
     o = L._Options()
     o.sketch = L.SKETCH[sketch]
     o.m = int(m)
@@ -87,21 +87,29 @@ def _options(m, sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, record_fit, so
     o.prec = L.PREC[prec]
     o.seed = int(seed)
     o.stream = L.stream_ptr()
-    o.flags = L.FLAG_RECORD_FIT if record_fit else 0
+    o.flags = (L.FLAG_FINAL_FIT if record_fit == "final"
+               else L.FLAG_RECORD_FIT if record_fit else 0)
     o.solve = L.SOLVE[solve]
     o.rsvd_k = int(rsvd_k)
+    o.first_sweep = int(first_sweep)
+    o.tol = float(tol)
     return o
 
 
 class TuckerPlan:
     """Pre-allocated outputs and workspace for repeated calls with one shape
-    (keeps allocation out of timed loops)."""
+    (keeps allocation out of timed loops).  record_fit: True (residual after
+    every sweep), "final" (after the last sweep only; earlier entries NaN) or
+    False.  first_sweep: absolute index of the first sweep (resume, with
+    init="user"); tol: stop when the residual changes by less (needs
+    record_fit=True)."""
 
     def __init__(self, T, ranks, m, sweeps, sketch="ts", init="rrf", prec="f32", seed=0,
-                 rrf_k1=0, rrf_k2=0, record_fit=True, solve="exact", rsvd_k=0):
+                 rrf_k1=0, rrf_k2=0, record_fit=True, solve="exact", rsvd_k=0, first_sweep=0,
+                 tol=0.0):
         self.T, self.ranks = T, tuple(int(r) for r in ranks)
         self.opt = _options(m, sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, record_fit,
-                            solve, rsvd_k)
+                            solve, rsvd_k, first_sweep, tol)
         self.ct = T.c_struct()
         self.cr = L.i32_array(self.ranks)
         nb = ctypes.c_size_t(0)
@@ -127,19 +135,20 @@ class TuckerPlan:
             ctypes.byref(self.ct), self.cr, ctypes.byref(self.opt), L.ptr(self.core),
             L.ptr_array(self.factors), self.fits if self.record_fit else None,
             ctypes.byref(done)))
-        fits = list(self.fits)[:self.sweeps] if self.record_fit else []
+        self.sweeps_done = done.value
+        fits = list(self.fits)[:done.value] if self.record_fit else []
         return self.core, self.factors, fits
 
 
 def tucker_sketch_als(T, ranks, m, sweeps, sketch="ts", init="rrf", prec="f32", seed=0,
                       rrf_k1=0, rrf_k2=0, record_fit=True, init_factors=None, solve="exact",
-                      rsvd_k=0):
+                      rsvd_k=0, first_sweep=0, tol=0.0):
     """Sketch-Tucker-ALS (Alg. 4).  Returns (core, factors, fits) -- FP64 device
     tensors and the per-sweep relative residuals.  solve = "exact" (truncated
     SVD of Z^+ Y) or "rsvd" (RSVD-LRLS, Alg. 5, rsvd_k test-matrix columns,
     0 = min(R + 10, r))."""
     plan = TuckerPlan(T, ranks, m, sweeps, sketch, init, prec, seed, rrf_k1, rrf_k2, record_fit,
-                      solve, rsvd_k)
+                      solve, rsvd_k, first_sweep, tol)
     return plan.run(init_factors)
 
 

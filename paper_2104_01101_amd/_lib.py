@@ -18,6 +18,7 @@ INIT = {"rrf": 0, "random": 1, "user": 2}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 SOLVE = {"exact": 0, "rsvd": 1}
 FLAG_RECORD_FIT = 1
+FLAG_FINAL_FIT = 2
 
 
 class TskError(RuntimeError):
@@ -40,7 +41,8 @@ class _Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("flags", ctypes.c_uint32), ("solve", ctypes.c_int32),
-                ("rsvd_k", ctypes.c_int32)]
+                ("rsvd_k", ctypes.c_int32), ("first_sweep", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
 
 
 _lib = None

@@ -174,6 +174,7 @@ struct TuckerArgs {
   // results of the run (device pointers into the workspace)
   double* fit_dev = nullptr;
   int* info_dev = nullptr;
+  int sweeps_done = 0;
 };
 
 // columns of the RSVD-LRLS test matrix: O(R) in Alg. 5, R + 10 by default
@@ -190,6 +191,12 @@ tsk_status validate_options(const TensorView& T, const int64_t* R, const tsk_opt
   TSK_REQUIRE(opt->prec >= TSK_PREC_F64 && opt->prec <= TSK_PREC_BF16, "unknown precision %d",
               opt->prec);
   TSK_REQUIRE(opt->sweeps >= 0, "sweeps = %d < 0", opt->sweeps);
+  TSK_REQUIRE(opt->first_sweep >= 0, "first_sweep = %d < 0", opt->first_sweep);
+  TSK_REQUIRE(opt->tol >= 0.0, "tol = %g < 0", opt->tol);
+  TSK_REQUIRE(opt->tol == 0.0 || ((opt->flags & TSK_FLAG_RECORD_FIT) &&
+                                  !(opt->flags & TSK_FLAG_FINAL_FIT)),
+              "tol > 0 needs the residual of every sweep (TSK_FLAG_RECORD_FIT without "
+              "TSK_FLAG_FINAL_FIT)");
   TSK_REQUIRE(opt->solve == TSK_SOLVE_EXACT || opt->solve == TSK_SOLVE_RSVD, "unknown solve %d",
               opt->solve);
   TSK_REQUIRE(opt->rsvd_k >= 0, "rsvd_k = %d < 0", opt->rsvd_k);
@@ -231,7 +238,9 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
   const int prec = o.prec;
   const bool run = !ws.measuring();
   const bool ts = o.sketch == TSK_SKETCH_TS;
-  const bool record = (o.flags & TSK_FLAG_RECORD_FIT) != 0;
+  const bool record = (o.flags & (TSK_FLAG_RECORD_FIT | TSK_FLAG_FINAL_FIT)) != 0;
+  const bool final_only = (o.flags & TSK_FLAG_FINAL_FIT) != 0;
+  const int sw0 = o.first_sweep;  // absolute index of the first sweep (per-sweep streams)
   hipStream_t st = as_stream(o.stream);
 
   int64_t rmax = 0, smax = 0, Rmax = 0;
@@ -320,8 +329,10 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
     ws.off = mark;
   };
 
-  // ---- preparation: maps, sketched right-hand sides, range finder ----
+  // ---- preparation: maps, sketched right-hand sides (Sec. 6.1) ----
   if (run) TSK_HIP(hipMemsetAsync(a.info_dev, 0, 4 * sizeof(int), st));
+  {
+  ProfScope phase(run ? "phase_prep" : "", st);
   if (ts) {  // maps and their inverse tables, batched when every table fits in LDS
     bool batch = true;
     for (int k = 0; k < N; ++k) batch = batch && table_batch_fits(T.dims[k], m);
@@ -361,6 +372,14 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
     TSK_TRY(sketch_pass(T, jobs.data(), int(jobs.size()), ws, st));
     release();
   }
+  if (ts && run)
+    for (int n = 0; n < N; ++n)
+      if (Yp[n] != Yt[n])
+        TSK_TRY(convert_tensor_to_prec(Yt[n], T.dtype, m * T.dims[n], Yp[n], prec, st));
+  }
+  // ---- initialisation of modes 2..N (Alg. 3, or a random orthonormal start) ----
+  {
+  ProfScope phase(run ? "phase_init" : "", st);
   if (o.init == TSK_INIT_RRF) {  // range-finder CountSketches of modes 2..N: one more pass
     std::vector<PassJob> jobs;
     for (int n = 1; n < N; ++n)
@@ -370,10 +389,6 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
     TSK_TRY(sketch_pass(T, jobs.data(), int(jobs.size()), ws, st));
     release();
   }
-  if (ts && run)
-    for (int n = 0; n < N; ++n)
-      if (Yp[n] != Yt[n])
-        TSK_TRY(convert_tensor_to_prec(Yt[n], T.dtype, m * T.dims[n], Yp[n], prec, st));
   if (o.init == TSK_INIT_RRF) {
     for (int n = 1; n < N; ++n) {
       TSK_TRY(rrf_finish(T, n, a.R[n], o.seed, rrf[n], a.factors[n], a.info_dev + 2, ws, st));
@@ -389,12 +404,13 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
       release();
     }
   }
+  }
 
   if (run && !Om_all.empty()) {  // Gaussian test matrices of every (sweep, n), batched
     GaussBatch gb{};
     for (int sw = 0; sw < o.sweeps; ++sw)
       for (int n = 0; n < N; ++n) {
-        gb.key[gb.n] = stream_key(o.seed, kRSVD, sw, n);
+        gb.key[gb.n] = stream_key(o.seed, kRSVD, sw0 + sw, n);
         gb.count[gb.n] =
             T.dims[n] * rsvd_width(o.rsvd_k, a.R[n], prod_except(a.R, N, n));
         gb.out[gb.n] = Om_all[size_t(sw) * N + n];
@@ -413,6 +429,7 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
     return p;
   }();
   for (int sweep = 0; sweep < o.sweeps; ++sweep) {
+    ProfScope phase(run ? "phase_sweeps" : "", st);
     for (int n = 0; n < N; ++n) {
       const int64_t r = prod_except(a.R, N, n);
       const void* Y = nullptr;
@@ -429,7 +446,7 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
         if (det) {
           TSK_TRY(select_rows(N, T.dims, a.R, n, sel[n], a.factors, lev_idx, lev_w, ws, st));
         } else {
-          TSK_TRY(leverage_sample(N, T.dims, a.R, n, m, o.seed, sweep, a.factors, lev_idx,
+          TSK_TRY(leverage_sample(N, T.dims, a.R, n, m, o.seed, sw0 + sweep, a.factors, lev_idx,
                                   lev_w, ws, st, prec, Z));
         }
         if (run) {
@@ -447,7 +464,8 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
         const int64_t k = rsvd_width(o.rsvd_k, a.R[n], r);
         double* Om_n = Om_all.empty() ? Om : Om_all[size_t(sweep) * N + n];
         if (run && Om_all.empty())
-          TSK_TRY(launch_gauss(stream_key(o.seed, kRSVD, sweep, n), T.dims[n] * k, 1.0, Om, st));
+          TSK_TRY(launch_gauss(stream_key(o.seed, kRSVD, sw0 + sweep, n), T.dims[n] * k, 1.0, Om,
+                               st));
         TSK_TRY(rsvd_solve(Z, Y, m, r, T.dims[n], int(a.R[n]), prec, Om_n, k, a.factors[n], W,
                            a.info_dev, ws, st));
       } else {
@@ -458,9 +476,19 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
     }
     if (run && a.core)
       TSK_HIP(hipMemcpyAsync(a.core, W, csize * sizeof(double), hipMemcpyDeviceToDevice, st));
-    if (record) {
-      TSK_TRY(fit_run(T, a.R, a.core, a.factors, sweep == 0, fs, a.fit_dev + sweep, ws, st));
+    phase.end();
+    if (record && (!final_only || sweep == o.sweeps - 1)) {
+      ProfScope prof(run ? "phase_fit" : "", st);
+      TSK_TRY(fit_run(T, a.R, a.core, a.factors, sweep == 0 || final_only, fs,
+                      a.fit_dev + sweep, ws, st));
       release();
+    }
+    a.sweeps_done = sweep + 1;
+    if (run && o.tol > 0.0 && sweep >= 1) {  // optional stop: |fit_i - fit_{i-1}| < tol
+      double f[2];
+      TSK_HIP(hipMemcpyAsync(f, a.fit_dev + sweep - 1, sizeof(f), hipMemcpyDeviceToHost, st));
+      TSK_HIP(hipStreamSynchronize(st));
+      if (std::fabs(f[1] - f[0]) < o.tol) break;
     }
   }
   ws.off = peak;
@@ -481,10 +509,17 @@ tsk_status finish_sync(TuckerArgs& a, double* fit_history, int32_t* sweeps_done)
   TSK_HIP(hipStreamSynchronize(st));
   int info[4] = {0, 0, 0, 0};
   TSK_HIP(hipMemcpy(info, a.info_dev, sizeof(info), hipMemcpyDeviceToHost));
-  if (fit_history && (a.opt.flags & TSK_FLAG_RECORD_FIT) && a.opt.sweeps > 0)
-    TSK_HIP(hipMemcpy(fit_history, a.fit_dev, a.opt.sweeps * sizeof(double),
-                      hipMemcpyDeviceToHost));
-  if (sweeps_done) *sweeps_done = a.opt.sweeps;
+  if (fit_history && a.sweeps_done > 0) {
+    if (a.opt.flags & TSK_FLAG_FINAL_FIT) {  // only the last sweep was evaluated
+      for (int i = 0; i < a.opt.sweeps; ++i) fit_history[i] = NAN;
+      TSK_HIP(hipMemcpy(fit_history + a.sweeps_done - 1, a.fit_dev + a.sweeps_done - 1,
+                        sizeof(double), hipMemcpyDeviceToHost));
+    } else if (a.opt.flags & TSK_FLAG_RECORD_FIT) {
+      TSK_HIP(hipMemcpy(fit_history, a.fit_dev, a.sweeps_done * sizeof(double),
+                        hipMemcpyDeviceToHost));
+    }
+  }
+  if (sweeps_done) *sweeps_done = a.sweeps_done;
   // info: [0] a sketched Gram's pivot, [1] the QR of a solve's factor, [2] the
   // initialisation (range finder or QR of the random start), [3] a zero
   // singular value of a subproblem

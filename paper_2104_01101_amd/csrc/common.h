@@ -173,7 +173,8 @@ hipStream_t as_stream(void* s);
 class ProfScope {
  public:
   ProfScope(const char* name, hipStream_t st);
-  ~ProfScope();
+  ~ProfScope() { end(); }
+  void end();  // record the closing event now (idempotent)
   ProfScope(const ProfScope&) = delete;
   ProfScope& operator=(const ProfScope&) = delete;
 

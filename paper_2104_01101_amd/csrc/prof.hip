@@ -56,10 +56,11 @@ ProfScope::ProfScope(const char* name, hipStream_t st) : st_(st), idx_(-1) {
   idx_ = int(g_recs.size()) - 1;
 }
 
-ProfScope::~ProfScope() {
+void ProfScope::end() {
   if (idx_ < 0) return;
   std::lock_guard<std::mutex> lk(g_mu);
   (void)hipEventRecord(g_recs[idx_].b, st_);
+  idx_ = -1;
 }
 
 }  // namespace tsk

@@ -30,10 +30,39 @@ def test_header_symbols_exported():
 
 
 def test_abi_version():
-    """Version 2: the options struct gained the subproblem solver (solve, rsvd_k)."""
+    """Version 5: the options struct gained first_sweep and tol (resume and
+    convergence test of the sweep loop) and the FINAL_FIT flag."""
     L = _lib()
-    assert L.lib().tsk_abi_version() == 4
-    assert L._Options.solve.offset == 76 and L._Options.rsvd_k.offset == 80
+    assert L.lib().tsk_abi_version() == 5
+
+
+def test_options_layout_matches_header(tmp_path):
+    """The ctypes mirror of tsk_options and tsk_tensor has the C compiler's
+    offsets and sizes (a C program built against include/tsk.h prints them)."""
+    import shutil
+    import subprocess
+    L = _lib()
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    opt_fields = [f for f, _ in L._Options._fields_]
+    ten_fields = [f for f, _ in L._Tensor._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"',
+           'int main(void) {',
+           '  printf("%zu %zu\\n", sizeof(tsk_options), sizeof(tsk_tensor));']
+    src += [f'  printf("%zu\\n", offsetof(tsk_options, {f}));' for f in opt_fields]
+    src += [f'  printf("%zu\\n", offsetof(tsk_tensor, {f}));' for f in ten_fields]
+    src += ['  return 0;', '}']
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    sizes, offs = [int(v) for v in out[:2]], [int(v) for v in out[2:]]
+    assert sizes == [ctypes.sizeof(L._Options), ctypes.sizeof(L._Tensor)]
+    want = [getattr(L._Options, f).offset for f in opt_fields] + \
+        [getattr(L._Tensor, f).offset for f in ten_fields]
+    assert offs == want
 
 
 def test_generator_matches_oracle_spec():
@@ -63,6 +92,26 @@ def _opts(L, m, sketch=0, solve=0, rsvd_k=0):
     o.m, o.sketch, o.sweeps, o.prec = m, sketch, 1, 0
     o.solve, o.rsvd_k = solve, rsvd_k
     return o
+
+
+@pytest.mark.parametrize("first_sweep,tol,flags,expect", [
+    (0, 0.0, 0, 0),
+    (3, 0.0, 0, 0),      # resume at sweep 3
+    (-1, 0.0, 0, -1),    # negative first sweep
+    (0, -1e-3, 1, -1),   # negative tolerance
+    (0, 1e-3, 0, -1),    # tolerance without the per-sweep residual
+    (0, 1e-3, 3, -1),    # tolerance with the final residual only
+    (0, 1e-3, 1, 0),
+])
+def test_resume_and_tolerance_validation(first_sweep, tol, flags, expect):
+    L = _lib()
+    t = _tensor(L, (10, 10, 10))
+    o = _opts(L, 50)
+    o.first_sweep, o.tol, o.flags = first_sweep, tol, flags
+    nb = ctypes.c_size_t(0)
+    st = L.lib().tsk_workspace_size(ctypes.byref(t), L.i32_array((3, 3, 3)), ctypes.byref(o),
+                                    ctypes.byref(nb))
+    assert st == expect
 
 
 @pytest.mark.parametrize("dims,ranks,m,sketch,layout,expect", [

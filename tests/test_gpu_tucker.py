@@ -251,3 +251,47 @@ def test_rsvd_exact_low_rank_recovered(tsk):
     _, _, fits = tsk.tucker_sketch_als(_dense(tsk, X), (4, 4, 4), 8 * 16, 1, prec="f64",
                                        solve="rsvd")
     assert fits[-1] < 1e-12
+
+
+@pytest.mark.parametrize("kind,solve", [("ts", "rsvd"), ("lev", "exact")])
+def test_resume_at_a_sweep_bitwise(tsk, kind, solve):
+    """first_sweep (checkpoint / resume of the sweep loop of Alg. 4): two sweeps in
+    one call equal one sweep followed by a call resumed at sweep 1 from its
+    factors, bit for bit (the per-sweep streams are keyed by the absolute sweep),
+    and the resumed call matches the oracle resumed the same way."""
+    X = workloads.tucker_dense((14, 13, 12), (3, 3, 3), 0.05, seed=4)
+    T = _dense(tsk, X)
+    kw = dict(sketch=kind, prec="f64", seed=5, solve=solve)
+    full = tsk.tucker_sketch_als(T, (3, 3, 3), 60, 2, **kw)
+    one = tsk.tucker_sketch_als(T, (3, 3, 3), 60, 1, **kw)
+    init = [F.clone() for F in one[1]]
+    rest = tsk.tucker_sketch_als(T, (3, 3, 3), 60, 1, init="user", init_factors=init,
+                                 first_sweep=1, **kw)
+    assert rest[2][0] == full[2][1]
+    assert all(torch.equal(a, b) for a, b in zip(full[1], rest[1]))
+    assert torch.equal(full[0], rest[0])
+    ref = otk.sketch_tucker_als(osk.Tensor.from_dense(X), (3, 3, 3), 60, 1, seed=5,
+                                sketch_kind=kind, solve_kind=solve, init="user",
+                                init_factors=[F.cpu().numpy() for F in init], first_sweep=1)
+    np.testing.assert_allclose(rest[2], ref["fits"], rtol=0, atol=1e-10)
+
+
+def test_tolerance_stops_and_final_fit(tsk):
+    """tol: the loop stops after the first sweep whose residual moved by less than
+    tol (the oracle's residual sequence says where); FINAL_FIT evaluates only the
+    last sweep and equals the per-sweep record there."""
+    w = workloads.dense40()
+    T = _dense(tsk, w.dense)
+    ref = otk.sketch_tucker_als(osk.Tensor.from_dense(w.dense), w.ranks, w.m, 8, seed=0)
+    d = np.abs(np.diff(ref["fits"]))
+    tol = 1e-12                          # d = 2.3e-7, 4.2e-11, 2.8e-15, ...: stop after sweep 4
+    expect = 1 + next(i for i in range(1, len(ref["fits"])) if d[i - 1] < tol)
+    assert expect == 4 and d[1] > 100 * tol and d[2] < tol / 100
+    plan = tsk.TuckerPlan(T, w.ranks, w.m, 8, prec="f64", seed=0, tol=tol)
+    _, _, fits = plan.run()
+    assert plan.sweeps_done == expect and len(fits) == expect
+    np.testing.assert_allclose(fits, ref["fits"][:expect], rtol=0, atol=1e-10)
+    _, _, every = tsk.tucker_sketch_als(T, w.ranks, w.m, 4, prec="f64", seed=0)
+    _, _, last = tsk.tucker_sketch_als(T, w.ranks, w.m, 4, prec="f64", seed=0,
+                                       record_fit="final")
+    assert all(np.isnan(last[:3])) and last[3] == every[3]
