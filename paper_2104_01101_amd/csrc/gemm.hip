@@ -486,12 +486,38 @@ tsk_status gemm_nn_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t
   return gemm_tn_t<double, true>(M, N, K, A, lda, M, A, lda, B, ldb, C, ldc, ws, st);
 }
 
+tsk_status gemm_nn(int prec, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+                   const void* B, int64_t ldb, double* C, int64_t ldc, Ws& ws, hipStream_t st) {
+  switch (prec) {
+    case TSK_PREC_F64:
+      return gemm_tn_t<double, true>(M, N, K, A, lda, M, A, lda, B, ldb, C, ldc, ws, st);
+    case TSK_PREC_F32:
+      return gemm_tn_t<float, true>(M, N, K, A, lda, M, A, lda, B, ldb, C, ldc, ws, st);
+    default:
+      return gemm_tn_t<uint16_t, true>(M, N, K, A, lda, M, A, lda, B, ldb, C, ldc, ws, st);
+  }
+}
+
 tsk_status gemm_small(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                       int64_t sai, int64_t sak, const double* B, int64_t sbk, int64_t sbj,
                       double beta, double* C, int64_t ldc, hipStream_t st) {
   if (M * N == 0) return TSK_OK;
   hipLaunchKernelGGL(k_gemm_small, dim3(ceil_div(M * N, 256)), dim3(256), 0, st, M, N, K, alpha,
                      A, sai, sak, B, sbk, sbj, beta, C, ldc);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+__global__ void k_from_f64(const double* src, int64_t n, void* dst, int prec) {
+  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) store_prec(dst, size_t(t), src[t], prec);
+}
+
+tsk_status convert_from_f64(const double* src, int64_t count, void* dst, int prec,
+                            hipStream_t st) {
+  if (count <= 0) return TSK_OK;
+  hipLaunchKernelGGL(k_from_f64, dim3(ceil_div(count, 256)), dim3(256), 0, st, src, count, dst,
+                     prec);
   TSK_LAUNCHED();
   return TSK_OK;
 }

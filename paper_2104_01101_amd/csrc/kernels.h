@@ -111,6 +111,12 @@ tsk_status gemm_small(int64_t M, int64_t N, int64_t K, double alpha, const doubl
                       double beta, double* C, int64_t ldc, hipStream_t st);
 tsk_status convert_to_f64(const void* src, int dtype_or_prec_bytes, int64_t count, double* dst,
                           hipStream_t st);
+// dst (count elements of precision prec) = src rounded to that precision
+tsk_status convert_from_f64(const double* src, int64_t count, void* dst, int prec,
+                            hipStream_t st);
+// C (M x N, FP64) = A B, A (M x K) and B (K x N) row-major, element type prec
+tsk_status gemm_nn(int prec, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+                   const void* B, int64_t ldb, double* C, int64_t ldc, Ws& ws, hipStream_t st);
 
 // ---- FP64 dense linear algebra (linalg.hip) ----
 // In-place lower Cholesky of the n x n matrix G (row-major, lda); sets *info
@@ -129,6 +135,12 @@ tsk_status sym_eig_top(double* M, int64_t q, int64_t R, double* lam, double* V, 
 // non-positive pivot.  Returns EUNSUPPORTED if G does not fit in LDS.
 tsk_status spd_inverse(double* G, int64_t n, int64_t lda, int* info, hipStream_t st);
 bool spd_inverse_fits(int64_t n);
+// Ginv (n x n, ldi) = G^{-1} for an SPD G (n x n, ldg) of any order: block
+// sweeps of 32 or 64 pivots, one launch per block, FP64 MFMA tile updates.
+// Ginv must not alias G.  *info = j+1 at the first non-positive pivot j when
+// it was 0.
+tsk_status spd_inverse_blocked(const double* G, int64_t n, int64_t ldg, double* Ginv,
+                               int64_t ldi, int* info, Ws& ws, hipStream_t st);
 // Make the entry of largest magnitude of every column of A (rows x R) positive.
 // sgn (optional, R entries) receives the sign applied to each column
 tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, hipStream_t st,

@@ -1518,6 +1518,185 @@ __global__ void k_transpose(const double* A, int64_t rows, int64_t cols, double*
   }
 }
 
+// ------------------------------------------------- blocked SPD inverse ----
+// Inverse of an SPD matrix of any order by the symmetric sweep operator taken
+// one pivot block of TB indices at a time (the block form of the sweeps
+// above): sweeping P maps A_PP -> -A_PP^{-1}, A_IP -> A_IP A_PP^{-1},
+// A_PJ -> A_PP^{-1} A_PJ and A_IJ -> A_IJ - A_IP A_PP^{-1} A_PJ; after the
+// last block the matrix is -G^{-1}.  One launch per block step, one
+// workgroup per TB x TB tile of the (full, row-major) matrix; the products
+// are FP64 MFMA 16x16x4 tiles from LDS.  The step reads matrix X and writes Y
+// (two buffers, so that no tile is overwritten while others still read it).
+// The pivot inverse comes from the previous launch: the workgroup of the tile
+// that becomes the next pivot block inverts it right after updating it (the
+// register-tiled pair sweeps above, on the LDS copy), so each step is one
+// launch.  Indices >= n are padded with the identity, which sweeps leave
+// untouched.  The pivots of the pair sweeps are those of the Schur complements,
+// i.e. the Cholesky pivots of G: the first non-positive one sets *info (global
+// index + 1) when *info is still 0.
+typedef double dx4 __attribute__((ext_vector_type(4)));
+
+template <int TB>
+constexpr size_t sweep_lds_bytes() {
+  return size_t(4) * TB * (TB + 1) * 8;
+}
+
+// acc (wave quadrant of a TB x TB tile, (TB/32)^2 MFMA blocks) += A B, both
+// TB x TB in LDS with row stride TB + 1
+template <int TB>
+__device__ __forceinline__ void sweep_tile_mma(const double* A, const double* B,
+                                               dx4 (&acc)[TB / 32][TB / 32], int lane, int wave) {
+  constexpr int SL = TB + 1, NW = TB / 32;
+  const int qi = (wave >> 1) * (TB / 2), qj = (wave & 1) * (TB / 2);
+  const int li = lane & 15, g = lane >> 4;
+#pragma unroll 4
+  for (int k0 = 0; k0 < TB; k0 += 4) {
+    double a[NW], b[NW];
+#pragma unroll
+    for (int x = 0; x < NW; ++x) a[x] = A[(qi + 16 * x + li) * SL + k0 + g];
+#pragma unroll
+    for (int y = 0; y < NW; ++y) b[y] = B[(k0 + g) * SL + qj + 16 * y + li];
+#pragma unroll
+    for (int x = 0; x < NW; ++x)
+#pragma unroll
+      for (int y = 0; y < NW; ++y)
+        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+  }
+}
+
+// element (i, j) of the matrix, identity beyond n
+__device__ __forceinline__ double sweep_ld(const double* X, int ldx, int n, int i, int j) {
+  return (i < n && j < n) ? X[int64_t(i) * ldx + j] : (i == j ? 1.0 : 0.0);
+}
+
+// TB x TB tile at (r0, c0) of X into LDS (stride TB + 1), identity-padded
+template <int TB>
+__device__ __forceinline__ void sweep_stage(double* S, const double* X, int ldx, int n, int r0,
+                                            int c0) {
+  for (int e = threadIdx.x; e < TB * TB; e += 256) {
+    const int i = e / TB, j = e % TB;
+    S[i * (TB + 1) + j] = sweep_ld(X, ldx, n, r0 + i, c0 + j);
+  }
+}
+
+// Inverse of the SPD tile held in LDS at T (stride TB + 1, identity-padded
+// beyond nb valid indices) into Pout (TB x TB, ld TB); S2 is LDS scratch of
+// TB x (TB + 1) doubles.  Pivot failures set *info to base + local pivot + 1.
+template <int TB>
+__device__ void sweep_pivot_inverse(double* T, int nb, double* S2, double* Pout, int* info,
+                                    int base) {
+  __shared__ int linfo;
+  if (threadIdx.x == 0) linfo = 0;
+  __syncthreads();
+  spd_inverse_pair_body<TB / 16>(T, nb, TB + 1, &linfo, S2);
+  __syncthreads();
+  for (int e = threadIdx.x; e < TB * TB; e += 256) {
+    const int i = e / TB, j = e % TB;
+    Pout[e] = (i < nb && j < nb) ? T[i * (TB + 1) + j] : (i == j ? 1.0 : 0.0);
+  }
+  if (threadIdx.x == 0 && linfo) atomicCAS(info, 0, base + linfo);
+}
+
+template <int TB>
+__global__ __launch_bounds__(256) void k_sweep_first(const double* X, int ldx, int n,
+                                                     double* Pout, int* info) {
+  extern __shared__ double sm[];
+  constexpr int SZ = TB * (TB + 1);
+  sweep_stage<TB>(sm, X, ldx, n, 0, 0);
+  __syncthreads();
+  sweep_pivot_inverse<TB>(sm, n < TB ? n : TB, sm + SZ, Pout, info, 0);
+}
+
+template <int TB>
+__global__ __launch_bounds__(256) void k_sweep_step(const double* X, int ldx, double* Y, int ldy,
+                                                    int n, int p, const double* Pin,
+                                                    double* Pout, int last, int* info) {
+  extern __shared__ double sm[];
+  constexpr int SL = TB + 1, SZ = TB * SL, NW = TB / 32;
+  double* sIP = sm;
+  double* sPin = sm + SZ;
+  double* sPJ = sm + 2 * SZ;
+  double* sF = sm + 3 * SZ;
+  const int I = blockIdx.y, J = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = I * TB, c0 = J * TB, p0 = p * TB;
+  const double sg = last ? -1.0 : 1.0;  // the swept matrix is -G^{-1}
+  const int qi = (wave >> 1) * (TB / 2), qj = (wave & 1) * (TB / 2);
+  const int li = lane & 15, g = lane >> 4;
+
+  dx4 acc[NW][NW];
+#pragma unroll
+  for (int x = 0; x < NW; ++x)
+#pragma unroll
+    for (int y = 0; y < NW; ++y) acc[x][y] = dx4{0.0, 0.0, 0.0, 0.0};
+
+  for (int e = tid; e < TB * TB; e += 256) sPin[(e / TB) * SL + e % TB] = Pin[e];
+  if (I != p) sweep_stage<TB>(sIP, X, ldx, n, r0, p0);
+  if (J != p) sweep_stage<TB>(sPJ, X, ldx, n, p0, c0);
+  __syncthreads();
+  if (I == p && J == p) {
+    // -A_PP^{-1}
+#pragma unroll
+    for (int x = 0; x < NW; ++x)
+#pragma unroll
+      for (int y = 0; y < NW; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          acc[x][y][v] = -sPin[(qi + 16 * x + g + 4 * v) * SL + qj + 16 * y + li];
+  } else if (J == p) {
+    sweep_tile_mma<TB>(sIP, sPin, acc, lane, wave);  // A_IP A_PP^{-1}
+  } else if (I == p) {
+    sweep_tile_mma<TB>(sPin, sPJ, acc, lane, wave);  // A_PP^{-1} A_PJ
+  } else {
+    // F = A_IP A_PP^{-1} to LDS, then A_IJ - F A_PJ
+    sweep_tile_mma<TB>(sIP, sPin, acc, lane, wave);
+#pragma unroll
+    for (int x = 0; x < NW; ++x)
+#pragma unroll
+      for (int y = 0; y < NW; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          sF[(qi + 16 * x + g + 4 * v) * SL + qj + 16 * y + li] = acc[x][y][v];
+          acc[x][y][v] = 0.0;
+        }
+    __syncthreads();
+    sweep_tile_mma<TB>(sF, sPJ, acc, lane, wave);
+#pragma unroll
+    for (int x = 0; x < NW; ++x)
+#pragma unroll
+      for (int y = 0; y < NW; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = r0 + qi + 16 * x + g + 4 * v, j = c0 + qj + 16 * y + li;
+          acc[x][y][v] = sweep_ld(X, ldx, n, i, j) - acc[x][y][v];
+        }
+  }
+  // store (the identity padding beyond n is not stored)
+#pragma unroll
+  for (int x = 0; x < NW; ++x)
+#pragma unroll
+    for (int y = 0; y < NW; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = r0 + qi + 16 * x + g + 4 * v, j = c0 + qj + 16 * y + li;
+        if (i < n && j < n) Y[int64_t(i) * ldy + j] = sg * acc[x][y][v];
+      }
+  if (!last && I == p + 1 && J == p + 1) {
+    // this tile is the next pivot block: invert it for the next launch
+    __syncthreads();  // every wave is done with sIP, sPJ and sF
+#pragma unroll
+    for (int x = 0; x < NW; ++x)
+#pragma unroll
+      for (int y = 0; y < NW; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          sPJ[(qi + 16 * x + g + 4 * v) * SL + qj + 16 * y + li] = acc[x][y][v];
+    __syncthreads();
+    const int nb = n - r0 < TB ? n - r0 : TB;
+    sweep_pivot_inverse<TB>(sPJ, nb, sIP, Pout, info, r0);
+  }
+}
+
 int max_lds_bytes() {
   static int v = -1;
   if (v < 0) {
@@ -1596,6 +1775,44 @@ tsk_status spd_inverse(double* G, int64_t n, int64_t lda, int* info, hipStream_t
                      int(lda), info);
   TSK_LAUNCHED();
   return TSK_OK;
+}
+
+template <int TB>
+tsk_status spd_inverse_blocked_t(const double* G, int64_t n, int64_t ldg, double* Ginv,
+                                 int64_t ldi, int* info, Ws& ws, hipStream_t st) {
+  const int nt = int(ceil_div(n, TB));
+  double* T1 = ws.take<double>(size_t(n) * n);
+  double* piv = ws.take<double>(size_t(2) * TB * TB);
+  if (ws.measuring()) return TSK_OK;
+  hipLaunchKernelGGL(k_sweep_first<TB>, dim3(1), dim3(256), sweep_lds_bytes<TB>() / 2, st, G,
+                     int(ldg), int(n), piv, info);
+  TSK_LAUNCHED();
+  const double* src = G;
+  int64_t lds = ldg;
+  for (int p = 0; p < nt; ++p) {
+    // the buffers alternate so that the last step writes Ginv
+    const bool to_out = ((nt - 1 - p) & 1) == 0;
+    double* dst = to_out ? Ginv : T1;
+    const int64_t ldd = to_out ? ldi : n;
+    hipLaunchKernelGGL(k_sweep_step<TB>, dim3(nt, nt), dim3(256), sweep_lds_bytes<TB>(), st, src,
+                       int(lds), dst, int(ldd), int(n), p, piv + size_t(p & 1) * TB * TB,
+                       piv + size_t((p + 1) & 1) * TB * TB, p == nt - 1 ? 1 : 0, info);
+    TSK_LAUNCHED();
+    src = dst;
+    lds = ldd;
+  }
+  return TSK_OK;
+}
+
+tsk_status spd_inverse_blocked(const double* G, int64_t n, int64_t ldg, double* Ginv,
+                               int64_t ldi, int* info, Ws& ws, hipStream_t st) {
+  if (n <= 0) return TSK_OK;
+  if (!ws.measuring() && G == Ginv) {
+    set_error("blocked SPD inverse needs distinct input and output");
+    return TSK_EINVAL;
+  }
+  if (n >= 384) return spd_inverse_blocked_t<64>(G, n, ldg, Ginv, ldi, info, ws, st);
+  return spd_inverse_blocked_t<32>(G, n, ldg, Ginv, ldi, info, ws, st);
 }
 
 tsk_status chol_solve_rows(const double* L, int64_t n, int64_t ldl, double* X, int64_t rows,

@@ -658,6 +658,12 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
     size_t q = g0;
     for (; q < all.size() && js.njobs < kMaxJobs && path_of(all[q]) == path; ++q) {
       Job j = all[q];
+      // the partition's LDS holds one cursor row of the largest slab and the
+      // longest packed table of the group: close the group before a slab that
+      // would overflow it (every slab fits alone by construction)
+      const int64_t need = fixed + 2 * int64_t(kWaves) * std::max(js.bmax, j.nbins) +
+                           2 * ceil_div(std::max(js.tab_max, j.tab_len), 8) * 8;
+      if (js.njobs > 0 && need > kLds) break;
       j.bin0 = bins;
       bins += j.nbins;
       js.bmax = std::max(js.bmax, j.nbins);
@@ -682,6 +688,10 @@ tsk_status sketch_pass(const TensorView& T, const PassJob* specs, int njobs, Ws&
       }
       const size_t lds =
           size_t(fixed + 2 * int64_t(kWaves) * js.bmax + 2 * int64_t(ceil_div(js.tab_max, 8) * 8));
+      if (lds > size_t(kLds)) {
+        set_error("sketch pass: partition needs %zu bytes of LDS (limit %d)", lds, kLds);
+        return TSK_EUNSUPPORTED;
+      }
       if (f64) {
         if (wide)
           launch_partition<double, 8, 8>(path, int(nchunks), lds, st, c, js, nnz);

@@ -461,3 +461,59 @@ def test_rsvd_solve_fp32_operands(tsk):
     Xg = W.cpu().numpy() @ A.cpu().numpy().T
     Xo = Wo @ Ao.T
     assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) < 1e-4
+
+
+# ------------------------------------------------- large Grams (r > 142) ----
+@pytest.mark.parametrize("m,r,s,R,k", [(2048, 256, 1500, 16, 26), (4000, 1000, 200, 10, 20),
+                                       (14400, 900, 500, 30, 40), (1300, 300, 700, 8, 40),
+                                       (700, 143, 90, 5, 12)])
+def test_rsvd_solve_large_r_fp64(tsk, m, r, s, R, k):
+    """RSVD-LRLS at the Gram orders of the 10000^3 (r = 256), 200^4 (r = 1000)
+    and 500^3 (r = 900) workloads: the Gram is inverted by block sweeps (64
+    pivots per block from r = 384, 32 below; r = 300 and 143 leave a ragged
+    last block) and the products with Y follow the O(m s k) order.  FP64
+    library vs the oracle with the same test matrix."""
+    rs = np.random.default_rng(m + r + 7)
+    Z = rs.standard_normal((m, r))
+    Y = Z @ rs.standard_normal((r, R)) @ rs.standard_normal((R, s)) + 0.1 * rs.standard_normal((m, s))
+    Om = rs.standard_normal((s, k))
+    A, W = tsk.rsvd_solve(torch.from_numpy(Z).to(DEV), torch.from_numpy(Y).to(DEV), R,
+                          torch.from_numpy(Om).to(DEV))
+    Ao, Wo = osv.rsvd_lrls(Z, Y, R, Om)
+    np.testing.assert_allclose(A.cpu().numpy(), Ao, atol=1e-9)
+    np.testing.assert_allclose(W.cpu().numpy(), Wo, atol=1e-9 * np.abs(Wo).max())
+
+
+@pytest.mark.parametrize("m,r,s,R", [(2048, 256, 1500, 16), (4000, 1000, 200, 10),
+                                     (1300, 300, 700, 8)])
+def test_rc_solve_large_r_fp64(tsk, m, r, s, R):
+    """The exact solve with the blocked inverse of the Gram (r > 142)."""
+    rs = np.random.default_rng(m * 3 + r)
+    Z = rs.standard_normal((m, r)) / np.sqrt(m)
+    Y = Z @ rs.standard_normal((r, R)) @ rs.standard_normal((R, s)) + 0.1 * rs.standard_normal((m, s))
+    A, W = tsk.rc_solve(torch.from_numpy(Z).to(DEV), torch.from_numpy(Y).to(DEV), R)
+    Ao, Wo, _ = osv.rc_solve(Z, Y, R)
+    A, W = A.cpu().numpy(), W.cpu().numpy()
+    np.testing.assert_allclose(A, Ao, atol=1e-9 * max(1, np.abs(Ao).max()))
+    np.testing.assert_allclose(W, Wo, atol=1e-9 * max(1, np.abs(Wo).max()))
+
+
+@pytest.mark.parametrize("solver", ["rsvd", "exact"])
+@pytest.mark.parametrize("r,zero", [(200, 150), (400, 0), (400, 399)])
+def test_blocked_inverse_singular_gram(tsk, solver, r, zero):
+    """A zero column of Z makes the Gram singular: its Schur pivot is exactly 0
+    in every block position (first, inner, last index), and both solvers report
+    a breakdown from the blocked inverse."""
+    from paper_2104_01101_amd import _lib as L
+    rs = np.random.default_rng(r + zero)
+    m, s, R, k = 3 * r, 80, 4, 12
+    Z = rs.standard_normal((m, r))
+    Z[:, zero] = 0.0
+    Y = torch.from_numpy(rs.standard_normal((m, s))).to(DEV)
+    Zg = torch.from_numpy(Z).to(DEV)
+    with pytest.raises(L.TskError) as e:
+        if solver == "rsvd":
+            tsk.rsvd_solve(Zg, Y, R, torch.from_numpy(rs.standard_normal((s, k))).to(DEV))
+        else:
+            tsk.rc_solve(Zg, Y, R)
+    assert e.value.status == L.ENUMERIC
