@@ -1,16 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of sketched Tucker-ALS (Alg. 4) on one MI355X.
 
-Workload (default): sparse 3-way 2000^3 tensor, 1e6 distinct uniform
-coordinates, values = Tucker rank-(10,10,10) Gaussian signal + N(0,1), FP32;
-TensorSketch with m = 16 * 10^2 = 1600, range-finder initialisation, 10 sweeps,
-FP32 operands (FP64 factorisations).  Inputs are synthetic and seeded (seed 0)
-and resident in HBM before timing.
+Workload (default, zipf10k): sparse 3-way 10000^3 tensor with 1e7 distinct
+coordinates drawn per mode from Zipf(1.1), lognormal(0,1) values, FP32; Tucker
+rank (16,16,16), TensorSketch with m = 8 * 16^2 = 2048, range-finder
+initialisation, 5 sweeps, FP32 operands (FP64 factorisations).  Other
+workloads: sparse2000 (2000^3, 1e6 uniform coordinates, rank 10, m = 1600, 10
+sweeps) and its leverage-sampling / deterministic-selection variants.  Inputs
+are synthetic and seeded (seed 0) and resident in HBM before timing.
 
 One step = one complete call: TensorSketch maps, the sketch pass of every mode
-(preparation), range-finder init of modes 2..3, 10 sweeps of the three sketched
-rank-constrained subproblems, and the relative residual after every sweep.
-value = completed sweeps per second of the whole job (10 * steps / time).
+(preparation), range-finder init of modes 2..N, the sweeps of the N sketched
+rank-constrained subproblems, and the relative residual after the last sweep.
+value = completed sweeps per second of the whole job (sweeps * steps / time).
+The phases (preparation, initialisation, sweep loop, residual) are timed
+separately with HIP events on the library's stream and reported beside it,
+with the sweep loop's own rate.
 
 Prints one JSON line (keys per the benchmark contract) with
   roofline              the launch group that takes the most time, timed live
@@ -50,7 +55,8 @@ GROUP_SOURCES = {
 }
 GROUPS = ["sketch_pass", "rrf_pass", "rrf", "ts_lhs", "gram", "solve_la", "eig", "fit",
           "leverage", "fiber_index", "fiber_rows", "select"]
-WORKLOADS = ["sparse2000", "zipf10k", "sparse2000lev", "sparse2000det"]
+WORKLOADS = ["zipf10k", "sparse2000", "sparse2000lev", "sparse2000det"]
+PHASES = ["phase_prep", "phase_init", "phase_sweeps", "phase_fit"]
 
 
 # The test tensors of Sec. 7 with the experiments' parameters: name -> (builder
@@ -134,9 +140,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sparse2000", choices=WORKLOADS,
-                    help="sparse2000 (default, the benchmark workload), zipf10k (sketch-pass "
-                         "study), sparse2000lev / sparse2000det (the same tensor under "
+    ap.add_argument("--workload", default="zipf10k", choices=WORKLOADS,
+                    help="zipf10k (default: 10000^3, 1e7 Zipf entries, rank 16, m = 2048), "
+                         "sparse2000 (2000^3, 1e6 uniform entries, rank 10, m = 1600), "
+                         "sparse2000lev / sparse2000det (the same tensor under "
                          "leverage-score sampling / deterministic leverage selection, "
                          "through the fibre indices)")
     ap.add_argument("--solve", default="rsvd", choices=["rsvd", "exact"],
@@ -180,7 +187,17 @@ def group_work(w, solve="exact"):
     pk = PEAK_TFLOPS[w.prec]
     eig = lambda n: 4.0 / 3.0 * n ** 3 + 2.0 * n * n * R
     kk = min(R + 10, r)  # RSVD-LRLS test-matrix columns
-    if solve == "rsvd":
+    # the library's choice of product order (solve.hip): the fused chain for
+    # r <= 128, k <= 24; otherwise the O(m s k) order when r >= 4k
+    yside = solve == "rsvd" and not (r <= 128 and kk <= 24) and r >= 4 * kk
+    gram = 2.0 * m * r * (r + s)  # [Z^T Z; Y^T Z]
+    if yside:
+        gram = 2.0 * m * r * r + 4.0 * m * s * kk  # Z^T Z, Y Omega, Y^T (Z P)
+        # inverse, C0 = Z^T (Y Omega), C^T = C0^T B, thin QR, B Q, Z P, D D^T (FP64)
+        la = r ** 3 + 2.0 * m * r * kk + 4.0 * kk * r * r + 4.0 * kk * kk * r \
+            + 2.0 * m * r * kk + 2.0 * kk * kk * s
+        q_eig = kk
+    elif solve == "rsvd":
         # inverse, Om^T H^T, C^T, thin QR, B Q, D^T, D D^T (FP64)
         la = r ** 3 + 2.0 * kk * r * s + 4.0 * kk * r * r + 4.0 * kk * kk * r \
             + 2.0 * s * r * kk + 2.0 * kk * kk * s
@@ -198,13 +215,14 @@ def group_work(w, solve="exact"):
                 PEAK_TFLOPS["f64"], "TFLOP/s"),
         # CountSketches read, Z written
         "ts_lhs": ("hbm", subs * ((N - 1) * s * R * 8 + m * r * vo), HBM_PEAK_GBS, "GB/s"),
-        # G = Z^T Z and Z^T Y
-        "gram": ("mfma", subs * 2.0 * m * r * (r + s), pk, "TFLOP/s"),
+        # G = Z^T Z and Z^T Y (or the two products with Y in the O(m s k) order)
+        "gram": ("mfma", subs * gram, pk, "TFLOP/s"),
         "solve_la": ("mfma", subs * la, PEAK_TFLOPS["f64"], "TFLOP/s"),
         # tridiagonalisation + back-transformation of R vectors (FP64 vector ALU)
         "eig": ("alu", subs * eig(q_eig) + (N - 1) * eig(k1), FP64_VECTOR_TFLOPS, "TFLOP/s"),
-        # per entry: core contraction R^3 + R^2 + R multiply-adds (FP64)
-        "fit": ("alu", sweeps * nnz * 2.0 * (R ** 3 + R ** 2 + R), FP64_VECTOR_TFLOPS, "TFLOP/s"),
+        # after the last sweep, per entry: core contraction R^3 + R^2 + R
+        # multiply-adds (FP64)
+        "fit": ("alu", nnz * 2.0 * (R ** 3 + R ** 2 + R), FP64_VECTOR_TFLOPS, "TFLOP/s"),
         # sampled Kronecker rows: factors read, Z written
         "leverage": ("hbm", subs * ((N - 1) * s * R * 8 + m * r * vo), HBM_PEAK_GBS, "GB/s"),
         # per mode: keys built (indices read, keys written), then sorted pairs written once
@@ -294,7 +312,7 @@ def main():
         w["prec"] = args.prec
     T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(dev), torch.from_numpy(w.val).to(dev), w.dims)
     plan = tsk.TuckerPlan(T, w.ranks, w.m, w.sweeps, sketch=w.sketch, init="rrf", prec=w.prec,
-                          seed=0, record_fit=True, solve=args.solve)
+                          seed=0, record_fit="final", solve=args.solve)
     second = "sketch_pass" if w.sketch == "ts" else "fiber_rows"
     lib = L.lib()
     lib.tsk_profile_enable.argtypes = [ctypes.c_char_p]
@@ -323,7 +341,7 @@ def main():
 
     # timed region: the dominant group's and the sketch pass's (leverage:
     # the fibre gather's) launches are timed with events on the library's stream
-    timed = dominant if dominant == second else f"{dominant},{second}"
+    timed = ",".join(dict.fromkeys([dominant, second] + PHASES))
     L.check(lib.tsk_profile_enable(timed.encode()))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -334,6 +352,7 @@ def main():
     elapsed = time.perf_counter() - t0
     dom = read(dominant)
     sp = read(second)
+    phases = {p: read(p)[0] / args.steps for p in PHASES}
     L.check(lib.tsk_profile_enable(b""))
 
     work = group_work(w, args.solve)
@@ -371,18 +390,22 @@ def main():
                    "m": w.m, "sweeps": w.sweeps, "prec": w.prec,
                    "solve": "RSVD-LRLS (Alg. 5)" if args.solve == "rsvd" else "exact truncated SVD"},
         "final_relative_residual": fits[-1] if fits else None,
+        "phases_ms_per_step": {p[6:]: round(v, 4) for p, v in phases.items()},
+        "sweep_loop_sweeps_per_s": (w.sweeps / (phases["phase_sweeps"] / 1e3)
+                                    if phases["phase_sweeps"] > 0 else None),
         "roofline": roofline(dominant, work, dom[0], dom[1], args.steps, args.workload),
         f"{second}_roofline": roofline(second, work, sp[0], sp[1], args.steps, args.workload),
     }
-    if not args.no_cpu_baseline and args.workload.startswith("sparse2000"):
-        out["cpu_baseline"] = cpu_baseline(w, args.solve)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.solve, 1 if args.workload == "zipf10k" else 3)
     print(json.dumps(out))
 
 
 def cpu_baseline(w, solve="exact", sample_sweeps=3):
     """FP64 oracle on the same input: preparation (maps, sketched right-hand
-    sides, range finder) and `sample_sweeps` of the sweeps are timed; the job
-    time is extrapolated to preparation + all sweeps."""
+    sides, range finder), `sample_sweeps` of the sweeps and one relative
+    residual are timed; the job time is extrapolated to preparation + all
+    sweeps + the residual after the last one (what the GPU job computes)."""
     import numpy as np
     from oracle import sketch as osk, solve as osv, tucker as otk
     try:
@@ -420,13 +443,16 @@ def cpu_baseline(w, solve="exact", sample_sweeps=3):
                 A, W, _ = osv.rc_solve(Z, Y, ranks[n])
             factors[n] = A
             core = otk.W_to_core(W, ranks, n)
-        otk.relative_residual(T, core, factors)
     t_sweep = (time.perf_counter() - t1) / sample_sweeps
-    job = t_prep + w.sweeps * t_sweep
+    t2 = time.perf_counter()
+    otk.relative_residual(T, core, factors)
+    t_fit = time.perf_counter() - t2
+    job = t_prep + w.sweeps * t_sweep + t_fit
     return {"value": w.sweeps / job, "unit": "sweeps/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"full input; preparation ({t_prep:.2f} s) + {sample_sweeps} of "
-                      f"{w.sweeps} sweeps ({t_sweep:.2f} s each) timed, "
-                      f"job = preparation + {w.sweeps} sweeps"}
+            "sample": f"full input; preparation ({t_prep:.2f} s), {sample_sweeps} of "
+                      f"{w.sweeps} sweeps ({t_sweep:.2f} s each) and one residual "
+                      f"({t_fit:.2f} s) timed, job = preparation + {w.sweeps} sweeps + "
+                      f"residual"}
 
 
 if __name__ == "__main__":

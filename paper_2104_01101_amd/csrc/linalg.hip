@@ -26,6 +26,8 @@ namespace tsk {
 
 namespace {
 
+typedef double dx4 __attribute__((ext_vector_type(4)));  // FP64 MFMA accumulator
+
 // ------------------------------------------------------------ reductions ----
 template <int NT>
 __device__ double block_sum(double v, double* red) {
@@ -978,7 +980,8 @@ constexpr int kQrMaxK = 64;
 
 template <bool LDSW>
 __global__ __launch_bounds__(64) void k_qr_rows(const double* Ct, int k, int r, double* Qt,
-                                                double* gwork) {
+                                                double* gwork, const int* gate) {
+  if (gate && *gate == 0) return;  // run only when the Cholesky QR below asked for it
   extern __shared__ double qsm[];
   __shared__ double betas[kQrMaxK];
   double* V = LDSW ? qsm : gwork;          // k x r: reduced columns, reflector j in row j
@@ -1054,6 +1057,154 @@ __global__ __launch_bounds__(64) void k_qr_rows(const double* Ct, int k, int r, 
   }
   if (LDSW)
     for (int t = lane; t < k * r; t += 64) Qt[t] = Q[t];
+}
+
+// Thin QR by shifted Cholesky QR, three passes (Fukaya, Kannan, Nakatsukasa,
+// Zhang & Yamamoto, SIAM J. Sci. Comput. 2020): X_0 = C; pass p forms the
+// Gram X_p^T X_p (plus the shift 11 (r k + k (k + 1)) u ||C||_F^2 on the
+// diagonal in the first pass), its Cholesky factor R_p and X_{p+1} =
+// X_p R_p^{-1}; after three passes Q = X_3 has orthonormal columns to working
+// precision whenever C has full numerical column rank.  Any orthonormal basis
+// of range(C) serves the randomized solve (its SVD of Q^T B Z^T Y fixes A and
+// W), so this replaces the Householder QR beyond the register-resident shapes.  A non-positive pivot in
+// the unshifted passes (C of numerical rank below k, e.g. an exactly low-rank
+// right-hand side) sets *fallback, and the Householder kernel that follows in
+// the stream runs only then.
+//
+// One workgroup of 4 waves, k <= KP (32 or 64).  Grams: FP64 MFMA 16x16x4
+// over 64-column blocks of X_p^T (block b to wave b mod 4), wave partials
+// summed in LDS in wave order.  Cholesky and the triangular inverse: wave 0 in
+// LDS.  X_{p+1}^T = R_p^{-T} X_p^T: MFMA over 16-column pieces of the same
+// blocks, so each wave reads back only what it wrote.  The passes write X1, X2
+// and Qt, so no buffer is read after it was written within a pass.
+template <int KP>
+__global__ __launch_bounds__(256) void k_cholqr3(const double* Ct, int k, int r, double* X1,
+                                                 double* X2, double* Qt, int* fallback) {
+  extern __shared__ double csm[];
+  constexpr int SL = KP + 1, SZ = KP * SL, NB = KP / 16;
+  __shared__ int bad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  double* Gs = csm;           // Gram, then R (upper triangle)
+  double* Ri = csm + SZ;      // R^{-1}
+  if (tid == 0) bad = 0;
+  for (int pass = 0; pass < 3; ++pass) {
+    const double* in = pass == 0 ? Ct : pass == 1 ? X1 : X2;
+    double* out = pass == 0 ? X1 : pass == 1 ? X2 : Qt;
+    // ---- Gram partials over this wave's 64-column blocks ----
+    dx4 acc[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[a][b] = dx4{0.0, 0.0, 0.0, 0.0};
+    for (int i0 = wave * 64; i0 < r; i0 += 256)
+#pragma unroll 2
+      for (int ks = 0; ks < 64; ks += 4) {
+        const int i = i0 + ks + g;
+        double x[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          const int row = 16 * a + li;
+          x[a] = (row < k && i < r) ? in[int64_t(row) * r + i] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], x[b], acc[a][b], 0, 0, 0);
+      }
+    __syncthreads();  // the previous pass is done with Gs and Ri
+    double* part = csm + size_t(wave) * SZ;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[(16 * a + g + 4 * v) * SL + 16 * b + li] = acc[a][b][v];
+    __syncthreads();
+    for (int e = tid; e < KP * KP; e += 256) {
+      const int o = (e / KP) * SL + e % KP;
+      Gs[o] = ((csm[o] + csm[SZ + o]) + csm[2 * SZ + o]) + csm[3 * SZ + o];
+    }
+    __syncthreads();
+    // ---- Cholesky G = R^T R and R^{-1} (wave 0) ----
+    if (wave == 0) {
+      if (pass == 0) {
+        double tr = 0.0;
+        for (int j = 0; j < k; ++j) tr += Gs[j * SL + j];
+        const double shift = 11.0 * (double(r) * k + double(k) * (k + 1)) * 0x1.0p-53 * tr;
+        if (lane < k) Gs[lane * SL + lane] += shift;
+      }
+      for (int j = 0; j < k; ++j) {
+        const double d = Gs[j * SL + j];
+        if (!(d > 0.0)) {
+          if (lane == 0) bad = 1;
+          break;  // wave-uniform
+        }
+        const double rd = 1.0 / sqrt(d);
+        // row j of R: R_jj = sqrt(d), R_jl = G_jl / sqrt(d)
+        const double rjl = (lane >= j && lane < k) ? Gs[j * SL + lane] * rd : 0.0;
+        if (lane >= j && lane < k) Gs[j * SL + lane] = rjl;
+        // trailing update of the upper triangle: G_al -= R_ja R_jl, a <= l
+        for (int a = j + 1; a < k; ++a) {
+          const double rja = Gs[j * SL + a];
+          if (lane >= a && lane < k) Gs[a * SL + lane] -= rja * rjl;
+        }
+      }
+      if (!bad) {
+        // R^{-1} by back substitution, lane c holding column c; rows l from
+        // k - 1 down, uniform across lanes (R_lt is a broadcast read, and
+        // R^{-1}_tc = 0 for t > c makes the masked terms vanish)
+        const int c = lane;
+        for (int l = lane; l < KP; l += 64)
+          for (int t = 0; t < KP; ++t) Ri[t * SL + l] = 0.0;
+        for (int l = k - 1; l >= 0; --l) {
+          double sacc = (l == c) ? 1.0 : 0.0;
+          int t = l + 1;
+          for (; t + 3 < k; t += 4) {
+            const double a0 = Gs[l * SL + t] * Ri[t * SL + c];
+            const double a1 = Gs[l * SL + t + 1] * Ri[(t + 1) * SL + c];
+            const double a2 = Gs[l * SL + t + 2] * Ri[(t + 2) * SL + c];
+            const double a3 = Gs[l * SL + t + 3] * Ri[(t + 3) * SL + c];
+            sacc -= (a0 + a1) + (a2 + a3);
+          }
+          for (; t < k; ++t) sacc -= Gs[l * SL + t] * Ri[t * SL + c];
+          if (c < k && c >= l) Ri[l * SL + c] = sacc / Gs[l * SL + l];
+        }
+      }
+    }
+    __syncthreads();
+    if (bad) {
+      if (tid == 0) *fallback = 1;
+      return;  // workgroup-uniform
+    }
+    // ---- X_{p+1}^T = R^{-T} X_p^T over the 16-column pieces of this wave's
+    // 64-column blocks (the columns its Gram partials read in the next pass) ----
+    for (int i0 = wave * 64; i0 < r; i0 += (i0 & 63) == 48 ? 256 - 48 : 16) {
+      dx4 o[NB];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) o[cb] = dx4{0.0, 0.0, 0.0, 0.0};
+      const int i = i0 + li;
+#pragma unroll
+      for (int k0 = 0; k0 < KP; k0 += 4) {
+        const int l = k0 + g;
+        const double xb = (l < k && i < r) ? in[int64_t(l) * r + i] : 0.0;
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+          o[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ri[l * SL + 16 * cb + li], xb, o[cb], 0, 0,
+                                                       0);
+      }
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = 16 * cb + g + 4 * v;
+          if (c < k && i < r) out[int64_t(c) * r + i] = o[cb][v];
+        }
+    }
+    __syncthreads();  // every wave's columns of X_{p+1} are written
+  }
+  if (tid == 0) *fallback = 0;
 }
 
 // Register-resident variant for r <= 128 and k <= KM <= 24: lane l holds rows
@@ -1534,8 +1685,6 @@ __global__ void k_transpose(const double* A, int64_t rows, int64_t cols, double*
 // untouched.  The pivots of the pair sweeps are those of the Schur complements,
 // i.e. the Cholesky pivots of G: the first non-positive one sets *info (global
 // index + 1) when *info is still 0.
-typedef double dx4 __attribute__((ext_vector_type(4)));
-
 template <int TB>
 constexpr size_t sweep_lds_bytes() {
   return size_t(4) * TB * (TB + 1) * 8;
@@ -1907,11 +2056,28 @@ tsk_status qr_rows(const double* Ct, int64_t k, int64_t r, double* Qt, Ws& ws, h
   const size_t lds = size_t(2) * k * r * 8;
   const bool fits = lds + 1024 <= size_t(max_lds_bytes());
   double* work = fits ? nullptr : ws.take<double>(size_t(k) * r);
+  // shifted Cholesky QR (three passes); the Householder kernel runs only as
+  // its fallback
+  const bool chol = true;
+  double* X1 = chol ? ws.take<double>(size_t(k) * r) : nullptr;
+  double* X2 = chol ? ws.take<double>(size_t(k) * r) : nullptr;
+  int* flag = chol ? ws.take<int>(1) : nullptr;
   if (ws.measuring()) return TSK_OK;
+  if (chol) {
+    if (k <= 32)
+      hipLaunchKernelGGL(k_cholqr3<32>, dim3(1), dim3(256), size_t(4) * 32 * 33 * 8, st, Ct,
+                         int(k), int(r), X1, X2, Qt, flag);
+    else
+      hipLaunchKernelGGL(k_cholqr3<64>, dim3(1), dim3(256), size_t(4) * 64 * 65 * 8, st, Ct,
+                         int(k), int(r), X1, X2, Qt, flag);
+    TSK_LAUNCHED();
+  }
   if (fits)
-    hipLaunchKernelGGL(k_qr_rows<true>, dim3(1), dim3(64), lds, st, Ct, int(k), int(r), Qt, work);
+    hipLaunchKernelGGL(k_qr_rows<true>, dim3(1), dim3(64), lds, st, Ct, int(k), int(r), Qt, work,
+                       flag);
   else
-    hipLaunchKernelGGL(k_qr_rows<false>, dim3(1), dim3(64), 0, st, Ct, int(k), int(r), Qt, work);
+    hipLaunchKernelGGL(k_qr_rows<false>, dim3(1), dim3(64), 0, st, Ct, int(k), int(r), Qt, work,
+                       flag);
   TSK_LAUNCHED();
   return TSK_OK;
 }

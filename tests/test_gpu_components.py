@@ -517,3 +517,19 @@ def test_blocked_inverse_singular_gram(tsk, solver, r, zero):
         else:
             tsk.rc_solve(Zg, Y, R)
     assert e.value.status == L.ENUMERIC
+
+
+@pytest.mark.parametrize("m,r,s,R,k", [(800, 200, 120, 4, 30), (900, 260, 150, 2, 50)])
+def test_rsvd_solve_rank_deficient_large(tsk, m, r, s, R, k):
+    """Z^+ Y of rank R < k at Gram orders beyond the register kernels: the
+    sketched range C = B Z^T Y Omega has rank R, the shifted Cholesky QR breaks
+    down in its second pass and the Householder fallback runs; the rank-R
+    solution is still exact."""
+    rs = np.random.default_rng(m + s)
+    Z = rs.standard_normal((m, r))
+    X = rs.standard_normal((r, R)) @ rs.standard_normal((R, s))
+    Y = Z @ X
+    Om = rs.standard_normal((s, k))
+    A, W = tsk.rsvd_solve(torch.from_numpy(Z).to(DEV), torch.from_numpy(Y).to(DEV), R,
+                          torch.from_numpy(Om).to(DEV))
+    np.testing.assert_allclose(W.cpu().numpy() @ A.cpu().numpy().T, X, atol=1e-9 * np.abs(X).max())
