@@ -215,10 +215,11 @@ __global__ __launch_bounds__(kSkT) void k_gram_batch(GramBatch gb) {
 // the next slab is fetched into registers while the current one feeds the
 // MFMAs.  Requires M1, lda1, lda2, ldb multiples of 4 and 16-byte aligned
 // bases (k_gemm_tn covers the rest).
-constexpr int kF4K = 64, kF4LD = 80;
+constexpr int kF4K = 64, kF4LD = 80, kF4LDA = 68;
 
 __device__ inline float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 
+template <bool A_MK>
 __global__ __launch_bounds__(kThreads) void k_gemm_tn_f32v(int64_t M, int64_t N, int64_t K,
                                                           const float* A1, int64_t lda1,
                                                           int64_t M1, const float* A2,
@@ -240,13 +241,27 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_f32v(int64_t M, int64_t N,
   const bool a_in = ia + 3 < M, b_in = jb + 3 < N;
   const float* abase = ia < M1 ? A1 + ia : A2 + (ia - M1);
   const int64_t alda = ia < M1 ? lda1 : lda2;
+  // A_MK (A given M x K, row-major): thread covers k quad cq of rows
+  // mr + 16 u, staged as [m][k] (row stride kF4LDA: the 16 rows one operand
+  // read touches fall in different banks)
+  const int mr = tid >> 4;
   float4 ra[4], rb[4];
   auto fetch = [&](int64_t k0) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t k = k0 + kr + 16 * u;
       const bool kv = k < kend;
-      if (kv && a_in) {
+      if constexpr (A_MK) {
+        const int64_t i = i0 + mr + 16 * u, kq = k0 + cq;
+        if (i < M && kq + 3 < kend) {
+          ra[u] = ld4(A1 + i * lda1 + kq);
+        } else {
+          float t[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) t[e] = (i < M && kq + e < kend) ? A1[i * lda1 + kq + e] : 0.f;
+          ra[u] = make_float4(t[0], t[1], t[2], t[3]);
+        }
+      } else if (kv && a_in) {
         ra[u] = ld4(abase + k * alda);
       } else {
         float t[4];
@@ -270,7 +285,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_f32v(int64_t M, int64_t N,
   auto stash = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      *reinterpret_cast<float4*>(&As[buf][(kr + 16 * u) * kF4LD + cq]) = ra[u];
+      if constexpr (A_MK)
+        *reinterpret_cast<float4*>(&As[buf][(mr + 16 * u) * kF4LDA + cq]) = ra[u];
+      else
+        *reinterpret_cast<float4*>(&As[buf][(kr + 16 * u) * kF4LD + cq]) = ra[u];
       *reinterpret_cast<float4*>(&Bs[buf][(kr + 16 * u) * kF4LD + cq]) = rb[u];
     }
   };
@@ -295,7 +313,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_f32v(int64_t M, int64_t N,
       const int kk = 4 * t + g;
       float av[2], bv[2];
 #pragma unroll
-      for (int sm = 0; sm < 2; ++sm) av[sm] = as[kk * kF4LD + wm * 32 + sm * 16 + li];
+      for (int sm = 0; sm < 2; ++sm)
+        av[sm] = A_MK ? as[(wm * 32 + sm * 16 + li) * kF4LDA + kk]
+                      : as[kk * kF4LD + wm * 32 + sm * 16 + li];
 #pragma unroll
       for (int sn = 0; sn < 2; ++sn) bv[sn] = bs[kk * kF4LD + wn * 32 + sn * 16 + li];
 #pragma unroll
@@ -401,7 +421,7 @@ tsk_status gemm_tn_t(int64_t M, int64_t N, int64_t K, const void* A1, int64_t ld
     return TSK_OK;
   }
   dim3 grid(tm, tn, splits);
-  if (std::is_same<E, float>::value && !A_MK) {
+  if (std::is_same<E, float>::value) {
     const bool vec = M1 % 4 == 0 && lda1 % 4 == 0 && lda2 % 4 == 0 && ldb % 4 == 0 &&
                      reinterpret_cast<uintptr_t>(A1) % 16 == 0 &&
                      reinterpret_cast<uintptr_t>(A2) % 16 == 0 &&
@@ -410,7 +430,7 @@ tsk_status gemm_tn_t(int64_t M, int64_t N, int64_t K, const void* A1, int64_t ld
       const int64_t kch = ceil_div(kchunk, kF4K) * kF4K;
       const int64_t spl = ceil_div(K, kch);
       double* dst = spl > 1 ? part : C;
-      hipLaunchKernelGGL(k_gemm_tn_f32v, dim3(tm, tn, spl), dim3(kThreads), 0, st, M, N, K,
+      hipLaunchKernelGGL(k_gemm_tn_f32v<A_MK>, dim3(tm, tn, spl), dim3(kThreads), 0, st, M, N, K,
                          static_cast<const float*>(A1), lda1, M1,
                          static_cast<const float*>(A2), lda2, static_cast<const float*>(B), ldb,
                          kch, dst, spl > 1 ? N : ldc, spl > 1 ? M * N : int64_t(0));
@@ -508,16 +528,19 @@ tsk_status gemm_small(int64_t M, int64_t N, int64_t K, double alpha, const doubl
   return TSK_OK;
 }
 
-__global__ void k_from_f64(const double* src, int64_t n, void* dst, int prec) {
+__global__ void k_from_f64(const double* src, int64_t rows, int64_t cols, void* dst,
+                           int64_t ldd, int prec) {
   int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < n) store_prec(dst, size_t(t), src[t], prec);
+  if (t >= rows * ldd) return;
+  const int64_t i = t / ldd, j = t % ldd;  // padding columns are zeroed
+  store_prec(dst, size_t(t), j < cols ? src[i * cols + j] : 0.0, prec);
 }
 
-tsk_status convert_from_f64(const double* src, int64_t count, void* dst, int prec,
-                            hipStream_t st) {
-  if (count <= 0) return TSK_OK;
-  hipLaunchKernelGGL(k_from_f64, dim3(ceil_div(count, 256)), dim3(256), 0, st, src, count, dst,
-                     prec);
+tsk_status convert_from_f64(const double* src, int64_t rows, int64_t cols, void* dst,
+                            int64_t ldd, int prec, hipStream_t st) {
+  if (rows * ldd <= 0) return TSK_OK;
+  hipLaunchKernelGGL(k_from_f64, dim3(ceil_div(rows * ldd, 256)), dim3(256), 0, st, src, rows,
+                     cols, dst, ldd, prec);
   TSK_LAUNCHED();
   return TSK_OK;
 }

@@ -111,9 +111,10 @@ tsk_status gemm_small(int64_t M, int64_t N, int64_t K, double alpha, const doubl
                       double beta, double* C, int64_t ldc, hipStream_t st);
 tsk_status convert_to_f64(const void* src, int dtype_or_prec_bytes, int64_t count, double* dst,
                           hipStream_t st);
-// dst (count elements of precision prec) = src rounded to that precision
-tsk_status convert_from_f64(const double* src, int64_t count, void* dst, int prec,
-                            hipStream_t st);
+// dst (rows x ldd elements of precision prec) = src (rows x cols, FP64)
+// rounded to that precision, columns cols..ldd-1 set to 0
+tsk_status convert_from_f64(const double* src, int64_t rows, int64_t cols, void* dst,
+                            int64_t ldd, int prec, hipStream_t st);
 // C (M x N, FP64) = A B, A (M x K) and B (K x N) row-major, element type prec
 tsk_status gemm_nn(int prec, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
                    const void* B, int64_t ldb, double* C, int64_t ldc, Ws& ws, hipStream_t st);

@@ -1073,8 +1073,8 @@ __global__ __launch_bounds__(64) void k_qr_rows(const double* Ct, int k, int r, 
 //
 // One workgroup of 4 waves, k <= KP (32 or 64).  Grams: FP64 MFMA 16x16x4
 // over 64-column blocks of X_p^T (block b to wave b mod 4), wave partials
-// summed in LDS in wave order.  Cholesky and the triangular inverse: wave 0 in
-// LDS.  X_{p+1}^T = R_p^{-T} X_p^T: MFMA over 16-column pieces of the same
+// summed in LDS in a fixed order.  Cholesky in LDS with every thread in the
+// trailing updates; the triangular inverse by wave 0.  X_{p+1}^T = R_p^{-T} X_p^T: MFMA over 16-column pieces of the same
 // blocks, so each wave reads back only what it wrote.  The passes write X1, X2
 // and Qt, so no buffer is read after it was written within a pass.
 template <int KP>
@@ -1086,7 +1086,7 @@ __global__ __launch_bounds__(256) void k_cholqr3(const double* Ct, int k, int r,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   double* Gs = csm;           // Gram, then R (upper triangle)
-  double* Ri = csm + SZ;      // R^{-1}
+  double* Ri = csm + SZ;      // R^{-1} (row-major)
   if (tid == 0) bad = 0;
   for (int pass = 0; pass < 3; ++pass) {
     const double* in = pass == 0 ? Ct : pass == 1 ? X1 : X2;
@@ -1114,63 +1114,73 @@ __global__ __launch_bounds__(256) void k_cholqr3(const double* Ct, int k, int r,
             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], x[b], acc[a][b], 0, 0, 0);
       }
     __syncthreads();  // the previous pass is done with Gs and Ri
-    double* part = csm + size_t(wave) * SZ;
+    // partials: waves 0, 1 store to regions 0, 1; waves 2, 3 add theirs; then
+    // G = (P0 + P2) + (P1 + P3)
+    double* part = csm + size_t(wave & 1) * SZ;
+    if (wave < 2) {
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
+      for (int a = 0; a < NB; ++a)
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) part[(16 * a + g + 4 * v) * SL + 16 * b + li] = acc[a][b][v];
+          for (int v = 0; v < 4; ++v) part[(16 * a + g + 4 * v) * SL + 16 * b + li] = acc[a][b][v];
+    }
+    __syncthreads();
+    if (wave >= 2) {
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) part[(16 * a + g + 4 * v) * SL + 16 * b + li] += acc[a][b][v];
+    }
     __syncthreads();
     for (int e = tid; e < KP * KP; e += 256) {
       const int o = (e / KP) * SL + e % KP;
-      Gs[o] = ((csm[o] + csm[SZ + o]) + csm[2 * SZ + o]) + csm[3 * SZ + o];
+      Gs[o] = csm[o] + csm[SZ + o];
     }
     __syncthreads();
-    // ---- Cholesky G = R^T R and R^{-1} (wave 0) ----
-    if (wave == 0) {
-      if (pass == 0) {
-        double tr = 0.0;
-        for (int j = 0; j < k; ++j) tr += Gs[j * SL + j];
-        const double shift = 11.0 * (double(r) * k + double(k) * (k + 1)) * 0x1.0p-53 * tr;
-        if (lane < k) Gs[lane * SL + lane] += shift;
-      }
-      for (int j = 0; j < k; ++j) {
+    if (pass == 0 && wave == 0) {  // the shift of the first pass
+      double tr = 0.0;
+      for (int j = 0; j < k; ++j) tr += Gs[j * SL + j];
+      const double shift = 11.0 * (double(r) * k + double(k) * (k + 1)) * 0x1.0p-53 * tr;
+      if (lane < k) Gs[lane * SL + lane] += shift;
+    }
+    // ---- Cholesky G = R^T R in LDS, one step per pivot: wave 0 scales row
+    // j, every thread takes part in the trailing update ----
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+      if (wave == 0) {  // every lane reads the pivot before any lane writes
         const double d = Gs[j * SL + j];
-        if (!(d > 0.0)) {
-          if (lane == 0) bad = 1;
-          break;  // wave-uniform
-        }
+        if (lane == 0 && !(d > 0.0)) bad = 1;
         const double rd = 1.0 / sqrt(d);
-        // row j of R: R_jj = sqrt(d), R_jl = G_jl / sqrt(d)
-        const double rjl = (lane >= j && lane < k) ? Gs[j * SL + lane] * rd : 0.0;
-        if (lane >= j && lane < k) Gs[j * SL + lane] = rjl;
-        // trailing update of the upper triangle: G_al -= R_ja R_jl, a <= l
-        for (int a = j + 1; a < k; ++a) {
-          const double rja = Gs[j * SL + a];
-          if (lane >= a && lane < k) Gs[a * SL + lane] -= rja * rjl;
-        }
+        if (lane >= j && lane < k) Gs[j * SL + lane] *= rd;  // R_jj = sqrt(d)
       }
-      if (!bad) {
-        // R^{-1} by back substitution, lane c holding column c; rows l from
-        // k - 1 down, uniform across lanes (R_lt is a broadcast read, and
-        // R^{-1}_tc = 0 for t > c makes the masked terms vanish)
-        const int c = lane;
-        for (int l = lane; l < KP; l += 64)
-          for (int t = 0; t < KP; ++t) Ri[t * SL + l] = 0.0;
-        for (int l = k - 1; l >= 0; --l) {
-          double sacc = (l == c) ? 1.0 : 0.0;
-          int t = l + 1;
-          for (; t + 3 < k; t += 4) {
-            const double a0 = Gs[l * SL + t] * Ri[t * SL + c];
-            const double a1 = Gs[l * SL + t + 1] * Ri[(t + 1) * SL + c];
-            const double a2 = Gs[l * SL + t + 2] * Ri[(t + 2) * SL + c];
-            const double a3 = Gs[l * SL + t + 3] * Ri[(t + 3) * SL + c];
-            sacc -= (a0 + a1) + (a2 + a3);
-          }
-          for (; t < k; ++t) sacc -= Gs[l * SL + t] * Ri[t * SL + c];
-          if (c < k && c >= l) Ri[l * SL + c] = sacc / Gs[l * SL + l];
+      __syncthreads();
+      const int n1 = k - j - 1;  // trailing upper triangle: G_ab -= R_ja R_jb
+      for (int e = tid; e < n1 * n1; e += 256) {
+        const int a = j + 1 + e / n1, b = j + 1 + e % n1;
+        if (a <= b) Gs[a * SL + b] = fma(-Gs[j * SL + a], Gs[j * SL + b], Gs[a * SL + b]);
+      }
+      __syncthreads();
+    }
+    // ---- S = R^{-1} by back substitution (wave 0, lane c holds column c) ----
+    if (wave == 0 && !bad) {
+      const int c = lane;
+      if (c < KP)
+        for (int t = 0; t < KP; ++t) Ri[t * SL + c] = 0.0;
+      for (int l = k - 1; l >= 0; --l) {
+        double sacc = (l == c) ? 1.0 : 0.0;
+        int t = l + 1;
+        for (; t + 3 < k; t += 4) {
+          const double a0 = Gs[l * SL + t] * Ri[t * SL + c];
+          const double a1 = Gs[l * SL + t + 1] * Ri[(t + 1) * SL + c];
+          const double a2 = Gs[l * SL + t + 2] * Ri[(t + 2) * SL + c];
+          const double a3 = Gs[l * SL + t + 3] * Ri[(t + 3) * SL + c];
+          sacc -= (a0 + a1) + (a2 + a3);
         }
+        for (; t < k; ++t) sacc -= Gs[l * SL + t] * Ri[t * SL + c];
+        if (c < k && c >= l) Ri[l * SL + c] = sacc / Gs[l * SL + l];
       }
     }
     __syncthreads();
@@ -2065,10 +2075,10 @@ tsk_status qr_rows(const double* Ct, int64_t k, int64_t r, double* Qt, Ws& ws, h
   if (ws.measuring()) return TSK_OK;
   if (chol) {
     if (k <= 32)
-      hipLaunchKernelGGL(k_cholqr3<32>, dim3(1), dim3(256), size_t(4) * 32 * 33 * 8, st, Ct,
+      hipLaunchKernelGGL(k_cholqr3<32>, dim3(1), dim3(256), size_t(2) * 32 * 33 * 8, st, Ct,
                          int(k), int(r), X1, X2, Qt, flag);
     else
-      hipLaunchKernelGGL(k_cholqr3<64>, dim3(1), dim3(256), size_t(4) * 64 * 65 * 8, st, Ct,
+      hipLaunchKernelGGL(k_cholqr3<64>, dim3(1), dim3(256), size_t(2) * 64 * 65 * 8, st, Ct,
                          int(k), int(r), X1, X2, Qt, flag);
     TSK_LAUNCHED();
   }

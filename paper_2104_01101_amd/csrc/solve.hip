@@ -90,9 +90,12 @@ tsk_status rsvd_solve_yside(const void* Z, const void* Y, int64_t m, int64_t r, 
                             Ws& ws, hipStream_t st) {
   const bool f64 = prec == TSK_PREC_F64;
   const size_t eb = prec_bytes(prec);
+  // the rounded copies of Omega and Z P get rows of a multiple of 4 elements
+  // (vector loads in the FP32 products)
+  const int64_t kp = ceil_div(k, 4) * 4;
   double* G = ws.take<double>(size_t(r) * r);
   void* Om_e = f64 ? static_cast<void*>(const_cast<double*>(Om))
-                   : static_cast<void*>(ws.take<char>(size_t(s) * k * eb));
+                   : static_cast<void*>(ws.take<char>(size_t(s) * kp * eb));
   double* YO = ws.take<double>(size_t(m) * k);
   const double* Z64 = f64 ? static_cast<const double*>(Z) : ws.take<double>(size_t(m) * r);
   double* C0 = ws.take<double>(size_t(r) * k);
@@ -101,7 +104,7 @@ tsk_status rsvd_solve_yside(const void* Z, const void* Y, int64_t m, int64_t r, 
   double* Pt = ws.take<double>(size_t(k) * r);
   double* P = ws.take<double>(size_t(r) * k);
   double* ZP = ws.take<double>(size_t(m) * k);
-  void* ZP_e = f64 ? static_cast<void*>(ZP) : static_cast<void*>(ws.take<char>(size_t(m) * k * eb));
+  void* ZP_e = f64 ? static_cast<void*>(ZP) : static_cast<void*>(ws.take<char>(size_t(m) * kp * eb));
   double* Dt = ws.take<double>(size_t(s) * k);
   double* Mk = ws.take<double>(size_t(k) * k);
   double* lam = ws.take<double>(R);
@@ -113,8 +116,8 @@ tsk_status rsvd_solve_yside(const void* Z, const void* Y, int64_t m, int64_t r, 
   {
     ProfScope prof(run ? "gram" : "", st);
     TSK_TRY(gemm_tn(prec, r, r, m, Z, r, r, nullptr, 0, Z, r, G, r, ws, st));
-    if (run && !f64) TSK_TRY(convert_from_f64(Om, s * k, Om_e, prec, st));
-    TSK_TRY(gemm_nn(prec, m, k, s, Y, s, Om_e, k, YO, k, ws, st));
+    if (run && !f64) TSK_TRY(convert_from_f64(Om, s, k, Om_e, kp, prec, st));
+    TSK_TRY(gemm_nn(prec, m, k, s, Y, s, Om_e, f64 ? k : kp, YO, k, ws, st));
   }
   {
     ProfScope prof(run ? "solve_la" : "", st);
@@ -133,8 +136,8 @@ tsk_status rsvd_solve_yside(const void* Z, const void* Y, int64_t m, int64_t r, 
   }
   {
     ProfScope prof(run ? "gram" : "", st);
-    if (run && !f64) TSK_TRY(convert_from_f64(ZP, m * k, ZP_e, prec, st));
-    TSK_TRY(gemm_tn(prec, s, k, m, Y, s, s, nullptr, 0, ZP_e, k, Dt, k, ws, st));
+    if (run && !f64) TSK_TRY(convert_from_f64(ZP, m, k, ZP_e, kp, prec, st));
+    TSK_TRY(gemm_tn(prec, s, k, m, Y, s, s, nullptr, 0, ZP_e, f64 ? k : kp, Dt, k, ws, st));
   }
   TSK_TRY(gemm_tn(TSK_PREC_F64, k, k, s, Dt, k, k, nullptr, 0, Dt, k, Mk, k, ws, st));
   TSK_TRY(sym_eig_top(Mk, k, R, lam, U, ws, st));
