@@ -289,6 +289,21 @@ tsk_status tsk_rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, in
                           int32_t R, int32_t prec, const double* Omega, int32_t k, double* A,
                           double* W, void* ws, size_t* ws_bytes, void* stream);
 
+/* tsk_rsvd_solve for callers that cannot allocate device memory (serving
+ * loops and harnesses in which hipMalloc is not allowed): the same solve,
+ * kernels and results, with no workspace argument.  Its scratch is a fixed
+ * 32 MiB array in the library's device code, one copy per GPU, held from the
+ * library's load until the process ends; the call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine).  Shapes whose scratch
+ * exceeds 32 MiB (about m r + 3 r^2 + (m + 2 s) k doubles for r > 128) return
+ * TSK_ENOMEM with a message, before any work.  All calls on one GPU share its
+ * array, so calls that overlap on one GPU (several threads or streams) race;
+ * successive calls on one stream are safe.  Arguments, errors and
+ * synchronisation as tsk_rsvd_solve. */
+tsk_status tsk_rsvd_solve_noalloc(const void* Z, const void* Y, int64_t m, int64_t r, int64_t s,
+                                  int32_t R, int32_t prec, const double* Omega, int32_t k,
+                                  double* A, double* W, void* stream);
+
 /* Init-RRF of mode n (Alg. 3 with the composite sketch of Sec. 5):
  * W = T_(n) Omega^T with the CountSketch g : [K] -> [k2], tau (stream
  * (seed, 2, n) at the other-mode row-major index), G (k2 x k1) i.i.d.

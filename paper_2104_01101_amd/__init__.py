@@ -15,6 +15,7 @@ import torch
 from . import _lib as L
 
 __all__ = ["Tensor", "tucker_sketch_als", "cp_via_tucker", "hash_tables", "sketch_rhs_ts",
+           "rsvd_solve_noalloc",
            "sketch_lhs_ts", "rc_solve", "rrf_init", "leverage_sample", "leverage_select", "sketch_lev",
            "FiberIndex", "fiber_index", "sketch_lev_coo", "fit",
            "sketched_residual", "sketched_residual_grads", "SketchedResidual", "lib"]
@@ -222,6 +223,24 @@ def rc_solve(Z, Y, R, prec=None):
                              (L.ptr(Z.contiguous()), L.ptr(Y.contiguous()), m, r, s, int(R),
                               L.PREC[prec], L.ptr(A), L.ptr(W)), (L.stream_ptr(),), Z.device)
     del keep
+    return A, W
+
+
+def rsvd_solve_noalloc(Z, Y, R, Omega, prec=None):
+    """rsvd_solve through the entry point that allocates no device memory (its
+    scratch is the library's static per-GPU buffer); the outputs A and W are
+    the only allocations, made here by the caller's side."""
+    if prec is None:
+        prec = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16"}[Z.dtype]
+    m, r = Z.shape
+    s = Y.shape[1]
+    Om = Omega.to(torch.float64).contiguous()
+    A = torch.empty((s, R), dtype=torch.float64, device=Z.device)
+    W = torch.empty((r, R), dtype=torch.float64, device=Z.device)
+    Zc, Yc = Z.contiguous(), Y.contiguous()
+    L.check(L.lib().tsk_rsvd_solve_noalloc(L.ptr(Zc), L.ptr(Yc), m, r, s, int(R), L.PREC[prec],
+                                           L.ptr(Om), int(Om.shape[1]), L.ptr(A), L.ptr(W),
+                                           L.stream_ptr()))
     return A, W
 
 

@@ -73,6 +73,8 @@ def lib():
             "tsk_rc_solve": (i32, [vp, vp, i64, i64, i64, i32, i32, vp, vp, vp, sz, vp]),
             "tsk_rsvd_solve": (i32, [vp, vp, i64, i64, i64, i32, i32, vp, i32, vp, vp, vp, sz,
                                      vp]),
+            "tsk_rsvd_solve_noalloc": (i32, [vp, vp, i64, i64, i64, i32, i32, vp, i32, vp, vp,
+                                             vp]),
             "tsk_rrf_init": (i32, [T, i32, i32, i32, i32, u64, vp, vp, sz, vp]),
             "tsk_leverage_sample": (i32, [i32, vp, vp, i32, i64, u64, i32, vp, vp, vp, vp, sz, vp]),
             "tsk_leverage_select": (i32, [i32, vp, vp, i32, i64, vp, vp, vp, sz, vp]),
