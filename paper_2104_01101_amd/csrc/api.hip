@@ -115,6 +115,7 @@ void rrf_sizes(int64_t m, const int64_t* R, int N, int n, int32_t k1o, int32_t k
 // ---------------------------------------------------------------- RRF ----
 struct RrfBufs {
   int64_t k1, k2;
+  bool dense;     // B from the dense structured-GEMM pass (no W)
   void* Wt;       // k2 x s_n, tensor dtype (sketch-pass output)
   double* Wt64;   // k2 x s_n
   double* G;      // k2 x k1
@@ -124,13 +125,20 @@ struct RrfBufs {
   double* V;      // k1 x R
 };
 
+// Dense tensors take the structured-GEMM pass (rrf_dense.hip), which forms
+// B = T_(n) Omega^T G directly; other tensors the CountSketch pass into W.
+bool rrf_uses_dense_pass(const TensorView& T, int64_t k1) { return rrf_dense_supported(T, k1); }
+
 tsk_status rrf_plan(const TensorView& T, int n, int64_t R, int64_t k1, int64_t k2, RrfBufs& b,
                     Ws& ws) {
   const int64_t s = T.dims[n];
   b.k1 = k1;
   b.k2 = k2;
-  b.Wt = T.dtype == TSK_F64 ? (void*)ws.take<double>(k2 * s) : (void*)ws.take<float>(k2 * s);
-  b.Wt64 = ws.take<double>(k2 * s);
+  b.dense = rrf_uses_dense_pass(T, k1);
+  b.Wt = b.dense ? nullptr
+                 : T.dtype == TSK_F64 ? (void*)ws.take<double>(k2 * s)
+                                      : (void*)ws.take<float>(k2 * s);
+  b.Wt64 = b.dense ? nullptr : ws.take<double>(k2 * s);
   b.G = ws.take<double>(k2 * k1);
   b.B = ws.take<double>(s * k1);
   b.Mq = ws.take<double>(k1 * k1);
@@ -139,19 +147,51 @@ tsk_status rrf_plan(const TensorView& T, int n, int64_t R, int64_t k1, int64_t k
   return TSK_OK;
 }
 
-// after the sketch pass filled b.Wt: B = W G, A = leading left singular vectors of B
+// G (k2 x k1), i.i.d. N(0, 1/k1), stream (seed, RRF Gaussian, n)
+tsk_status rrf_gaussian(int n, uint64_t seed, const RrfBufs& b, hipStream_t st) {
+  return launch_gauss(stream_key(seed, kRRFGauss, n), b.k2 * b.k1, 1.0 / std::sqrt(double(b.k1)),
+                      b.G, st);
+}
+
+// Range-finder passes of the modes `modes`: dense tensors one structured GEMM
+// per mode into b.B (G drawn first), others one CountSketch pass over the
+// entries for all modes into b.Wt
+tsk_status rrf_passes(const TensorView& T, const int* modes, int nm, uint64_t seed, int prec,
+                      RrfBufs* bufs, Ws& ws, hipStream_t st) {
+  const bool run = !ws.measuring();
+  ProfScope prof(run ? "rrf_pass" : "", st);
+  std::vector<PassJob> jobs;
+  for (int t = 0; t < nm; ++t) {
+    const int n = modes[t];
+    RrfBufs& b = bufs[t];
+    if (b.dense) {
+      if (run) TSK_TRY(rrf_gaussian(n, seed, b, st));
+      const size_t mark = ws.off;
+      TSK_TRY(rrf_dense(T, n, b.k1, b.k2, stream_key(seed, kRRF, n), b.G, prec, b.B, ws, st));
+      ws.off = std::max(ws.off, mark);
+    } else {
+      jobs.push_back(PassJob{1, n, b.k2, nullptr, nullptr, stream_key(seed, kRRF, n), b.Wt});
+    }
+  }
+  if (!jobs.empty()) TSK_TRY(sketch_pass(T, jobs.data(), int(jobs.size()), ws, st));
+  return TSK_OK;
+}
+
+// after the range-finder pass: B = W G unless the dense pass formed B, then
+// A = leading left singular vectors of B
 tsk_status rrf_finish(const TensorView& T, int n, int64_t R, uint64_t seed, RrfBufs& b,
                       double* A, int* info, Ws& ws, hipStream_t st) {
   const int64_t s = T.dims[n];
   const bool run = !ws.measuring();
   ProfScope prof(run ? "rrf" : "", st);
-  if (run) {
-    TSK_TRY(convert_to_f64(b.Wt, T.dtype == TSK_F64 ? 8 : 4, b.k2 * s, b.Wt64, st));
-    TSK_TRY(launch_gauss(stream_key(seed, kRRFGauss, n), b.k2 * b.k1, 1.0 / std::sqrt(double(b.k1)),
-                         b.G, st));
+  if (!b.dense) {  // B = W G from the CountSketch pass's W (k2 x s_n, transposed)
+    if (run) {
+      TSK_TRY(convert_to_f64(b.Wt, T.dtype == TSK_F64 ? 8 : 4, b.k2 * s, b.Wt64, st));
+      TSK_TRY(rrf_gaussian(n, seed, b, st));
+    }
+    TSK_TRY(gemm_tn(TSK_PREC_F64, s, b.k1, b.k2, b.Wt64, s, s, nullptr, 0, b.G, b.k1, b.B, b.k1,
+                    ws, st));
   }
-  TSK_TRY(gemm_tn(TSK_PREC_F64, s, b.k1, b.k2, b.Wt64, s, s, nullptr, 0, b.G, b.k1, b.B, b.k1, ws,
-                  st));
   TSK_TRY(gemm_tn(TSK_PREC_F64, b.k1, b.k1, s, b.B, b.k1, b.k1, nullptr, 0, b.B, b.k1, b.Mq, b.k1,
                   ws, st));
   TSK_TRY(sym_eig_top(b.Mq, b.k1, R, b.lam, b.V, ws, st));
@@ -380,13 +420,10 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
   // ---- initialisation of modes 2..N (Alg. 3, or a random orthonormal start) ----
   {
   ProfScope phase(run ? "phase_init" : "", st);
-  if (o.init == TSK_INIT_RRF) {  // range-finder CountSketches of modes 2..N: one more pass
-    std::vector<PassJob> jobs;
-    for (int n = 1; n < N; ++n)
-      jobs.push_back(PassJob{1, n, rrf[n].k2, nullptr, nullptr, stream_key(o.seed, kRRF, n),
-                             rrf[n].Wt});
-    ProfScope prof(run ? "rrf_pass" : "", st);
-    TSK_TRY(sketch_pass(T, jobs.data(), int(jobs.size()), ws, st));
+  if (o.init == TSK_INIT_RRF) {  // range-finder sketches of modes 2..N: one more pass
+    std::vector<int> modes;
+    for (int n = 1; n < N; ++n) modes.push_back(n);
+    TSK_TRY(rrf_passes(T, modes.data(), int(modes.size()), o.seed, prec, rrf.data() + 1, ws, st));
     release();
   }
   if (o.init == TSK_INIT_RRF) {
@@ -732,8 +769,9 @@ tsk_status tsk_rrf_init(const tsk_tensor* T, int32_t n, int32_t R, int32_t k1, i
     RrfBufs b{};
     TSK_TRY(rrf_plan(tv, n, R, k1, k2, b, w));
     if (!w.measuring()) TSK_HIP(hipMemsetAsync(info, 0, 4 * sizeof(int), st));
-    PassJob job{1, n, k2, nullptr, nullptr, stream_key(seed, kRRF, n), b.Wt};
-    TSK_TRY(sketch_pass(tv, &job, 1, w, st));
+    const int modes[1] = {n};
+    TSK_TRY(rrf_passes(tv, modes, 1, seed, tv.dtype == TSK_F64 ? TSK_PREC_F64 : TSK_PREC_F32, &b,
+                       w, st));
     return rrf_finish(tv, n, R, seed, b, A, info, w, st);
   });
   if (stt != TSK_OK || ws == nullptr) return stt;

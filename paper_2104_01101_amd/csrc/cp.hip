@@ -12,6 +12,7 @@
 
 #include "common.h"
 #include "cp.h"
+#include "fit.h"
 #include "kernels.h"
 
 namespace tsk {
@@ -46,27 +47,81 @@ struct Facs {
   const double* A[TSK_MAX_ORDER];
 };
 
-// M[i][r] = sum_{rho : rho_n = i} C[rho] prod_{k != n} A_k[rho_k][r]
-__global__ void k_mttkrp(const double* C, CoreDesc cd, Facs f, int n, int64_t Rc, double* M) {
-  const int64_t Rn = cd.R[n];
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= Rn * Rc) return;
-  const int64_t i = t / Rc, r = t % Rc;
+struct CpFitArgs {
+  int N;
+  int layout;
+  int dtype;
+  int64_t dims[TSK_MAX_ORDER];
+  const int32_t* idx[TSK_MAX_ORDER];
+  const void* vals;
+  const double* F[TSK_MAX_ORDER];
+  int64_t Rc;
+};
+
+
+// M[i][r] = sum_{rho : rho_n = i} C[rho] prod_{k != n} A_k[rho_k][r]: one
+// workgroup per row i; thread (chunk, r) sums every nchunk-th tuple of the
+// other modes, the chunks are added in order
+constexpr int kMtT = 256;
+__global__ __launch_bounds__(kMtT) void k_mttkrp(const double* C, CoreDesc cd, Facs f, int n,
+                                                 int64_t Rc, double* M) {
+  __shared__ double part[kMtT];
+  const int64_t i = blockIdx.x;
+  const int nchunk = Rc >= kMtT ? 1 : int(kMtT / Rc);
+  const int tid = threadIdx.x, r = int(tid % Rc), chunk = int(tid / Rc);
+  const int64_t other = cd.csize / cd.R[n];
   double s = 0.0;
-  for (int64_t p = 0; p < cd.csize; ++p) {
-    int64_t x = p, rho_n = 0;
-    double w = 1.0;
-    for (int k = cd.N - 1; k >= 0; --k) {
-      int64_t rk = x % cd.R[k];
-      x /= cd.R[k];
-      if (k == n)
-        rho_n = rk;
-      else
-        w *= f.A[k][rk * Rc + r];
+  if (chunk < nchunk)
+    for (int64_t u = chunk; u < other; u += nchunk) {
+      // u: row-major index of (rho_k)_{k != n}; p: its position in the core
+      int64_t x = u, p = 0, stride = 1;
+      double w = 1.0;
+      for (int k = cd.N - 1; k >= 0; --k) {
+        int64_t rk;
+        if (k == n) {
+          rk = i;
+        } else {
+          rk = x % cd.R[k];
+          x /= cd.R[k];
+          w *= f.A[k][rk * Rc + r];
+        }
+        p += rk * stride;
+        stride *= cd.R[k];
+      }
+      s = fma(C[p], w, s);
     }
-    if (rho_n == i) s += C[p] * w;
+  part[tid] = s;
+  __syncthreads();
+  if (tid < Rc) {
+    double t = 0.0;
+    for (int c = 0; c < nchunk; ++c) t += part[c * Rc + tid];
+    M[i * Rc + tid] = t;
   }
-  M[t] = s;
+}
+
+// Khatri-Rao product of the factors of modes 1..N-1, transposed:
+// KR[r][j] = prod_{k >= 1} F_k[j_k][r], j the row-major index of (j_1, .., j_{N-1})
+__global__ void k_khatri_rao_t(CpFitArgs a, int64_t J, double* KR) {
+  const int64_t total = a.Rc * J;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = t / J, j = t % J;
+    int64_t x = j;
+    double w = 1.0;
+    for (int k = a.N - 1; k >= 1; --k) {
+      w *= a.F[k][(x % a.dims[k]) * a.Rc + r];
+      x /= a.dims[k];
+    }
+    KR[t] = w;
+  }
+}
+
+// relative residual from the per-block sums of (T - T~)^2 and T^2
+__global__ void k_cp_finish_direct(const double* pd, const double* pn, int nb, double* out) {
+  if (threadIdx.x != 0) return;
+  double d = 0.0, n2 = 0.0;
+  for (int b = 0; b < nb; ++b) d += pd[b], n2 += pn[b];
+  *out = sqrt(d) / sqrt(n2);
 }
 
 // Gam = hadamard_{k != n} A_k^T A_k (Rc x Rc), from precomputed per-mode Grams
@@ -92,16 +147,6 @@ __global__ void k_pinv_from_eig(const double* V, const double* lam, int64_t Rc, 
   P[t] = s;
 }
 
-struct CpFitArgs {
-  int N;
-  int layout;
-  int dtype;
-  int64_t dims[TSK_MAX_ORDER];
-  const int32_t* idx[TSK_MAX_ORDER];
-  const void* vals;
-  const double* F[TSK_MAX_ORDER];
-  int64_t Rc;
-};
 
 __global__ void k_cp_inner(CpFitArgs a, int64_t nnz, int64_t per, double* pn, double* pi) {
   __shared__ double rn[4], ri[4];
@@ -227,8 +272,8 @@ tsk_status cp_run(const TensorView& T, const int64_t* R, int Rc, int sweeps,
         hipLaunchKernelGGL(k_pinv_from_eig, dim3(ceil_div(Rc * Rc, 256)), dim3(256), 0, st, V, lam,
                            int64_t(Rc), P);
         TSK_LAUNCHED();
-        hipLaunchKernelGGL(k_mttkrp, dim3(ceil_div(R[n] * Rc, 256)), dim3(256), 0, st, tb.core, cd,
-                           f, n, int64_t(Rc), M);
+        hipLaunchKernelGGL(k_mttkrp, dim3(unsigned(R[n])), dim3(kMtT), 0, st, tb.core, cd, f, n,
+                           int64_t(Rc), M);
         TSK_LAUNCHED();
         TSK_TRY(gemm_small(R[n], Rc, Rc, 1.0, M, Rc, 1, P, Rc, 1, 0.0, A[n], Rc, st));
       }
@@ -239,7 +284,7 @@ tsk_status cp_run(const TensorView& T, const int64_t* R, int Rc, int sweeps,
     if (run && cp_factors)
       TSK_TRY(gemm_small(T.dims[k], Rc, R[k], 1.0, tb.factors[k], R[k], 1, A[k], Rc, 1, 0.0,
                          cp_factors[k], Rc, st));
-  if (fit_dev && cp_factors) {
+  if (fit_dev && (cp_factors || !run)) {  // (the workspace query passes no factors)
     CpFitArgs a{};
     a.N = N;
     a.layout = T.layout;
@@ -249,12 +294,27 @@ tsk_status cp_run(const TensorView& T, const int64_t* R, int Rc, int sweeps,
     for (int k = 0; k < N; ++k) {
       a.dims[k] = T.dims[k];
       a.idx[k] = T.idx[k];
-      a.F[k] = cp_factors[k];
+      a.F[k] = cp_factors ? cp_factors[k] : nullptr;
       if (run)
         TSK_TRY(gemm_small(Rc, Rc, T.dims[k], 1.0, cp_factors[k], 1, Rc, cp_factors[k], Rc, 1, 0.0,
                            fgrams + k * Rc * Rc, Rc, st));
     }
-    if (run) {
+    if (T.layout == TSK_DENSE && Rc <= kDenseFitMaxR) {
+      // dense: T~(i, j) = sum_r F_0(i, r) KR(r, j), squared differences summed
+      int64_t J = 1;
+      for (int k = 1; k < N; ++k) J *= T.dims[k];
+      double* KR = ws.take<double>(size_t(Rc) * J);
+      double* pd = ws.take<double>(nb);
+      if (run) {
+        hipLaunchKernelGGL(k_khatri_rao_t,
+                           dim3(unsigned(std::min<int64_t>(ceil_div(Rc * J, 256), 8192))),
+                           dim3(256), 0, st, a, J, KR);
+        TSK_LAUNCHED();
+        TSK_TRY(dense_residual_partials(T, KR, cp_factors[0], Rc, nb, pd, pn, pi, st));
+        hipLaunchKernelGGL(k_cp_finish_direct, dim3(1), dim3(64), 0, st, pd, pn, nb, fit);
+        TSK_LAUNCHED();
+      }
+    } else if (run) {
       int64_t per = ceil_div(T.nnz, nb);
       hipLaunchKernelGGL(k_cp_inner, dim3(nb), dim3(256), 0, st, a, T.nnz, per, pn, pi);
       TSK_LAUNCHED();
@@ -263,7 +323,7 @@ tsk_status cp_run(const TensorView& T, const int64_t* R, int Rc, int sweeps,
       TSK_LAUNCHED();
     }
   }
-  ws.off = peak;
+  ws.off = std::max(peak, ws.off);
   return TSK_OK;
 }
 

@@ -3,11 +3,20 @@
 #include "kernels.h"
 
 namespace tsk {
+// largest R_1 of the dense residual path (the column of M kept in registers)
+constexpr int kDenseFitMaxR = 64;
 struct FitScratch {
   int nblocks;
   double *partial_norm, *partial_inner, *partial_direct, *grams, *buf0, *buf1, *model2, *nT2;
+  double* ttm[2];  // dense tensors: mode products of the core (R_1 x s_2 x ... x s_N)
 };
 tsk_status fit_plan(const TensorView& T, const int64_t* R, FitScratch& fs, Ws& ws);
+// Dense T (s_1 x J, row-major) against T~ = A1 M, A1 s_1 x R1 (R1 <= kDenseFitMaxR),
+// M R1 x J: per-block sums of (T - T~)^2 into pdirect and of T^2 into pnorm
+// (nblocks blocks; pinner set to 0), fixed order.
+tsk_status dense_residual_partials(const TensorView& T, const double* M, const double* A1,
+                                   int64_t R1, int nblocks, double* pdirect, double* pnorm,
+                                   double* pinner, hipStream_t st);
 // res (device double) <- relative residual; with_norm recomputes ||T||^2 into fs.nT2
 tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
                    const double* const* factors, bool with_norm, FitScratch& fs, double* res,

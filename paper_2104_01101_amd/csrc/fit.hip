@@ -1,5 +1,7 @@
 // Relative residual ||T - T~||_F / ||T||_F of a Tucker model (1 - fitness,
-// Sec. 7), in FP64.  Dense tensors: sum of (T - T~)^2 over all entries.  COO
+// Sec. 7), in FP64.  Dense tensors: sum of (T - T~)^2 over all entries, T~
+// from the mode products of the core with every factor but the first and one
+// R_1-term product per entry.  COO
 // tensors (T~ is dense, T is not): ||T||^2 - 2 <T, T~> + ||T~||^2, whose
 // cancellation limits the relative residual to ~1e-8 near an exact fit:
 //   <T, T~>  per stored entry, T~(i) = sum_rho C(rho) prod_k A^(k)(i_k, rho_k)
@@ -270,6 +272,64 @@ __device__ double block_sum_of(const double* p, int n, double* red) {
   return s;
 }
 
+// ---- dense tensors: T~ from one mode product per entry ----
+// M = C x_2 A^(2) ... x_N A^(N) (R_1 x s_2 x ... x s_N) by mode products
+// (k_ttm); then T~(i, j) = sum_a A^(1)(i, a) M(a, j) with j the row-major
+// index of the modes 2..N, so each entry costs R_1 multiply-adds and the
+// model is never stored.
+// out (P x s_k x Q) = in (P x R_k x Q) contracted with A (s_k x R_k) over R_k
+__global__ void k_ttm(const double* in, int64_t P, int64_t Rk, int64_t Q, const double* A,
+                      int64_t sk, double* out) {
+  const int64_t total = P * sk * Q;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t q = t % Q, pi = t / Q, i = pi % sk, pp = pi / sk;
+    const double* a = A + i * Rk;
+    const double* x = in + pp * Rk * Q + q;
+    double acc = 0.0;
+    for (int64_t c = 0; c < Rk; ++c) acc = fma(a[c], x[c * Q], acc);
+    out[t] = acc;
+  }
+}
+
+// per block: sum over its columns j and every i of (T(i, j) - T~(i, j))^2,
+// and of T(i, j)^2; one thread per column, the column of M in registers, the
+// rows of A^(1) read as wave-uniform (scalar) loads
+template <class V, int RM>
+__global__ __launch_bounds__(kT) void k_fit_dense(const V* __restrict__ X, const double* __restrict__ M,
+                                                  const double* __restrict__ A1, int64_t s1,
+                                                  int R1, int64_t J, int64_t per_block,
+                                                  double* pdirect, double* pnorm, double* pinner) {
+  __shared__ double red[kT / 64];
+  const int64_t lo = int64_t(blockIdx.x) * per_block;
+  const int64_t hi = lo + per_block < J ? lo + per_block : J;
+  double acc = 0.0, nrm = 0.0;
+  for (int64_t j = lo + threadIdx.x; j < hi; j += kT) {
+    double m[RM];
+#pragma unroll
+    for (int a = 0; a < RM; ++a) m[a] = a < R1 ? M[a * J + j] : 0.0;
+    for (int64_t i = 0; i < s1; ++i) {
+      const double* ar = A1 + i * R1;
+      double t = 0.0;
+#pragma unroll
+      for (int a = 0; a < RM; ++a)
+        if (a < R1) t = fma(ar[a], m[a], t);
+      const double v = double(X[i * J + j]);
+      const double d = v - t;
+      acc = fma(d, d, acc);
+      nrm = fma(v, v, nrm);
+    }
+  }
+  acc = block_reduce(acc, red);
+  __syncthreads();
+  nrm = block_reduce(nrm, red);
+  if (threadIdx.x == 0) {
+    pdirect[blockIdx.x] = acc;
+    pnorm[blockIdx.x] = nrm;
+    pinner[blockIdx.x] = 0.0;
+  }
+}
+
 // k_model_norm2 and k_finish in one workgroup, the mode products of the
 // model norm ping-ponging between two LDS buffers of csize doubles.
 __global__ __launch_bounds__(kT) void k_finish_model(FitArgs a, const double* core, int64_t csize,
@@ -337,6 +397,37 @@ __global__ __launch_bounds__(kT) void k_finish(const double* pn, int nbn, const 
 
 }  // namespace
 
+tsk_status dense_residual_partials(const TensorView& T, const double* M, const double* A1,
+                                   int64_t R1, int nblocks, double* pdirect, double* pnorm,
+                                   double* pinner, hipStream_t st) {
+  if (T.layout != TSK_DENSE || R1 < 1 || R1 > kDenseFitMaxR) {
+    set_error("dense residual: not a dense tensor or rank %lld outside [1, %d]", (long long)R1,
+              kDenseFitMaxR);
+    return TSK_EUNSUPPORTED;
+  }
+  const int64_t s1 = T.dims[0], J = T.nnz / s1;
+  const int64_t perj = ceil_div(J, nblocks);
+  const int r1 = int(R1);
+#define TSK_FITD(V, RM)                                                                       \
+  hipLaunchKernelGGL((k_fit_dense<V, RM>), dim3(nblocks), dim3(kT), 0, st,                    \
+                     static_cast<const V*>(T.values), M, A1, s1, r1, J, perj, pdirect, pnorm, \
+                     pinner)
+  if (T.dtype == TSK_F64) {
+    if (r1 <= 8) TSK_FITD(double, 8);
+    else if (r1 <= 16) TSK_FITD(double, 16);
+    else if (r1 <= 32) TSK_FITD(double, 32);
+    else TSK_FITD(double, 64);
+  } else {
+    if (r1 <= 8) TSK_FITD(float, 8);
+    else if (r1 <= 16) TSK_FITD(float, 16);
+    else if (r1 <= 32) TSK_FITD(float, 32);
+    else TSK_FITD(float, 64);
+  }
+#undef TSK_FITD
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
 tsk_status fit_plan(const TensorView& T, const int64_t* R, FitScratch& fs, Ws& ws) {
   int64_t csize = 1, gsz = 0;
   for (int k = 0; k < T.order; ++k) csize *= R[k], gsz += R[k] * R[k];
@@ -351,6 +442,20 @@ tsk_status fit_plan(const TensorView& T, const int64_t* R, FitScratch& fs, Ws& w
   fs.buf1 = ws.take<double>(csize);
   fs.model2 = ws.take<double>(1);
   fs.nT2 = ws.take<double>(1);
+  fs.ttm[0] = fs.ttm[1] = nullptr;
+  if (T.layout == TSK_DENSE && R[0] <= kDenseFitMaxR) {
+    // mode products k = N-1 .. 1 alternate between two buffers, the last
+    // (the largest, R_1 x s_2 x ... x s_N) landing in ttm[0]
+    int64_t need[2] = {0, 0};
+    int64_t size = csize;
+    for (int k = T.order - 1, step = 0; k >= 1; --k, ++step) {
+      size = size / R[k] * T.dims[k];
+      const int buf = ((T.order - 1 - step) & 1) ? 0 : 1;  // the last step (k = 1) -> 0
+      need[buf] = std::max(need[buf], size);
+    }
+    fs.ttm[0] = ws.take<double>(need[0]);
+    fs.ttm[1] = ws.take<double>(std::max<int64_t>(need[1], 1));
+  }
   return TSK_OK;
 }
 
@@ -385,6 +490,37 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
   ProfScope prof("fit", st);
   if (rmax_g <= 64)  // the factor Grams of every mode in one launch
     TSK_TRY(gram_batch_f64(T.order, R, T.dims, factors, gp, st));
+  if (T.layout == TSK_DENSE && fs.ttm[0]) {
+    // M = C x_2 A^(2) ... x_N A^(N), then the fused residual over the entries
+    const int N = T.order;
+    const double* in = core;
+    int64_t P = csize, Q = 1;
+    for (int k = N - 1, step = 0; k >= 1; --k, ++step) {
+      P /= R[k];
+      double* out = fs.ttm[((N - 1 - step) & 1) ? 0 : 1];
+      const int64_t total = P * T.dims[k] * Q;
+      hipLaunchKernelGGL(k_ttm, dim3(unsigned(std::min<int64_t>(ceil_div(total, kT), 8192))),
+                         dim3(kT), 0, st, in, P, R[k], Q, factors[k], T.dims[k], out);
+      TSK_LAUNCHED();
+      in = out;
+      Q *= T.dims[k];
+    }
+    TSK_TRY(dense_residual_partials(T, in, factors[0], R[0], fs.nblocks, fs.partial_direct,
+                                    fs.partial_norm, fs.partial_inner, st));
+    // with_norm is implied: the fused kernel sums T^2 as well
+    if (csize <= 4096) {
+      hipLaunchKernelGGL(k_finish_model, dim3(1), dim3(kT), size_t(2 * csize) * 8, st, a, core,
+                         csize, fs.grams, fs.partial_norm, fs.nblocks, fs.partial_inner,
+                         fs.nblocks, fs.partial_direct, 1, fs.nT2, res);
+      TSK_LAUNCHED();
+      return TSK_OK;
+    }
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kT), 0, st, fs.partial_norm, fs.nblocks,
+                       fs.partial_inner, fs.nblocks, fs.partial_direct, 1, fs.model2, fs.nT2,
+                       res);
+    TSK_LAUNCHED();
+    return TSK_OK;
+  }
   int64_t per = ceil_div(T.nnz, fs.nblocks);
   if (with_norm) {
     hipLaunchKernelGGL(k_norm2, dim3(fs.nblocks), dim3(kT), 0, st, a, T.nnz, per,

@@ -32,6 +32,15 @@ struct PassJob {
 tsk_status sketch_pass(const TensorView& T, const PassJob* jobs, int njobs, Ws& ws,
                        hipStream_t st);
 
+// ---- dense range-finder pass (rrf_dense.hip) ----
+// B (s_n x k1, FP64) = T_(n) Omega^T G for a dense T: CountSketch (g, tau) of
+// the other-mode row-major index from draw(key, j), G k2 x k1 (device FP64);
+// one structured GEMM over T in the operand precision (FP64 for FP64 tensors
+// or prec = F64, BF16 with FP32 accumulation for prec = BF16, else FP32).
+bool rrf_dense_supported(const TensorView& T, int64_t k1);
+tsk_status rrf_dense(const TensorView& T, int n, int64_t k1, int64_t k2, uint64_t key,
+                     const double* G, int prec, double* B, Ws& ws, hipStream_t st);
+
 // ---- random tables (rng.hip) ----
 // h[i] = bucket_m(draw(key, i)), sg[i] = sign(draw(key, i)), i < s
 tsk_status launch_hash_table(uint64_t key, int64_t s, int64_t m, int32_t* h, int8_t* sg,

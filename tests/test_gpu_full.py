@@ -12,9 +12,13 @@ and after 9 sweeps (same test matrices: the streams are keyed by the absolute
 sweep); all within 1e-5, the FP32 operand tolerance; and bitwise
 repeatability of the whole job.
 
-zipf10k -- 10000^3 with 10^7 Zipf(1.1) entries: the FP32 sketch pass of one
-mode against the oracle's FP64 per-cell sums, within the bound of FP32
-summation in input order, and bitwise repeatable.
+zipf10k -- 10000^3 with 10^7 Zipf(1.1) entries, the default benchmark job
+(TensorSketch m = 2048, rank 16, RRF init, 5 sweeps, RSVD-LRLS with the
+Gram inverted by block sweeps and the products with Y in the O(m s k)
+order, FP32 operands): the first two sweeps of the whole job and one sweep
+replayed by the oracle from the GPU's factors after 4 sweeps, within 1e-5;
+the FP32 sketch pass of one mode against the oracle's FP64 per-cell sums,
+within the bound of FP32 summation in input order, and bitwise repeatable.
 
 Leverage sampling of the COO tensors (fibre indices): the sampled fibres of
 sparse2000 and zipf10k (whose head fibres hold thousands of entries) equal the
@@ -83,6 +87,21 @@ def test_sparse2000_job_repeatable(tsk, sparse2000):
     assert torch.equal(c1, c2)
     for a, b in zip(f1, f2):
         assert torch.equal(a, b)
+
+
+def test_zipf10k_job_vs_oracle(tsk, zipf10k):
+    w = zipf10k
+    To = osk.Tensor(w.dims, w.idx, w.val.astype(np.float64))
+    _, _, fits = _plan(tsk, w).run()
+    assert len(fits) == w.sweeps
+    ref = otk.sketch_tucker_als(To, w.ranks, w.m, 2, seed=0, solve_kind="rsvd")
+    np.testing.assert_allclose(fits[:2], ref["fits"], rtol=0, atol=1e-5)
+    t = w.sweeps - 1
+    _, factors_t, _ = _plan(tsk, w, sweeps=t).run()
+    step = otk.sketch_tucker_als(To, w.ranks, w.m, 1, seed=0, solve_kind="rsvd", init="user",
+                                 init_factors=[F.cpu().numpy() for F in factors_t],
+                                 first_sweep=t)
+    np.testing.assert_allclose(fits[t], step["fits"][0], rtol=0, atol=1e-5)
 
 
 def _tables_np(h, s):
