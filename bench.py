@@ -47,15 +47,15 @@ FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 
 # source files whose kernels make up each launch group (for the traffic check)
 GROUP_SOURCES = {
-    "sketch_pass": ["sketch_pass.hip"], "rrf_pass": ["sketch_pass.hip"],
+    "sketch_pass": ["sketch_pass.hip"], "rrf_pass": ["sketch_pass.hip", "rrf_dense.hip"],
     "ts_lhs": ["ts_lhs.hip"], "gram": ["gemm.hip"], "solve_la": ["linalg.hip", "gemm.hip"],
     "eig": ["linalg.hip"], "fit": ["fit.hip"], "rrf": ["linalg.hip", "gemm.hip", "api.hip"],
     "leverage": ["leverage.hip"], "fiber_index": ["fibers.hip"], "fiber_rows": ["fibers.hip"],
-    "select": ["select.hip"],
+    "select": ["select.hip"], "cp_core": ["cp.hip", "fit.hip"],
 }
 GROUPS = ["sketch_pass", "rrf_pass", "rrf", "ts_lhs", "gram", "solve_la", "eig", "fit",
-          "leverage", "fiber_index", "fiber_rows", "select"]
-WORKLOADS = ["zipf10k", "sparse2000", "sparse2000lev", "sparse2000det"]
+          "leverage", "fiber_index", "fiber_rows", "select", "cp_core"]
+WORKLOADS = ["zipf10k", "sparse2000", "sparse2000lev", "sparse2000det", "dense4d200", "cp500"]
 PHASES = ["phase_prep", "phase_init", "phase_sweeps", "phase_fit"]
 
 
@@ -145,7 +145,9 @@ def parse():
                          "sparse2000 (2000^3, 1e6 uniform entries, rank 10, m = 1600), "
                          "sparse2000lev / sparse2000det (the same tensor under "
                          "leverage-score sampling / deterministic leverage selection, "
-                         "through the fibre indices)")
+                         "through the fibre indices), dense4d200 (dense 200^4, rank 10, "
+                         "leverage m = 4000), cp500 (dense 500^3 CP rank 20, leverage "
+                         "Tucker to rank 30, m = 14400, then CP-ALS on the core)")
     ap.add_argument("--solve", default="rsvd", choices=["rsvd", "exact"],
                     help="subproblem solver: rsvd = RSVD-LRLS (Alg. 5, the solver Alg. 4 "
                          "calls) or exact = truncated SVD of Z^+ Y")
@@ -176,7 +178,9 @@ def group_work(w, solve="exact"):
     bytes for HBM-bound groups, flops otherwise."""
     N = len(w.dims)
     s, R, m, sweeps = w.dims[0], w.ranks[0], w.m, w.sweeps
-    nnz = w.val.shape[0]
+    dense = w.dense is not None
+    nnz = w.dense.size if dense else w.val.shape[0]
+    ib = 0 if dense else 4 * N  # index bytes per stored entry
     r = R ** (N - 1)
     q = min(r, s)
     k1 = math.ceil(math.sqrt(m / r) * R - 1e-9)
@@ -208,8 +212,11 @@ def group_work(w, solve="exact"):
         q_eig = q
     return {
         # COO stream (N int32 indices + value) read once, every Y^(n) written once
-        "sketch_pass": ("hbm", nnz * (4 * N + vb) + N * m * s * vb, HBM_PEAK_GBS, "GB/s"),
-        "rrf_pass": ("hbm", nnz * (4 * N + vb) + (N - 1) * k2 * s * vb, HBM_PEAK_GBS, "GB/s"),
+        "sketch_pass": ("hbm", nnz * (ib + vb) + N * m * s * vb, HBM_PEAK_GBS, "GB/s"),
+        # sparse: one pass over the entries writing W; dense: the tensor read
+        # once per initialised mode by the structured GEMM
+        "rrf_pass": (("hbm", (N - 1) * nnz * vb, HBM_PEAK_GBS, "GB/s") if dense else
+                     ("hbm", nnz * (ib + vb) + (N - 1) * k2 * s * vb, HBM_PEAK_GBS, "GB/s")),
         # B = W G (s x k2 x k1) and the Gram of B, per initialised mode
         "rrf": ("mfma", (N - 1) * (2.0 * s * k2 * k1 + 2.0 * s * k1 * k1),
                 PEAK_TFLOPS["f64"], "TFLOP/s"),
@@ -220,9 +227,12 @@ def group_work(w, solve="exact"):
         "solve_la": ("mfma", subs * la, PEAK_TFLOPS["f64"], "TFLOP/s"),
         # tridiagonalisation + back-transformation of R vectors (FP64 vector ALU)
         "eig": ("alu", subs * eig(q_eig) + (N - 1) * eig(k1), FP64_VECTOR_TFLOPS, "TFLOP/s"),
-        # after the last sweep, per entry: core contraction R^3 + R^2 + R
-        # multiply-adds (FP64)
-        "fit": ("alu", nnz * 2.0 * (R ** 3 + R ** 2 + R), FP64_VECTOR_TFLOPS, "TFLOP/s"),
+        # after the last sweep: sparse, per entry the core contraction
+        # R^3 + R^2 + R multiply-adds (FP64); dense, the tensor read once
+        "fit": (("hbm", nnz * vb, HBM_PEAK_GBS, "GB/s") if dense else
+                ("alu", nnz * 2.0 * (R ** 3 + R ** 2 + R), FP64_VECTOR_TFLOPS, "TFLOP/s")),
+        # CP-ALS on the core and the CP residual against the dense tensor
+        "cp_core": ("hbm", nnz * vb, HBM_PEAK_GBS, "GB/s"),
         # sampled Kronecker rows: factors read, Z written
         "leverage": ("hbm", subs * ((N - 1) * s * R * 8 + m * r * vo), HBM_PEAK_GBS, "GB/s"),
         # per mode: keys built (indices read, keys written), then sorted pairs written once
@@ -310,10 +320,24 @@ def main():
     w = workload(args.workload)
     if args.prec:
         w["prec"] = args.prec
-    T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(dev), torch.from_numpy(w.val).to(dev), w.dims)
-    plan = tsk.TuckerPlan(T, w.ranks, w.m, w.sweeps, sketch=w.sketch, init="rrf", prec=w.prec,
-                          seed=0, record_fit="final", solve=args.solve)
-    second = "sketch_pass" if w.sketch == "ts" else "fiber_rows"
+    dense = w.dense is not None
+    if dense:
+        T = tsk.Tensor.dense(torch.from_numpy(w.dense).to(dev))
+    else:
+        T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(dev), torch.from_numpy(w.val).to(dev),
+                           w.dims)
+    cp = w.get("cp_rank") is not None
+    if cp:  # Alg. 6: the job is CP-Sketch-Tucker; its CP residual is the result
+        class _CpJob:
+            def run(self):
+                _, f = tsk.cp_via_tucker(T, w.cp_rank, w.ranks, w.m, w.sweeps, w.cp_sweeps,
+                                         sketch=w.sketch, prec=w.prec, seed=0, solve=args.solve)
+                return None, None, [f]
+        plan = _CpJob()
+    else:
+        plan = tsk.TuckerPlan(T, w.ranks, w.m, w.sweeps, sketch=w.sketch, init="rrf",
+                              prec=w.prec, seed=0, record_fit="final", solve=args.solve)
+    second = ("sketch_pass" if w.sketch == "ts" else "rrf_pass" if dense else "fiber_rows")
     lib = L.lib()
     lib.tsk_profile_enable.argtypes = [ctypes.c_char_p]
     lib.tsk_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -383,13 +407,22 @@ def main():
                                         "of Alg. 4, FP32 operands",
                        "zipf10k": "sparse 10000^3, 1e7 nnz Zipf(1.1), lognormal values, "
                                   "Tucker rank 16, TensorSketch m=2048, RRF init, 5 sweeps, "
-                                  "FP32 operands"}[args.workload].replace(
+                                  "FP32 operands",
+                       "dense4d200": "dense 200^4 FP32 (6.4 GB), Tucker rank 10 + 1% noise, "
+                                     "leverage-score sampling m=4000, RRF init, 5 sweeps of "
+                                     "Alg. 4, FP32 operands",
+                       "cp500": "dense 500^3 FP32, CP rank 20 (collinearity 0.9) + 1% noise; "
+                                "Alg. 6: leverage-sampled Tucker to rank 30 (m=14400, RRF "
+                                "init, 5 sweeps), CP-ALS rank 20 on the core (25 sweeps), "
+                                "FP32 operands"}[args.workload].replace(
                        "FP32 operands", {"f32": "FP32", "bf16": "BF16 (FP32-accumulated)",
                                          "f64": "FP64"}[w.prec] + " operands"),
-                   "dims": list(w.dims), "nnz": int(w.val.shape[0]), "ranks": list(w.ranks),
+                   "dims": list(w.dims),
+                   "nnz": int(w.dense.size if dense else w.val.shape[0]), "ranks": list(w.ranks),
                    "m": w.m, "sweeps": w.sweeps, "prec": w.prec,
                    "solve": "RSVD-LRLS (Alg. 5)" if args.solve == "rsvd" else "exact truncated SVD"},
-        "final_relative_residual": fits[-1] if fits else None,
+        ("final_cp_relative_residual" if cp else "final_relative_residual"):
+            fits[-1] if fits else None,
         "phases_ms_per_step": {p[6:]: round(v, 4) for p, v in phases.items()},
         "sweep_loop_sweeps_per_s": (w.sweeps / (phases["phase_sweeps"] / 1e3)
                                     if phases["phase_sweeps"] > 0 else None),
@@ -397,7 +430,8 @@ def main():
         f"{second}_roofline": roofline(second, work, sp[0], sp[1], args.steps, args.workload),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.solve, 1 if args.workload == "zipf10k" else 3)
+        out["cpu_baseline"] = (cpu_baseline_dense(w, args.solve) if dense else
+                               cpu_baseline(w, args.solve, 1 if args.workload == "zipf10k" else 3))
     print(json.dumps(out))
 
 
@@ -453,6 +487,58 @@ def cpu_baseline(w, solve="exact", sample_sweeps=3):
                       f"{w.sweeps} sweeps ({t_sweep:.2f} s each) and one residual "
                       f"({t_fit:.2f} s) timed, job = preparation + {w.sweeps} sweeps + "
                       f"residual"}
+
+
+def cpu_baseline_dense(w, solve="rsvd", slab=0.02):
+    """FP64 oracle on a bounded sample of a dense workload: one sweep of the
+    leverage-sampled subproblems on the full tensor (from random orthonormal
+    factors), and the range finder of one mode and the residual on a slab of
+    the first `slab` of the mode-0 slices, scaled by the entry count to all
+    the range-finder modes and the whole tensor."""
+    import numpy as np
+    from oracle import sketch as osk, solve as osv, tucker as otk
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    X, N, m, ranks = w.dense, len(w.dims), w.m, w.ranks
+    rs = np.random.default_rng(0)
+    factors = [np.linalg.qr(rs.standard_normal((d, R)))[0] for d, R in zip(w.dims, ranks)]
+    t0 = time.perf_counter()
+    for n in range(N):
+        idx, wt = osk.leverage_sample(factors, m, 0, 0, n)
+        Z = osk.leverage_lhs(factors, idx, wt, n)
+        Y = osk.leverage_rhs_dense(X, idx, wt, n)
+        if solve == "rsvd":
+            kk = otk.rsvd_width(ranks[n], Z.shape[1])
+            A, W = osv.rsvd_lrls(Z, Y, ranks[n], otk.rsvd_omega(0, 0, n, w.dims[n], kk))
+        else:
+            A, W, _ = osv.rc_solve(Z, Y, ranks[n])
+        factors[n] = A
+        core = otk.W_to_core(W, ranks, n)
+    t_sweep = time.perf_counter() - t0
+    rows = max(1, int(round(slab * w.dims[0])))
+    Xs = np.ascontiguousarray(X[:rows], dtype=np.float64)
+    scale = X.shape[0] / rows
+    Ts = osk.Tensor.from_dense(Xs)
+    t1 = time.perf_counter()
+    k1, k2 = otk.default_rrf_sizes(m, ranks, 1)
+    otk.init_rrf(Ts, 1, ranks[1], k1, k2, 0)
+    t_rrf = (time.perf_counter() - t1) * scale * (N - 1)
+    fs = [factors[0][:rows]] + factors[1:]
+    t2 = time.perf_counter()
+    otk.relative_residual(Ts, core, fs)
+    t_fit = (time.perf_counter() - t2) * scale
+    job = t_rrf + w.sweeps * t_sweep + t_fit
+    return {"value": w.sweeps / job, "unit": "sweeps/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"one sweep of the {N} leverage-sampled subproblems on the full tensor "
+                      f"({t_sweep:.2f} s); range finder of one mode and the residual on "
+                      f"{rows} of {w.dims[0]} mode-0 slices, scaled by entries to "
+                      f"{N - 1} modes ({t_rrf:.2f} s) and the whole tensor ({t_fit:.2f} s); "
+                      f"job = range finder + {w.sweeps} sweeps + residual"
+                      + ("; the CP-ALS on the 30^3 core is not timed" if
+                         w.get("cp_rank") else "")}
 
 
 if __name__ == "__main__":

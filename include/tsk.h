@@ -207,10 +207,13 @@ tsk_status tsk_cp_workspace_size(const tsk_tensor* T, int32_t cp_rank,
  * {A^(n)} <- CP-ALS(C, cp_rank) (Alg. 2, normal equations with the
  * pseudo-inverse of the Hadamard product of Grams, cp_sweeps sweeps) started
  * from the HOSVD of the core (Sec. 7); returns cp_factors[n] = B^(n) A^(n).
+ * The Hadamard product of the Grams is positive definite when the core
+ * factors have full column rank, and its pseudo-inverse is then its inverse.
  *   cp_rank <= min_n tucker_ranks[n]
  *   cp_factors host array of N device double*, s_n x cp_rank (output)
  *   cp_fit     host double or NULL: ||T - sum_r a_r o b_r o ...|| / ||T||
- * Synchronous.  Errors as tsk_tucker_sketch_als. */
+ * Synchronous.  Errors as tsk_tucker_sketch_als; ENUMERIC also when a Hadamard
+ * product of Grams is not positive definite (core factors of lower rank). */
 tsk_status tsk_cp_via_tucker(const tsk_tensor* T, int32_t cp_rank,
                              const int32_t* tucker_ranks, int32_t cp_sweeps,
                              const tsk_options* opt, double* const* cp_factors,

@@ -71,11 +71,13 @@ def cp_relative_residual(T, factors):
 
 
 def cp_sketch_tucker(T, cp_rank, tucker_ranks, m, tucker_sweeps, cp_sweeps, seed=0,
-                     sketch_kind="lev", init="rrf"):
-    """Alg. 6: Tucker compression by Alg. 4, CP-ALS on the core (HOSVD init),
-    return the factors B^(n) A^(n) and the CP relative residual."""
+                     sketch_kind="lev", init="rrf", solve_kind="exact"):
+    """Alg. 6: Tucker compression by Alg. 4 (subproblem solver solve_kind),
+    CP-ALS on the core (HOSVD init), return the factors B^(n) A^(n) and the CP
+    relative residual."""
     tk = tucker.sketch_tucker_als(T, tucker_ranks, m, tucker_sweeps, seed=seed,
-                                  sketch_kind=sketch_kind, init=init, record_fit=False)
+                                  sketch_kind=sketch_kind, init=init, record_fit=False,
+                                  solve_kind=solve_kind)
     C, B = tk["core"], tk["factors"]
     init_cp = tucker.hosvd(C, [cp_rank] * C.ndim)
     A = cp_als(C, init_cp, cp_sweeps)

@@ -205,6 +205,9 @@ tsk_status rrf_finish(const TensorView& T, int n, int64_t R, uint64_t seed, RrfB
 }
 
 // ------------------------------------------------------------ driver ----
+// device breakdown flags of a driver run (see finish_sync)
+constexpr int kInfoSlots = 5;
+
 struct TuckerArgs {
   TensorView T;
   int64_t R[TSK_MAX_ORDER];
@@ -290,7 +293,7 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
     Rmax = std::max<int64_t>(Rmax, a.R[n]);
   }
   // ---- persistent allocations ----
-  a.info_dev = ws.take<int>(4);
+  a.info_dev = ws.take<int>(kInfoSlots);
   a.fit_dev = ws.take<double>(std::max(1, o.sweeps));
   std::vector<int32_t*> h(N * N, nullptr);
   std::vector<int8_t*> sg(N * N, nullptr);
@@ -370,7 +373,7 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
   };
 
   // ---- preparation: maps, sketched right-hand sides (Sec. 6.1) ----
-  if (run) TSK_HIP(hipMemsetAsync(a.info_dev, 0, 4 * sizeof(int), st));
+  if (run) TSK_HIP(hipMemsetAsync(a.info_dev, 0, kInfoSlots * sizeof(int), st));
   {
   ProfScope phase(run ? "phase_prep" : "", st);
   if (ts) {  // maps and their inverse tables, batched when every table fits in LDS
@@ -544,7 +547,7 @@ tsk_status make_args(const tsk_tensor* T, const int32_t* ranks, const tsk_option
 tsk_status finish_sync(TuckerArgs& a, double* fit_history, int32_t* sweeps_done) {
   hipStream_t st = as_stream(a.opt.stream);
   TSK_HIP(hipStreamSynchronize(st));
-  int info[4] = {0, 0, 0, 0};
+  int info[kInfoSlots] = {0, 0, 0, 0, 0};
   TSK_HIP(hipMemcpy(info, a.info_dev, sizeof(info), hipMemcpyDeviceToHost));
   if (fit_history && a.sweeps_done > 0) {
     if (a.opt.flags & TSK_FLAG_FINAL_FIT) {  // only the last sweep was evaluated
@@ -559,13 +562,14 @@ tsk_status finish_sync(TuckerArgs& a, double* fit_history, int32_t* sweeps_done)
   if (sweeps_done) *sweeps_done = a.sweeps_done;
   // info: [0] a sketched Gram's pivot, [1] the QR of a solve's factor, [2] the
   // initialisation (range finder or QR of the random start), [3] a zero
-  // singular value of a subproblem
-  if (info[0] || info[1] || info[2] || info[3]) {
-    set_error("numerical breakdown: %s%s%s%s",
+  // singular value of a subproblem, [4] a Hadamard Gram of CP-ALS
+  if (info[0] || info[1] || info[2] || info[3] || info[4]) {
+    set_error("numerical breakdown: %s%s%s%s%s",
               info[0] ? "sketched Gram not positive definite; " : "",
               info[1] ? "factor QR of a solve failed; " : "",
               info[2] ? "initialisation failed (zero or rank-deficient range); " : "",
-              info[3] ? "sketched right-hand side of rank below R; " : "");
+              info[3] ? "sketched right-hand side of rank below R; " : "",
+              info[4] ? "CP-ALS Gram of the core factors not positive definite; " : "");
     return TSK_ENUMERIC;
   }
   return TSK_OK;
@@ -580,7 +584,8 @@ tsk_status run_cp(TuckerArgs& a, int Rc, int cp_sweeps, double* const* cp_factor
   for (int k = 0; k < a.T.order; ++k) a.factors[k] = tb.factors[k];
   TSK_TRY(run_tucker(a, ws));
   double* fd = nullptr;
-  TSK_TRY(cp_run(a.T, a.R, Rc, cp_sweeps, tb, cp_factors, &fd, ws, as_stream(a.opt.stream)));
+  TSK_TRY(cp_run(a.T, a.R, Rc, cp_sweeps, tb, cp_factors, &fd, a.info_dev + 4, ws,
+                 as_stream(a.opt.stream)));
   if (fit_dev) *fit_dev = fd;
   return TSK_OK;
 }

@@ -3,8 +3,9 @@
 //         (eigenvectors of C_(k) C_(k)^T, sign rule of the factors)
 //   CP-ALS (Alg. 2) on the core, subproblem eq. (subproblem) by the normal
 //         equations: A_n = MTTKRP(C, n) pinv(hadamard_{k != n} A_k^T A_k);
-//         the pseudo-inverse from the eigen-decomposition of the R_cp x R_cp
-//         Gram, eigenvalues below 1e-15 * max treated as zero
+//         the Hadamard Gram is SPD when the factors have full column rank,
+//         so its pseudo-inverse is its inverse, taken by symmetric sweeps (a
+//         non-positive pivot is reported as a breakdown)
 //   output B^(n) A_n and the CP relative residual against the input tensor.
 // All FP64; the core (at most a few 10^4 entries) stays in device memory.
 
@@ -134,20 +135,6 @@ __global__ void k_hadamard_grams(const double* grams, int N, int n, int64_t Rc, 
   Gam[t] = v;
 }
 
-// P = V diag(1/lam if lam > 1e-15 max lam) V^T
-__global__ void k_pinv_from_eig(const double* V, const double* lam, int64_t Rc, double* P) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= Rc * Rc) return;
-  const int64_t a = t / Rc, b = t % Rc;
-  double lmax = 0.0;
-  for (int64_t c = 0; c < Rc; ++c) lmax = fmax(lmax, fabs(lam[c]));
-  double s = 0.0;
-  for (int64_t c = 0; c < Rc; ++c)
-    if (lam[c] > 1e-15 * lmax) s += V[a * Rc + c] * V[b * Rc + c] / lam[c];
-  P[t] = s;
-}
-
-
 __global__ void k_cp_inner(CpFitArgs a, int64_t nnz, int64_t per, double* pn, double* pi) {
   __shared__ double rn[4], ri[4];
   int64_t lo = int64_t(blockIdx.x) * per, hi = lo + per < nnz ? lo + per : nnz;
@@ -208,8 +195,8 @@ tsk_status cp_tucker_bufs(const TensorView& T, const int64_t* R, CpTuckerBufs& b
 }
 
 tsk_status cp_run(const TensorView& T, const int64_t* R, int Rc, int sweeps,
-                  const CpTuckerBufs& tb, double* const* cp_factors, double** fit_dev, Ws& ws,
-                  hipStream_t st) {
+                  const CpTuckerBufs& tb, double* const* cp_factors, double** fit_dev, int* info,
+                  Ws& ws, hipStream_t st) {
   const int N = T.order;
   const bool run = !ws.measuring();
   CoreDesc cd{};
@@ -227,7 +214,6 @@ tsk_status cp_run(const TensorView& T, const int64_t* R, int Rc, int sweeps,
   double* lam = ws.take<double>(Rmax);
   double* grams = ws.take<double>(N * Rc * Rc);
   double* Gam = ws.take<double>(Rc * Rc);
-  double* V = ws.take<double>(Rc * Rc);
   double* P = ws.take<double>(Rc * Rc);
   double* M = ws.take<double>(Rmax * Rc);
   double* fgrams = ws.take<double>(N * Rc * Rc);
@@ -267,15 +253,21 @@ tsk_status cp_run(const TensorView& T, const int64_t* R, int Rc, int sweeps,
                            N, n, int64_t(Rc), Gam);
         TSK_LAUNCHED();
       }
-      TSK_TRY(sym_eig_top(Gam, Rc, Rc, lam, V, ws, st));
+      // the Hadamard Gram is SPD for factors of full column rank, so its
+      // pseudo-inverse is its inverse (sweeps; a non-positive pivot is
+      // reported as a breakdown)
+      const double* Pinv = P;
+      if (spd_inverse_fits(Rc)) {
+        if (run) TSK_TRY(spd_inverse(Gam, Rc, Rc, info, st));
+        Pinv = Gam;
+      } else {
+        TSK_TRY(spd_inverse_blocked(Gam, Rc, Rc, P, Rc, info, ws, st));
+      }
       if (run) {
-        hipLaunchKernelGGL(k_pinv_from_eig, dim3(ceil_div(Rc * Rc, 256)), dim3(256), 0, st, V, lam,
-                           int64_t(Rc), P);
-        TSK_LAUNCHED();
         hipLaunchKernelGGL(k_mttkrp, dim3(unsigned(R[n])), dim3(kMtT), 0, st, tb.core, cd, f, n,
                            int64_t(Rc), M);
         TSK_LAUNCHED();
-        TSK_TRY(gemm_small(R[n], Rc, Rc, 1.0, M, Rc, 1, P, Rc, 1, 0.0, A[n], Rc, st));
+        TSK_TRY(gemm_small(R[n], Rc, Rc, 1.0, M, Rc, 1, Pinv, Rc, 1, 0.0, A[n], Rc, st));
       }
       release();
     }

@@ -202,3 +202,84 @@ def test_sparse2000det_k16_breakdown_is_reported(tsk, monkeypatch):
         tsk.tucker_sketch_als(T, w.ranks, w.m, w.sweeps, sketch="lev_det", init="rrf",
                               prec=w.prec, seed=0, solve="rsvd")
     assert e.value.status == L.ENUMERIC
+
+
+# ---------------------------------------------------------------- dense ----
+def test_dense4d200_rrf_rank_one_full_size(tsk):
+    """The dense range-finder pass at the 200^4 shape (6.4 GB FP32 and the
+    FP64 pass on the same values): for a rank-one tensor a o b o c o d,
+    T_(n) Omega^T G = (mode-n vector) x (row vector), so the range finder's
+    single left singular vector is the normalised mode-n vector (sign rule) --
+    a closed form that every indexing or hashing mistake in the pass breaks."""
+    rs = np.random.default_rng(41)
+    vecs = [rs.standard_normal(200) for _ in range(4)]
+    v = [torch.from_numpy(x).to(DEV) for x in vecs]
+    for dt, tol in ((torch.float32, 1e-5), (torch.float64, 1e-10)):
+        # the outer product formed in the tensor's precision (FP32: entries
+        # rounded, so the mode-n vector holds to FP32 rounding)
+        vv = [x.to(dt) for x in v]
+        T = tsk.Tensor.dense(torch.einsum("a,b,c,d->abcd", *vv).contiguous())
+        for n in range(4):
+            A = tsk.rrf_init(T, n, 1, 4, 8, 3).cpu().numpy()[:, 0]
+            e = vecs[n] / np.linalg.norm(vecs[n])
+            e = e if e[np.argmax(np.abs(e))] > 0 else -e
+            np.testing.assert_allclose(A, e, rtol=0, atol=tol)
+        del T
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def dense4d200():
+    return workloads.dense4d200()
+
+
+def test_dense4d200_leverage_sketch_full_size(tsk, dense4d200):
+    """200^4, m = 4000: the range-finder factors of modes 2..4 (FP32 pass) and
+    a random orthonormal first factor drive the leverage sampler of every mode;
+    the sample indices equal the oracle's bit for bit, the weights, the
+    sampled Z and the fibres Y agree in FP64 to rounding."""
+    w = dense4d200
+    X = w.dense
+    T = tsk.Tensor.dense(torch.from_numpy(X).to(DEV))
+    facs = [torch.from_numpy(np.linalg.qr(np.random.default_rng(2).standard_normal((200, 10)))[0]).to(DEV)]
+    for n in range(1, 4):
+        facs.append(tsk.rrf_init(T, n, 10, 20, 120, 0))
+    fn = [F.cpu().numpy() for F in facs]
+    for n in range(4):
+        idx, wt = tsk.leverage_sample(w.dims, w.ranks, n, w.m, 0, 0, facs)
+        io, wo = osk.leverage_sample(fn, w.m, 0, 0, n)
+        assert np.array_equal(idx.cpu().numpy(), io)
+        np.testing.assert_allclose(wt.cpu().numpy(), wo, rtol=1e-15)
+        Z, Y = tsk.sketch_lev(T, w.ranks, n, w.m, idx, wt, facs, prec="f64")
+        np.testing.assert_allclose(Z.cpu().numpy(), osk.leverage_lhs(fn, io, wo, n),
+                                   rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(Y.cpu().numpy(), osk.leverage_rhs_dense(X, io, wo, n),
+                                   rtol=2e-15, atol=0)
+    del T
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def cp500():
+    return workloads.cp500()
+
+
+def test_cp500_fp64_operands_vs_oracle(tsk, cp500):
+    """500^3 CP rank 20 (collinearity 0.9): leverage-sampled Tucker to rank 30
+    (m = 14400) with FP64 operands on the FP32-valued tensor, so that both
+    sides sample the same rows: the residual after the first sweep within
+    1e-10 of the oracle's; then CP-via-Tucker (2 Tucker + 25 CP sweeps) with
+    the CP residual within 1e-8."""
+    w = cp500
+    T = tsk.Tensor.dense(torch.from_numpy(w.dense).to(DEV))
+    To = osk.Tensor.from_dense(w.dense.astype(np.float64))
+    _, _, fits = tsk.tucker_sketch_als(T, w.ranks, w.m, 1, sketch="lev", prec="f64", seed=0,
+                                       solve="rsvd")
+    ref = otk.sketch_tucker_als(To, w.ranks, w.m, 1, seed=0, sketch_kind="lev", solve_kind="rsvd")
+    np.testing.assert_allclose(fits, ref["fits"], rtol=0, atol=1e-10)
+    from oracle import cp as ocp
+    _, cpfit = tsk.cp_via_tucker(T, w.cp_rank, w.ranks, w.m, 2, 25, sketch="lev", prec="f64",
+                                 seed=0, solve="rsvd")
+    ref = ocp.cp_sketch_tucker(To, w.cp_rank, w.ranks, w.m, 2, 25, seed=0, sketch_kind="lev",
+                               solve_kind="rsvd")
+    assert abs(cpfit - ref["fit"]) <= 1e-8, (cpfit, ref["fit"])
