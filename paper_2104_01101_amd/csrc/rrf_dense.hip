@@ -12,9 +12,10 @@
 //
 // The tensor is viewed as P x s_n x Q (P, Q the products of the dimensions
 // before and after mode n), so j = p Q + q.  A workgroup (4 waves) owns 64
-// rows i of B and a range of j; per step of KT values of j it stages the
+// rows i of B and a range of j; per step of KT = 64 values of j it stages the
 // tensor tile (64 x KT) and the generated rows (KT x NP, NP = k1 padded) in
-// LDS, both with the contraction index contiguous, and accumulates on the
+// LDS, both with the contraction index contiguous (the next step's values
+// are loaded into registers meanwhile), and accumulates on the
 // matrix cores: FP64 16x16x4 (FP64 tensors or operands), FP32 16x16x4, or
 // BF16 16x16x32 with FP32 accumulation (BF16 operands: the tensor and G
 // rounded to BF16).  Each workgroup writes its partial sums (FP64) for its
@@ -34,7 +35,8 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int kRT = 256;  // threads
 constexpr int kBM = 64;   // rows of B per workgroup (16 per wave)
-constexpr int kKT = 32;   // contraction values per step
+constexpr int kKT = 64;   // contraction values per step
+constexpr int kTU = kBM * kKT / kRT;  // tensor values per thread per step
 
 template <class E>
 struct Op;
@@ -43,18 +45,21 @@ struct Op<double> {
   typedef d4 Acc;
   static constexpr int LD = kKT + 1;
   __device__ static double cvt(double v) { return v; }
+  __device__ static double cvt(float v) { return double(v); }
 };
 template <>
 struct Op<float> {
   typedef f4 Acc;
   static constexpr int LD = kKT + 1;
   __device__ static float cvt(double v) { return float(v); }
+  __device__ static float cvt(float v) { return v; }
 };
 template <>
 struct Op<uint16_t> {
   typedef f4 Acc;
   static constexpr int LD = kKT + 8;  // 16-byte aligned rows of 8 bf16 groups
   __device__ static uint16_t cvt(double v) { return f32_to_bf16_bits(float(v)); }
+  __device__ static uint16_t cvt(float v) { return f32_to_bf16_bits(v); }
 };
 
 struct RrfDenseArgs {
@@ -68,9 +73,12 @@ struct RrfDenseArgs {
   double* part;     // splits x s x k1
 };
 
+// The next step's tensor values and generated rows are loaded into registers
+// while the current step's products run from LDS (one LDS buffer, two
+// barriers per step).
 template <class V, class E, int NP>
 __global__ __launch_bounds__(kRT) void k_rrf_dense(RrfDenseArgs a) {
-  constexpr int LD = Op<E>::LD, NB = NP / 16;
+  constexpr int LD = Op<E>::LD, NB = NP / 16, GU = NP / 4;
   typedef typename Op<E>::Acc Acc;
   __shared__ __attribute__((aligned(16))) E As[kBM * LD];  // [i][j]
   __shared__ __attribute__((aligned(16))) E Bs[NP * LD];   // [c][j]
@@ -80,56 +88,88 @@ __global__ __launch_bounds__(kRT) void k_rrf_dense(RrfDenseArgs a) {
   const int64_t jbeg = int64_t(blockIdx.y) * a.kchunk;
   const int64_t jend = jbeg + a.kchunk < a.K ? jbeg + a.kchunk : a.K;
   const V* X = static_cast<const V*>(a.X);
+  const bool last_mode = a.Q == 1;
   Acc acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = Acc{0, 0, 0, 0};
 
-  for (int64_t j0 = jbeg; j0 < jend; j0 += kKT) {
-    // ---- tensor tile: T_(n)[i0 + ii, j0 + jj] = X[(p s + i) Q + q] ----
-    if (a.Q == 1) {  // mode n is the last: consecutive i are contiguous
-      const int ii = tid & 63;
-      for (int jj = tid >> 6; jj < kKT; jj += kRT / 64) {
-        const int64_t i = i0 + ii, j = j0 + jj;
-        const double v = (i < a.s && j < jend) ? double(X[j * a.s + i]) : 0.0;
-        As[ii * LD + jj] = Op<E>::cvt(v);
-      }
-    } else {  // consecutive j (within one p) are contiguous
-      const int jj = tid & (kKT - 1);
-      const int64_t j = j0 + jj;
-      const int64_t p = j / a.Q, q = j - p * a.Q;
-      const bool jv = j < jend;
-      for (int ii = tid / kKT; ii < kBM; ii += kRT / kKT) {
-        const int64_t i = i0 + ii;
-        const double v = (jv && i < a.s) ? double(X[(p * a.s + i) * a.Q + q]) : 0.0;
-        As[ii * LD + jj] = Op<E>::cvt(v);
-      }
-    }
-    // ---- generated rows tau(j) G[g(j), :] for the KT values of j ----
-    {
-      const int jj = tid / (kRT / kKT);          // 8 threads per row
-      const int cg = tid % (kRT / kKT);
-      const int64_t j = j0 + jj;
-      const bool jv = j < jend;
-      const uint64_t x = draw(a.key, uint64_t(j));
-      const int64_t row = int64_t(bucket_of(x, uint64_t(a.k2)));
-      const double sg = sign_of(x) < 0 ? -1.0 : 1.0;
-      for (int c = cg; c < NP; c += kRT / kKT) {
-        const double v = (jv && c < a.k1) ? sg * a.G[row * a.k1 + c] : 0.0;
-        Bs[c * LD + jj] = Op<E>::cvt(v);
-      }
-    }
-    __syncthreads();
-    // ---- products: wave w rows 16 w .. 16 w + 15, every column block ----
-    if constexpr (sizeof(E) == 2) {
-      bf8 av, bv;
-      __builtin_memcpy(&av, &As[(16 * wave + li) * LD + 8 * g], 16);
+  // Raw values are held in registers and converted at the stash, after the
+  // products of the current step: a conversion right after a load would wait
+  // for it.  Loads use clamped (always valid) indices and the values outside
+  // the tile are replaced by zero at the stash, so no load sits in a branch.
+  V tv[kTU];
+  double gv[GU];
+  double gsign = 0.0;  // tau(j), or 0 past the end of the range
+  // tensor tile T_(n)[i0 + ii, j0 + jj] = X[(p s + i) Q + q]: for the last
+  // mode consecutive i are contiguous (thread: one i, every 4th j), else
+  // consecutive j within one p (thread: one j, every 4th i)
+  auto fetch = [&](int64_t j0) {
+    if (last_mode) {
+      const int64_t i = min(i0 + (tid & 63), a.s - 1);
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        __builtin_memcpy(&bv, &Bs[(16 * b + li) * LD + 8 * g], 16);
-        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[b], 0, 0, 0);
+      for (int u = 0; u < kTU; ++u) {
+        const int64_t j = min(j0 + (tid >> 6) + 4 * u, jend - 1);
+        tv[u] = X[j * a.s + i];
       }
     } else {
+      const int64_t j = min(j0 + (tid & 63), jend - 1);
+      const int64_t p = j / a.Q, q = j - p * a.Q;
+      const V* base = X + p * a.s * a.Q + q;
 #pragma unroll
+      for (int u = 0; u < kTU; ++u) {
+        const int64_t i = min(i0 + (tid >> 6) + 4 * u, a.s - 1);
+        tv[u] = base[i * a.Q];
+      }
+    }
+    // generated row tau(j) G[g(j), :] of j = j0 + tid / 4: columns tid % 4 + 4 t
+    const int64_t j = j0 + (tid >> 2);
+    const uint64_t x = draw(a.key, uint64_t(j));
+    const double* grow = a.G + int64_t(bucket_of(x, uint64_t(a.k2))) * a.k1;
+    gsign = j < jend ? (sign_of(x) < 0 ? -1.0 : 1.0) : 0.0;
+#pragma unroll
+    for (int t = 0; t < GU; ++t) gv[t] = grow[min((tid & 3) + 4 * t, a.k1 - 1)];
+  };
+  auto stash = [&](int64_t j0) {
+    if (last_mode) {
+      const bool iv = i0 + (tid & 63) < a.s;
+#pragma unroll
+      for (int u = 0; u < kTU; ++u) {
+        const bool ok = iv && j0 + (tid >> 6) + 4 * u < jend;
+        As[(tid & 63) * LD + (tid >> 6) + 4 * u] = Op<E>::cvt(ok ? tv[u] : V(0));
+      }
+    } else {
+      const bool jv = j0 + (tid & 63) < jend;
+#pragma unroll
+      for (int u = 0; u < kTU; ++u) {
+        const bool ok = jv && i0 + (tid >> 6) + 4 * u < a.s;
+        As[((tid >> 6) + 4 * u) * LD + (tid & 63)] = Op<E>::cvt(ok ? tv[u] : V(0));
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < GU; ++t) {
+      const int c = (tid & 3) + 4 * t;
+      Bs[c * LD + (tid >> 2)] = Op<E>::cvt(c < a.k1 ? gsign * gv[t] : 0.0);
+    }
+  };
+
+  if (jbeg < jend) fetch(jbeg);
+  for (int64_t j0 = jbeg; j0 < jend; j0 += kKT) {
+    stash(j0);
+    __syncthreads();
+    if (j0 + kKT < jend) fetch(j0 + kKT);  // in flight during the products
+    if constexpr (sizeof(E) == 2) {
+#pragma unroll
+      for (int ks = 0; ks < kKT; ks += 32) {
+        bf8 av, bv;
+        __builtin_memcpy(&av, &As[(16 * wave + li) * LD + ks + 8 * g], 16);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          __builtin_memcpy(&bv, &Bs[(16 * b + li) * LD + ks + 8 * g], 16);
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[b], 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll 4
       for (int kk = 0; kk < kKT; kk += 4) {
         const E av = As[(16 * wave + li) * LD + kk + g];
 #pragma unroll
@@ -203,9 +243,9 @@ tsk_status rrf_dense(const TensorView& T, int n, int64_t k1, int64_t k2, uint64_
   a.key = key;
   a.G = G;
   const int64_t mblocks = ceil_div(a.s, kBM);
-  // about 1024 workgroups, each with at least 32 steps of the contraction
+  // about 1024 workgroups, each with at least 16 steps of the contraction
   int64_t splits = ceil_div(1024, mblocks);
-  splits = std::max<int64_t>(1, std::min<int64_t>(splits, ceil_div(a.K, 32 * kKT)));
+  splits = std::max<int64_t>(1, std::min<int64_t>(splits, ceil_div(a.K, 16 * kKT)));
   a.kchunk = ceil_div(ceil_div(a.K, splits), kKT) * kKT;
   splits = ceil_div(a.K, a.kchunk);
   a.part = ws.take<double>(size_t(splits) * a.s * k1);
