@@ -289,6 +289,55 @@ def roofline(name, work, ms_total, launches, steps, wname):
             "launches": launches}
 
 
+def adjoint_timing(tsk, L, lib, read, w, reps=5):
+    """Sketched mode-0 residual (forward) and its adjoint (backward) at the
+    shape of this job's subproblem (m x s_0 FP32 Y, r = prod of the other
+    ranks, R = R_0), seeded inputs.  Whole calls are timed with events on the
+    launching stream; the pass over Y (one launch per call) with the library's
+    own events.  Backward pass: 6 m s R FP64 flops on the matrix cores
+    (E = P A^T - Y, E^T P, E A); forward: Y read once (HBM)."""
+    import numpy as np
+    import torch
+    dims, ranks, m, n = tuple(w.dims), tuple(w.ranks), w.m, 0
+    s, R = dims[n], ranks[n]
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    fg = [torch.randn((d, r), dtype=torch.float64, device="cuda:0", generator=g) / d ** 0.5
+          for d, r in zip(dims, ranks)]
+    cg = torch.randn(ranks, dtype=torch.float64, device="cuda:0", generator=g)
+    Y = torch.randn((m, s), dtype=torch.float32, device="cuda:0", generator=g)
+    h, sg = tsk.hash_tables(dims, n, m, 3)
+    res = {}
+    for name, call in (("fwd", lambda: tsk.sketched_residual(dims, ranks, n, m, h, sg, fg, cg, Y)),
+                       ("bwd", lambda: tsk.sketched_residual_grads(dims, ranks, n, m, h, sg, fg,
+                                                                   cg, Y))):
+        call()
+        torch.cuda.synchronize()
+        L.check(lib.tsk_profile_enable(b"adjoint_pass"))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        ms, launches = read("adjoint_pass")
+        L.check(lib.tsk_profile_enable(b""))
+        if launches == 0:
+            raise RuntimeError("no timed launches of the adjoint pass were recorded")
+        per = ms / launches
+        if name == "fwd":
+            amount, bound, peak, unit = m * s * 4 + (m + s) * R * 8, "hbm", 8000.0, "GB/s"
+            achieved = amount / (per / 1e3) / 1e9
+        else:
+            amount, bound, peak, unit = 6 * m * s * R, "mfma", 78.6, "TFLOP/s"
+            achieved = amount / (per / 1e3) / 1e12
+        res[name] = {"call_ms": e0.elapsed_time(e1) / reps,
+                     "pass": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                              "frac": achieved / peak, "algorithmic_per_launch": amount,
+                              "avg_launch_ms": per, "launches": launches}}
+    res["shape"] = f"m={m}, s={s}, r={int(np.prod(ranks[1:]))}, R={R}, FP32 Y, FP64 arithmetic"
+    return res
+
+
 def copy_calibration():
     import torch
     n = 1 << 28  # 1 GiB of float32
@@ -429,6 +478,8 @@ def main():
         "roofline": roofline(dominant, work, dom[0], dom[1], args.steps, args.workload),
         f"{second}_roofline": roofline(second, work, sp[0], sp[1], args.steps, args.workload),
     }
+    if args.workload == "zipf10k":
+        out["adjoint"] = adjoint_timing(tsk, L, lib, read, w, reps=max(3, args.steps))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = (cpu_baseline_dense(w, args.solve) if dense else
                                cpu_baseline(w, args.solve, 1 if args.workload == "zipf10k" else 3))

@@ -143,7 +143,8 @@ uint64_t tsk_draw(uint64_t key, uint64_t counter);
 /* Launch timing for measurement.  tsk_profile_enable(name) makes the library
  * record HIP events on the launching stream around every launch group called
  * `name` ("sketch_pass", "rrf_pass", "gram", "ts_lhs", "solve_la", "eig", "fit", "rrf",
- * "leverage", "cp_core", "adjoint"; the driver's phases "phase_prep" (maps and
+ * "leverage", "cp_core", "adjoint_pass" (the pass over Y of the sketched
+ * residual and its adjoint); the driver's phases "phase_prep" (maps and
  * sketched right-hand sides), "phase_init" (initialisation), "phase_sweeps"
  * (one per sweep, the subproblems only) and "phase_fit"; a comma-separated list
  * selects several;

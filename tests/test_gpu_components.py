@@ -30,9 +30,15 @@ def _gpu_tensor(tsk, dims, idx=None, val=None, dense=None):
     return tsk.Tensor.coo(torch.from_numpy(idx).to(DEV), torch.from_numpy(val).to(DEV), dims)
 
 
-def _tables_np(h, s):
-    return {k: (h[k].cpu().numpy().astype(np.int64), s[k].cpu().numpy().astype(np.float64))
-            for k in range(len(h)) if h[k] is not None}
+def _maps(dims, n, m, seed):
+    """The oracle's TensorSketch maps of subproblem n ({k: (h, sigma)}), and the
+    same maps as device tensors (int32 h, int8 sigma) handed to the library."""
+    tabs = osk.ts_tables(dims, m, seed, n)
+    h = [None if k == n else torch.from_numpy(tabs[k][0].astype(np.int32)).to(DEV)
+         for k in range(len(dims))]
+    s = [None if k == n else torch.from_numpy(tabs[k][1].astype(np.int8)).to(DEV)
+         for k in range(len(dims))]
+    return tabs, h, s
 
 
 # ---------------------------------------------------------------- a1 ----
@@ -77,9 +83,9 @@ def test_sketch_rhs_fp64_bitwise(tsk, dims, nnz, m, n):
         val = rs.standard_normal(nnz)
         T = _gpu_tensor(tsk, dims, idx, val)
         To = osk.Tensor(dims, idx, val)
-    h, s = tsk.hash_tables(dims, n, m, 5, DEV)
+    tabs, h, s = _maps(dims, n, m, 5)
     Y = tsk.sketch_rhs_ts(T, n, m, h, s).cpu().numpy()
-    Yo = osk.ts_rhs(To, m, _tables_np(h, s), n)
+    Yo = osk.ts_rhs(To, m, tabs, n)
     assert np.array_equal(Y, Yo)
 
 
@@ -88,12 +94,11 @@ def test_sketch_rhs_fp32_bound_and_determinism(tsk):
     w = workloads.sparse_tucker(dims, nnz, (10, 10, 10), seed=2)
     idx, val = w
     T = _gpu_tensor(tsk, dims, idx, val)
-    h, s = tsk.hash_tables(dims, n, m, 0, DEV)
+    tabs, h, s = _maps(dims, n, m, 0)
     Y1 = tsk.sketch_rhs_ts(T, n, m, h, s)
     Y2 = tsk.sketch_rhs_ts(T, n, m, h, s)
     assert torch.equal(Y1, Y2)
     To = osk.Tensor(dims, idx, val.astype(np.float64))
-    tabs = _tables_np(h, s)
     Yo = osk.ts_rhs(To, m, tabs, n)
     H, S = osk.ts_hash_sign(tabs, To.idx, m)
     key = H * dims[n] + To.idx[:, n]
@@ -123,8 +128,8 @@ def test_sketch_lhs_matches_convolution(tsk, dims, ranks, m, n):
     rs = np.random.default_rng(m)
     facs = [np.linalg.qr(rs.standard_normal((d, r)))[0] for d, r in zip(dims, ranks)]
     fg = [torch.from_numpy(F).to(DEV) for F in facs]
-    h, s = tsk.hash_tables(dims, n, m, 1, DEV)
-    Zo = osk.ts_lhs(facs, _tables_np(h, s), m, n)
+    tabs, h, s = _maps(dims, n, m, 1)
+    Zo = osk.ts_lhs(facs, tabs, m, n)
     scale = np.abs(Zo).max() + 1e-300
     Z = tsk.sketch_lhs_ts(dims, ranks, n, m, h, s, fg, "f64").cpu().numpy()
     assert np.abs(Z - Zo).max() <= 1e-13 * scale * np.log2(m + 1)
@@ -157,10 +162,10 @@ def test_rc_solve_low_precision(tsk, prec, tol):
     Z = rs.standard_normal((m, r)) / np.sqrt(m)
     Y = Z @ (10 * rs.standard_normal((r, R))) @ rs.standard_normal((R, s)) + 0.1 * rs.standard_normal((m, s))
     dt = {"f32": torch.float32, "bf16": torch.bfloat16}[prec]
-    Zg, Yg = torch.from_numpy(Z).to(DEV).to(dt), torch.from_numpy(Y).to(DEV).to(dt)
-    A, W = tsk.rc_solve(Zg, Yg, R, prec)
+    Zc, Yc = torch.from_numpy(Z).to(dt), torch.from_numpy(Y).to(dt)  # rounded on the host
+    A, W = tsk.rc_solve(Zc.to(DEV), Yc.to(DEV), R, prec)
     # oracle on the rounded operands: the only difference left is the accumulation
-    Ao, Wo, _ = osv.rc_solve(Zg.double().cpu().numpy(), Yg.double().cpu().numpy(), R)
+    Ao, Wo, _ = osv.rc_solve(Zc.double().numpy(), Yc.double().numpy(), R)
     A = A.cpu().numpy()
     assert np.abs(A @ A.T - Ao @ Ao.T).max() < tol
 
@@ -208,10 +213,11 @@ def test_leverage_rows_match(tsk):
     X = rs.standard_normal(dims)
     facs = [np.linalg.qr(rs.standard_normal((d, r)))[0] for d, r in zip(dims, ranks)]
     fg = [torch.from_numpy(F).to(DEV) for F in facs]
-    idx, w = tsk.leverage_sample(dims, ranks, n, m, 1, 0, fg)
+    io, wo = osk.leverage_sample(facs, m, 1, 0, n)  # oracle samples, handed to the library
+    idx = torch.from_numpy(io.astype(np.int32)).to(DEV)
+    w = torch.from_numpy(wo).to(DEV)
     T = _gpu_tensor(tsk, dims, dense=X)
     Z, Y = tsk.sketch_lev(T, ranks, n, m, idx, w, fg, "f64")
-    io, wo = idx.cpu().numpy().astype(np.int64), w.cpu().numpy()
     np.testing.assert_array_equal(Z.cpu().numpy(), osk.leverage_lhs(facs, io, wo, n))
     np.testing.assert_allclose(Y.cpu().numpy(), osk.leverage_rhs_dense(X, io, wo, n), rtol=1e-15)
 
@@ -346,8 +352,7 @@ def test_adjoint_matches_oracle_and_fd(tsk):
     facs = [rs.standard_normal((d, r)) for d, r in zip(dims, ranks)]
     core = rs.standard_normal(ranks)
     X = rs.standard_normal(dims)
-    h, s = tsk.hash_tables(dims, n, m, 2, DEV)
-    tabs = _tables_np(h, s)
+    tabs, h, s = _maps(dims, n, m, 2)
     Yo = osk.ts_rhs(osk.Tensor.from_dense(X), m, tabs, n)
     fg = [torch.from_numpy(F).to(DEV) for F in facs]
     cg = torch.from_numpy(core).to(DEV)

@@ -7,16 +7,16 @@ relative residual stays near 1.004 and ALS wanders instead of converging), so
 FP32-rounding differences grow about threefold per sweep and whole 10-sweep
 trajectories are not comparable.  The checks are therefore: the first three
 sweeps of the whole job against the FP64 oracle on the same FP32-valued
-input; one sweep replayed by the oracle from the GPU's own factors after 3
-and after 9 sweeps (same test matrices: the streams are keyed by the absolute
-sweep); all within 1e-5, the FP32 operand tolerance; and bitwise
-repeatability of the whole job.
+input; sweep 4 resumed by the library from the oracle's factors after 3
+sweeps against the oracle's own sweep 4 (same test matrices: the streams are
+keyed by the absolute sweep); all within 1e-5, the FP32 operand tolerance;
+and bitwise repeatability of the whole job.
 
 zipf10k -- 10000^3 with 10^7 Zipf(1.1) entries, the default benchmark job
 (TensorSketch m = 2048, rank 16, RRF init, 5 sweeps, RSVD-LRLS with the
 Gram inverted by block sweeps and the products with Y in the O(m s k)
-order, FP32 operands): the first two sweeps of the whole job and one sweep
-replayed by the oracle from the GPU's factors after 4 sweeps, within 1e-5;
+order, FP32 operands): the first two sweeps of the whole job and sweep 3
+resumed by the library from the oracle's factors after 2 sweeps, within 1e-5;
 the FP32 sketch pass of one mode against the oracle's FP64 per-cell sums,
 within the bound of FP32 summation in input order, and bitwise repeatable.
 
@@ -63,6 +63,19 @@ def _plan(tsk, w, sweeps=None):
                           prec=w.prec, seed=0, record_fit=True, solve="rsvd")
 
 
+def _resume_vs_oracle(tsk, w, To, factors_t, t):
+    """Sweep t (0-based, the test matrices keyed by the absolute sweep) from the
+    oracle's factors after t sweeps: the library's resumed sweep against the
+    oracle's, within the FP32 operand tolerance."""
+    T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(DEV), torch.from_numpy(w.val).to(DEV), w.dims)
+    plan = tsk.TuckerPlan(T, w.ranks, w.m, 1, sketch="ts", init="user", prec=w.prec, seed=0,
+                          record_fit=True, solve="rsvd", first_sweep=t)
+    _, _, fit = plan.run(init_factors=[torch.from_numpy(F).to(DEV) for F in factors_t])
+    step = otk.sketch_tucker_als(To, w.ranks, w.m, 1, seed=0, solve_kind="rsvd", init="user",
+                                 init_factors=factors_t, first_sweep=t)
+    np.testing.assert_allclose(fit, step["fits"], rtol=0, atol=1e-5)
+
+
 def test_sparse2000_job_vs_oracle(tsk, sparse2000):
     w = sparse2000
     To = osk.Tensor(w.dims, w.idx, w.val.astype(np.float64))
@@ -70,12 +83,8 @@ def test_sparse2000_job_vs_oracle(tsk, sparse2000):
     assert len(fits) == w.sweeps
     ref = otk.sketch_tucker_als(To, w.ranks, w.m, 3, seed=0, solve_kind="rsvd")
     np.testing.assert_allclose(fits[:3], ref["fits"], rtol=0, atol=1e-5)
-    for t in (3, w.sweeps - 1):
-        _, factors_t, _ = _plan(tsk, w, sweeps=t).run()
-        step = otk.sketch_tucker_als(To, w.ranks, w.m, 1, seed=0, solve_kind="rsvd", init="user",
-                                     init_factors=[F.cpu().numpy() for F in factors_t],
-                                     first_sweep=t)
-        np.testing.assert_allclose(fits[t], step["fits"][0], rtol=0, atol=1e-5)
+    # sweep 4 from the oracle's factors after 3 sweeps, on both sides
+    _resume_vs_oracle(tsk, w, To, ref["factors"], 3)
 
 
 def test_sparse2000_job_repeatable(tsk, sparse2000):
@@ -96,29 +105,30 @@ def test_zipf10k_job_vs_oracle(tsk, zipf10k):
     assert len(fits) == w.sweeps
     ref = otk.sketch_tucker_als(To, w.ranks, w.m, 2, seed=0, solve_kind="rsvd")
     np.testing.assert_allclose(fits[:2], ref["fits"], rtol=0, atol=1e-5)
-    t = w.sweeps - 1
-    _, factors_t, _ = _plan(tsk, w, sweeps=t).run()
-    step = otk.sketch_tucker_als(To, w.ranks, w.m, 1, seed=0, solve_kind="rsvd", init="user",
-                                 init_factors=[F.cpu().numpy() for F in factors_t],
-                                 first_sweep=t)
-    np.testing.assert_allclose(fits[t], step["fits"][0], rtol=0, atol=1e-5)
+    # sweep 3 from the oracle's factors after 2 sweeps, on both sides
+    _resume_vs_oracle(tsk, w, To, ref["factors"], 2)
 
 
-def _tables_np(h, s):
-    return {k: (h[k].cpu().numpy().astype(np.int64), s[k].cpu().numpy().astype(np.float64))
-            for k in range(len(h)) if h[k] is not None}
+def _maps(dims, n, m, seed):
+    """The oracle's TensorSketch maps of subproblem n ({k: (h, sigma)}), and the
+    same maps as device tensors (int32 h, int8 sigma) handed to the library."""
+    tabs = osk.ts_tables(dims, m, seed, n)
+    h = [None if k == n else torch.from_numpy(tabs[k][0].astype(np.int32)).to(DEV)
+         for k in range(len(dims))]
+    s = [None if k == n else torch.from_numpy(tabs[k][1].astype(np.int8)).to(DEV)
+         for k in range(len(dims))]
+    return tabs, h, s
 
 
 def test_zipf10k_sketch_pass_mode0(tsk, zipf10k):
     w = zipf10k
     n, m = 0, w.m
     T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(DEV), torch.from_numpy(w.val).to(DEV), w.dims)
-    h, s = tsk.hash_tables(w.dims, n, m, 7, DEV)
+    tabs, h, s = _maps(w.dims, n, m, 7)
     Y1 = tsk.sketch_rhs_ts(T, n, m, h, s)
     Y2 = tsk.sketch_rhs_ts(T, n, m, h, s)
     assert torch.equal(Y1, Y2)
     To = osk.Tensor(w.dims, w.idx, w.val.astype(np.float64))
-    tabs = _tables_np(h, s)
     Yo = osk.ts_rhs(To, m, tabs, n)
     H, S = osk.ts_hash_sign(tabs, To.idx, m)
     key = H * w.dims[n] + To.idx[:, n]
@@ -130,16 +140,15 @@ def test_zipf10k_sketch_pass_mode0(tsk, zipf10k):
 
 def _fibre_parity(tsk, w, n, seed):
     """Sampled mode-n fibres at full size: m samples, half at the other-mode
-    coordinates of stored entries, half from the library's leverage sampler
+    coordinates of stored entries, half from the oracle's leverage sampler
     with random orthonormal factors; FP64 output compared bit for bit."""
     rs = np.random.default_rng(seed)
     T = tsk.Tensor.coo(torch.from_numpy(w.idx).to(DEV), torch.from_numpy(w.val).to(DEV), w.dims)
     fx = tsk.fiber_index(T, n)
-    facs = [torch.linalg.qr(torch.randn(d, R, dtype=torch.float64,
-                                        generator=torch.Generator().manual_seed(seed + d)))[0]
-            .to(DEV) for d, R in zip(w.dims, w.ranks)]
-    ig, wg = tsk.leverage_sample(w.dims, w.ranks, n, w.m, seed, 0, facs)
-    io, wo = ig.cpu().numpy(), wg.cpu().numpy()
+    facs = [np.linalg.qr(rs.standard_normal((d, R)))[0] for d, R in zip(w.dims, w.ranks)]
+    io, wo = osk.leverage_sample(facs, w.m, seed, 0, n)
+    io = io.astype(np.int32)
+    wg = torch.from_numpy(wo).to(DEV)
     others = [k for k in range(len(w.dims)) if k != n]
     half = w.m // 2
     io[:half] = w.idx[rs.integers(0, w.idx.shape[0], half)][:, others]
@@ -234,17 +243,18 @@ def dense4d200():
 
 
 def test_dense4d200_leverage_sketch_full_size(tsk, dense4d200):
-    """200^4, m = 4000: the range-finder factors of modes 2..4 (FP32 pass) and
-    a random orthonormal first factor drive the leverage sampler of every mode;
-    the sample indices equal the oracle's bit for bit, the weights, the
-    sampled Z and the fibres Y agree in FP64 to rounding."""
+    """200^4, m = 4000: orthonormal factors with a few coherent rows (rows
+    0..4 weighted 10x before the QR, so the leverage scores are far from
+    uniform) drive the leverage sampler of every mode; the sample indices equal
+    the oracle's bit for bit, the weights, the sampled Z and the fibres Y agree
+    in FP64 to rounding."""
     w = dense4d200
     X = w.dense
     T = tsk.Tensor.dense(torch.from_numpy(X).to(DEV))
-    facs = [torch.from_numpy(np.linalg.qr(np.random.default_rng(2).standard_normal((200, 10)))[0]).to(DEV)]
-    for n in range(1, 4):
-        facs.append(tsk.rrf_init(T, n, 10, 20, 120, 0))
-    fn = [F.cpu().numpy() for F in facs]
+    rs = np.random.default_rng(2)
+    lift = 1.0 + 9.0 * (np.arange(200) < 5)
+    fn = [np.linalg.qr(rs.standard_normal((200, 10)) * lift[:, None])[0] for _ in range(4)]
+    facs = [torch.from_numpy(F).to(DEV) for F in fn]
     for n in range(4):
         idx, wt = tsk.leverage_sample(w.dims, w.ranks, n, w.m, 0, 0, facs)
         io, wo = osk.leverage_sample(fn, w.m, 0, 0, n)
@@ -283,3 +293,62 @@ def test_cp500_fp64_operands_vs_oracle(tsk, cp500):
     ref = ocp.cp_sketch_tucker(To, w.cp_rank, w.ranks, w.m, 2, 25, seed=0, sketch_kind="lev",
                                solve_kind="rsvd")
     assert abs(cpfit - ref["fit"]) <= 1e-8, (cpfit, ref["fit"])
+
+
+def test_adjoint_zipf10k_shape_vs_oracle_and_fd(tsk):
+    """Sketched mode-0 residual and its adjoint at the shape of the 10000^3
+    rank-16 job's subproblem: m = 2048, s = 10^4, r = 256, R = 16, FP32 Y
+    (seeded N(0,1) values in place of the sketched tensor).  L and every
+    gradient against the oracle's dense FP64 evaluation; central differences
+    with h = 1e-3 on 64 entries (16 of each factor, 16 of the core) against
+    the adjoint.  L is quadratic in any single entry, so the difference
+    quotient is exact up to the rounding of L: |fd - g| <= 64 u L / h."""
+    from oracle import adjoint as oadj
+    dims, ranks, m, n = (10000, 10000, 10000), (16, 16, 16), 2048, 0
+    rs = np.random.default_rng(17)
+    facs = [rs.standard_normal((d, r)) / np.sqrt(d) for d, r in zip(dims, ranks)]
+    core = rs.standard_normal(ranks) * 30.0
+    Yo = rs.standard_normal((m, dims[n])).astype(np.float32)
+    tabs, h, s = _maps(dims, n, m, 3)
+    fg = [torch.from_numpy(F).to(DEV) for F in facs]
+    cg = torch.from_numpy(core).to(DEV)
+    Yg = torch.from_numpy(Yo).to(DEV)
+    L = tsk.sketched_residual(dims, ranks, n, m, h, s, fg, cg, Yg).item()
+    grads, gC = tsk.sketched_residual_grads(dims, ranks, n, m, h, s, fg, cg, Yg)
+    Lo, go, gCo = oadj.residual_and_grads(facs, core, tabs, Yo.astype(np.float64), m, n)
+    assert abs(L - Lo) <= 1e-12 * Lo
+    for k in range(3):
+        np.testing.assert_allclose(grads[k].cpu().numpy(), go[k], rtol=0,
+                                   atol=1e-10 * np.abs(go[k]).max())
+    np.testing.assert_allclose(gC.cpu().numpy(), gCo, rtol=0, atol=1e-10 * np.abs(gCo).max())
+    hstep, u = 1e-3, 2.0 ** -53
+    bound = 64 * u * L / hstep
+
+    def fd(perturb):
+        vals = []
+        for sgn in (1.0, -1.0):
+            fp = [F.clone() for F in fg]
+            cp = cg.clone()
+            perturb(fp, cp, sgn * hstep)
+            vals.append(tsk.sketched_residual(dims, ranks, n, m, h, s, fp, cp, Yg).item())
+        return (vals[0] - vals[1]) / (2 * hstep)
+
+    checked = 0
+    for k in range(3):
+        for _ in range(16):
+            i, c = int(rs.integers(dims[k])), int(rs.integers(ranks[k]))
+
+            def pert(fp, cp, d, k=k, i=i, c=c):
+                fp[k][i, c] += d
+            g = grads[k][i, c].item()
+            assert abs(fd(pert) - g) <= bound + 1e-9 * abs(g), (k, i, c)
+            checked += 1
+    for _ in range(16):
+        ix = tuple(int(rs.integers(r)) for r in ranks)
+
+        def pert(fp, cp, d, ix=ix):
+            cp[ix] += d
+        g = gC[ix].item()
+        assert abs(fd(pert) - g) <= bound + 1e-9 * abs(g), ix
+        checked += 1
+    assert checked == 64

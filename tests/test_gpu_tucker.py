@@ -270,10 +270,9 @@ def test_resume_at_a_sweep_bitwise(tsk, kind, solve):
     assert rest[2][0] == full[2][1]
     assert all(torch.equal(a, b) for a, b in zip(full[1], rest[1]))
     assert torch.equal(full[0], rest[0])
-    ref = otk.sketch_tucker_als(osk.Tensor.from_dense(X), (3, 3, 3), 60, 1, seed=5,
-                                sketch_kind=kind, solve_kind=solve, init="user",
-                                init_factors=[F.cpu().numpy() for F in init], first_sweep=1)
-    np.testing.assert_allclose(rest[2], ref["fits"], rtol=0, atol=1e-10)
+    ref = otk.sketch_tucker_als(osk.Tensor.from_dense(X), (3, 3, 3), 60, 2, seed=5,
+                                sketch_kind=kind, solve_kind=solve)
+    np.testing.assert_allclose(rest[2], ref["fits"][1:], rtol=0, atol=1e-10)
 
 
 def test_tolerance_stops_and_final_fit(tsk):
