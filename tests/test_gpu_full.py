@@ -352,3 +352,21 @@ def test_adjoint_zipf10k_shape_vs_oracle_and_fd(tsk):
         assert abs(fd(pert) - g) <= bound + 1e-9 * abs(g), ix
         checked += 1
     assert checked == 64
+
+
+def test_skewed_tensor_job_vs_oracle(tsk):
+    """30000 x 1000 x 1000 with 10^6 distinct uniform entries, TensorSketch
+    m = 2048, rank (16, 16, 16): the preparation sketches all three modes in one
+    pass whose slabs have very different bin counts and table lengths (the
+    partition's LDS plan must close a group before it overflows).  The first two
+    sweeps of the whole job (RRF init, RSVD-LRLS, FP32 operands) against the FP64
+    oracle on the same FP32-valued input, within 1e-5."""
+    dims, nnz, ranks, m = (30000, 1000, 1000), 1_000_000, (16, 16, 16), 2048
+    idx, val = workloads.sparse_tucker(dims, nnz, ranks, seed=9)
+    T = tsk.Tensor.coo(torch.from_numpy(idx).to(DEV), torch.from_numpy(val).to(DEV), dims)
+    plan = tsk.TuckerPlan(T, ranks, m, 2, sketch="ts", init="rrf", prec="f32", seed=0,
+                          record_fit=True, solve="rsvd")
+    _, _, fits = plan.run()
+    To = osk.Tensor(dims, idx, val.astype(np.float64))
+    ref = otk.sketch_tucker_als(To, ranks, m, 2, seed=0, solve_kind="rsvd")
+    np.testing.assert_allclose(fits, ref["fits"], rtol=0, atol=1e-5)
