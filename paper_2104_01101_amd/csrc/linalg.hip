@@ -631,7 +631,7 @@ __global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, do
 }
 
 // ------------------------------------------ small symmetric eigenproblems ----
-// Leading R eigenpairs of a symmetric q x q matrix with q <= QM <= 24, in one
+// Leading R eigenpairs of a symmetric q x q matrix with q <= QM <= 28, in one
 // wavefront (no block barriers), same method as k_sym_eig_top:
 //   * Householder tridiagonalisation with row `lane` of the matrix in
 //     registers; v and w = p - K v are broadcast through LDS, and only the
@@ -649,8 +649,9 @@ __global__ __launch_bounds__(NT) void k_sym_eig_top(double* Mg, int q, int R, do
 //     1e-3 ||T||_1 of each other (elsewhere inverse iteration already gives
 //     orthogonal vectors), then back-transformation through the reflectors,
 //     four vectors per batched wave reduction.
-// order 24 at most: at 32 the kernel needs every VGPR and spills SGPRs
-constexpr int kEigSmallMax = 24;
+// order 28 at most (234 VGPRs, SGPR spills into VGPR lanes only); at 32 the
+// kernel needs every VGPR
+constexpr int kEigSmallMax = 28;
 
 template <int QM>
 __device__ inline void sturm4(const double (&d)[QM], const double (&e2)[QM], int q,
@@ -2010,8 +2011,11 @@ tsk_status sym_eig_top(double* M, int64_t q, int64_t R, double* lam, double* V, 
     else if (q <= 20)
       hipLaunchKernelGGL(k_sym_eig_small<20>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V,
                          nt);
-    else
+    else if (q <= 24)
       hipLaunchKernelGGL(k_sym_eig_small<24>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V,
+                         nt);
+    else
+      hipLaunchKernelGGL(k_sym_eig_small<28>, dim3(1), dim3(64), 0, st, M, int(q), int(R), lam, V,
                          nt);
     TSK_LAUNCHED();
     return TSK_OK;
