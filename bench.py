@@ -55,7 +55,8 @@ GROUP_SOURCES = {
 }
 GROUPS = ["sketch_pass", "rrf_pass", "rrf", "ts_lhs", "gram", "solve_la", "eig", "fit",
           "leverage", "fiber_index", "fiber_rows", "select", "cp_core"]
-WORKLOADS = ["zipf10k", "sparse2000", "sparse2000lev", "sparse2000det", "dense4d200", "cp500"]
+WORKLOADS = ["zipf10k", "sparse2000", "sparse2000lev", "sparse2000det", "dense4d200", "cp500",
+             "dense40"]
 PHASES = ["phase_prep", "phase_init", "phase_sweeps", "phase_fit"]
 
 
@@ -176,6 +177,7 @@ def workload(name):
 def group_work(w, solve="exact"):
     """Algorithmic work of one job per launch group: name -> (bound, amount, peak, unit).
     bytes for HBM-bound groups, flops otherwise."""
+    import numpy as np
     N = len(w.dims)
     s, R, m, sweeps = w.dims[0], w.ranks[0], w.m, w.sweeps
     dense = w.dense is not None
@@ -185,7 +187,8 @@ def group_work(w, solve="exact"):
     q = min(r, s)
     k1 = math.ceil(math.sqrt(m / r) * R - 1e-9)
     k2 = R * R + k1
-    vb = 4  # FP32 tensor values (and the sketched right-hand sides of the pass)
+    # tensor values (and the sketched right-hand sides of the pass): FP32, or FP64
+    vb = 8 if (w.dense if dense else w.val).dtype == np.float64 else 4
     vo = {"f32": 4, "bf16": 2, "f64": 8}[w.prec]  # operand bytes of Z and sampled Y
     subs = N * sweeps
     pk = PEAK_TFLOPS[w.prec]
@@ -460,6 +463,8 @@ def main():
                        "dense4d200": "dense 200^4 FP32 (6.4 GB), Tucker rank 10 + 1% noise, "
                                      "leverage-score sampling m=4000, RRF init, 5 sweeps of "
                                      "Alg. 4, FP32 operands",
+                       "dense40": "dense 40^3 FP64, Tucker rank 5 + 1% noise, TensorSketch "
+                                  "m=200, RRF init, 5 sweeps of Alg. 4, FP64 operands",
                        "cp500": "dense 500^3 FP32, CP rank 20 (collinearity 0.9) + 1% noise; "
                                 "Alg. 6: leverage-sampled Tucker to rank 30 (m=14400, RRF "
                                 "init, 5 sweeps), CP-ALS rank 20 on the core (25 sweeps), "
@@ -481,7 +486,8 @@ def main():
     if args.workload == "zipf10k":
         out["adjoint"] = adjoint_timing(tsk, L, lib, read, w, reps=max(3, args.steps))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = (cpu_baseline_dense(w, args.solve) if dense else
+        out["cpu_baseline"] = (cpu_baseline_whole(w, args.solve) if args.workload == "dense40"
+                               else cpu_baseline_dense(w, args.solve) if dense else
                                cpu_baseline(w, args.solve, 1 if args.workload == "zipf10k" else 3))
     print(json.dumps(out))
 
@@ -538,6 +544,26 @@ def cpu_baseline(w, solve="exact", sample_sweeps=3):
                       f"{w.sweeps} sweeps ({t_sweep:.2f} s each) and one residual "
                       f"({t_fit:.2f} s) timed, job = preparation + {w.sweeps} sweeps + "
                       f"residual"}
+
+
+def cpu_baseline_whole(w, solve="rsvd"):
+    """FP64 oracle running the whole job (small workloads): maps, sketched
+    right-hand sides, range finder, every sweep and the final residual."""
+    import numpy as np
+    from oracle import sketch as osk, tucker as otk
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    T = osk.Tensor.from_dense(np.asarray(w.dense, dtype=np.float64))
+    t0 = time.perf_counter()
+    ref = otk.sketch_tucker_als(T, w.ranks, w.m, w.sweeps, seed=0, sketch_kind=w.sketch,
+                                solve_kind=solve, record_fit=False)
+    secs = time.perf_counter() - t0
+    res = otk.relative_residual(T, ref["core"], ref["factors"])
+    return {"value": w.sweeps / secs, "unit": "sweeps/s", "cores": cores, "kind": "oracle",
+            "sample": f"the whole job ({w.sweeps} sweeps, final residual {res:.10f})"}
 
 
 def cpu_baseline_dense(w, solve="rsvd", slab=0.02):
