@@ -1971,7 +1971,7 @@ tsk_status spd_inverse_blocked(const double* G, int64_t n, int64_t ldg, double* 
     set_error("blocked SPD inverse needs distinct input and output");
     return TSK_EINVAL;
   }
-  if (n >= 384) return spd_inverse_blocked_t<64>(G, n, ldg, Ginv, ldi, info, ws, st);
+  if (n >= 4096) return spd_inverse_blocked_t<64>(G, n, ldg, Ginv, ldi, info, ws, st);
   return spd_inverse_blocked_t<32>(G, n, ldg, Ginv, ldi, info, ws, st);
 }
 
