@@ -341,6 +341,137 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_f32v(int64_t M, int64_t N,
       }
 }
 
+// BF16 operands, both K-major (A = [A1 | A2] as K x M, B as K x N), 64 x 64
+// tiles, 4 waves (2 x 2, 32 x 32 each), K slabs of 128 double-buffered in LDS
+// in [m][k] layout (row stride 136 elements: the 16 rows of one operand read
+// start in different banks), so that a lane feeds its 16x16x32 MFMA from one
+// 16-byte read.  Each thread loads one task of A and one of B per slab: 8 k
+// rows x 4 consecutive columns (eight 8-byte global loads), transposed in
+// registers into 4 columns x 8 k and stored with four 16-byte LDS writes; the
+// next slab is fetched into registers while the current one feeds the MFMAs.
+// Requires M1, lda1, lda2, ldb multiples of 4 and 8-byte aligned bases
+// (k_gemm_tn covers the rest).
+constexpr int kB8K = 128, kB8LD = 136;
+
+__global__ __launch_bounds__(kThreads) void k_gemm_tn_bf16v(int64_t M, int64_t N, int64_t K,
+                                                           const uint16_t* A1, int64_t lda1,
+                                                           int64_t M1, const uint16_t* A2,
+                                                           int64_t lda2, const uint16_t* B,
+                                                           int64_t ldb, int64_t kchunk,
+                                                           double* C, int64_t ldc,
+                                                           int64_t split_stride) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][kBM * kB8LD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kBN * kB8LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t i0 = int64_t(blockIdx.x) * kBM, j0 = int64_t(blockIdx.y) * kBN;
+  const int64_t kbeg = int64_t(blockIdx.z) * kchunk;
+  const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
+  const int g = lane >> 4, li = lane & 15;
+  // loader task of this thread (the same for A and B): k group kg (8 rows),
+  // column quad cq
+  const int kg = tid >> 4, cq = (tid & 15) * 4;
+  const int64_t ca = i0 + cq, cb = j0 + cq;
+  const bool fa = ca + 3 < M, fb = cb + 3 < N;
+  const uint16_t* abase = ca < M1 ? A1 + ca : A2 + (ca - M1);
+  const int64_t alda = ca < M1 ? lda1 : lda2;
+  uint2 ra[8], rb[8];
+  auto pack4 = [](const uint16_t (&t)[4]) {
+    return make_uint2(t[0] | (uint32_t(t[1]) << 16), t[2] | (uint32_t(t[3]) << 16));
+  };
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int64_t k = k0 + 8 * kg + r;
+      const bool kv = k < kend;
+      if (kv && fa) {
+        ra[r] = *reinterpret_cast<const uint2*>(abase + k * alda);
+      } else {
+        uint16_t t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t c = ca + e;
+          t[e] = (kv && c < M) ? (c < M1 ? A1[k * lda1 + c] : A2[k * lda2 + (c - M1)]) : 0;
+        }
+        ra[r] = pack4(t);
+      }
+      if (kv && fb) {
+        rb[r] = *reinterpret_cast<const uint2*>(B + k * ldb + cb);
+      } else {
+        uint16_t t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = (kv && cb + e < N) ? B[k * ldb + cb + e] : 0;
+        rb[r] = pack4(t);
+      }
+    }
+  };
+  // column c (0..3) of 8 rows as 8 consecutive k: one 16-byte word
+  auto column = [](const uint2 (&v)[8], int c) {
+    auto h = [&](int r) -> uint32_t {
+      const uint32_t w = c < 2 ? v[r].x : v[r].y;
+      return (c & 1) ? (w >> 16) : (w & 0xffffu);
+    };
+    return make_uint4(h(0) | (h(1) << 16), h(2) | (h(3) << 16), h(4) | (h(5) << 16),
+                      h(6) | (h(7) << 16));
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      *reinterpret_cast<uint4*>(&As[buf][(cq + c) * kB8LD + 8 * kg]) = column(ra, c);
+      *reinterpret_cast<uint4*>(&Bs[buf][(cq + c) * kB8LD + 8 * kg]) = column(rb, c);
+    }
+  };
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0, 0, 0, 0};
+  int buf = 0;
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kB8K) {
+    const bool more = k0 + kB8K < kend;
+    if (more) fetch(k0 + kB8K);
+    const uint16_t* as = As[buf];
+    const uint16_t* bs = Bs[buf];
+#pragma unroll
+    for (int ks = 0; ks < kB8K / 32; ++ks) {
+      bf16x8 av[2], bv[2];
+#pragma unroll
+      for (int sm = 0; sm < 2; ++sm)
+        av[sm] = *reinterpret_cast<const bf16x8*>(as + (wm * 32 + sm * 16 + li) * kB8LD +
+                                                  32 * ks + 8 * g);
+#pragma unroll
+      for (int sn = 0; sn < 2; ++sn)
+        bv[sn] = *reinterpret_cast<const bf16x8*>(bs + (wn * 32 + sn * 16 + li) * kB8LD +
+                                                  32 * ks + 8 * g);
+#pragma unroll
+      for (int sm = 0; sm < 2; ++sm)
+#pragma unroll
+        for (int sn = 0; sn < 2; ++sn)
+          acc[sm][sn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[sm], bv[sn], acc[sm][sn], 0,
+                                                                0, 0);
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  double* Cz = C + int64_t(blockIdx.z) * split_stride;
+#pragma unroll
+  for (int sm = 0; sm < 2; ++sm)
+#pragma unroll
+    for (int sn = 0; sn < 2; ++sn)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = i0 + wm * 32 + sm * 16 + 4 * g + v;
+        const int64_t j = j0 + wn * 32 + sn * 16 + li;
+        if (i < M && j < N) Cz[i * ldc + j] = double(acc[sm][sn][v]);
+      }
+}
+
 __global__ void k_reduce_splits(const double* part, int64_t M, int64_t N, int splits,
                                 double* C, int64_t ldc) {
   int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -434,6 +565,29 @@ tsk_status gemm_tn_t(int64_t M, int64_t N, int64_t K, const void* A1, int64_t ld
                          static_cast<const float*>(A1), lda1, M1,
                          static_cast<const float*>(A2), lda2, static_cast<const float*>(B), ldb,
                          kch, dst, spl > 1 ? N : ldc, spl > 1 ? M * N : int64_t(0));
+      TSK_LAUNCHED();
+      if (spl > 1) {
+        hipLaunchKernelGGL(k_reduce_splits, dim3(ceil_div(M * N, 256)), dim3(256), 0, st, part, M,
+                           N, int(spl), C, ldc);
+        TSK_LAUNCHED();
+      }
+      return TSK_OK;
+    }
+  }
+  if constexpr (std::is_same<E, uint16_t>::value && !A_MK) {
+    const bool vec = M1 % 4 == 0 && lda1 % 4 == 0 && lda2 % 4 == 0 && ldb % 4 == 0 &&
+                     reinterpret_cast<uintptr_t>(A1) % 8 == 0 &&
+                     reinterpret_cast<uintptr_t>(A2) % 8 == 0 &&
+                     reinterpret_cast<uintptr_t>(B) % 8 == 0;
+    if (vec) {
+      const int64_t kch = ceil_div(kchunk, kB8K) * kB8K;
+      const int64_t spl = ceil_div(K, kch);
+      double* dst = spl > 1 ? part : C;
+      hipLaunchKernelGGL(k_gemm_tn_bf16v, dim3(tm, tn, spl), dim3(kThreads), 0, st, M, N, K,
+                         static_cast<const uint16_t*>(A1), lda1, M1,
+                         static_cast<const uint16_t*>(A2), lda2,
+                         static_cast<const uint16_t*>(B), ldb, kch, dst, spl > 1 ? N : ldc,
+                         spl > 1 ? M * N : int64_t(0));
       TSK_LAUNCHED();
       if (spl > 1) {
         hipLaunchKernelGGL(k_reduce_splits, dim3(ceil_div(M * N, 256)), dim3(256), 0, st, part, M,

@@ -489,6 +489,32 @@ def test_rsvd_solve_large_r_fp64(tsk, m, r, s, R, k):
     np.testing.assert_allclose(W.cpu().numpy(), Wo, atol=1e-9 * np.abs(Wo).max())
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("m,r,s,R,k", [(2048, 256, 1500, 16, 26), (14400, 900, 500, 30, 40),
+                                       (1000, 102, 301, 6, 20)])
+def test_rsvd_solve_large_r_low_precision(tsk, prec, m, r, s, R, k):
+    """RSVD-LRLS with FP32 or BF16 operands at the shapes of the 10000^3 and
+    500^3 jobs (the vectorised FP32 / BF16 matrix-core products: r = 900 has
+    rows of 900 elements, 8-byte but not 16-byte aligned; r = 102 and s = 301
+    leave ragged tiles).  The operands are rounded on the host and the oracle
+    runs on the rounded values in FP64.  In the O(m s k) order the library
+    also rounds the test matrix Omega and the product Z P to the operand type
+    before the products with Y: the rank-R solution X = W A^T is within 1e-5
+    of the oracle's with FP32 operands (accumulation and that rounding) and
+    within 1e-3 with BF16 (unit roundoff 2^-8 on Omega and Z P)."""
+    rs = np.random.default_rng(m + r + 11)
+    Z = rs.standard_normal((m, r))
+    Y = Z @ rs.standard_normal((r, R)) @ rs.standard_normal((R, s)) + 0.1 * rs.standard_normal((m, s))
+    Om = rs.standard_normal((s, k))
+    dt = {"f32": torch.float32, "bf16": torch.bfloat16}[prec]
+    Zc, Yc = torch.from_numpy(Z).to(dt), torch.from_numpy(Y).to(dt)  # rounded on the host
+    A, W = tsk.rsvd_solve(Zc.to(DEV), Yc.to(DEV), R, torch.from_numpy(Om).to(DEV), prec=prec)
+    Ao, Wo = osv.rsvd_lrls(Zc.double().numpy(), Yc.double().numpy(), R, Om)
+    Xg = W.cpu().numpy() @ A.cpu().numpy().T
+    Xo = Wo @ Ao.T
+    assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) < (1e-5 if prec == "f32" else 1e-3)
+
+
 @pytest.mark.parametrize("m,r,s,R", [(2048, 256, 1500, 16), (4000, 1000, 200, 10),
                                      (1300, 300, 700, 8)])
 def test_rc_solve_large_r_fp64(tsk, m, r, s, R):
