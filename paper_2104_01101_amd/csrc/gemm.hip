@@ -190,6 +190,23 @@ __global__ __launch_bounds__(64 * kSkW16) void k_gemm_skinny16(
                                 blockIdx.y, red);
 }
 
+// Products of one to four tiles over a very long K (K >= 4096): blockIdx.z
+// takes a range of K, partial tiles in FP64 are summed in split order by
+// k_reduce_splits (deterministic).
+__global__ __launch_bounds__(kSkT) void k_gemm_skinny_split(int64_t M, int64_t N, int64_t K,
+                                                            int64_t kc, const double* A1,
+                                                            int64_t lda1, int64_t M1,
+                                                            const double* A2, int64_t lda2,
+                                                            const double* B, int64_t ldb,
+                                                            double* part) {
+  __shared__ double red[kSkW][16][17];
+  const int64_t k0 = int64_t(blockIdx.z) * kc;
+  const int64_t kn = k0 + kc < K ? kc : K - k0;
+  skinny_tile<kSkW, false>(M, N, kn, A1 + k0 * lda1, lda1, M1, A2 ? A2 + k0 * lda2 : nullptr,
+                           lda2, B + k0 * ldb, ldb, part + int64_t(blockIdx.z) * M * N, N,
+                           blockIdx.x, blockIdx.y, red);
+}
+
 // Grams A^T A of several row-major K x R matrices in one launch: blockIdx.z
 // picks the matrix, workgroups beyond its tiles leave at once.
 struct GramBatch {
@@ -525,6 +542,21 @@ tsk_status gemm_tn_t(int64_t M, int64_t N, int64_t K, const void* A1, int64_t ld
                      const void* A2, int64_t lda2, const void* B, int64_t ldb, double* C,
                      int64_t ldc, Ws& ws, hipStream_t st) {
   if (std::is_same<E, double>::value && (M <= 64 || N <= 64) && K > 0) {
+    if (!A_MK && ceil_div(M, 16) * ceil_div(N, 16) <= 4 && K >= 4096) {
+      const int64_t kc = ceil_div(ceil_div(K, std::min<int64_t>(32, K / 256)), 4) * 4;
+      const int64_t spl = ceil_div(K, kc);
+      double* part = ws.take<double>(size_t(spl * M * N));
+      if (ws.measuring() || M == 0 || N == 0) return TSK_OK;
+      hipLaunchKernelGGL(k_gemm_skinny_split, dim3(ceil_div(M, 16), ceil_div(N, 16), spl),
+                         dim3(kSkT), 0, st, M, N, K, kc, static_cast<const double*>(A1), lda1, M1,
+                         static_cast<const double*>(A2), lda2, static_cast<const double*>(B), ldb,
+                         part);
+      TSK_LAUNCHED();
+      hipLaunchKernelGGL(k_reduce_splits, dim3(ceil_div(M * N, 256)), dim3(256), 0, st, part, M, N,
+                         int(spl), C, ldc);
+      TSK_LAUNCHED();
+      return TSK_OK;
+    }
     if (ws.measuring() || M == 0 || N == 0) return TSK_OK;
     if (ceil_div(M, 16) * ceil_div(N, 16) <= 4 && K >= 1024) {
       hipLaunchKernelGGL((k_gemm_skinny16<A_MK>), dim3(ceil_div(M, 16), ceil_div(N, 16)),

@@ -471,13 +471,14 @@ def test_rsvd_solve_fp32_operands(tsk):
 # ------------------------------------------------- large Grams (r > 142) ----
 @pytest.mark.parametrize("m,r,s,R,k", [(2048, 256, 1500, 16, 26), (4000, 1000, 200, 10, 20),
                                        (14400, 900, 500, 30, 40), (1300, 300, 700, 8, 40),
-                                       (700, 143, 90, 5, 12)])
+                                       (700, 143, 90, 5, 12), (2048, 256, 10000, 16, 26)])
 def test_rsvd_solve_large_r_fp64(tsk, m, r, s, R, k):
     """RSVD-LRLS at the Gram orders of the 10000^3 (r = 256), 200^4 (r = 1000)
-    and 500^3 (r = 900) workloads: the Gram is inverted by block sweeps (64
-    pivots per block from r = 384, 32 below; r = 300 and 143 leave a ragged
-    last block) and the products with Y follow the O(m s k) order.  FP64
-    library vs the oracle with the same test matrix."""
+    and 500^3 (r = 900) workloads: the Gram is inverted by block sweeps (32
+    pivots per block; r = 300 and 143 leave a ragged last block) and the
+    products with Y follow the O(m s k) order; s = 10^4 (the 10000^3 shape)
+    takes D D^T over K = s by split partial tiles.  FP64 library vs the oracle
+    with the same test matrix."""
     rs = np.random.default_rng(m + r + 7)
     Z = rs.standard_normal((m, r))
     Y = Z @ rs.standard_normal((r, R)) @ rs.standard_normal((R, s)) + 0.1 * rs.standard_normal((m, s))
