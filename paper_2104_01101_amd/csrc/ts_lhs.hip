@@ -320,35 +320,32 @@ __global__ __launch_bounds__(kFftBlock) void k_spectra(SpecJob sj, int64_t m, Ra
     const int32_t* ptr = sj.ptr[q];
     const int32_t* items = sj.items[q];
     const int64_t sq = sj.s[q];
-    if (sq <= 2 * m) {
-      // staged: the signed entries of every item into the (still unused) FFT
-      // work buffer b, all loads in flight, and the bucket starts into LDS
-      // after the twiddles; then each bucket summed in item order (the sums
-      // of the loop below, bit for bit)
-      double* val = reinterpret_cast<double*>(b);
-      int32_t* ps = reinterpret_cast<int32_t*>(buf + 3 * m);
+    // the signed entries of the items staged into the (still unused) FFT work
+    // buffer b, 2m at a time with all loads in flight, and the bucket starts
+    // into LDS after the twiddles; each bucket is summed in item order across
+    // the chunks (the in-order sums of k_cs_gather, bit for bit)
+    double* val = reinterpret_cast<double*>(b);
+    int32_t* ps = reinterpret_cast<int32_t*>(buf + 3 * m);
+    for (int64_t f = threadIdx.x; f <= m; f += blockDim.x) ps[f] = ptr[f];
+    for (int64_t f = threadIdx.x; f < m; f += blockDim.x) a[f] = make_double2(0.0, 0.0);
+    const int64_t CH = 2 * m;
+    for (int64_t c0 = 0; c0 < sq; c0 += CH) {
+      const int64_t c1 = c0 + CH < sq ? c0 + CH : sq;
+      __syncthreads();  // the previous chunk is summed
 #pragma unroll 4
-      for (int64_t p = threadIdx.x; p < sq; p += blockDim.x) {
+      for (int64_t p = c0 + threadIdx.x; p < c1; p += blockDim.x) {
         const int32_t i = items[p];
         const double v = A[int64_t(i) * R + c];
-        val[p] = sg[i] > 0 ? v : -v;
+        val[p - c0] = sg[i] > 0 ? v : -v;
       }
-      for (int64_t f = threadIdx.x; f <= m; f += blockDim.x) ps[f] = ptr[f];
       __syncthreads();
       for (int64_t f = threadIdx.x; f < m; f += blockDim.x) {
-        double acc = 0.0;
-        for (int32_t p = ps[f]; p < ps[f + 1]; ++p) acc += val[p];
-        a[f] = make_double2(acc, 0.0);
-      }
-    } else {
-      for (int64_t f = threadIdx.x; f < m; f += blockDim.x) {
-        double acc = 0.0;
-        for (int32_t p = ptr[f]; p < ptr[f + 1]; ++p) {
-          const int32_t i = items[p];
-          const double v = A[int64_t(i) * R + c];
-          acc += sg[i] > 0 ? v : -v;
+        const int64_t lo = ps[f] > c0 ? ps[f] : c0, hi = ps[f + 1] < c1 ? ps[f + 1] : c1;
+        if (lo < hi) {
+          double acc = a[f].x;
+          for (int64_t p = lo; p < hi; ++p) acc += val[p - c0];
+          a[f].x = acc;
         }
-        a[f] = make_double2(acc, 0.0);
       }
     }
   } else {
