@@ -242,6 +242,30 @@ def dense4d200():
     return workloads.dense4d200()
 
 
+def test_dense4d200_first_sweep_vs_oracle(tsk, dense4d200):
+    """200^4 FP32 (6.4 GB), leverage sampling m = 4000: one sweep of Alg. 4
+    (four sampled subproblems, RSVD-LRLS) from orthonormal factors drawn on the
+    host (the same start on both sides; the range finder has its own
+    full-size test), FP32 operands on the GPU against the FP64 oracle on the
+    same FP32-valued tensor: the relative residual after the sweep within
+    1e-5, and the factors after the sign rule within 1e-3."""
+    w = dense4d200
+    rs = np.random.default_rng(4)
+    init = [np.linalg.qr(rs.standard_normal((d, R)))[0] for d, R in zip(w.dims, w.ranks)]
+    T = tsk.Tensor.dense(torch.from_numpy(w.dense).to(DEV))
+    _, facs, fits = tsk.tucker_sketch_als(T, w.ranks, w.m, 1, sketch="lev", init="user",
+                                          init_factors=[torch.from_numpy(F).to(DEV) for F in init],
+                                          prec="f32", seed=0, solve="rsvd")
+    del T
+    torch.cuda.empty_cache()
+    To = osk.Tensor.from_dense(w.dense.astype(np.float64))
+    ref = otk.sketch_tucker_als(To, w.ranks, w.m, 1, seed=0, sketch_kind="lev",
+                                solve_kind="rsvd", init="user", init_factors=init)
+    assert abs(fits[0] - ref["fits"][0]) <= 1e-5, (fits, ref["fits"])
+    for F, Fo in zip(facs, ref["factors"]):
+        np.testing.assert_allclose(F.cpu().numpy(), Fo, rtol=0, atol=1e-3)
+
+
 def test_dense4d200_leverage_sketch_full_size(tsk, dense4d200):
     """200^4, m = 4000: orthonormal factors with a few coherent rows (rows
     0..4 weighted 10x before the QR, so the leverage scores are far from
