@@ -181,7 +181,8 @@ tsk_status tsk_workspace_size(const tsk_tensor* T, const int32_t* ranks,
  *   ranks       host int32[N], 1 <= R_n < s_n
  *   core        device double[prod R_n]          (output)
  *   factors     host array of N device double*, factors[n] is s_n x R_n with
- *               orthonormal columns, the entry of largest magnitude of each
+ *               orthonormal columns (with RSVD-LRLS to O(u kappa^2), see
+ *               tsk_rsvd_solve), the entry of largest magnitude of each
  *               column positive (output; input too when init = USER)
  *   fit_history host double[sweeps] or NULL: ||T - T~||_F / ||T||_F after each
  *               sweep (TSK_FLAG_RECORD_FIT) or after the last one
