@@ -1065,7 +1065,12 @@ __global__ __launch_bounds__(64) void k_qr_rows(const double* Ct, int k, int r, 
 // Gram X_p^T X_p (plus the shift 11 (r k + k (k + 1)) u ||C||_F^2 on the
 // diagonal in the first pass), its Cholesky factor R_p and X_{p+1} =
 // X_p R_p^{-1}; after three passes Q = X_3 has orthonormal columns to working
-// precision whenever C has full numerical column rank.  Any orthonormal basis
+// precision whenever C has full numerical column rank.  The kernel first runs
+// the first pass unshifted: if its factor is well conditioned (largest over
+// smallest diagonal entry of R at most 1e4) and the second pass finds X_1
+// nearly orthonormal (every diagonal entry of its R within 0.1 of 1), the two
+// plain passes finish (Cholesky QR2, Yamamoto et al., ETNA 2015); otherwise it
+// restarts from C with the three shifted passes.  Any orthonormal basis
 // of range(C) serves the randomized solve (its SVD of Q^T B Z^T Y fixes A and
 // W), so this replaces the Householder QR beyond the register-resident shapes.  A non-positive pivot in
 // the unshifted passes (C of numerical rank below k, e.g. an exactly low-rank
@@ -1083,15 +1088,19 @@ __global__ __launch_bounds__(256) void k_cholqr3(const double* Ct, int k, int r,
                                                  double* X2, double* Qt, int* fallback) {
   extern __shared__ double csm[];
   constexpr int SL = KP + 1, SZ = KP * SL, NB = KP / 16;
-  __shared__ int bad;
+  __shared__ int bad, restart;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   double* Gs = csm;           // Gram, then R (upper triangle)
   double* Ri = csm + SZ;      // R^{-1} (row-major)
-  if (tid == 0) bad = 0;
-  for (int pass = 0; pass < 3; ++pass) {
+  if (tid == 0) bad = 0, restart = 0;
+  // Two unshifted passes (Cholesky QR2) when the first factor is well
+  // conditioned, else the three passes of the shifted algorithm from C again
+  int npass = 2;
+  bool shifted = false;
+  for (int pass = 0; pass < npass; ++pass) {
     const double* in = pass == 0 ? Ct : pass == 1 ? X1 : X2;
-    double* out = pass == 0 ? X1 : pass == 1 ? X2 : Qt;
+    double* out = pass == npass - 1 ? Qt : pass == 0 ? X1 : X2;
     // ---- Gram partials over this wave's 64-column blocks ----
     dx4 acc[NB][NB];
 #pragma unroll
@@ -1141,7 +1150,7 @@ __global__ __launch_bounds__(256) void k_cholqr3(const double* Ct, int k, int r,
       Gs[o] = csm[o] + csm[SZ + o];
     }
     __syncthreads();
-    if (pass == 0 && wave == 0) {  // the shift of the first pass
+    if (pass == 0 && shifted && wave == 0) {  // the shift of the first pass
       double tr = 0.0;
       for (int j = 0; j < k; ++j) tr += Gs[j * SL + j];
       const double shift = 11.0 * (double(r) * k + double(k) * (k + 1)) * 0x1.0p-53 * tr;
@@ -1164,6 +1173,33 @@ __global__ __launch_bounds__(256) void k_cholqr3(const double* Ct, int k, int r,
         if (a <= b) Gs[a * SL + b] = fma(-Gs[j * SL + a], Gs[j * SL + b], Gs[a * SL + b]);
       }
       __syncthreads();
+    }
+    if (!shifted) {
+      // Cholesky QR2 leaves O(u) orthogonality for kappa(C) well below
+      // u^{-1/2}.  First pass: the ratio of the largest to the smallest
+      // diagonal entry of R (a lower bound on kappa(C)) at most 1e4.  Second
+      // pass: X_1 must already be nearly orthonormal, every R_jj within 0.1 of
+      // 1 (X_1^T X_1 = R^T R).  Otherwise restart with the shifted passes.
+      if (wave == 0) {
+        double dmax = lane < k ? Gs[lane * SL + lane] : 0.0;
+        double dmin = lane < k ? Gs[lane * SL + lane] : DBL_MAX;
+        for (int off = 32; off > 0; off >>= 1) {
+          dmax = fmax(dmax, __shfl_xor(dmax, off));
+          dmin = fmin(dmin, __shfl_xor(dmin, off));
+        }
+        const bool ok = pass == 0 ? dmax <= 1e4 * dmin : (dmax <= 1.1 && dmin >= 0.9);
+        if (lane == 0 && (bad || !ok)) restart = 1;
+      }
+      __syncthreads();
+      if (restart) {  // workgroup-uniform
+        shifted = true;
+        npass = 3;
+        pass = -1;
+        __syncthreads();
+        if (tid == 0) bad = 0;
+        __syncthreads();
+        continue;
+      }
     }
     // ---- S = R^{-1} by back substitution (wave 0, lane c holds column c) ----
     if (wave == 0 && !bad) {

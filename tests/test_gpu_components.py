@@ -490,6 +490,28 @@ def test_rsvd_solve_large_r_fp64(tsk, m, r, s, R, k):
     np.testing.assert_allclose(W.cpu().numpy(), Wo, atol=1e-9 * np.abs(Wo).max())
 
 
+@pytest.mark.parametrize("noise", [1e-2, 1e-6, 1e-9])
+def test_rsvd_solve_range_basis_conditioning(tsk, noise):
+    """The thin QR of C = B Z^T Y Omega at r = 256, k = 26 with Y of rank R = 16
+    plus noise: C has R large and k - R small singular values, so kappa(C)
+    grows as the noise shrinks.  Noise 1e-2 keeps two plain Cholesky QR passes,
+    1e-6 and 1e-9 make the first factor ill conditioned and the kernel restart
+    with the three shifted passes.  FP64 against the oracle: the rank-R
+    solution W A^T within 1e-9 relative."""
+    rs = np.random.default_rng(31)
+    m, r, s, R, k = 2048, 256, 1500, 16, 26
+    Z = rs.standard_normal((m, r))
+    Y = Z @ rs.standard_normal((r, R)) @ rs.standard_normal((R, s)) + noise * rs.standard_normal((m, s))
+    Om = rs.standard_normal((s, k))
+    A, W = tsk.rsvd_solve(torch.from_numpy(Z).to(DEV), torch.from_numpy(Y).to(DEV), R,
+                          torch.from_numpy(Om).to(DEV))
+    Ao, Wo = osv.rsvd_lrls(Z, Y, R, Om)
+    Xg = W.cpu().numpy() @ A.cpu().numpy().T
+    Xo = Wo @ Ao.T
+    assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) < 1e-9
+    np.testing.assert_allclose(A.cpu().numpy().T @ A.cpu().numpy(), np.eye(R), atol=1e-10)
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("m,r,s,R,k", [(2048, 256, 1500, 16, 26), (14400, 900, 500, 30, 40),
                                        (1000, 102, 301, 6, 20)])
