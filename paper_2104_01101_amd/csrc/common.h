@@ -53,6 +53,9 @@ struct Ws {
   char* base = nullptr;
   size_t off = 0;
   size_t cap = 0;
+  // set by callers that may create no streams or events: every step stays on
+  // the caller's stream
+  bool serial = false;
   template <class T>
   T* take(size_t count) {
     off = (off + 255) & ~size_t(255);

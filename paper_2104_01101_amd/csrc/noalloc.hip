@@ -83,6 +83,7 @@ extern "C" tsk_status tsk_rsvd_solve_noalloc(const void* Z, const void* Y, int64
   Ws w;
   w.base = static_cast<char*>(base);
   w.cap = kScratchBytes;
+  w.serial = true;
   int* info = w.take<int>(4);
   hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, st, info, 4);
   TSK_LAUNCHED();
