@@ -9,6 +9,16 @@ struct FitScratch {
   int nblocks;
   double *partial_norm, *partial_inner, *partial_direct, *grams, *buf0, *buf1, *model2, *nT2;
   double* ttm[2];  // dense tensors: mode products of the core (R_1 x s_2 x ... x s_N)
+  // order-3 COO tensors of rank 16: the entries sorted by their last index
+  // (once per plan), W = C x_3 A^(3) (s_3 x R x R), <T, T~> at R^2 per entry
+  bool by_last = false;  // this path is planned
+  bool sorted = false;   // the sorted copy is in place
+  uint32_t *keys_in, *keys;  // i_3, then i_3 sorted
+  void *ents_in, *ents;       // (i_1, i_2, value) of every entry, then sorted with the keys
+  double* W;
+  void* sort_tmp;
+  size_t sort_bytes;
+  unsigned key_bits;
 };
 tsk_status fit_plan(const TensorView& T, const int64_t* R, FitScratch& fs, Ws& ws);
 // Dense T (s_1 x J, row-major) against T~ = A1 M, A1 s_1 x R1 (R1 <= kDenseFitMaxR),

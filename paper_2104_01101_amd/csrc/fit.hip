@@ -7,6 +7,14 @@
 //   <T, T~>  per stored entry, T~(i) = sum_rho C(rho) prod_k A^(k)(i_k, rho_k)
 //   ||T~||^2 = <C x_1 G_1 ... x_N G_N, C>, G_k = A^(k)T A^(k)
 // Reductions are two-level with a fixed order (deterministic).
+// Order-3 COO tensors of equal ranks 16 take <T, T~> in another order: with
+// the entries grouped by their last index k (a stable sort, once per plan),
+//   T~(i, j, k) = sum_{x,y} A^(1)(i, x) A^(2)(j, y) W_k(x, y),
+//   W_k = sum_z C(:, :, z) A^(3)(k, z),
+// R^2 + R multiply-adds per entry instead of R^3 + R^2 + R, W_k being the
+// same for a whole run of entries.
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.h"
 #include "kernels.h"
@@ -230,6 +238,99 @@ __global__ __launch_bounds__(kT) void k_inner3x(FitArgs a, int64_t nnz, int64_t 
   if (threadIdx.x == 0) partial[blockIdx.x] = acc, partial_direct[blockIdx.x] = acc2;
 }
 
+// ---- <T, T~> over entries grouped by their last index ----
+// the payload that travels with the sort key i_3
+template <class V>
+struct Ent {
+  int32_t i0, i1;
+  V v;
+};
+
+template <class V>
+__global__ __launch_bounds__(kT) void k_last_keys(const int32_t* __restrict__ i0,
+                                                  const int32_t* __restrict__ i1,
+                                                  const int32_t* __restrict__ i2,
+                                                  const V* __restrict__ v, int64_t nnz,
+                                                  uint32_t* keys, Ent<V>* ents) {
+  for (int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x; e < nnz;
+       e += int64_t(gridDim.x) * kT) {
+    keys[e] = uint32_t(i2[e]);
+    ents[e] = Ent<V>{i0[e], i1[e], v[e]};
+  }
+}
+
+// W[k][x][y] = sum_z C[x][y][z] A3[k][z], one thread per (k, x, y)
+template <int RR>
+__global__ __launch_bounds__(kT) void k_core_last(const double* __restrict__ C,
+                                                  const double* __restrict__ A3, int64_t s3,
+                                                  double* W) {
+  const int64_t t = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (t >= s3 * RR * RR) return;
+  const int64_t k = t / (RR * RR), xy = t - k * (RR * RR);
+  double acc = 0.0;
+#pragma unroll
+  for (int z = 0; z < RR; ++z) acc = fma(C[xy * RR + z], A3[k * RR + z], acc);
+  W[t] = acc;
+}
+
+// One lane per entry of the sorted list.  The lanes of a wave share few
+// distinct k (runs of equal k are contiguous), so the wave takes them in
+// turn: W_k is wave-uniform, read with scalar loads into SGPRs and used as the
+// FMAs' scalar operand; the lanes of that k keep the result.
+template <int RR, class V>
+__global__ __launch_bounds__(kT) void k_inner3s(const uint32_t* __restrict__ ks,
+                                                const Ent<V>* __restrict__ ents,
+                                                const double* __restrict__ A0,
+                                                const double* __restrict__ A1,
+                                                const double* __restrict__ W, int64_t nnz,
+                                                int64_t per_block, double* partial) {
+  __shared__ double red[kT / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t lo = int64_t(blockIdx.x) * per_block;
+  const int64_t hi = lo + per_block < nnz ? lo + per_block : nnz;
+  double acc = 0.0;
+  for (int64_t g = lo + wave * 64; g < hi; g += kT) {
+    const int64_t e = g + lane;
+    const bool valid = e < hi;
+    const int64_t ec = valid ? e : hi - 1;
+    const uint32_t k = ks[ec];
+    const Ent<V> en = ents[ec];
+    const int64_t r0 = en.i0, r1 = en.i1;
+    double u0[RR], u1[RR];
+#pragma unroll
+    for (int c = 0; c < RR; ++c) {
+      u0[c] = A0[r0 * RR + c];
+      u1[c] = A1[r1 * RR + c];
+    }
+    const double v = valid ? double(en.v) : 0.0;
+    uint64_t pend = __ballot(valid);
+    double tv = 0.0;
+    while (pend) {
+      const int first = __ffsll((unsigned long long)pend) - 1;
+      const uint32_t kk = uint32_t(__builtin_amdgcn_readlane(int(k), first));
+      const double* __restrict__ w = W + size_t(kk) * (RR * RR);
+      double t = 0.0;
+#pragma unroll
+      for (int x = 0; x < RR; ++x) {
+        double pe = 0.0, po = 0.0;  // even and odd y as two chains
+#pragma unroll
+        for (int y = 0; y + 1 < RR; y += 2) {
+          pe = fma(w[x * RR + y], u1[y], pe);
+          po = fma(w[x * RR + y + 1], u1[y + 1], po);
+        }
+        if (RR & 1) pe = fma(w[x * RR + RR - 1], u1[RR - 1], pe);
+        t = fma(pe + po, u0[x], t);
+      }
+      const bool mine = ((pend >> lane) & 1ull) && k == kk;
+      if (mine) tv = t;
+      pend &= ~__ballot(mine);
+    }
+    acc = fma(v, tv, acc);
+  }
+  acc = block_reduce(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
 // ||T~||^2 = <C x_k G_k, C>, single block; buf0/buf1 scratch of csize
 __global__ __launch_bounds__(kT) void k_model_norm2(FitArgs a, const double* core, int64_t csize,
                                                    const double* grams, double* buf0,
@@ -428,6 +529,24 @@ tsk_status dense_residual_partials(const TensorView& T, const double* M, const d
   return TSK_OK;
 }
 
+// stable radix sort of the entries by i_3 (the temporary size when tmp is NULL)
+template <class V>
+tsk_status sort_entries(void* tmp, size_t& bytes, const FitScratch& fs, size_t n,
+                        hipStream_t st) {
+  TSK_HIP(rocprim::radix_sort_pairs(tmp, bytes, fs.keys_in, fs.keys,
+                                    static_cast<const Ent<V>*>(fs.ents_in),
+                                    static_cast<Ent<V>*>(fs.ents), n, 0u, fs.key_bits, st));
+  return TSK_OK;
+}
+
+// The grouped order pays where R^3 per entry outweighs the sort: rank 16,
+// at least 2^16 entries, indices of the last mode below 2^31.
+static bool fit_by_last(const TensorView& T, const int64_t* R) {
+  return T.layout == TSK_COO && T.order == 3 && R[0] == 16 && R[1] == 16 && R[2] == 16 &&
+         T.nnz >= (int64_t(1) << 16) && T.nnz < (int64_t(1) << 32) &&
+         T.dims[2] <= (int64_t(1) << 31);
+}
+
 tsk_status fit_plan(const TensorView& T, const int64_t* R, FitScratch& fs, Ws& ws) {
   int64_t csize = 1, gsz = 0;
   for (int k = 0; k < T.order; ++k) csize *= R[k], gsz += R[k] * R[k];
@@ -443,6 +562,26 @@ tsk_status fit_plan(const TensorView& T, const int64_t* R, FitScratch& fs, Ws& w
   fs.model2 = ws.take<double>(1);
   fs.nT2 = ws.take<double>(1);
   fs.ttm[0] = fs.ttm[1] = nullptr;
+  fs.by_last = fit_by_last(T, R);
+  fs.sorted = false;
+  if (fs.by_last) {
+    const size_t n = size_t(T.nnz);
+    const bool f64 = T.dtype == TSK_F64;
+    const size_t eb = f64 ? sizeof(Ent<double>) : sizeof(Ent<float>);
+    fs.keys_in = ws.take<uint32_t>(n);
+    fs.keys = ws.take<uint32_t>(n);
+    fs.ents_in = ws.take<char>(n * eb);
+    fs.ents = ws.take<char>(n * eb);
+    fs.W = ws.take<double>(size_t(T.dims[2]) * R[0] * R[1]);
+    fs.key_bits = 1;
+    while (fs.key_bits < 32 && (int64_t(1) << fs.key_bits) < T.dims[2]) ++fs.key_bits;
+    fs.sort_bytes = 0;
+    if (f64)
+      TSK_TRY(sort_entries<double>(nullptr, fs.sort_bytes, fs, n, hipStream_t(nullptr)));
+    else
+      TSK_TRY(sort_entries<float>(nullptr, fs.sort_bytes, fs, n, hipStream_t(nullptr)));
+    fs.sort_tmp = ws.take<char>(fs.sort_bytes);
+  }
   if (T.layout == TSK_DENSE && R[0] <= kDenseFitMaxR) {
     // mode products k = N-1 .. 1 alternate between two buffers, the last
     // (the largest, R_1 x s_2 x ... x s_N) landing in ttm[0]
@@ -487,6 +626,27 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
       TSK_TRY(gemm_tn(TSK_PREC_F64, R[k], R[k], T.dims[k], factors[k], R[k], R[k], nullptr, 0,
                       factors[k], R[k], gp[k], R[k], ws, st));
   if (ws.measuring()) return TSK_OK;
+  if (fs.by_last && !fs.sorted) {
+    // the entries grouped by their last index, stably (input order within a run)
+    ProfScope prof("fit_sort", st);
+    const int64_t n = T.nnz;
+    const unsigned grid = unsigned(std::min<int64_t>(ceil_div(n, kT), 8192));
+    size_t bytes = fs.sort_bytes;
+    if (T.dtype == TSK_F64) {
+      hipLaunchKernelGGL(k_last_keys<double>, dim3(grid), dim3(kT), 0, st, T.idx[0], T.idx[1],
+                         T.idx[2], static_cast<const double*>(T.values), n, fs.keys_in,
+                         static_cast<Ent<double>*>(fs.ents_in));
+      TSK_LAUNCHED();
+      TSK_TRY(sort_entries<double>(fs.sort_tmp, bytes, fs, size_t(n), st));
+    } else {
+      hipLaunchKernelGGL(k_last_keys<float>, dim3(grid), dim3(kT), 0, st, T.idx[0], T.idx[1],
+                         T.idx[2], static_cast<const float*>(T.values), n, fs.keys_in,
+                         static_cast<Ent<float>*>(fs.ents_in));
+      TSK_LAUNCHED();
+      TSK_TRY(sort_entries<float>(fs.sort_tmp, bytes, fs, size_t(n), st));
+    }
+    fs.sorted = true;
+  }
   ProfScope prof("fit", st);
   if (rmax_g <= 64)  // the factor Grams of every mode in one launch
     TSK_TRY(gram_batch_f64(T.order, R, T.dims, factors, gp, st));
@@ -529,7 +689,20 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
   }
   int64_t rmax = 0;
   for (int k = 0; k < T.order; ++k) rmax = std::max<int64_t>(rmax, R[k]);
-  if (T.order == 3 && rmax <= 32) {
+  if (fs.by_last) {
+    const int64_t s3 = T.dims[2];
+    hipLaunchKernelGGL(k_core_last<16>, dim3(unsigned(ceil_div(s3 * 256, kT))), dim3(kT), 0, st,
+                       core, factors[2], s3, fs.W);
+    TSK_LAUNCHED();
+    if (T.dtype == TSK_F64)
+      hipLaunchKernelGGL((k_inner3s<16, double>), dim3(fs.nblocks), dim3(kT), 0, st, fs.keys,
+                         static_cast<const Ent<double>*>(fs.ents), factors[0], factors[1], fs.W,
+                         T.nnz, per, fs.partial_inner);
+    else
+      hipLaunchKernelGGL((k_inner3s<16, float>), dim3(fs.nblocks), dim3(kT), 0, st, fs.keys,
+                         static_cast<const Ent<float>*>(fs.ents), factors[0], factors[1], fs.W,
+                         T.nnz, per, fs.partial_inner);
+  } else if (T.order == 3 && rmax <= 32) {
     const int core_lds = csize * 8 <= 150000 ? 1 : 0;
     const size_t lds = core_lds ? size_t(csize) * 8 : 0;
     const bool eq = R[0] == R[1] && R[1] == R[2];

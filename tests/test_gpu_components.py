@@ -345,6 +345,60 @@ def test_fit_matches_oracle(tsk, sparse):
     assert abs(f - otk.relative_residual(To, core, facs)) < 1e-12
 
 
+def _distinct_coo(dims, nnz, rs, last_probs=None):
+    """nnz distinct coordinates in random order; the last mode's index drawn
+    from last_probs when given (skewed run lengths), else uniformly."""
+    idx = np.zeros((0, 3), dtype=np.int64)
+    while idx.shape[0] < nnz:
+        c = 2 * nnz
+        last = (rs.choice(dims[2], c, p=last_probs) if last_probs is not None
+                else rs.integers(0, dims[2], c))
+        new = np.stack([rs.integers(0, dims[0], c), rs.integers(0, dims[1], c), last], 1)
+        idx = np.concatenate([idx, new])
+        lin = np.ravel_multi_index(idx.T, dims)
+        _, first = np.unique(lin, return_index=True)
+        idx = idx[np.sort(first)]
+    return idx[rs.permutation(idx.shape[0])[:nnz]].astype(np.int32)
+
+
+@pytest.mark.parametrize("case", ["zipf_last", "one_last_index", "uniform_f32", "below_cutoff"])
+def test_fit_rank16_grouped_by_last_index(tsk, case):
+    """Rank-16 order-3 COO residuals from 2^16 entries on group the entries by
+    their last index (a stable sort) and take <T, T~> as u0^T W_k u1 with
+    W_k = C x_3 A^(3)(k, :); compared with the oracle's definition (Sec. 7) on
+    skewed runs (a Zipf last index: runs of 3 to 14439 of the 100003
+    entries), a single last index (one run over every wave), FP32 values, and
+    one entry below the cutoff (the per-entry R^3 kernel)."""
+    rs = np.random.default_rng({"zipf_last": 31, "one_last_index": 32, "uniform_f32": 33,
+                                "below_cutoff": 34}[case])
+    R = 16
+    if case == "zipf_last":
+        dims, nnz = (300, 200, 1000), 100_003
+        p = 1.0 / np.arange(1, dims[2] + 1) ** 1.1
+        idx = _distinct_coo(dims, nnz, rs, p / p.sum())
+    elif case == "one_last_index":
+        dims, nnz = (400, 300, 20), 70_001
+        idx = _distinct_coo(dims, nnz, rs, np.eye(dims[2])[5])
+    else:
+        dims = (200, 150, 3000)
+        nnz = 65_536 if case == "uniform_f32" else 65_535
+        idx = _distinct_coo(dims, nnz, rs)
+    facs = [rs.standard_normal((d, R)) for d in dims]  # not orthonormal
+    core = rs.standard_normal((R, R, R))
+    model = otk.values_at(core, facs, idx)
+    val = model + 0.3 * model.std() * rs.standard_normal(nnz)
+    if case == "uniform_f32":
+        val = val.astype(np.float32)
+    T = _gpu_tensor(tsk, dims, idx, val)
+    f = tsk.fit(T, torch.from_numpy(core).to(DEV), [torch.from_numpy(F).to(DEV) for F in facs])
+    v64 = val.astype(np.float64)
+    want = otk.relative_residual(osk.Tensor(dims, idx, v64), core, facs)
+    # the tolerance resolves a relative error of 1e-6 in <T, T~>:
+    # d(res)/res = -d<T, T~> / (res^2 ||T||^2)
+    assert np.dot(v64, model) / (want ** 2 * np.dot(v64, v64)) > 1e-4
+    assert abs(f - want) < 1e-10 * want
+
+
 # ---------------------------------------------------------------- a12 ----
 def test_adjoint_matches_oracle_and_fd(tsk):
     dims, ranks, m, n = (60, 50, 40), (3, 4, 2), 64, 1
