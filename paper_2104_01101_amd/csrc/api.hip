@@ -364,6 +364,19 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
   }
   FitScratch fs{};
   if (record) TSK_TRY(fit_plan(T, a.R, fs, ws));
+  // The residual's sorted copy of the entries depends on the tensor alone: it
+  // is built on a side stream beside the preparation and the sweeps, and
+  // joined before the first residual.
+  SideJob presort(st);
+  if (run && record && fs.by_last && !ws.serial) {
+    hipStream_t side = nullptr;
+    TSK_TRY(side_stream(&side));
+    if (side) {
+      TSK_TRY(presort.fork(side));
+      TSK_TRY(fit_presort(T, fs, side));
+      TSK_TRY(presort.done());
+    }
+  }
 
   const size_t mark = ws.off;
   size_t peak = mark;
@@ -519,6 +532,7 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
     phase.end();
     if (record && (!final_only || sweep == o.sweeps - 1)) {
       ProfScope prof(run ? "phase_fit" : "", st);
+      TSK_TRY(presort.join());
       TSK_TRY(fit_run(T, a.R, a.core, a.factors, sweep == 0 || final_only, fs,
                       a.fit_dev + sweep, ws, st));
       release();

@@ -186,4 +186,55 @@ class ProfScope {
   int idx_;
 };
 
+// A second stream of the current device (default priority, non-blocking),
+// created on first use and kept until the process ends; *out = NULL where the
+// device index is beyond the table (the caller then stays on its stream).
+tsk_status side_stream(hipStream_t* out);
+
+// Work forked from the caller's stream onto a side stream and joined back:
+// fork() makes the side stream wait for the caller's work so far, done()
+// marks the end of the side work, join() makes the caller's stream wait for
+// it.  The destructor joins too, so that no return path leaves side work
+// running past the call that owns its buffers.
+class SideJob {
+ public:
+  explicit SideJob(hipStream_t st) : st_(st) {}
+  ~SideJob() {
+    (void)join();
+    if (ev_fork_) (void)hipEventDestroy(ev_fork_);
+    if (ev_done_) (void)hipEventDestroy(ev_done_);
+  }
+  tsk_status fork(hipStream_t side) {
+    TSK_HIP(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
+    TSK_HIP(hipEventCreateWithFlags(&ev_done_, hipEventDisableTiming));
+    TSK_HIP(hipEventRecord(ev_fork_, st_));
+    TSK_HIP(hipStreamWaitEvent(side, ev_fork_, 0));
+    side_ = side;
+    return TSK_OK;
+  }
+  hipStream_t side() const { return side_; }
+  tsk_status done() {
+    if (side_ && !recorded_) {
+      TSK_HIP(hipEventRecord(ev_done_, side_));
+      recorded_ = true;
+    }
+    return TSK_OK;
+  }
+  tsk_status join() {
+    if (!side_ || joined_) return TSK_OK;
+    joined_ = true;
+    TSK_TRY(done());
+    TSK_HIP(hipStreamWaitEvent(st_, ev_done_, 0));
+    return TSK_OK;
+  }
+  SideJob(const SideJob&) = delete;
+  SideJob& operator=(const SideJob&) = delete;
+
+ private:
+  hipStream_t st_;
+  hipStream_t side_ = nullptr;
+  hipEvent_t ev_fork_ = nullptr, ev_done_ = nullptr;
+  bool recorded_ = false, joined_ = false;
+};
+
 }  // namespace tsk

@@ -27,6 +27,10 @@ tsk_status fit_plan(const TensorView& T, const int64_t* R, FitScratch& fs, Ws& w
 tsk_status dense_residual_partials(const TensorView& T, const double* M, const double* A1,
                                    int64_t R1, int nblocks, double* pdirect, double* pnorm,
                                    double* pinner, hipStream_t st);
+// The sorted copy of the entries that the rank-16 COO path reads (a no-op
+// unless fs.by_last and not yet built): enqueued on st, which may be a side
+// stream joined into the residual's stream before fit_run.
+tsk_status fit_presort(const TensorView& T, FitScratch& fs, hipStream_t st);
 // res (device double) <- relative residual; with_norm recomputes ||T||^2 into fs.nT2
 tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
                    const double* const* factors, bool with_norm, FitScratch& fs, double* res,

@@ -11,8 +11,8 @@
 // the entries grouped by their last index k (a stable sort, once per plan),
 //   T~(i, j, k) = sum_{x,y} A^(1)(i, x) A^(2)(j, y) W_k(x, y),
 //   W_k = sum_z C(:, :, z) A^(3)(k, z),
-// R^2 + R multiply-adds per entry instead of R^3 + R^2 + R, W_k being the
-// same for a whole run of entries.
+// R^2 multiply-adds per entry (on the FP64 matrix cores) instead of
+// R^3 + R^2 + R, W_k being the same for a whole run of entries.
 
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -259,73 +259,102 @@ __global__ __launch_bounds__(kT) void k_last_keys(const int32_t* __restrict__ i0
   }
 }
 
-// W[k][x][y] = sum_z C[x][y][z] A3[k][z], one thread per (k, x, y)
+// Wt[k][y][x] = sum_z C[x][y][z] A3[k][z] (W_k transposed): one thread per
+// (y, x) with its row of C in registers, kCoreK values of k per workgroup
+// (A3 rows wave-uniform)
+constexpr int kCoreK = 16;
+
 template <int RR>
-__global__ __launch_bounds__(kT) void k_core_last(const double* __restrict__ C,
-                                                  const double* __restrict__ A3, int64_t s3,
-                                                  double* W) {
-  const int64_t t = int64_t(blockIdx.x) * kT + threadIdx.x;
-  if (t >= s3 * RR * RR) return;
-  const int64_t k = t / (RR * RR), xy = t - k * (RR * RR);
-  double acc = 0.0;
+__global__ __launch_bounds__(RR * RR) void k_core_last(const double* __restrict__ C,
+                                                       const double* __restrict__ A3, int64_t s3,
+                                                       double* Wt) {
+  const int t = threadIdx.x, y = t / RR, x = t - y * RR;
+  double c[RR];
 #pragma unroll
-  for (int z = 0; z < RR; ++z) acc = fma(C[xy * RR + z], A3[k * RR + z], acc);
-  W[t] = acc;
+  for (int z = 0; z < RR; ++z) c[z] = C[(x * RR + y) * RR + z];
+  const int64_t k0 = int64_t(blockIdx.x) * kCoreK;
+  for (int64_t k = k0; k < k0 + kCoreK && k < s3; ++k) {
+    const double* a = A3 + k * RR;
+    double acc = 0.0;
+#pragma unroll
+    for (int z = 0; z < RR; ++z) acc = fma(c[z], a[z], acc);
+    Wt[k * (RR * RR) + t] = acc;
+  }
 }
 
-// One lane per entry of the sorted list.  The lanes of a wave share few
-// distinct k (runs of equal k are contiguous), so the wave takes them in
-// turn: W_k is wave-uniform, read with scalar loads into SGPRs and used as the
-// FMAs' scalar operand; the lanes of that k keep the result.
-template <int RR, class V>
+// <T, T~> over the sorted entries, 64 per wave at a time, on
+// v_mfma_f64_16x16x4 (lane l = li + 16 g feeds A(li, g) and B(g, li) and holds
+// D(g + 4 v, li)).  For each of the four 16-entry tiles m of the group,
+// D_m = U0_m W_k (entries x y) over four steps s, with A(li, g) = u0(x = 4 g + s)
+// of entry 16 m + li and B(g, li) = W_k(4 g + s, li); then every lane adds
+// D(e, y) v_e u1_e(y) for its four entries e = 16 m + g + 4 v and its y = li.
+// The group's distinct k (runs of equal k are contiguous) are taken in turn,
+// each with its own W_k and only its entries kept (a ballot mask).
+template <class V>
 __global__ __launch_bounds__(kT) void k_inner3s(const uint32_t* __restrict__ ks,
                                                 const Ent<V>* __restrict__ ents,
                                                 const double* __restrict__ A0,
                                                 const double* __restrict__ A1,
-                                                const double* __restrict__ W, int64_t nnz,
+                                                const double* __restrict__ Wt, int64_t nnz,
                                                 int64_t per_block, double* partial) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
   __shared__ double red[kT / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
   const int64_t lo = int64_t(blockIdx.x) * per_block;
   const int64_t hi = lo + per_block < nnz ? lo + per_block : nnz;
   double acc = 0.0;
-  for (int64_t g = lo + wave * 64; g < hi; g += kT) {
-    const int64_t e = g + lane;
+  for (int64_t g0 = lo + wave * 64; g0 < hi; g0 += kT) {
+    const int64_t e = g0 + lane;
     const bool valid = e < hi;
     const int64_t ec = valid ? e : hi - 1;
     const uint32_t k = ks[ec];
     const Ent<V> en = ents[ec];
-    const int64_t r0 = en.i0, r1 = en.i1;
-    double u0[RR], u1[RR];
+    // A operands: u0 of entry 16 m + li, x = 4 g .. 4 g + 3
+    double a[4][4];
 #pragma unroll
-    for (int c = 0; c < RR; ++c) {
-      u0[c] = A0[r0 * RR + c];
-      u1[c] = A1[r1 * RR + c];
+    for (int m = 0; m < 4; ++m) {
+      const int64_t r0 = __shfl(en.i0, 16 * m + li);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[m][s] = A0[r0 * 16 + 4 * g + s];
     }
-    const double v = valid ? double(en.v) : 0.0;
+    // v_e u1_e(li) of the entries e = 16 m + g + 4 v whose D rows this lane holds
+    double w[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int src = 16 * m + g + 4 * v;
+        const int64_t r1 = __shfl(en.i1, src);
+        const double val = double(__shfl(en.v, src));
+        w[m][v] = val * A1[r1 * 16 + li];
+      }
     uint64_t pend = __ballot(valid);
-    double tv = 0.0;
     while (pend) {
       const int first = __ffsll((unsigned long long)pend) - 1;
       const uint32_t kk = uint32_t(__builtin_amdgcn_readlane(int(k), first));
-      const double* __restrict__ w = W + size_t(kk) * (RR * RR);
-      double t = 0.0;
+      const uint64_t sel = __ballot(valid && k == kk);
+      const double* wk = Wt + size_t(kk) * 256 + li * 16 + 4 * g;
+      double b[4];
 #pragma unroll
-      for (int x = 0; x < RR; ++x) {
-        double pe = 0.0, po = 0.0;  // even and odd y as two chains
+      for (int s = 0; s < 4; ++s) b[s] = wk[s];
+      d4 d[4];
 #pragma unroll
-        for (int y = 0; y + 1 < RR; y += 2) {
-          pe = fma(w[x * RR + y], u1[y], pe);
-          po = fma(w[x * RR + y + 1], u1[y + 1], po);
-        }
-        if (RR & 1) pe = fma(w[x * RR + RR - 1], u1[RR - 1], pe);
-        t = fma(pe + po, u0[x], t);
+      for (int m = 0; m < 4; ++m) {
+        d[m] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          d[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m][s], b[s], d[m], 0, 0, 0);
       }
-      const bool mine = ((pend >> lane) & 1ull) && k == kk;
-      if (mine) tv = t;
-      pend &= ~__ballot(mine);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool mine = (sel >> (16 * m + g + 4 * v)) & 1ull;
+          acc = fma(mine ? d[m][v] : 0.0, w[m][v], acc);
+        }
+      pend &= ~sel;
     }
-    acc = fma(v, tv, acc);
   }
   acc = block_reduce(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
@@ -432,26 +461,35 @@ __global__ __launch_bounds__(kT) void k_fit_dense(const V* __restrict__ X, const
 }
 
 // k_model_norm2 and k_finish in one workgroup, the mode products of the
-// model norm ping-ponging between two LDS buffers of csize doubles.
+// model norm ping-ponging between two LDS buffers of csize doubles (the core
+// is staged in the second first); the factor Grams are staged in LDS too when
+// they take at most kGramLds doubles (gl = their total, else 0).
+constexpr int kGramLds = 2048;
+
 __global__ __launch_bounds__(kT) void k_finish_model(FitArgs a, const double* core, int64_t csize,
-                                                     const double* grams, const double* pn,
-                                                     int nbn, const double* pi, int nbi,
-                                                     const double* pd, int dense,
+                                                     const double* grams, int gl,
+                                                     const double* pn, int nbn, const double* pi,
+                                                     int nbi, const double* pd, int dense,
                                                      double* nT2_out, double* res_out) {
-  extern __shared__ double lbuf[];  // 2 csize
+  extern __shared__ double lbuf[];  // 2 csize + gl
   __shared__ double red[kT / 64];
-  const double* in = core;
-  int64_t goff = 0;
+  const int cs = int(csize);
+  double* gl_s = lbuf + 2 * cs;
+  for (int t = threadIdx.x; t < cs; t += kT) lbuf[cs + t] = core[t];
+  for (int t = threadIdx.x; t < gl; t += kT) gl_s[t] = grams[t];
+  __syncthreads();
+  const double* in = lbuf + cs;
+  int goff = 0;
   for (int k = 0; k < a.N; ++k) {
-    const int64_t Rk = a.R[k];
-    int64_t inner = 1;
-    for (int l = k + 1; l < a.N; ++l) inner *= a.R[l];
-    const double* G = grams + goff;
-    double* o = lbuf + (k & 1) * csize;
-    for (int64_t t = threadIdx.x; t < csize; t += kT) {
-      int64_t rk = (t / inner) % Rk, base = t - rk * inner;
+    const int Rk = int(a.R[k]);
+    int inner = 1;
+    for (int l = k + 1; l < a.N; ++l) inner *= int(a.R[l]);
+    const double* G = (gl ? gl_s : grams) + goff;
+    double* o = lbuf + (k & 1) * cs;
+    for (int t = threadIdx.x; t < cs; t += kT) {
+      const int rk = (t / inner) % Rk, base = t - rk * inner;
       double s = 0.0;
-      for (int64_t c = 0; c < Rk; ++c) s += G[rk * Rk + c] * in[base + c * inner];
+      for (int c = 0; c < Rk; ++c) s += G[rk * Rk + c] * in[base + c * inner];
       o[t] = s;
     }
     __syncthreads();
@@ -598,6 +636,30 @@ tsk_status fit_plan(const TensorView& T, const int64_t* R, FitScratch& fs, Ws& w
   return TSK_OK;
 }
 
+tsk_status fit_presort(const TensorView& T, FitScratch& fs, hipStream_t st) {
+  if (!fs.by_last || fs.sorted) return TSK_OK;
+  // the entries grouped by their last index, stably (input order within a run)
+  ProfScope prof("fit_sort", st);
+  const int64_t n = T.nnz;
+  const unsigned grid = unsigned(std::min<int64_t>(ceil_div(n, kT), 8192));
+  size_t bytes = fs.sort_bytes;
+  if (T.dtype == TSK_F64) {
+    hipLaunchKernelGGL(k_last_keys<double>, dim3(grid), dim3(kT), 0, st, T.idx[0], T.idx[1],
+                       T.idx[2], static_cast<const double*>(T.values), n, fs.keys_in,
+                       static_cast<Ent<double>*>(fs.ents_in));
+    TSK_LAUNCHED();
+    TSK_TRY(sort_entries<double>(fs.sort_tmp, bytes, fs, size_t(n), st));
+  } else {
+    hipLaunchKernelGGL(k_last_keys<float>, dim3(grid), dim3(kT), 0, st, T.idx[0], T.idx[1],
+                       T.idx[2], static_cast<const float*>(T.values), n, fs.keys_in,
+                       static_cast<Ent<float>*>(fs.ents_in));
+    TSK_LAUNCHED();
+    TSK_TRY(sort_entries<float>(fs.sort_tmp, bytes, fs, size_t(n), st));
+  }
+  fs.sorted = true;
+  return TSK_OK;
+}
+
 tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
                    const double* const* factors, bool with_norm, FitScratch& fs, double* res,
                    Ws& ws, hipStream_t st) {
@@ -621,32 +683,13 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
     goff += R[k] * R[k];
     rmax_g = std::max<int64_t>(rmax_g, R[k]);
   }
+  const int gl = goff <= kGramLds ? int(goff) : 0;  // Grams staged in LDS
   if (rmax_g > 64)
     for (int k = 0; k < T.order; ++k)
       TSK_TRY(gemm_tn(TSK_PREC_F64, R[k], R[k], T.dims[k], factors[k], R[k], R[k], nullptr, 0,
                       factors[k], R[k], gp[k], R[k], ws, st));
   if (ws.measuring()) return TSK_OK;
-  if (fs.by_last && !fs.sorted) {
-    // the entries grouped by their last index, stably (input order within a run)
-    ProfScope prof("fit_sort", st);
-    const int64_t n = T.nnz;
-    const unsigned grid = unsigned(std::min<int64_t>(ceil_div(n, kT), 8192));
-    size_t bytes = fs.sort_bytes;
-    if (T.dtype == TSK_F64) {
-      hipLaunchKernelGGL(k_last_keys<double>, dim3(grid), dim3(kT), 0, st, T.idx[0], T.idx[1],
-                         T.idx[2], static_cast<const double*>(T.values), n, fs.keys_in,
-                         static_cast<Ent<double>*>(fs.ents_in));
-      TSK_LAUNCHED();
-      TSK_TRY(sort_entries<double>(fs.sort_tmp, bytes, fs, size_t(n), st));
-    } else {
-      hipLaunchKernelGGL(k_last_keys<float>, dim3(grid), dim3(kT), 0, st, T.idx[0], T.idx[1],
-                         T.idx[2], static_cast<const float*>(T.values), n, fs.keys_in,
-                         static_cast<Ent<float>*>(fs.ents_in));
-      TSK_LAUNCHED();
-      TSK_TRY(sort_entries<float>(fs.sort_tmp, bytes, fs, size_t(n), st));
-    }
-    fs.sorted = true;
-  }
+  if (fs.by_last && !fs.sorted) TSK_TRY(fit_presort(T, fs, st));
   ProfScope prof("fit", st);
   if (rmax_g <= 64)  // the factor Grams of every mode in one launch
     TSK_TRY(gram_batch_f64(T.order, R, T.dims, factors, gp, st));
@@ -669,9 +712,9 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
                                     fs.partial_norm, fs.partial_inner, st));
     // with_norm is implied: the fused kernel sums T^2 as well
     if (csize <= 4096) {
-      hipLaunchKernelGGL(k_finish_model, dim3(1), dim3(kT), size_t(2 * csize) * 8, st, a, core,
-                         csize, fs.grams, fs.partial_norm, fs.nblocks, fs.partial_inner,
-                         fs.nblocks, fs.partial_direct, 1, fs.nT2, res);
+      hipLaunchKernelGGL(k_finish_model, dim3(1), dim3(kT), size_t(2 * csize + gl) * 8, st, a,
+                         core, csize, fs.grams, gl, fs.partial_norm, fs.nblocks,
+                         fs.partial_inner, fs.nblocks, fs.partial_direct, 1, fs.nT2, res);
       TSK_LAUNCHED();
       return TSK_OK;
     }
@@ -691,15 +734,15 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
   for (int k = 0; k < T.order; ++k) rmax = std::max<int64_t>(rmax, R[k]);
   if (fs.by_last) {
     const int64_t s3 = T.dims[2];
-    hipLaunchKernelGGL(k_core_last<16>, dim3(unsigned(ceil_div(s3 * 256, kT))), dim3(kT), 0, st,
+    hipLaunchKernelGGL(k_core_last<16>, dim3(unsigned(ceil_div(s3, kCoreK))), dim3(256), 0, st,
                        core, factors[2], s3, fs.W);
     TSK_LAUNCHED();
     if (T.dtype == TSK_F64)
-      hipLaunchKernelGGL((k_inner3s<16, double>), dim3(fs.nblocks), dim3(kT), 0, st, fs.keys,
+      hipLaunchKernelGGL(k_inner3s<double>, dim3(fs.nblocks), dim3(kT), 0, st, fs.keys,
                          static_cast<const Ent<double>*>(fs.ents), factors[0], factors[1], fs.W,
                          T.nnz, per, fs.partial_inner);
     else
-      hipLaunchKernelGGL((k_inner3s<16, float>), dim3(fs.nblocks), dim3(kT), 0, st, fs.keys,
+      hipLaunchKernelGGL(k_inner3s<float>, dim3(fs.nblocks), dim3(kT), 0, st, fs.keys,
                          static_cast<const Ent<float>*>(fs.ents), factors[0], factors[1], fs.W,
                          T.nnz, per, fs.partial_inner);
   } else if (T.order == 3 && rmax <= 32) {
@@ -734,9 +777,9 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
   }
   TSK_LAUNCHED();
   if (csize <= 4096) {  // model norm in LDS inside the final reduction
-    hipLaunchKernelGGL(k_finish_model, dim3(1), dim3(kT), size_t(2 * csize) * 8, st, a, core,
-                       csize, fs.grams, with_norm ? fs.partial_norm : nullptr, fs.nblocks,
-                       fs.partial_inner, fs.nblocks, fs.partial_direct,
+    hipLaunchKernelGGL(k_finish_model, dim3(1), dim3(kT), size_t(2 * csize + gl) * 8, st, a,
+                       core, csize, fs.grams, gl, with_norm ? fs.partial_norm : nullptr,
+                       fs.nblocks, fs.partial_inner, fs.nblocks, fs.partial_direct,
                        T.layout == TSK_DENSE ? 1 : 0, fs.nT2, res);
     TSK_LAUNCHED();
     return TSK_OK;

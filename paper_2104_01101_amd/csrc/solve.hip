@@ -80,27 +80,6 @@ tsk_status rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t 
 //   W = Q (D A)                     = Q U S with the signs of A
 namespace {
 
-// A second stream of the current device, created once (default priority,
-// non-blocking), for the blocked Gram inverse, which runs beside the products
-// with Y: it needs only G, and its steps leave most of the chip idle.  Work
-// put on it is joined back into the caller's stream before the solve returns.
-constexpr int kMaxSideDevices = 64;
-hipStream_t g_side[kMaxSideDevices];
-std::mutex g_side_mu;
-
-tsk_status side_stream(hipStream_t* out) {
-  int dev = 0;
-  TSK_HIP(hipGetDevice(&dev));
-  if (dev < 0 || dev >= kMaxSideDevices) {
-    *out = nullptr;
-    return TSK_OK;
-  }
-  std::lock_guard<std::mutex> lock(g_side_mu);
-  if (!g_side[dev]) TSK_HIP(hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking));
-  *out = g_side[dev];
-  return TSK_OK;
-}
-
 // The same solve with the products ordered for the cost of Sec. 6.1, O(m s k)
 // in Y instead of O(m s r): Z^T Y (r x s) is never formed.
 //   G = Z^T Z;  Y Omega (m x k);  C0 = Z^T (Y Omega)
@@ -136,31 +115,18 @@ tsk_status rsvd_solve_yside(const void* Z, const void* Y, int64_t m, int64_t r, 
   const bool gj = spd_inverse_fits(r);
   double* Bi = gj ? G : ws.take<double>(size_t(r) * r);
   const bool run = !ws.measuring();
-  // the blocked inverse of G goes to the side stream as soon as G is formed
-  // and the main stream waits for it before C^T = C0^T B
+  // the blocked inverse of G goes to a side stream as soon as G is formed;
+  // the caller's stream waits for it before C^T = C0^T B
+  SideJob inv(st);
   hipStream_t side = nullptr;
-  struct Events {
-    hipEvent_t g = nullptr, b = nullptr;
-    ~Events() {
-      if (g) (void)hipEventDestroy(g);
-      if (b) (void)hipEventDestroy(b);
-    }
-  } ev;
-  if (run && !gj && !ws.serial) {
-    TSK_TRY(side_stream(&side));
-    if (side) {
-      TSK_HIP(hipEventCreateWithFlags(&ev.g, hipEventDisableTiming));
-      TSK_HIP(hipEventCreateWithFlags(&ev.b, hipEventDisableTiming));
-    }
-  }
+  if (run && !gj && !ws.serial) TSK_TRY(side_stream(&side));
   {
     ProfScope prof(run ? "gram" : "", st);
     TSK_TRY(gemm_tn(prec, r, r, m, Z, r, r, nullptr, 0, Z, r, G, r, ws, st));
     if (side) {
-      TSK_HIP(hipEventRecord(ev.g, st));
-      TSK_HIP(hipStreamWaitEvent(side, ev.g, 0));
+      TSK_TRY(inv.fork(side));
       TSK_TRY(spd_inverse_blocked(G, r, r, Bi, r, info, ws, side));
-      TSK_HIP(hipEventRecord(ev.b, side));
+      TSK_TRY(inv.done());
     }
     if (run && !f64) TSK_TRY(convert_from_f64(Om, s, k, Om_e, kp, prec, st));
     TSK_TRY(gemm_nn(prec, m, k, s, Y, s, Om_e, f64 ? k : kp, YO, k, ws, st));
@@ -172,7 +138,7 @@ tsk_status rsvd_solve_yside(const void* Z, const void* Y, int64_t m, int64_t r, 
     if (gj) {
       if (run) TSK_TRY(spd_inverse(G, r, r, info, st));
     } else if (side) {
-      TSK_HIP(hipStreamWaitEvent(st, ev.b, 0));
+      TSK_TRY(inv.join());
     } else {
       TSK_TRY(spd_inverse_blocked(G, r, r, Bi, r, info, ws, st));
     }
@@ -196,7 +162,22 @@ tsk_status rsvd_solve_yside(const void* Z, const void* Y, int64_t m, int64_t r, 
   return TSK_OK;
 }
 
+constexpr int kMaxSideDevices = 64;
+hipStream_t g_side[kMaxSideDevices];
+std::mutex g_side_mu;
+
 }  // namespace
+
+tsk_status side_stream(hipStream_t* out) {
+  int dev = 0;
+  TSK_HIP(hipGetDevice(&dev));
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxSideDevices) return TSK_OK;
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  if (!g_side[dev]) TSK_HIP(hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking));
+  *out = g_side[dev];
+  return TSK_OK;
+}
 
 // The Y-side order pays when Z^T Y (2 m s r flops) costs well over the two
 // products with Y (4 m s k) and the one-workgroup fused chain does not apply.
