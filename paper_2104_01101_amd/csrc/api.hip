@@ -200,7 +200,7 @@ tsk_status rrf_finish(const TensorView& T, int n, int64_t R, uint64_t seed, RrfB
     TSK_TRY(scale_columns_inv_sqrt(A, s, R, b.lam, st, info));
   }
   TSK_TRY(cholqr(A, s, R, info, ws, st));
-  if (run) TSK_TRY(sign_fix_columns(A, s, R, st));
+  TSK_TRY(sign_fix_columns(A, s, R, ws, st));
   return TSK_OK;
 }
 
@@ -453,7 +453,7 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
         TSK_TRY(launch_gauss(stream_key(o.seed, kInit, n), T.dims[n] * a.R[n], 1.0,
                              a.factors[n], st));
       TSK_TRY(cholqr(a.factors[n], T.dims[n], a.R[n], a.info_dev + 2, ws, st));
-      if (run) TSK_TRY(sign_fix_columns(a.factors[n], T.dims[n], a.R[n], st));
+      TSK_TRY(sign_fix_columns(a.factors[n], T.dims[n], a.R[n], ws, st));
       release();
     }
   }

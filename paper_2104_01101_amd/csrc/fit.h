@@ -8,6 +8,7 @@ constexpr int kDenseFitMaxR = 64;
 struct FitScratch {
   int nblocks;
   double *partial_norm, *partial_inner, *partial_direct, *grams, *buf0, *buf1, *model2, *nT2;
+  double* gram_part;  // partial factor Grams over ranges of rows (R_k <= 64)
   double* ttm[2];  // dense tensors: mode products of the core (R_1 x s_2 x ... x s_N)
   // order-3 COO tensors of rank 16: the entries sorted by their last index
   // (once per plan), W = C x_3 A^(3) (s_3 x R x R), <T, T~> at R^2 per entry

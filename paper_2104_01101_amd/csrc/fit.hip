@@ -396,7 +396,15 @@ __device__ double block_sum_of(const double* p, int n, double* red) {
   const int per = (n + kT - 1) / kT;
   const int b0 = threadIdx.x * per, b1 = b0 + per < n ? b0 + per : n;
   double s = 0.0;
-  for (int b = b0; b < b1; ++b) s += p[b];
+  int b = b0;
+  for (; b + 8 <= b1; b += 8) {  // eight loads in flight, summed in index order
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = p[b + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += t[u];
+  }
+  for (; b < b1; ++b) s += p[b];
   s = block_reduce(s, red);
   __syncthreads();
   return s;
@@ -461,24 +469,38 @@ __global__ __launch_bounds__(kT) void k_fit_dense(const V* __restrict__ X, const
 }
 
 // k_model_norm2 and k_finish in one workgroup, the mode products of the
-// model norm ping-ponging between two LDS buffers of csize doubles (the core
-// is staged in the second first); the factor Grams are staged in LDS too when
-// they take at most kGramLds doubles (gl = their total, else 0).
+// model norm ping-ponging between two LDS buffers of csize doubles, read from
+// a third holding the core; the factor Grams are staged in LDS too when they
+// take at most kGramLds doubles (gl = their total, else 0).  The staging
+// keeps eight loads in flight per thread.
 constexpr int kGramLds = 2048;
+
+// dst[t] = src[t], t < n, by the workgroup with eight loads in flight per thread
+__device__ inline void stage8(const double* __restrict__ src, double* dst, int n) {
+  for (int t0 = threadIdx.x; t0 < n; t0 += 8 * kT) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = t0 + u * kT < n ? src[t0 + u * kT] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (t0 + u * kT < n) dst[t0 + u * kT] = v[u];
+  }
+}
 
 __global__ __launch_bounds__(kT) void k_finish_model(FitArgs a, const double* core, int64_t csize,
                                                      const double* grams, int gl,
                                                      const double* pn, int nbn, const double* pi,
                                                      int nbi, const double* pd, int dense,
                                                      double* nT2_out, double* res_out) {
-  extern __shared__ double lbuf[];  // 2 csize + gl
+  extern __shared__ double lbuf[];  // 3 csize + gl
   __shared__ double red[kT / 64];
   const int cs = int(csize);
-  double* gl_s = lbuf + 2 * cs;
-  for (int t = threadIdx.x; t < cs; t += kT) lbuf[cs + t] = core[t];
-  for (int t = threadIdx.x; t < gl; t += kT) gl_s[t] = grams[t];
+  double* core_s = lbuf + 2 * cs;
+  double* gl_s = lbuf + 3 * cs;
+  stage8(core, core_s, cs);
+  stage8(grams, gl_s, gl);
   __syncthreads();
-  const double* in = lbuf + cs;
+  const double* in = core_s;
   int goff = 0;
   for (int k = 0; k < a.N; ++k) {
     const int Rk = int(a.R[k]);
@@ -497,7 +519,7 @@ __global__ __launch_bounds__(kT) void k_finish_model(FitArgs a, const double* co
     goff += Rk * Rk;
   }
   double m2 = 0.0;
-  for (int64_t t = threadIdx.x; t < csize; t += kT) m2 += in[t] * core[t];
+  for (int t = threadIdx.x; t < cs; t += kT) m2 += in[t] * core_s[t];
   m2 = block_reduce(m2, red);
   __syncthreads();
   double nT2 = 0.0;
@@ -595,6 +617,7 @@ tsk_status fit_plan(const TensorView& T, const int64_t* R, FitScratch& fs, Ws& w
   fs.partial_inner = ws.take<double>(fs.nblocks);
   fs.partial_direct = ws.take<double>(fs.nblocks);
   fs.grams = ws.take<double>(gsz);
+  fs.gram_part = ws.take<double>(size_t(gram_batch_splits(T.order, T.dims)) * gsz);
   fs.buf0 = ws.take<double>(csize);
   fs.buf1 = ws.take<double>(csize);
   fs.model2 = ws.take<double>(1);
@@ -692,7 +715,7 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
   if (fs.by_last && !fs.sorted) TSK_TRY(fit_presort(T, fs, st));
   ProfScope prof("fit", st);
   if (rmax_g <= 64)  // the factor Grams of every mode in one launch
-    TSK_TRY(gram_batch_f64(T.order, R, T.dims, factors, gp, st));
+    TSK_TRY(gram_batch_f64(T.order, R, T.dims, factors, gp, fs.gram_part, st));
   if (T.layout == TSK_DENSE && fs.ttm[0]) {
     // M = C x_2 A^(2) ... x_N A^(N), then the fused residual over the entries
     const int N = T.order;
@@ -712,7 +735,7 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
                                     fs.partial_norm, fs.partial_inner, st));
     // with_norm is implied: the fused kernel sums T^2 as well
     if (csize <= 4096) {
-      hipLaunchKernelGGL(k_finish_model, dim3(1), dim3(kT), size_t(2 * csize + gl) * 8, st, a,
+      hipLaunchKernelGGL(k_finish_model, dim3(1), dim3(kT), size_t(3 * csize + gl) * 8, st, a,
                          core, csize, fs.grams, gl, fs.partial_norm, fs.nblocks,
                          fs.partial_inner, fs.nblocks, fs.partial_direct, 1, fs.nT2, res);
       TSK_LAUNCHED();
@@ -777,7 +800,7 @@ tsk_status fit_run(const TensorView& T, const int64_t* R, const double* core,
   }
   TSK_LAUNCHED();
   if (csize <= 4096) {  // model norm in LDS inside the final reduction
-    hipLaunchKernelGGL(k_finish_model, dim3(1), dim3(kT), size_t(2 * csize + gl) * 8, st, a,
+    hipLaunchKernelGGL(k_finish_model, dim3(1), dim3(kT), size_t(3 * csize + gl) * 8, st, a,
                        core, csize, fs.grams, gl, with_norm ? fs.partial_norm : nullptr,
                        fs.nblocks, fs.partial_inner, fs.nblocks, fs.partial_direct,
                        T.layout == TSK_DENSE ? 1 : 0, fs.nT2, res);

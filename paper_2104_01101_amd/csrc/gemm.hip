@@ -208,21 +208,40 @@ __global__ __launch_bounds__(kSkT) void k_gemm_skinny_split(int64_t M, int64_t N
 }
 
 // Grams A^T A of several row-major K x R matrices in one launch: blockIdx.z
-// picks the matrix, workgroups beyond its tiles leave at once.
+// picks the matrix and a range of K (splits ranges of kc rows), workgroups
+// beyond the matrix's tiles leave at once.  With one range the tile goes to
+// C; with more, each range's partial tile goes to part (matrix p, range q at
+// part[p] + q R^2) and k_gram_sum adds them in range order (deterministic).
 struct GramBatch {
-  int n;
+  int n, splits;
   int64_t R[TSK_MAX_ORDER];
   int64_t K[TSK_MAX_ORDER];
+  int64_t kc[TSK_MAX_ORDER];
   const double* A[TSK_MAX_ORDER];
   double* C[TSK_MAX_ORDER];
+  double* part[TSK_MAX_ORDER];
 };
 __global__ __launch_bounds__(kSkT) void k_gram_batch(GramBatch gb) {
   __shared__ double red[kSkW][16][17];
-  const int p = blockIdx.z;
+  const int p = blockIdx.z / gb.splits, q = blockIdx.z - p * gb.splits;
   const int64_t R = gb.R[p];
   if (int64_t(blockIdx.x) * 16 >= R || int64_t(blockIdx.y) * 16 >= R) return;  // uniform
-  skinny_tile<kSkW, false>(R, R, gb.K[p], gb.A[p], R, R, nullptr, 0, gb.A[p], R, gb.C[p], R,
-                           blockIdx.x, blockIdx.y, red);
+  const int64_t k0 = q * gb.kc[p];
+  const int64_t kn = k0 >= gb.K[p] ? 0 : (k0 + gb.kc[p] < gb.K[p] ? gb.kc[p] : gb.K[p] - k0);
+  const double* A = gb.A[p] + (kn > 0 ? k0 * R : 0);
+  double* out = gb.splits == 1 ? gb.C[p] : gb.part[p] + q * R * R;
+  skinny_tile<kSkW, false>(R, R, kn, A, R, R, nullptr, 0, A, R, out, R, blockIdx.x, blockIdx.y,
+                           red);
+}
+
+__global__ __launch_bounds__(256) void k_gram_sum(GramBatch gb) {
+  const int p = blockIdx.x;
+  const int64_t rr = gb.R[p] * gb.R[p];
+  for (int64_t t = threadIdx.x; t < rr; t += 256) {
+    double s = 0.0;
+    for (int q = 0; q < gb.splits; ++q) s += gb.part[p][q * rr + t];
+    gb.C[p][t] = s;
+  }
 }
 
 // FP32 operands, both K-major (A = [A1 | A2] as K x M, B as K x N), 64 x 64
@@ -499,6 +518,120 @@ __global__ void k_reduce_splits(const double* part, int64_t M, int64_t N, int sp
   C[i * ldc + j] = s;
 }
 
+// Skinny products with FP32 operands and at most 32 output columns, the
+// products with Y of the randomized solve: C (M x N, FP64) = A B with A given
+// as M x K (A_MK: rows along the contraction, Y Omega) or K x M (Y^T (Z P)),
+// and B given transposed (Bt: N x K, rows zero beyond K up to ldbt).  One
+// workgroup per 64 rows of C and range of 4 kcw contraction indices, one wave
+// per kcw of them, on v_mfma_f32_16x16x4 (lane l = li + 16 g feeds A(li, g),
+// B(g, li) and holds D(4 g + v, li)): for four contraction steps t the lane's
+// k is k0 + 4 g + t, so that the B values (and A's when A_MK) of one lane are
+// four consecutive floats, one vector load.  FP32 accumulation within a wave;
+// the four waves' tiles summed in FP64 in wave order through LDS; the ranges'
+// tiles summed in range order by k_reduce_splits.  No operands are staged:
+// A is streamed once from HBM, Bt (small) comes from L2.
+constexpr int kYsT = 256;
+
+template <bool A_MK>
+__global__ __launch_bounds__(kYsT) void k_gemm_yskinny(int64_t M, int N, int64_t K,
+                                                       const float* __restrict__ A, int64_t lda,
+                                                       const float* __restrict__ Bt,
+                                                       int64_t ldbt, int64_t kcw, double* out,
+                                                       int64_t ldo, int64_t split_stride) {
+  __shared__ float red[3][64][33];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t i0 = int64_t(blockIdx.x) * 64;
+  const int64_t kb = (int64_t(blockIdx.y) * 4 + wave) * kcw;
+  const int64_t ke = kb + kcw < K ? kb + kcw : K;
+  floatx4 acc[4][2];
+#pragma unroll
+  for (int sm = 0; sm < 4; ++sm)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) acc[sm][nt] = floatx4{0, 0, 0, 0};
+  // rows of A (A_MK) or columns (K x M) this lane reads, clamped into range
+  int64_t ia[4];
+  bool iv[4];
+#pragma unroll
+  for (int sm = 0; sm < 4; ++sm) {
+    const int64_t i = i0 + 16 * sm + li;
+    iv[sm] = i < M;
+    ia[sm] = iv[sm] ? i : M - 1;
+  }
+  const float* brow[2];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    const int n = 16 * nt + li;
+    brow[nt] = Bt + int64_t(n < N ? n : N - 1) * ldbt;
+  }
+  const bool bv0 = li < N, bv1 = 16 + li < N;
+  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+    const int64_t k = k0 + 4 * g;
+    float a[4][4], b[2][4];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const float4 v = *reinterpret_cast<const float4*>(brow[nt] + k);  // k < ceil16(K) <= ldbt
+      b[nt][0] = v.x, b[nt][1] = v.y, b[nt][2] = v.z, b[nt][3] = v.w;
+    }
+    if (!bv0)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) b[0][t] = 0.f;
+    if (!bv1)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) b[1][t] = 0.f;
+#pragma unroll
+    for (int sm = 0; sm < 4; ++sm) {
+      if (A_MK) {  // K % 4 == 0 and ranges of multiples of 16: all four in or out
+        float4 v = float4{0.f, 0.f, 0.f, 0.f};
+        if (k < ke) v = *reinterpret_cast<const float4*>(A + ia[sm] * lda + k);
+        a[sm][0] = v.x, a[sm][1] = v.y, a[sm][2] = v.z, a[sm][3] = v.w;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int64_t kt = k + t < ke ? k + t : ke - 1;
+          const float x = A[kt * lda + ia[sm]];
+          a[sm][t] = k + t < ke ? x : 0.f;
+        }
+      }
+      if (!iv[sm])
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[sm][t] = 0.f;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int sm = 0; sm < 4; ++sm)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+          acc[sm][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[sm][t], b[nt][t], acc[sm][nt], 0,
+                                                              0, 0);
+  }
+  if (wave > 0)
+#pragma unroll
+    for (int sm = 0; sm < 4; ++sm)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[wave - 1][16 * sm + 4 * g + v][16 * nt + li] = acc[sm][nt][v];
+  __syncthreads();
+  if (wave > 0) return;
+  double* o = out + int64_t(blockIdx.y) * split_stride;
+#pragma unroll
+  for (int sm = 0; sm < 4; ++sm)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * sm + 4 * g + v, c = 16 * nt + li;
+        const int64_t i = i0 + r;
+        if (i >= M || c >= N) continue;
+        double x = double(acc[sm][nt][v]);
+#pragma unroll
+        for (int w = 0; w < 3; ++w) x += double(red[w][r][c]);
+        o[i * ldo + c] = x;
+      }
+}
+
 __global__ void k_gemm_small(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                              int64_t sai, int64_t sak, const double* B, int64_t sbk, int64_t sbj,
                              double beta, double* C, int64_t ldc) {
@@ -648,23 +781,76 @@ tsk_status gemm_tn_t(int64_t M, int64_t N, int64_t K, const void* A1, int64_t ld
 
 }  // namespace
 
+int gram_batch_splits(int n, const int64_t* K) {
+  int64_t kmax = 0;
+  for (int p = 0; p < n; ++p) kmax = K[p] > kmax ? K[p] : kmax;
+  const int64_t s = kmax / 1024;  // at least 1024 rows per range
+  return int(s < 1 ? 1 : s > kGramSplitsMax ? kGramSplitsMax : s);
+}
+
 tsk_status gram_batch_f64(int n, const int64_t* R, const int64_t* K, const double* const* A,
-                          double* const* C, hipStream_t st) {
+                          double* const* C, double* part, hipStream_t st) {
   TSK_REQUIRE(n >= 1 && n <= TSK_MAX_ORDER, "gram batch of %d matrices", n);
   GramBatch gb{};
   gb.n = n;
-  int64_t rmax = 0;
+  gb.splits = part ? gram_batch_splits(n, K) : 1;
+  int64_t rmax = 0, off = 0;
   for (int p = 0; p < n; ++p) {
     TSK_REQUIRE(R[p] >= 1 && R[p] <= 64 && K[p] >= 1, "gram batch shapes");
     gb.R[p] = R[p];
     gb.K[p] = K[p];
+    gb.kc[p] = ceil_div(ceil_div(K[p], gb.splits), 4) * 4;
     gb.A[p] = A[p];
     gb.C[p] = C[p];
+    gb.part[p] = part ? part + off : nullptr;
+    off += int64_t(gb.splits) * R[p] * R[p];
     rmax = R[p] > rmax ? R[p] : rmax;
   }
   const unsigned t = unsigned(ceil_div(rmax, 16));
-  hipLaunchKernelGGL(k_gram_batch, dim3(t, t, unsigned(n)), dim3(kSkT), 0, st, gb);
+  hipLaunchKernelGGL(k_gram_batch, dim3(t, t, unsigned(n * gb.splits)), dim3(kSkT), 0, st, gb);
   TSK_LAUNCHED();
+  if (gb.splits > 1) {
+    hipLaunchKernelGGL(k_gram_sum, dim3(unsigned(n)), dim3(256), 0, st, gb);
+    TSK_LAUNCHED();
+  }
+  return TSK_OK;
+}
+
+bool yskinny_fits(bool a_mk, int64_t N, int64_t K, const void* A, int64_t lda, const void* Bt,
+                  int64_t ldbt) {
+  const bool vec_b = ldbt % 4 == 0 && ldbt >= ceil_div(K, 16) * 16 &&
+                     reinterpret_cast<uintptr_t>(Bt) % 16 == 0;
+  const bool vec_a = !a_mk || (K % 4 == 0 && lda % 4 == 0 &&
+                               reinterpret_cast<uintptr_t>(A) % 16 == 0);
+  return N >= 1 && N <= 32 && K >= 1 && vec_b && vec_a;
+}
+
+tsk_status gemm_yskinny_f32(bool a_mk, int64_t M, int64_t N, int64_t K, const float* A,
+                            int64_t lda, const float* Bt, int64_t ldbt, double* C, int64_t ldc,
+                            Ws& ws, hipStream_t st) {
+  // ranges of 4 kcw indices (kcw a multiple of 16) so that there are about 512
+  // workgroups
+  const int64_t tm = ceil_div(M, 64);
+  int64_t nr = std::max<int64_t>(1, std::min<int64_t>(ceil_div(512, tm), ceil_div(K, 64)));
+  const int64_t kcw = ceil_div(ceil_div(K, 4 * nr), 16) * 16;
+  nr = ceil_div(K, 4 * kcw);
+  double* part = nr > 1 ? ws.take<double>(size_t(nr) * M * N) : nullptr;
+  if (ws.measuring() || M == 0) return TSK_OK;
+  TSK_REQUIRE(yskinny_fits(a_mk, N, K, A, lda, Bt, ldbt), "skinny FP32 product: shapes");
+  double* dst = nr > 1 ? part : C;
+  const dim3 grid{unsigned(tm), unsigned(nr)};
+  if (a_mk)
+    hipLaunchKernelGGL(k_gemm_yskinny<true>, grid, dim3(kYsT), 0, st, M, int(N), K, A, lda, Bt,
+                       ldbt, kcw, dst, nr > 1 ? N : ldc, nr > 1 ? M * N : int64_t(0));
+  else
+    hipLaunchKernelGGL(k_gemm_yskinny<false>, grid, dim3(kYsT), 0, st, M, int(N), K, A, lda, Bt,
+                       ldbt, kcw, dst, nr > 1 ? N : ldc, nr > 1 ? M * N : int64_t(0));
+  TSK_LAUNCHED();
+  if (nr > 1) {
+    hipLaunchKernelGGL(k_reduce_splits, dim3(ceil_div(M * N, 256)), dim3(256), 0, st, part, M, N,
+                       int(nr), C, ldc);
+    TSK_LAUNCHED();
+  }
   return TSK_OK;
 }
 
@@ -727,6 +913,25 @@ tsk_status convert_from_f64(const double* src, int64_t rows, int64_t cols, void*
   if (rows * ldd <= 0) return TSK_OK;
   hipLaunchKernelGGL(k_from_f64, dim3(ceil_div(rows * ldd, 256)), dim3(256), 0, st, src, rows,
                      cols, dst, ldd, prec);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+// dst (cols x ldd, FP32) = src^T for src rows x cols (FP64, row-major); the
+// columns rows .. ldd - 1 of dst are zeroed
+__global__ void k_from_f64_t(const double* src, int64_t rows, int64_t cols, float* dst,
+                             int64_t ldd) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= cols * ldd) return;
+  const int64_t c = t / ldd, r = t % ldd;
+  dst[t] = r < rows ? float(src[r * cols + c]) : 0.f;
+}
+
+tsk_status convert_from_f64_t(const double* src, int64_t rows, int64_t cols, float* dst,
+                              int64_t ldd, hipStream_t st) {
+  if (cols * ldd <= 0) return TSK_OK;
+  hipLaunchKernelGGL(k_from_f64_t, dim3(ceil_div(cols * ldd, 256)), dim3(256), 0, st, src, rows,
+                     cols, dst, ldd);
   TSK_LAUNCHED();
   return TSK_OK;
 }

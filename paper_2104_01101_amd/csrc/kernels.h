@@ -103,9 +103,29 @@ tsk_status ts_conv_adjoint(const LhsMode* modes, int nmodes, int64_t m, const do
 // leading dims lda1/lda2) and B (K x N, ldb), all of element type `prec`.
 // `ldc` leading dimension of C.  Deterministic split-K.
 // Grams C[p] = A[p]^T A[p] (A[p] row-major K[p] x R[p], R[p] <= 64, FP64) of up to
-// TSK_MAX_ORDER matrices in one launch (skinny tiles).
+// TSK_MAX_ORDER matrices in one launch (skinny tiles).  With `part` (room for
+// gram_batch_splits(n, K) * sum_p R[p]^2 doubles) the rows are split into
+// ranges whose partial Grams are summed in range order by a second launch;
+// with part = NULL one workgroup per tile covers all rows.
+constexpr int kGramSplitsMax = 32;
+int gram_batch_splits(int n, const int64_t* K);
 tsk_status gram_batch_f64(int n, const int64_t* R, const int64_t* K, const double* const* A,
-                          double* const* C, hipStream_t st);
+                          double* const* C, double* part, hipStream_t st);
+// C (M x N, FP64) = A B for FP32 A (M x K row-major when a_mk, else K x M)
+// and B given transposed (Bt: N x K, row stride ldbt, zero from K up to
+// ldbt), N <= 32: the products with Y in the randomized solve, streaming A
+// once (matrix cores, deterministic range split).  yskinny_fits tells whether
+// the shapes and alignments allow it (ldbt a multiple of 4 and at least K
+// rounded up to a multiple of 16, 16-byte aligned Bt; for a_mk also K and lda
+// multiples of 4 and a 16-byte aligned A).
+bool yskinny_fits(bool a_mk, int64_t N, int64_t K, const void* A, int64_t lda, const void* Bt,
+                  int64_t ldbt);
+tsk_status gemm_yskinny_f32(bool a_mk, int64_t M, int64_t N, int64_t K, const float* A,
+                            int64_t lda, const float* Bt, int64_t ldbt, double* C, int64_t ldc,
+                            Ws& ws, hipStream_t st);
+// dst (cols x ldd, FP32) = src^T (src rows x cols, FP64), zero beyond rows
+tsk_status convert_from_f64_t(const double* src, int64_t rows, int64_t cols, float* dst,
+                              int64_t ldd, hipStream_t st);
 tsk_status gemm_tn(int prec, int64_t M, int64_t N, int64_t K, const void* A1, int64_t lda1,
                    int64_t M1, const void* A2, int64_t lda2, const void* B, int64_t ldb,
                    double* C, int64_t ldc, Ws& ws, hipStream_t st);
@@ -154,6 +174,10 @@ tsk_status spd_inverse_blocked(const double* G, int64_t n, int64_t ldg, double* 
 // Make the entry of largest magnitude of every column of A (rows x R) positive.
 // sgn (optional, R entries) receives the sign applied to each column
 tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, hipStream_t st,
+                            double* sgn = nullptr);
+// The same, for tall A in two launches over ranges of rows (partial results in
+// ws; call in the measuring pass too)
+tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, Ws& ws, hipStream_t st,
                             double* sgn = nullptr);
 // C = A^T B (A: K x M, B: K x N, row-major FP64) beside the in-place SPD
 // inverse of G (n x n, n <= 128) in one launch (c0_inverse_fits)

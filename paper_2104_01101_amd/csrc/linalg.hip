@@ -1600,6 +1600,84 @@ __global__ void k_sign_fix(double* A, int64_t rows, int64_t R, double* sgn) {
     for (int64_t i = threadIdx.x; i < rows; i += 256) A[i * R + c] = -A[i * R + c];
 }
 
+// The same rule for tall A (rows >= kSfSplitRows, R <= 256) in two launches
+// over ranges of rpb rows, reading A row-major in order: per range and
+// column the first largest magnitude (its index and signed value), then
+// every range combines the ranges' results in range order (largest, lowest
+// index on ties: the entry k_sign_fix picks) and flips its own rows.  Where
+// no entry compares (all NaN) the sign of row 0 decides, as in k_sign_fix.
+constexpr int64_t kSfSplitRows = 2048;
+constexpr int kSfMaxRanges = 64;
+
+__global__ __launch_bounds__(256) void k_sign_ranges(const double* A, int64_t rows, int R,
+                                                     int64_t rpb, double* pv, double* ps,
+                                                     int64_t* pix, double* row0) {
+  __shared__ double bv[256], bs[256];
+  __shared__ int64_t bi[256];
+  const int tid = threadIdx.x, RS = 256 / R, c = tid % R, ro = tid / R;
+  const int64_t i0 = int64_t(blockIdx.x) * rpb;
+  const int64_t i1 = i0 + rpb < rows ? i0 + rpb : rows;
+  double best = -1.0, bsig = 0.0;
+  int64_t bidx = INT64_MAX;
+  if (ro < RS)
+    for (int64_t i = i0 + ro; i < i1; i += RS) {
+      const double x = A[i * R + c];
+      const double a = fabs(x);
+      if (a > best) best = a, bidx = i, bsig = x;  // first maximum of this thread's rows
+    }
+  bv[tid] = best;
+  bs[tid] = bsig;
+  bi[tid] = bidx;
+  __syncthreads();
+  if (tid >= R) return;
+  for (int o = 1; o < RS; ++o) {
+    const int u = o * R + tid;
+    if (bv[u] > best || (bv[u] == best && bi[u] < bidx)) best = bv[u], bidx = bi[u], bsig = bs[u];
+  }
+  const int64_t q = int64_t(blockIdx.x) * R + tid;
+  pv[q] = best;
+  ps[q] = bsig;
+  pix[q] = bidx;
+  if (blockIdx.x == 0) row0[tid] = A[tid];
+}
+
+__global__ __launch_bounds__(256) void k_sign_apply(double* A, int64_t rows, int R, int64_t rpb,
+                                                    int nranges, const double* pv,
+                                                    const double* ps, const int64_t* pix,
+                                                    const double* row0, double* sgn) {
+  __shared__ bool flip[256];
+  const int tid = threadIdx.x;
+  if (tid < R) {
+    double best = -1.0, bsig = 0.0;
+    int64_t bidx = INT64_MAX;
+    for (int q0 = 0; q0 < nranges; q0 += 8) {  // eight ranges' loads in flight
+      double v[8], sg[8];
+      int64_t ix[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t e = int64_t(q0 + u < nranges ? q0 + u : nranges - 1) * R + tid;
+        v[u] = pv[e];
+        sg[u] = ps[e];
+        ix[u] = pix[e];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u < nranges && (v[u] > best || (v[u] == best && ix[u] < bidx)))
+          best = v[u], bidx = ix[u], bsig = sg[u];
+    }
+    const bool f = (bidx == INT64_MAX ? row0[tid] : bsig) < 0.0;
+    flip[tid] = f;
+    if (sgn && blockIdx.x == 0) sgn[tid] = f ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  const int64_t i0 = int64_t(blockIdx.x) * rpb;
+  const int64_t i1 = i0 + rpb < rows ? i0 + rpb : rows;
+  const int64_t n = (i1 - i0) * R;
+  double* a = A + i0 * R;
+  for (int64_t e = tid; e < n; e += 256)
+    if (flip[e % R]) a[e] = -a[e];
+}
+
 // W (r x R) = Q U diag(lam * sgn) with Q given by rows of Q^T (k x r) and U
 // (k x R) already scaled by lam^{-1/2}: Q times the left singular vectors
 // times the singular values, in the column signs chosen for the right ones.
@@ -2164,6 +2242,28 @@ tsk_status range_basis(const double* C0, const double* B, int64_t r, int64_t k, 
 
 tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, hipStream_t st, double* sgn) {
   hipLaunchKernelGGL(k_sign_fix, dim3(R), dim3(256), 0, st, A, rows, R, sgn);
+  TSK_LAUNCHED();
+  return TSK_OK;
+}
+
+tsk_status sign_fix_columns(double* A, int64_t rows, int64_t R, Ws& ws, hipStream_t st,
+                            double* sgn) {
+  if (rows < kSfSplitRows || R > 256) {
+    if (ws.measuring()) return TSK_OK;
+    return sign_fix_columns(A, rows, R, st, sgn);
+  }
+  const int64_t rpb = std::max<int64_t>(256, ceil_div(rows, kSfMaxRanges));
+  const int nr = int(ceil_div(rows, rpb));
+  double* pv = ws.take<double>(size_t(nr) * R);
+  double* ps = ws.take<double>(size_t(nr) * R);
+  int64_t* pix = ws.take<int64_t>(size_t(nr) * R);
+  double* row0 = ws.take<double>(size_t(R));
+  if (ws.measuring()) return TSK_OK;
+  hipLaunchKernelGGL(k_sign_ranges, dim3(unsigned(nr)), dim3(256), 0, st, A, rows, int(R), rpb,
+                     pv, ps, pix, row0);
+  TSK_LAUNCHED();
+  hipLaunchKernelGGL(k_sign_apply, dim3(unsigned(nr)), dim3(256), 0, st, A, rows, int(R), rpb,
+                     nr, pv, ps, pix, row0, sgn);
   TSK_LAUNCHED();
   return TSK_OK;
 }

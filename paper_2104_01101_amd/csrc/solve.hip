@@ -61,7 +61,7 @@ tsk_status rc_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_t 
     TSK_TRY(sym_eig_top(Mq, s, R, lam, A, ws, st));
   }
   TSK_TRY(cholqr(A, s, R, info + 1, ws, st));
-  if (run) TSK_TRY(sign_fix_columns(A, s, R, st));
+  TSK_TRY(sign_fix_columns(A, s, R, ws, st));
   TSK_TRY(gemm_tn(TSK_PREC_F64, r, R, s, Xt, r, r, nullptr, 0, A, R, W, R, ws, st));
   return TSK_OK;
 }
@@ -95,9 +95,15 @@ tsk_status rsvd_solve_yside(const void* Z, const void* Y, int64_t m, int64_t r, 
   // the rounded copies of Omega and Z P get rows of a multiple of 4 elements
   // (vector loads in the FP32 products)
   const int64_t kp = ceil_div(k, 4) * 4;
+  // FP32 operands with aligned rows of Y: the skinny products streaming Y,
+  // with Omega and Z P transposed (rows along the contraction)
+  const int64_t lds_t = ceil_div(s, 16) * 16, ldm_t = ceil_div(m, 16) * 16;
+  const bool ysk = prec == TSK_PREC_F32 && yskinny_fits(true, k, s, Y, s, nullptr, lds_t) &&
+                   yskinny_fits(false, k, m, Y, s, nullptr, ldm_t);
   double* G = ws.take<double>(size_t(r) * r);
   void* Om_e = f64 ? static_cast<void*>(const_cast<double*>(Om))
-                   : static_cast<void*>(ws.take<char>(size_t(s) * kp * eb));
+               : ysk ? static_cast<void*>(ws.take<float>(size_t(k) * lds_t))
+                     : static_cast<void*>(ws.take<char>(size_t(s) * kp * eb));
   double* YO = ws.take<double>(size_t(m) * k);
   const double* Z64 = f64 ? static_cast<const double*>(Z) : ws.take<double>(size_t(m) * r);
   double* C0 = ws.take<double>(size_t(r) * k);
@@ -106,7 +112,9 @@ tsk_status rsvd_solve_yside(const void* Z, const void* Y, int64_t m, int64_t r, 
   double* Pt = ws.take<double>(size_t(k) * r);
   double* P = ws.take<double>(size_t(r) * k);
   double* ZP = ws.take<double>(size_t(m) * k);
-  void* ZP_e = f64 ? static_cast<void*>(ZP) : static_cast<void*>(ws.take<char>(size_t(m) * kp * eb));
+  void* ZP_e = f64   ? static_cast<void*>(ZP)
+               : ysk ? static_cast<void*>(ws.take<float>(size_t(k) * ldm_t))
+                     : static_cast<void*>(ws.take<char>(size_t(m) * kp * eb));
   double* Dt = ws.take<double>(size_t(s) * k);
   double* Mk = ws.take<double>(size_t(k) * k);
   double* lam = ws.take<double>(R);
@@ -128,8 +136,14 @@ tsk_status rsvd_solve_yside(const void* Z, const void* Y, int64_t m, int64_t r, 
       TSK_TRY(spd_inverse_blocked(G, r, r, Bi, r, info, ws, side));
       TSK_TRY(inv.done());
     }
-    if (run && !f64) TSK_TRY(convert_from_f64(Om, s, k, Om_e, kp, prec, st));
-    TSK_TRY(gemm_nn(prec, m, k, s, Y, s, Om_e, f64 ? k : kp, YO, k, ws, st));
+    if (ysk) {
+      if (run) TSK_TRY(convert_from_f64_t(Om, s, k, static_cast<float*>(Om_e), lds_t, st));
+      TSK_TRY(gemm_yskinny_f32(true, m, k, s, static_cast<const float*>(Y), s,
+                               static_cast<const float*>(Om_e), lds_t, YO, k, ws, st));
+    } else {
+      if (run && !f64) TSK_TRY(convert_from_f64(Om, s, k, Om_e, kp, prec, st));
+      TSK_TRY(gemm_nn(prec, m, k, s, Y, s, Om_e, f64 ? k : kp, YO, k, ws, st));
+    }
   }
   {
     ProfScope prof(run ? "solve_la" : "", st);
@@ -150,14 +164,20 @@ tsk_status rsvd_solve_yside(const void* Z, const void* Y, int64_t m, int64_t r, 
   }
   {
     ProfScope prof(run ? "gram" : "", st);
-    if (run && !f64) TSK_TRY(convert_from_f64(ZP, m, k, ZP_e, kp, prec, st));
-    TSK_TRY(gemm_tn(prec, s, k, m, Y, s, s, nullptr, 0, ZP_e, f64 ? k : kp, Dt, k, ws, st));
+    if (ysk) {
+      if (run) TSK_TRY(convert_from_f64_t(ZP, m, k, static_cast<float*>(ZP_e), ldm_t, st));
+      TSK_TRY(gemm_yskinny_f32(false, s, k, m, static_cast<const float*>(Y), s,
+                               static_cast<const float*>(ZP_e), ldm_t, Dt, k, ws, st));
+    } else {
+      if (run && !f64) TSK_TRY(convert_from_f64(ZP, m, k, ZP_e, kp, prec, st));
+      TSK_TRY(gemm_tn(prec, s, k, m, Y, s, s, nullptr, 0, ZP_e, f64 ? k : kp, Dt, k, ws, st));
+    }
   }
   TSK_TRY(gemm_tn(TSK_PREC_F64, k, k, s, Dt, k, k, nullptr, 0, Dt, k, Mk, k, ws, st));
   TSK_TRY(sym_eig_top(Mk, k, R, lam, U, ws, st));
   if (run) TSK_TRY(scale_columns_inv_sqrt(U, k, R, lam, st, info + 3));
   TSK_TRY(gemm_nn_f64(s, R, k, Dt, k, U, R, A, R, ws, st));
-  if (run) TSK_TRY(sign_fix_columns(A, s, R, st, sgn));
+  TSK_TRY(sign_fix_columns(A, s, R, ws, st, sgn));
   if (run) TSK_TRY(rsvd_w(Qt, false, U, lam, sgn, k, r, R, W, st));
   return TSK_OK;
 }
@@ -251,7 +271,7 @@ tsk_status rsvd_solve(const void* Z, const void* Y, int64_t m, int64_t r, int64_
   TSK_TRY(sym_eig_top(Mk, k, R, lam, U, ws, st));
   if (run) TSK_TRY(scale_columns_inv_sqrt(U, k, R, lam, st, info + 3));
   TSK_TRY(gemm_nn_f64(s, R, k, Dt, k, U, R, A, R, ws, st));
-  if (run) TSK_TRY(sign_fix_columns(A, s, R, st, sgn));
+  TSK_TRY(sign_fix_columns(A, s, R, ws, st, sgn));
   if (run) TSK_TRY(rsvd_w(Qt, false, U, lam, sgn, k, r, R, W, st));
   return TSK_OK;
 }

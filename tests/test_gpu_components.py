@@ -568,12 +568,18 @@ def test_rsvd_solve_range_basis_conditioning(tsk, noise):
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("m,r,s,R,k", [(2048, 256, 1500, 16, 26), (14400, 900, 500, 30, 40),
-                                       (1000, 102, 301, 6, 20)])
+                                       (1000, 102, 301, 6, 20), (1000, 200, 4004, 8, 17),
+                                       (1500, 160, 2000, 4, 12), (777, 130, 1501, 5, 30)])
 def test_rsvd_solve_large_r_low_precision(tsk, prec, m, r, s, R, k):
     """RSVD-LRLS with FP32 or BF16 operands at the shapes of the 10000^3 and
     500^3 jobs (the vectorised FP32 / BF16 matrix-core products: r = 900 has
     rows of 900 elements, 8-byte but not 16-byte aligned; r = 102 and s = 301
-    leave ragged tiles).  The operands are rounded on the host and the oracle
+    leave ragged tiles).  With FP32 operands, rows of Y of a multiple of 4
+    elements and k <= 32, the products with Y take the skinny streaming
+    kernel: m = 1000 and s = 4004 leave ragged 64-row tiles and contraction
+    ranges, k = 17 one column in the second 16-column tile, k = 12 none;
+    s = 1501 (rows not a multiple of 4) takes the tiled kernel instead.  The
+    operands are rounded on the host and the oracle
     runs on the rounded values in FP64.  In the O(m s k) order the library
     also rounds the test matrix Omega and the product Z P to the operand type
     before the products with Y: the rank-R solution X = W A^T is within 1e-5
