@@ -230,9 +230,14 @@ def group_work(w, solve="exact"):
         "solve_la": ("mfma", subs * la, PEAK_TFLOPS["f64"], "TFLOP/s"),
         # tridiagonalisation + back-transformation of R vectors (FP64 vector ALU)
         "eig": ("alu", subs * eig(q_eig) + (N - 1) * eig(k1), FP64_VECTOR_TFLOPS, "TFLOP/s"),
-        # after the last sweep: sparse, per entry the core contraction
-        # R^3 + R^2 + R multiply-adds (FP64); dense, the tensor read once
+        # after the last sweep: dense, the tensor read once; sparse order 3 of
+        # rank 16 from 2^16 entries (entries grouped by their last index),
+        # W = C x_3 A^(3) and R^2 multiply-adds per entry on the FP64 matrix
+        # cores; other sparse shapes, per entry the core contraction
+        # R^3 + R^2 + R multiply-adds (FP64 vector ALU)
         "fit": (("hbm", nnz * vb, HBM_PEAK_GBS, "GB/s") if dense else
+                ("mfma", 2.0 * (nnz * R ** 2 + s * R ** 3), PEAK_TFLOPS["f64"], "TFLOP/s")
+                if N == 3 and R == 16 and all(x == R for x in w.ranks) and nnz >= (1 << 16) else
                 ("alu", nnz * 2.0 * (R ** 3 + R ** 2 + R), FP64_VECTOR_TFLOPS, "TFLOP/s")),
         # CP-ALS on the core and the CP residual against the dense tensor
         "cp_core": ("hbm", nnz * vb, HBM_PEAK_GBS, "GB/s"),

@@ -565,12 +565,14 @@ __global__ __launch_bounds__(kYsT) void k_gemm_yskinny(int64_t M, int N, int64_t
     brow[nt] = Bt + int64_t(n < N ? n : N - 1) * ldbt;
   }
   const bool bv0 = li < N, bv1 = 16 + li < N;
-  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+  // one 16-index step: B (and A when A_MK) as float4 loads, masked past ke
+  auto load = [&](int64_t k0, float (&a)[4][4], float (&b)[2][4]) {
     const int64_t k = k0 + 4 * g;
-    float a[4][4], b[2][4];
+    const bool kin = k0 < ke;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
-      const float4 v = *reinterpret_cast<const float4*>(brow[nt] + k);  // k < ceil16(K) <= ldbt
+      float4 v = float4{0.f, 0.f, 0.f, 0.f};
+      if (kin) v = *reinterpret_cast<const float4*>(brow[nt] + k);  // k < ceil16(K) <= ldbt
       b[nt][0] = v.x, b[nt][1] = v.y, b[nt][2] = v.z, b[nt][3] = v.w;
     }
     if (!bv0)
@@ -589,7 +591,7 @@ __global__ __launch_bounds__(kYsT) void k_gemm_yskinny(int64_t M, int N, int64_t
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int64_t kt = k + t < ke ? k + t : ke - 1;
-          const float x = A[kt * lda + ia[sm]];
+          const float x = kin ? A[kt * lda + ia[sm]] : 0.f;
           a[sm][t] = k + t < ke ? x : 0.f;
         }
       }
@@ -597,6 +599,8 @@ __global__ __launch_bounds__(kYsT) void k_gemm_yskinny(int64_t M, int N, int64_t
 #pragma unroll
         for (int t = 0; t < 4; ++t) a[sm][t] = 0.f;
     }
+  };
+  auto mma = [&](const float (&a)[4][4], const float (&b)[2][4]) {
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -605,6 +609,21 @@ __global__ __launch_bounds__(kYsT) void k_gemm_yskinny(int64_t M, int N, int64_t
         for (int nt = 0; nt < 2; ++nt)
           acc[sm][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[sm][t], b[nt][t], acc[sm][nt], 0,
                                                               0, 0);
+  };
+  if (A_MK) {  // two steps' loads in flight before their products
+    for (int64_t k0 = kb; k0 < ke; k0 += 32) {
+      float a0[4][4], b0[2][4], a1[4][4], b1[2][4];
+      load(k0, a0, b0);
+      load(k0 + 16, a1, b1);
+      mma(a0, b0);
+      mma(a1, b1);
+    }
+  } else {
+    for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+      float a0[4][4], b0[2][4];
+      load(k0, a0, b0);
+      mma(a0, b0);
+    }
   }
   if (wave > 0)
 #pragma unroll
@@ -829,9 +848,10 @@ tsk_status gemm_yskinny_f32(bool a_mk, int64_t M, int64_t N, int64_t K, const fl
                             int64_t lda, const float* Bt, int64_t ldbt, double* C, int64_t ldc,
                             Ws& ws, hipStream_t st) {
   // ranges of 4 kcw indices (kcw a multiple of 16) so that there are about 512
-  // workgroups
+  // workgroups (A_MK, two steps in flight per wave) or 1024 (K x M, one step)
   const int64_t tm = ceil_div(M, 64);
-  int64_t nr = std::max<int64_t>(1, std::min<int64_t>(ceil_div(512, tm), ceil_div(K, 64)));
+  const int64_t target = a_mk ? 512 : 1024;
+  int64_t nr = std::max<int64_t>(1, std::min<int64_t>(ceil_div(target, tm), ceil_div(K, 64)));
   const int64_t kcw = ceil_div(ceil_div(K, 4 * nr), 16) * 16;
   nr = ceil_div(K, 4 * kcw);
   double* part = nr > 1 ? ws.take<double>(size_t(nr) * M * N) : nullptr;
