@@ -31,8 +31,13 @@
  *    documented as synchronous synchronise `stream` before returning.
  *  - No C++ exception crosses the ABI.  On error the outputs are undefined and
  *    tsk_last_error() (thread-local) describes the failure.
- *  - Calls on different streams with different workspaces are independent; the
- *    only global state is the thread-local error message.
+ *  - Calls on different streams with different workspaces are independent.
+ *    Global state: the thread-local error message; one internal stream per
+ *    device (default priority, created on first use) on which the randomized
+ *    solve and the driver run work beside their own (the blocked Gram
+ *    inverse, the residual's sort), always joined back into `stream` before
+ *    the work that reads it, so ordering on `stream` is as if all ran there;
+ *    and the static scratch of tsk_rsvd_solve_noalloc.
  */
 #ifndef TSK_H
 #define TSK_H
@@ -161,8 +166,10 @@ tsk_status tsk_profile_read(const char* name, double* total_ms, int64_t* launche
 /* ---------------------------------------------------------------------- */
 /* Workspace size of tsk_tucker_sketch_als for this tensor, ranks and options.
  * Validation errors are reported without touching the device.  Leverage
- * sampling of a COO tensor and deterministic selection include the scratch of
- * a device radix sort, whose size depends on the current device: on a host
+ * sampling of a COO tensor, deterministic selection, and the residual of an
+ * order-3 COO tensor of ranks (16, 16, 16) with at least 2^16 entries (a
+ * copy of the entries sorted by their last index) include the scratch of a
+ * device radix sort, whose size depends on the current device: on a host
  * without one that part of the query fails with EHIP. */
 tsk_status tsk_workspace_size(const tsk_tensor* T, const int32_t* ranks,
                               const tsk_options* opt, size_t* bytes);
@@ -394,8 +401,13 @@ tsk_status tsk_sketch_lev_coo(const tsk_tensor* T, int32_t n, const void* index,
                               void* stream);
 
 /* Relative residual ||T - C x_1 A^(1) ... x_N A^(N)||_F / ||T||_F (Sec. 7,
- * 1 - fitness), accumulated in FP64 as ||T||^2 - 2 <T, T~> + ||T~||^2.
- * Synchronous; result in *rel_residual (host). */
+ * 1 - fitness), accumulated in FP64 as ||T||^2 - 2 <T, T~> + ||T~||^2.  For a
+ * COO tensor ||T||^2 is the sum of the squares of the stored values, so its
+ * coordinates must be distinct (duplicates are not merged here, unlike in the
+ * sketches).  Order-3 COO tensors of ranks (16, 16, 16) with at least 2^16
+ * entries are sorted by their last index (in the workspace) and take
+ * <T, T~> as u0^T W_k u1, W_k = C x_3 A^(3)(k, :); other shapes entry by
+ * entry.  Synchronous; result in *rel_residual (host). */
 tsk_status tsk_fit(const tsk_tensor* T, const int32_t* ranks, const double* core,
                    const double* const* factors, double* rel_residual, void* ws,
                    size_t* ws_bytes, void* stream);
