@@ -16,6 +16,7 @@ namespace tsk {
 
 namespace {
 
+constexpr int64_t kTableLdsBytes = 160 * 1024;  // LDS of one workgroup on gfx950
 constexpr int kFftBlock = 512;
 constexpr int kMaxRadices = 48;
 
@@ -183,10 +184,14 @@ __global__ __launch_bounds__(64) void k_inverse_hash(const int32_t* h, int s, in
   }
 }
 
-// The same table with h staged in LDS by a 256-thread workgroup (all loads in
-// flight, counts by every thread) and the ordered scan and placement by wave 0
-// out of LDS; for (m + 1 + s) * 4 bytes within 64 KiB.  One workgroup per
-// table of the batch; the hash tables themselves come from k_hash_table_batch.
+// The same table by a 256-thread workgroup with h staged in LDS (all loads in
+// flight): the items are cut into four contiguous quarters, one per wave;
+// each wave counts its quarter per bucket, wave 0 scans the bucket totals,
+// every bucket's start is split between the waves in wave order, and the
+// waves place their quarters at once, each as the one-wave kernel does (rows
+// still increase within a bucket).  For (5 (m + 1) + s) * 4 bytes of LDS
+// within kTableLdsBytes.  One workgroup per table of the batch; the hash
+// tables themselves come from k_hash_table_batch.
 __global__ void k_hash_table_batch(TableBatch b, uint64_t m) {
   const int q = blockIdx.y;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -203,40 +208,63 @@ __global__ __launch_bounds__(256) void k_inverse_hash_lds(TableBatch tb, int m) 
   const int s = int(tb.s[q]);
   int32_t* ptr = tb.csr[q].ptr;
   int32_t* items = tb.csr[q].items;
-  int32_t* cur = sh;          // m + 1
-  int32_t* hs = sh + m + 1;   // s
-  const int tid = threadIdx.x, lane = tid & 63;
-  for (int b = tid; b <= m; b += 256) cur[b] = 0;
+  int32_t* cur = sh;                // m + 1: bucket starts
+  int32_t* wc = sh + (m + 1);       // 4 x (m + 1): per-wave counts, then cursors
+  int32_t* hs = sh + 5 * (m + 1);   // s
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int b = tid; b < 5 * (m + 1); b += 256) sh[b] = 0;
 #pragma unroll 4
   for (int i = tid; i < s; i += 256) hs[i] = h[i];
   __syncthreads();
-  for (int i = tid; i < s; i += 256) atomicAdd(&cur[hs[i] + 1], 1);
+  const int quarter = (s + 255) / 256 * 64;  // multiple of 64
+  const int i_lo = wave * quarter, i_hi = min(s, i_lo + quarter);
+  int32_t* mine = wc + wave * (m + 1);
+  for (int i = i_lo + lane; i < i_hi; i += 64) atomicAdd(&mine[hs[i]], 1);
   __syncthreads();
-  if (tid >= 64) return;  // one wave from here on: no more block barriers
-  const int chunk = (m + 1 + 63) / 64;
-  const int b0 = lane * chunk, b1 = b0 + chunk < m + 1 ? b0 + chunk : m + 1;
-  int32_t run = 0;
-  for (int b = b0; b < b1; ++b) run += cur[b];
-  int32_t incl = run;
-  for (int off = 1; off < 64; off <<= 1) {
-    int32_t o = __shfl_up(incl, off);
-    if (lane >= off) incl += o;
+  if (wave == 0) {
+    // totals of bucket b - 1 at b, inclusive scan = bucket starts
+    const int chunk = (m + 1 + 63) / 64;
+    const int b0 = lane * chunk, b1 = b0 + chunk < m + 1 ? b0 + chunk : m + 1;
+    int32_t run = 0;
+    for (int b = b0; b < b1; ++b) {
+      const int32_t t = b == 0 ? 0
+                               : wc[b - 1] + wc[(m + 1) + b - 1] + wc[2 * (m + 1) + b - 1] +
+                                     wc[3 * (m + 1) + b - 1];
+      cur[b] = t;
+      run += t;
+    }
+    int32_t incl = run;
+    for (int off = 1; off < 64; off <<= 1) {
+      int32_t o = __shfl_up(incl, off);
+      if (lane >= off) incl += o;
+    }
+    int32_t base = incl - run;
+    for (int b = b0; b < b1; ++b) {
+      base += cur[b];
+      cur[b] = base;
+      ptr[b] = base;
+    }
   }
-  int32_t base = incl - run;
-  for (int b = b0; b < b1; ++b) {
-    base += cur[b];
-    cur[b] = base;
-    ptr[b] = base;
+  __syncthreads();
+  // wave w's cursor of bucket b (over its count): the bucket's start plus
+  // the counts of the waves before w
+  for (int b = tid; b < m; b += 256) {
+    int32_t c = cur[b];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      int32_t* ww = wc + w * (m + 1);
+      const int32_t n = ww[b];
+      ww[b] = c;
+      c += n;
+    }
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __syncthreads();
   int bits = 1;
   while ((1 << bits) < m) ++bits;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  for (int i0 = 0; i0 < s; i0 += 64) {
+  for (int i0 = i_lo; i0 < i_hi; i0 += 64) {
     const int i = i0 + lane;
-    const bool valid = i < s;
+    const bool valid = i < i_hi;
     const uint32_t key = valid ? uint32_t(hs[i]) : 0u;
     uint64_t mt = __ballot(valid);
     for (int bt = 0; bt < bits; ++bt) {
@@ -247,8 +275,8 @@ __global__ __launch_bounds__(256) void k_inverse_hash_lds(TableBatch tb, int m) 
     const int rank = __popcll(mt & lt);
     int bs = 0;
     if (valid && rank == 0) {
-      bs = cur[key];
-      cur[key] = bs + __popcll(mt);
+      bs = mine[key];
+      mine[key] = bs + __popcll(mt);
     }
     const int leader = valid ? __ffsll((unsigned long long)mt) - 1 : lane;
     bs = __shfl(bs, leader);
@@ -451,8 +479,8 @@ tsk_status build_inverse_hash(const int32_t* h, int64_t s, int64_t m, CsrTable c
     tb.s[0] = s;
     tb.h[0] = const_cast<int32_t*>(h);
     tb.csr[0] = csr;
-    hipLaunchKernelGGL(k_inverse_hash_lds, dim3(1), dim3(256), size_t(m + 1 + s) * 4, st, tb,
-                       int(m));
+    hipLaunchKernelGGL(k_inverse_hash_lds, dim3(1), dim3(256), size_t(5 * (m + 1) + s) * 4, st,
+                       tb, int(m));
   } else {
     hipLaunchKernelGGL(k_inverse_hash, dim3(1), dim3(64), size_t(m + 1) * 4, st, h, int(s),
                        int(m), csr.ptr, csr.items);
@@ -461,7 +489,11 @@ tsk_status build_inverse_hash(const int32_t* h, int64_t s, int64_t m, CsrTable c
   return TSK_OK;
 }
 
-bool table_batch_fits(int64_t s, int64_t m) { return (m + 1 + s) * 4 <= 65536; }
+static int fft_max_lds();
+
+bool table_batch_fits(int64_t s, int64_t m) {
+  return (5 * (m + 1) + s) * 4 <= std::min<int64_t>(kTableLdsBytes, fft_max_lds());
+}
 
 tsk_status hash_tables_batch(const TableBatch& b, int64_t m, hipStream_t st) {
   if (b.n <= 0) return TSK_OK;
@@ -474,7 +506,7 @@ tsk_status hash_tables_batch(const TableBatch& b, int64_t m, hipStream_t st) {
                      dim3(256), 0, st, b, uint64_t(m));
   TSK_LAUNCHED();
   hipLaunchKernelGGL(k_inverse_hash_lds, dim3(unsigned(b.n)), dim3(256),
-                     size_t(m + 1 + smax) * 4, st, b, int(m));
+                     size_t(5 * (m + 1) + smax) * 4, st, b, int(m));
   TSK_LAUNCHED();
   return TSK_OK;
 }
