@@ -1067,7 +1067,7 @@ __global__ __launch_bounds__(64) void k_qr_rows(const double* Ct, int k, int r, 
 // X_p R_p^{-1}; after three passes Q = X_3 has orthonormal columns to working
 // precision whenever C has full numerical column rank.  The kernel first runs
 // the first pass unshifted: if its factor is well conditioned (largest over
-// smallest diagonal entry of R at most 1e4) and the second pass finds X_1
+// smallest diagonal entry of R at most 1e6) and the second pass finds X_1
 // nearly orthonormal (every diagonal entry of its R within 0.1 of 1), the two
 // plain passes finish (Cholesky QR2, Yamamoto et al., ETNA 2015); otherwise it
 // restarts from C with the three shifted passes.  Any orthonormal basis
@@ -1077,7 +1077,7 @@ __global__ __launch_bounds__(64) void k_qr_rows(const double* Ct, int k, int r, 
 // right-hand side) sets *fallback, and the Householder kernel that follows in
 // the stream runs only then.
 //
-// One workgroup of 4 waves, k <= KP (32 or 64).  Grams: FP64 MFMA 16x16x4
+// One workgroup of 4 waves, k <= KP (32, 48 or 64).  Grams: FP64 MFMA 16x16x4
 // over 64-column blocks of X_p^T (block b to wave b mod 4), wave partials
 // summed in LDS in a fixed order.  Cholesky in LDS with every thread in the
 // trailing updates; the triangular inverse by wave 0.  X_{p+1}^T = R_p^{-T} X_p^T: MFMA over 16-column pieces of the same
@@ -1176,10 +1176,11 @@ __global__ __launch_bounds__(256) void k_cholqr3(const double* Ct, int k, int r,
     }
     if (!shifted) {
       // Cholesky QR2 leaves O(u) orthogonality for kappa(C) well below
-      // u^{-1/2}.  First pass: the ratio of the largest to the smallest
-      // diagonal entry of R (a lower bound on kappa(C)) at most 1e4.  Second
-      // pass: X_1 must already be nearly orthonormal, every R_jj within 0.1 of
-      // 1 (X_1^T X_1 = R^T R).  Otherwise restart with the shifted passes.
+      // u^{-1/2} (about 7e7).  First pass: the ratio of the largest to the
+      // smallest diagonal entry of R (a lower bound on kappa(C)) at most 1e6.
+      // Second pass: X_1 must already be nearly orthonormal, every R_jj within
+      // 0.1 of 1 (X_1^T X_1 = R^T R), which also catches a kappa(C) that the
+      // ratio underestimates.  Otherwise restart with the shifted passes.
       if (wave == 0) {
         double dmax = lane < k ? Gs[lane * SL + lane] : 0.0;
         double dmin = lane < k ? Gs[lane * SL + lane] : DBL_MAX;
@@ -1187,7 +1188,7 @@ __global__ __launch_bounds__(256) void k_cholqr3(const double* Ct, int k, int r,
           dmax = fmax(dmax, __shfl_xor(dmax, off));
           dmin = fmin(dmin, __shfl_xor(dmin, off));
         }
-        const bool ok = pass == 0 ? dmax <= 1e4 * dmin : (dmax <= 1.1 && dmin >= 0.9);
+        const bool ok = pass == 0 ? dmax <= 1e6 * dmin : (dmax <= 1.1 && dmin >= 0.9);
         if (lane == 0 && (bad || !ok)) restart = 1;
       }
       __syncthreads();
@@ -2194,6 +2195,9 @@ tsk_status qr_rows(const double* Ct, int64_t k, int64_t r, double* Qt, Ws& ws, h
   if (chol) {
     if (k <= 32)
       hipLaunchKernelGGL(k_cholqr3<32>, dim3(1), dim3(256), size_t(2) * 32 * 33 * 8, st, Ct,
+                         int(k), int(r), X1, X2, Qt, flag);
+    else if (k <= 48)  // three 16-wide tiles: 44 % less matrix-core work than 64
+      hipLaunchKernelGGL(k_cholqr3<48>, dim3(1), dim3(256), size_t(2) * 48 * 49 * 8, st, Ct,
                          int(k), int(r), X1, X2, Qt, flag);
     else
       hipLaunchKernelGGL(k_cholqr3<64>, dim3(1), dim3(256), size_t(2) * 64 * 65 * 8, st, Ct,

@@ -548,10 +548,12 @@ def test_rsvd_solve_large_r_fp64(tsk, m, r, s, R, k):
 def test_rsvd_solve_range_basis_conditioning(tsk, noise):
     """The thin QR of C = B Z^T Y Omega at r = 256, k = 26 with Y of rank R = 16
     plus noise: C has R large and k - R small singular values, so kappa(C)
-    grows as the noise shrinks.  Noise 1e-2 keeps two plain Cholesky QR passes,
-    1e-6 and 1e-9 make the first factor ill conditioned and the kernel restart
-    with the three shifted passes.  FP64 against the oracle: the rank-R
-    solution W A^T within 1e-9 relative."""
+    grows as the noise shrinks.  Noise 1e-2 (kappa(C) 5.2e4, first-factor
+    diagonal ratio 1.4e4) keeps two plain Cholesky QR passes; at 1e-6 and 1e-9
+    the first unshifted Cholesky factorisation breaks down (the Gram of C is
+    not numerically positive definite) and the kernel restarts with the three
+    shifted passes.  FP64 against the oracle: the rank-R solution W A^T within
+    1e-9 relative."""
     rs = np.random.default_rng(31)
     m, r, s, R, k = 2048, 256, 1500, 16, 26
     Z = rs.standard_normal((m, r))
