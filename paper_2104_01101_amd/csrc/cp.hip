@@ -100,6 +100,54 @@ __global__ __launch_bounds__(kMtT) void k_mttkrp(const double* C, CoreDesc cd, F
   }
 }
 
+// The same sums for order-3 cores with the core slice of row i and the two
+// other factors staged in LDS (dynamic: Ra Rb + (Ra + Rb) Rc doubles, a < b
+// the other modes): the same tuples u = rho_a Rb + rho_b in the same order per
+// thread, the same products (A_b then A_a) and the same chunk sums, so the
+// result is that of k_mttkrp bit for bit, without its 64-bit index
+// arithmetic and dependent global loads.
+__global__ __launch_bounds__(kMtT) void k_mttkrp3(const double* C, CoreDesc cd, Facs f, int n,
+                                                  int Rc, double* M) {
+  extern __shared__ double ms[];
+  __shared__ double part[kMtT];
+  const int i = blockIdx.x;
+  const int a = n == 0 ? 1 : 0, b = n == 2 ? 1 : 2;
+  const int Ra = int(cd.R[a]), Rb = int(cd.R[b]), R1 = int(cd.R[1]), R2 = int(cd.R[2]);
+  const int other = Ra * Rb;
+  double* S = ms;                    // S[u] = C at (rho_n = i, rho_a, rho_b), u = rho_a Rb + rho_b
+  double* Fa = ms + other;           // Ra x Rc
+  double* Fb = Fa + Ra * Rc;         // Rb x Rc
+  const int tid = threadIdx.x;
+  for (int u = tid; u < other; u += kMtT) {
+    const int ra = u / Rb, rb = u - ra * Rb;
+    const int p = n == 0 ? (i * R1 + ra) * R2 + rb
+                  : n == 1 ? (ra * R1 + i) * R2 + rb
+                           : (ra * R1 + rb) * R2 + i;
+    S[u] = C[p];
+  }
+  for (int t = tid; t < Ra * Rc; t += kMtT) Fa[t] = f.A[a][t];
+  for (int t = tid; t < Rb * Rc; t += kMtT) Fb[t] = f.A[b][t];
+  __syncthreads();
+  const int nchunk = Rc >= kMtT ? 1 : kMtT / Rc;
+  const int r = tid % Rc, chunk = tid / Rc;
+  double s = 0.0;
+  if (chunk < nchunk)
+    for (int u = chunk; u < other; u += nchunk) {
+      const int ra = u / Rb, rb = u - ra * Rb;
+      const double w = Fb[rb * Rc + r] * Fa[ra * Rc + r];
+      s = fma(S[u], w, s);
+    }
+  part[tid] = s;
+  __syncthreads();
+  if (tid < Rc) {
+    double t = 0.0;
+    for (int c = 0; c < nchunk; ++c) t += part[c * Rc + tid];
+    M[int64_t(i) * Rc + tid] = t;
+  }
+}
+
+constexpr size_t kMttkrp3Lds = 64 * 1024;
+
 // Khatri-Rao product of the factors of modes 1..N-1, transposed:
 // KR[r][j] = prod_{k >= 1} F_k[j_k][r], j the row-major index of (j_1, .., j_{N-1})
 __global__ void k_khatri_rao_t(CpFitArgs a, int64_t J, double* KR) {
@@ -264,8 +312,15 @@ tsk_status cp_run(const TensorView& T, const int64_t* R, int Rc, int sweeps,
         TSK_TRY(spd_inverse_blocked(Gam, Rc, Rc, P, Rc, info, ws, st));
       }
       if (run) {
-        hipLaunchKernelGGL(k_mttkrp, dim3(unsigned(R[n])), dim3(kMtT), 0, st, tb.core, cd, f, n,
-                           int64_t(Rc), M);
+        const int a3 = n == 0 ? 1 : 0, b3 = n == 2 ? 1 : 2;
+        const size_t lds3 =
+            N == 3 ? size_t(R[a3] * R[b3] + (R[a3] + R[b3]) * Rc) * 8 : kMttkrp3Lds + 1;
+        if (lds3 <= kMttkrp3Lds && Rc <= kMtT)
+          hipLaunchKernelGGL(k_mttkrp3, dim3(unsigned(R[n])), dim3(kMtT), lds3, st, tb.core, cd,
+                             f, n, int(Rc), M);
+        else
+          hipLaunchKernelGGL(k_mttkrp, dim3(unsigned(R[n])), dim3(kMtT), 0, st, tb.core, cd, f,
+                             n, int64_t(Rc), M);
         TSK_LAUNCHED();
         TSK_TRY(gemm_small(R[n], Rc, Rc, 1.0, M, Rc, 1, Pinv, Rc, 1, 0.0, A[n], Rc, st));
       }
