@@ -106,8 +106,12 @@ __global__ __launch_bounds__(kMtT) void k_mttkrp(const double* C, CoreDesc cd, F
 // thread, the same products (A_b then A_a) and the same chunk sums, so the
 // result is that of k_mttkrp bit for bit, without its 64-bit index
 // arithmetic and dependent global loads.
+//
+// With P (Rc x Rc) the row of the updated factor follows in the same launch:
+// A[i][c] = sum_r M[i][r] P[r][c], summed as gemm_small does (r in order).
 __global__ __launch_bounds__(kMtT) void k_mttkrp3(const double* C, CoreDesc cd, Facs f, int n,
-                                                  int Rc, double* M) {
+                                                  int Rc, double* M, const double* P,
+                                                  double* A) {
   extern __shared__ double ms[];
   __shared__ double part[kMtT];
   const int i = blockIdx.x;
@@ -139,10 +143,19 @@ __global__ __launch_bounds__(kMtT) void k_mttkrp3(const double* C, CoreDesc cd, 
     }
   part[tid] = s;
   __syncthreads();
+  double t = 0.0;
   if (tid < Rc) {
-    double t = 0.0;
     for (int c = 0; c < nchunk; ++c) t += part[c * Rc + tid];
-    M[int64_t(i) * Rc + tid] = t;
+    if (!P) M[int64_t(i) * Rc + tid] = t;
+  }
+  if (!P) return;
+  __syncthreads();  // every thread has read its chunk sums
+  if (tid < Rc) part[tid] = t;
+  __syncthreads();
+  if (tid < Rc) {
+    double acc = 0.0;
+    for (int r2 = 0; r2 < Rc; ++r2) acc += part[r2] * P[r2 * Rc + tid];
+    A[int64_t(i) * Rc + tid] = 1.0 * acc;
   }
 }
 
@@ -315,14 +328,16 @@ tsk_status cp_run(const TensorView& T, const int64_t* R, int Rc, int sweeps,
         const int a3 = n == 0 ? 1 : 0, b3 = n == 2 ? 1 : 2;
         const size_t lds3 =
             N == 3 ? size_t(R[a3] * R[b3] + (R[a3] + R[b3]) * Rc) * 8 : kMttkrp3Lds + 1;
-        if (lds3 <= kMttkrp3Lds && Rc <= kMtT)
+        if (lds3 <= kMttkrp3Lds && Rc <= kMtT) {  // the factor row in the same launch
           hipLaunchKernelGGL(k_mttkrp3, dim3(unsigned(R[n])), dim3(kMtT), lds3, st, tb.core, cd,
-                             f, n, int(Rc), M);
-        else
+                             f, n, int(Rc), M, Pinv, A[n]);
+          TSK_LAUNCHED();
+        } else {
           hipLaunchKernelGGL(k_mttkrp, dim3(unsigned(R[n])), dim3(kMtT), 0, st, tb.core, cd, f,
                              n, int64_t(Rc), M);
-        TSK_LAUNCHED();
-        TSK_TRY(gemm_small(R[n], Rc, Rc, 1.0, M, Rc, 1, Pinv, Rc, 1, 0.0, A[n], Rc, st));
+          TSK_LAUNCHED();
+          TSK_TRY(gemm_small(R[n], Rc, Rc, 1.0, M, Rc, 1, Pinv, Rc, 1, 0.0, A[n], Rc, st));
+        }
       }
       release();
     }
