@@ -446,7 +446,26 @@ __global__ __launch_bounds__(kT) void k_fit_dense(const V* __restrict__ X, const
     double m[RM];
 #pragma unroll
     for (int a = 0; a < RM; ++a) m[a] = a < R1 ? M[a * J + j] : 0.0;
-    for (int64_t i = 0; i < s1; ++i) {
+    // rows eight at a time with their loads in flight together; the sums
+    // still run over i in order
+    int64_t i = 0;
+    for (; i + 8 <= s1; i += 8) {
+      double v8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v8[u] = double(X[(i + u) * J + j]);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double* ar = A1 + (i + u) * R1;
+        double t = 0.0;
+#pragma unroll
+        for (int a = 0; a < RM; ++a)
+          if (a < R1) t = fma(ar[a], m[a], t);
+        const double d = v8[u] - t;
+        acc = fma(d, d, acc);
+        nrm = fma(v8[u], v8[u], nrm);
+      }
+    }
+    for (; i < s1; ++i) {
       const double* ar = A1 + i * R1;
       double t = 0.0;
 #pragma unroll
