@@ -2146,12 +2146,18 @@ tsk_status sym_eig_top(double* M, int64_t q, int64_t R, double* lam, double* V, 
     set_error("eigenproblem of order %lld exceeds the LDS budget", (long long)q);
     return TSK_EUNSUPPORTED;
   }
+  // everything in LDS when it fits; else the matrix (read and updated in
+  // every tridiagonalisation step) before the inverse-iteration vectors
   const bool m_lds = sbytes + mbytes + vbytes <= budget;
-  const bool v_lds = sbytes + (m_lds ? mbytes : 0) + vbytes <= budget;
-  const size_t lds = sbytes + (m_lds ? mbytes : 0) + (v_lds ? vbytes : 0);
+  const bool m_only = !m_lds && sbytes + mbytes <= budget;
+  const bool v_lds = !m_only && sbytes + (m_lds ? mbytes : 0) + vbytes <= budget;
+  const size_t lds = sbytes + (m_lds || m_only ? mbytes : 0) + (v_lds ? vbytes : 0);
   ProfScope prof("eig", st);
   if (m_lds)
     hipLaunchKernelGGL((k_sym_eig_top<kEigT, true, true>), dim3(1), dim3(kEigT), lds, st, M,
+                       int(q), int(R), lam, V, scratch, pivs, nt);
+  else if (m_only)
+    hipLaunchKernelGGL((k_sym_eig_top<kEigT, true, false>), dim3(1), dim3(kEigT), lds, st, M,
                        int(q), int(R), lam, V, scratch, pivs, nt);
   else if (v_lds)
     hipLaunchKernelGGL((k_sym_eig_top<kEigT, false, true>), dim3(1), dim3(kEigT), lds, st, M,
