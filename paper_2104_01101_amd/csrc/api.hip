@@ -365,18 +365,10 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
   FitScratch fs{};
   if (record) TSK_TRY(fit_plan(T, a.R, fs, ws));
   // The residual's sorted copy of the entries depends on the tensor alone: it
-  // is built on a side stream beside the preparation and the sweeps, and
-  // joined before the first residual.
+  // is built on a side stream beside the sweeps (chains of small launches
+  // that leave most of the chip idle; the passes over the entries before them
+  // do not), and joined before the first residual.
   SideJob presort(st);
-  if (run && record && fs.by_last && !ws.serial) {
-    hipStream_t side = nullptr;
-    TSK_TRY(side_stream(&side));
-    if (side) {
-      TSK_TRY(presort.fork(side));
-      TSK_TRY(fit_presort(T, fs, side));
-      TSK_TRY(presort.done());
-    }
-  }
 
   const size_t mark = ws.off;
   size_t peak = mark;
@@ -473,6 +465,16 @@ tsk_status run_tucker(TuckerArgs& a, Ws& ws) {
         }
       }
     TSK_TRY(launch_gauss_batch(gb, st));
+  }
+
+  if (run && record && fs.by_last && !ws.serial) {
+    hipStream_t side = nullptr;
+    TSK_TRY(side_stream(&side));
+    if (side) {
+      TSK_TRY(presort.fork(side));
+      TSK_TRY(fit_presort(T, fs, side));
+      TSK_TRY(presort.done());
+    }
   }
 
   // ---- sweeps (Alg. 4) ----
